@@ -1,0 +1,212 @@
+"""TEST INFRASTRUCTURE -- NOT PART OF THE PRODUCT.
+
+ctypes wrapper of the plain C++ HSIG reference (``hsig_ref.cpp``): the build by
+Alg. 6 (with Alg. 1, 4, 5 and the skip list), the plain HNSW build by Alg. 3,
+the search strategies of Sec. 4.2 and the index file.  Only the tests, the
+smoke check and the CPU-baseline leg of the benchmark may import it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hsig_ref.cpp")
+_LIB = os.path.join(_HERE, "liboracle_hsig.so")
+
+AUTO, PRE, HYBRID, POST = 0, 1, 2, 3
+# per-query counters written by search(): see the C_* enum in hsig_ref.cpp
+NDIST, NEXP, NVISIT0, MAXCAND, MAXLIVE, STRAT, LO, HI, NCOUNT = range(9)
+
+
+def compile_oracle(force: bool = False) -> str:
+    """Compiles the reference with g++ (no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-fno-fast-math", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = C.CDLL(compile_oracle())
+        P, I64, I32, D, F = C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_float
+        L.orc_build.restype = P
+        L.orc_build.argtypes = [P, P, P, I64, I32, I32, I32, I32, I32, D, C.c_uint64, I32]
+        L.orc_read.restype = P
+        L.orc_read.argtypes = [C.c_char_p]
+        L.orc_write.restype = I32
+        L.orc_write.argtypes = [P, C.c_char_p]
+        L.orc_free.argtypes = [P]
+        L.orc_info.argtypes = [P, P]
+        L.orc_last_error.restype = C.c_char_p
+        L.orc_dist32.restype = F
+        L.orc_dist32.argtypes = [P, P, I32]
+        L.orc_level_of.restype = I32
+        L.orc_level_of.argtypes = [D, D]
+        L.orc_dist64.restype = D
+        L.orc_dist64.argtypes = [P, P, I32]
+        L.orc_search.restype = I32
+        L.orc_search.argtypes = [P, P, I64, P, P, I32, I32, I32, I32, I32, D, D, P, P, P, I32]
+        L.orc_layer_search.restype = I32
+        L.orc_layer_search.argtypes = [P, P, I32, I32, I32, I32, I32, I32, I32, I32, I64, I64, P, P]
+        L.orc_prune.restype = I32
+        L.orc_prune.argtypes = [P, P, I32, I32, I32, P]
+        L.orc_get_attr.argtypes = [P, P]
+        L.orc_get_ext.argtypes = [P, P]
+        L.orc_get_level.argtypes = [P, P]
+        L.orc_get_segments.argtypes = [P, P, P, P]
+        L.orc_get_layer.argtypes = [P, I32, P, P]
+        L.orc_skiplist_range.restype = I64
+        L.orc_skiplist_range.argtypes = [P, I64, I64, P, I64]
+        L.orc_build_chunk.restype = I32
+        L.orc_build_chunk.argtypes = [P, I64, I32, I32, P, I32]
+        L.orc_build_level.restype = I32
+        L.orc_build_level.argtypes = [P, I64]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def dist32(q: np.ndarray, x: np.ndarray) -> np.float32:
+    q = np.ascontiguousarray(q, np.float32)
+    x = np.ascontiguousarray(x, np.float32)
+    return np.float32(lib().orc_dist32(_p(q), _p(x), q.shape[0]))
+
+
+def dist64(q: np.ndarray, x: np.ndarray) -> float:
+    q = np.ascontiguousarray(q, np.float32)
+    x = np.ascontiguousarray(x, np.float32)
+    return float(lib().orc_dist64(_p(q), _p(x), q.shape[0]))
+
+
+def level_of(u: float, M: int) -> int:
+    """Level drawn for uniform variate u with mL = 1/ln(M) (Alg. 6)."""
+    import math
+    return int(lib().orc_level_of(float(u), 1.0 / math.log(M)))
+
+
+def prune(owner: np.ndarray, cands: np.ndarray, M: int) -> list[int]:
+    owner = np.ascontiguousarray(owner, np.float32)
+    cands = np.ascontiguousarray(cands, np.float32)
+    out = np.zeros(max(1, len(cands)), np.int32)
+    c = lib().orc_prune(_p(owner), _p(cands), len(cands), owner.shape[0], M, _p(out))
+    return out[:c].tolist()
+
+
+class Index:
+    """A reference HSIG (or plain HNSW) built or read by the C++ oracle."""
+
+    def __init__(self, handle):
+        if not handle:
+            raise RuntimeError(lib().orc_last_error().decode())
+        self._h = handle
+        info = np.zeros(9, np.int64)
+        lib().orc_info(self._h, _p(info))
+        (self.n, self.d, self.S, self.M0, self.MU, self.L, self.gentry, self.R, self.ef_cons) = map(int, info)
+
+    @classmethod
+    def build(cls, X, attr, level_u, S, M, ef_cons, M0=0, mL=0.0, seed=0, hnsw=False):
+        X = np.ascontiguousarray(X, np.float32)
+        attr = np.ascontiguousarray(attr, np.int64)
+        level_u = np.ascontiguousarray(level_u, np.float64)
+        n, d = X.shape
+        h = lib().orc_build(_p(X), _p(attr), _p(level_u), n, d, S, M, M0, ef_cons, mL, seed, int(hnsw))
+        return cls(h)
+
+    @classmethod
+    def read(cls, path: str):
+        return cls(lib().orc_read(path.encode()))
+
+    def write(self, path: str) -> None:
+        rc = lib().orc_write(self._h, path.encode())
+        if rc != 0:
+            raise OSError(f"orc_write failed ({rc})")
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_free(self._h)
+            self._h = None
+
+    # --- tables of the frozen view (internal ids = attribute rank) ---
+    def attr_sorted(self):
+        a = np.zeros(self.n, np.int64)
+        lib().orc_get_attr(self._h, _p(a))
+        return a
+
+    def ext_ids(self):
+        a = np.zeros(self.n, np.int64)
+        lib().orc_get_ext(self._h, _p(a))
+        return a
+
+    def levels(self):
+        a = np.zeros(self.n, np.int32)
+        lib().orc_get_level(self._h, _p(a))
+        return a
+
+    def segments(self):
+        ss = np.zeros(self.S + 1, np.int64)
+        en = np.zeros(self.S, np.int32)
+        ml = np.zeros(self.S, np.int32)
+        lib().orc_get_segments(self._h, _p(ss), _p(en), _p(ml))
+        return ss, en, ml
+
+    def layer(self, l: int):
+        """(adj [n, S, mcap], glist [n, S*mcap]) of layer l, internal ids, -1 padded."""
+        mc = self.M0 if l == 0 else self.MU
+        adj = np.zeros((self.n, self.S, mc), np.int32)
+        gl = np.zeros((self.n, self.S * mc), np.int32)
+        lib().orc_get_layer(self._h, l, _p(adj), _p(gl))
+        return adj, gl
+
+    def skiplist_range(self, l: int, h: int):
+        out = np.zeros(self.n, np.int64)
+        c = lib().orc_skiplist_range(self._h, l, h, _p(out), self.n)
+        if c < 0:
+            raise RuntimeError("no build-side skip list (index was read from a file)")
+        return out[:c]
+
+    def build_chunk(self, v: int, l: int, j: int):
+        out = np.zeros(4096, np.int64)
+        c = lib().orc_build_chunk(self._h, v, l, j, _p(out), 4096)
+        if c < 0:
+            raise IndexError((v, l, j))
+        return out[:c].tolist()
+
+    def build_level(self, v: int) -> int:
+        return lib().orc_build_level(self._h, v)
+
+    def search(self, Q, l, h, k, ef, m=0, p=1, strategy=AUTO, tau_a=0.01, tau_b=0.5,
+               counters=False, batch_form=False):
+        Q = np.ascontiguousarray(Q, np.float32)
+        l = np.ascontiguousarray(l, np.int64)
+        h = np.ascontiguousarray(h, np.int64)
+        nq = Q.shape[0]
+        ids = np.zeros((nq, k), np.int64)
+        dist = np.zeros((nq, k), np.float32)
+        cnt = np.zeros((nq, NCOUNT), np.int64)
+        rc = lib().orc_search(self._h, _p(Q), nq, _p(l), _p(h), k, ef, m, p, strategy, tau_a, tau_b,
+                              _p(ids), _p(dist), _p(cnt), int(batch_form))
+        if rc != 0:
+            raise ValueError(lib().orc_last_error().decode())
+        return (ids, dist, cnt) if counters else (ids, dist)
+
+    def layer_search(self, q, ep, layer, ef, hybrid, a=0, b=0, c=0, filter=False, l=0, h=0):
+        q = np.ascontiguousarray(q, np.float32)
+        ids = np.zeros(max(ef, 1), np.int32)
+        dist = np.zeros(max(ef, 1), np.float32)
+        cnt = lib().orc_layer_search(self._h, _p(q), ep, layer, ef, int(hybrid), a, b, c, int(filter),
+                                     l, h, _p(ids), _p(dist))
+        return ids[:cnt], dist[:cnt]

@@ -1,0 +1,1156 @@
+// TEST INFRASTRUCTURE -- NOT PART OF THE PRODUCT.
+//
+// Plain, slow CPU reference of the HSIG index of UNIFY (Liang, Zhang, Yao,
+// Chen, Song, Cheng, "UNIFY: Unified Index for Range Filtered Approximate
+// Nearest Neighbors Search", PVLDB 18(4), 2024).  Only the test suite, the
+// smoke check and the CPU-baseline leg of the benchmark may load this code; the
+// product library shares nothing with it.
+//
+// What it computes, and where the paper defines it:
+//   * attribute segmentation by an equi-depth histogram        (Sec. 3.1; Example 2 of Sec. 3.2)
+//   * level draw of an inserted object                          (Alg. 6, "HSIGInsert")
+//   * Prune heuristic                                           (Sec. 2.2, text after Alg. 3)
+//   * ANNSearch on one layer                                    (Alg. 1)
+//   * BackboneConnectionsBuild                                  (Alg. 4)
+//   * skip-list connections (Pugh's insertion)                  (Sec. 4.1, "Fusing Skip List Connections")
+//   * GlobalEdgeMasking                                         (Alg. 5)
+//   * HSIGInsert                                                (Alg. 6)
+//   * plain HNSW InsertLayer, for the S = 1 reduction           (Alg. 3)
+//   * search strategies A (pre), B (post), C (hybrid, Alg. 7),
+//     the hierarchical scheme (Alg. 2) and the range-aware
+//     selection rule                                            (Sec. 4.2)
+//
+// Readings of passages the paper leaves open (each is listed in the design notes):
+//   R1  segment boundaries b_j = attr_sorted[floor(j n / S)], j = 1..S-1; segment j
+//       is [b_j, b_{j+1}); an object equal to a boundary goes to the higher segment.
+//   R2  level = floor(-ln(U) * mL) with U in (0,1] and mL = 1/ln(M); the printed
+//       formula places mL inside the logarithm, which is taken as a typesetting slip.
+//   R3  one chunk capacity per layer: M0 on layer 0 (default M0 = M), M above.
+//   R4  Prune: candidates sorted by (distance, id); r is dropped when an already
+//       selected e has d(e, r) < d(v, r) (strict); no refill of pruned candidates.
+//   R5  chunks stay sorted by (distance to owner, id) after every insert and prune,
+//       since the hybrid search takes the first entries of each chunk.
+//   R6  HSIGInsert visits every segment; an empty segment is skipped; when the new
+//       object's level exceeds a segment's top level, it connects only on the layers
+//       that segment has; the entry of segment j changes only when j is the object's
+//       own segment and its level is higher than the segment's top level.
+//   R7  global-edge marks are kept as target ids; a mark is dropped when its target
+//       is pruned out of the owner's chunks; Alg. 5's re-prune runs over all chunks.
+//   R8  the global entry is the first object to reach the global top level.
+//   R9  build distances are FP64; search distances are the canonical FP32 distance
+//       (dist32 below), so that a GPU implementation can match them bit for bit.
+//   R10 every comparison of two objects by distance uses the key (distance, id).
+//   R11 hybrid search: the entry is the entry of the active segment with the highest
+//       top level (ties: nearer to q, then smaller id); upper layers run the k = 1
+//       search over the active chunks with no range test; on layer 0 the entry goes
+//       into cand always and into ann only when in range; while ann holds fewer than
+//       ef objects its worst distance counts as +infinity; the active segments are
+//       those holding at least one in-range object; a chunk shorter than
+//       ceil(m/S') contributes all its entries.
+//   R12 strategy rule: pre when Y <= floor(tau_A n), post when Y >= ceil(tau_B n),
+//       hybrid otherwise (tau_A = 1%, tau_B = 50%).
+//   R13 beam width p (an extension for parallel hardware): pop up to p candidates
+//       that pass the stopping test, expand them as one batch whose admission test
+//       uses the threshold from before the batch.  For p = 1 this gives the same
+//       result as the sequential loop of Alg. 7; the tests check that.
+//
+// Pins (tests/test_oracle_*.py): Definition 1 and Eq. 1 by hand examples and a
+// library routine; dist32 by exact integer cases, a crafted rounding case and
+// the FP64 error bound; the level law P(level >= l) = M^-l; Prune by hand-built
+// cases; Example 2's segments; S = 1 HSIG = HNSW (Alg. 3) edge for edge;
+// single-segment inclusiveness = 1 and > 80% on 1..8 segments (Sec. 6.4);
+// layer search with ef >= n = brute force over the reachable set; pre-filter =
+// exact k-NN; the skip-list walk = the attribute slice; the beam form at p = 1
+// = the sequential loop.  Parity unpinned: the exact set of global-edge marks
+// that GlobalEdgeMasking leaves (only its invariants are checked: at most M
+// marks per node and layer, each mark an existing chunk edge), and the exact
+// graph the full build produces on realistic inputs (no printed graph exists).
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <queue>
+#include <string>
+#include <vector>
+
+namespace {
+
+typedef std::pair<double, int> DI;  // (FP64 distance, id): build-side key
+typedef std::pair<float, int> FI;   // (FP32 distance, internal id): search-side key
+
+// ---------------------------------------------------------------------------
+// Distances
+// ---------------------------------------------------------------------------
+
+// Squared Euclidean distance in FP64 (the paper uses Euclidean distance, Sec. 6.1).
+double dist64(const float* a, const float* b, int d) {
+  double s = 0.0;
+  for (int t = 0; t < d; ++t) {
+    double e = (double)a[t] - (double)b[t];
+    s += e * e;
+  }
+  return s;
+}
+
+// Canonical FP32 squared distance: e_t = x_t - q_t rounded to FP32; sixteen
+// partial sums, partial p takes the 4-element groups g with g mod 16 == p in
+// increasing order, each element accumulated with a fused multiply-add; then
+// a butterfly P[i] + P[i ^ s] for s = 8, 4, 2, 1.  d must be a multiple of 4.
+float dist32(const float* q, const float* x, int d) {
+  float P[16];
+  for (int i = 0; i < 16; ++i) P[i] = 0.0f;
+  const int G = d / 4;
+  for (int g = 0; g < G; ++g) {
+    float& acc = P[g % 16];
+    for (int t = 4 * g; t < 4 * g + 4; ++t) {
+      float e = x[t] - q[t];
+      acc = std::fma(e, e, acc);
+    }
+  }
+  for (int s = 8; s >= 1; s >>= 1) {
+    float T[16];
+    for (int i = 0; i < 16; ++i) T[i] = P[i] + P[i ^ s];
+    for (int i = 0; i < 16; ++i) P[i] = T[i];
+  }
+  return P[0];
+}
+
+// Level of an inserted object (Alg. 6, second step; reading R2).
+int draw_level(double u, double mL) {
+  double lv = std::floor(-std::log(u) * mL);
+  return (int)std::min(lv, 30.0);
+}
+
+// ---------------------------------------------------------------------------
+// Build (external ids, dynamic adjacency)
+// ---------------------------------------------------------------------------
+
+struct Builder {
+  int64_t n = 0;
+  int d = 0, S = 1, M = 16, M0 = 16, efCons = 100;
+  double mL = 0.0;
+  bool hnsw_mode = false;  // plain HNSW (Alg. 3): one segment, no masking
+  std::vector<float> X;        // [n][d], row = external id
+  std::vector<int64_t> attr;   // [n]
+  std::vector<int64_t> bnd;    // b_1 .. b_{S-1}
+  std::vector<int> seg, level;
+  // adj[v][l][j] = chunk j of v on layer l, sorted by (distance to v, id)
+  std::vector<std::vector<std::vector<std::vector<DI>>>> adj;
+  // marks[v][l] = global-edge targets of v on layer l (sorted ids)
+  std::vector<std::vector<std::vector<int>>> marks;
+  std::vector<int> entry, maxlev;  // per segment
+  int gentry = -1, gmax = -1;
+  // skip list: next[v][l]; the head is a separate array
+  std::vector<std::vector<int>> next;
+  std::vector<int> head_next;
+  // visited stamps for ANNSearch
+  std::vector<uint32_t> stamp;
+  uint32_t cur = 0;
+  int64_t n_inserted = 0;
+
+  const float* vec(int v) const { return &X[(size_t)v * d]; }
+  double dv(int a, int b) const { return dist64(vec(a), vec(b), d); }
+  int cap(int l) const { return l == 0 ? M0 : M; }
+
+  void new_visit() {
+    if (++cur == 0) {
+      std::fill(stamp.begin(), stamp.end(), 0u);
+      cur = 1;
+    }
+  }
+  bool seen(int v) const { return stamp[v] == cur; }
+  void see(int v) { stamp[v] = cur; }
+
+  int seg_of(int64_t a) const {
+    return (int)(std::upper_bound(bnd.begin(), bnd.end(), a) - bnd.begin());
+  }
+
+  // Prune heuristic (Sec. 2.2): candidates sorted by distance to v; r is
+  // dropped when some already selected e is closer to r than v is.
+  std::vector<DI> prune(int v, std::vector<DI> cands, int Mcap) const {
+    std::sort(cands.begin(), cands.end());
+    std::vector<DI> out;
+    for (const DI& r : cands) {
+      if ((int)out.size() >= Mcap) break;
+      if (r.second == v) continue;
+      bool keep = true;
+      for (const DI& e : out) {
+        if (dv(e.second, r.second) < r.first) {
+          keep = false;
+          break;
+        }
+      }
+      if (keep) out.push_back(r);
+    }
+    return out;
+  }
+
+  // Alg. 1 (ANNSearch) on layer l, restricted to the sub-graph of segment j:
+  // nodes of segment j, edges of their chunk j.
+  std::vector<DI> ann_search(const float* q, int ep, int ef, int l, int j) {
+    new_visit();
+    std::priority_queue<DI, std::vector<DI>, std::greater<DI>> cand;
+    std::priority_queue<DI> ann;
+    DI e0(dist64(q, vec(ep), d), ep);
+    cand.push(e0);
+    ann.push(e0);
+    see(ep);
+    while (!cand.empty()) {
+      DI o = cand.top();
+      cand.pop();
+      if (o > ann.top()) break;
+      for (const DI& nb : adj[o.second][l][j]) {
+        int v = nb.second;
+        if (seen(v)) continue;
+        see(v);
+        DI kv(dist64(q, vec(v), d), v);
+        if ((int)ann.size() < ef || kv < ann.top()) {
+          cand.push(kv);
+          ann.push(kv);
+          if ((int)ann.size() > ef) ann.pop();
+        }
+      }
+    }
+    std::vector<DI> out;
+    while (!ann.empty()) {
+      out.push_back(ann.top());
+      ann.pop();
+    }
+    std::reverse(out.begin(), out.end());
+    return out;
+  }
+
+  // Removes the marks of v on layer l whose target is no longer in v's chunks.
+  void drop_stale_marks(int v, int l, const std::vector<DI>& removed_from) {
+    (void)removed_from;
+    std::vector<int>& mk = marks[v][l];
+    std::vector<int> keep;
+    for (int t : mk) {
+      bool present = false;
+      for (const auto& ch : adj[v][l])
+        for (const DI& e : ch)
+          if (e.second == t) present = true;
+      if (present) keep.push_back(t);
+    }
+    mk.swap(keep);
+  }
+
+  // Inserts (key) into a chunk that is kept sorted (R5).
+  static void sorted_insert(std::vector<DI>& ch, DI key) {
+    ch.insert(std::upper_bound(ch.begin(), ch.end(), key), key);
+  }
+
+  // Alg. 4 (BackboneConnectionsBuild) of object v (segment i) into segment j on layer l.
+  std::vector<DI> backbone(int l, int ep, int v, int i, int j) {
+    std::vector<DI> ann = ann_search(vec(v), ep, efCons, l, j);
+    std::vector<DI> N = prune(v, ann, cap(l));
+    adj[v][l][j] = N;  // sorted by (distance to v, id)
+    for (const DI& on : N) {
+      int o = on.second;
+      std::vector<DI>& ch = adj[o][l][i];
+      sorted_insert(ch, DI(on.first, v));
+      if ((int)ch.size() > cap(l)) {
+        std::vector<DI> before = ch;
+        ch = prune(o, before, cap(l));
+        if (!hnsw_mode) drop_stale_marks(o, l, before);
+      }
+    }
+    return ann;
+  }
+
+  std::vector<DI> all_chunks(int v, int l) const {
+    std::vector<DI> c;
+    for (const auto& ch : adj[v][l]) c.insert(c.end(), ch.begin(), ch.end());
+    std::sort(c.begin(), c.end());
+    return c;
+  }
+
+  static void set_from(std::vector<int>& mk, const std::vector<DI>& N) {
+    mk.clear();
+    for (const DI& e : N) mk.push_back(e.second);
+    std::sort(mk.begin(), mk.end());
+  }
+
+  // Alg. 5 (GlobalEdgeMasking) of object v on layer l.
+  void global_mask(int l, int v) {
+    std::vector<DI> N = prune(v, all_chunks(v, l), M);
+    set_from(marks[v][l], N);
+    for (const DI& on : N) {
+      int o = on.second;
+      bool has_v = false;
+      for (const auto& ch : adj[o][l])
+        for (const DI& e : ch)
+          if (e.second == v) has_v = true;
+      if (!has_v) continue;
+      std::vector<int>& mk = marks[o][l];
+      if (!std::binary_search(mk.begin(), mk.end(), v)) {
+        mk.insert(std::upper_bound(mk.begin(), mk.end(), v), v);
+      }
+      if ((int)mk.size() > M) {
+        std::vector<DI> N2 = prune(o, all_chunks(o, l), M);
+        set_from(mk, N2);
+      }
+    }
+  }
+
+  // Skip-list insertion (Pugh) with the object's HSIG level as its list height;
+  // the order is by (attribute, external id).
+  bool before_key(int a, int64_t attr_b, int b) const {
+    return attr[a] < attr_b || (attr[a] == attr_b && a < b);
+  }
+  void skiplist_insert(int v) {
+    int lev = level[v];
+    if ((int)head_next.size() < lev + 1) head_next.resize(lev + 1, -1);
+    next[v].assign(lev + 1, -1);
+    int top = (int)head_next.size() - 1;
+    int x = -1;  // -1 = head
+    for (int l = top; l >= 0; --l) {
+      while (true) {
+        int nx = (x < 0) ? head_next[l] : next[x][l];
+        if (nx >= 0 && before_key(nx, attr[v], v)) x = nx;
+        else break;
+      }
+      if (l <= lev) {
+        int nx = (x < 0) ? head_next[l] : next[x][l];
+        next[v][l] = nx;
+        if (x < 0) head_next[l] = v;
+        else next[x][l] = v;
+      }
+    }
+  }
+
+  // Alg. 6 (HSIGInsert); with hnsw_mode it is Alg. 3 per layer with one segment.
+  void insert(int v, double u) {
+    int i = hnsw_mode ? 0 : seg[v];
+    int lev = draw_level(u, mL);
+    level[v] = lev;
+    adj[v].assign(lev + 1, std::vector<std::vector<DI>>(S));
+    marks[v].assign(lev + 1, std::vector<int>());
+    for (int j = 0; j < S; ++j) {
+      if (entry[j] < 0) {
+        if (j == i) {
+          entry[j] = v;
+          maxlev[j] = lev;
+        }
+        continue;
+      }
+      int L = maxlev[j];
+      int ep = entry[j];
+      for (int l = L; l >= lev + 1; --l) ep = ann_search(vec(v), ep, 1, l, j)[0].second;
+      for (int l = std::min(lev, L); l >= 0; --l) {
+        std::vector<DI> ann = backbone(l, ep, v, i, j);
+        ep = ann[0].second;
+      }
+      if (j == i && lev > L) {
+        entry[j] = v;
+        maxlev[j] = lev;
+      }
+    }
+    if (!hnsw_mode) {
+      skiplist_insert(v);
+      for (int l = 0; l <= lev; ++l) global_mask(l, v);
+    }
+    if (lev > gmax) {
+      gmax = lev;
+      gentry = v;
+    }
+    ++n_inserted;
+  }
+
+  void init(const float* X_, const int64_t* attr_, int64_t n_, int d_, int S_, int M_, int M0_,
+            int efCons_, double mL_) {
+    n = n_;
+    d = d_;
+    S = S_;
+    M = M_;
+    M0 = M0_ > 0 ? M0_ : M_;
+    efCons = efCons_;
+    mL = mL_ > 0 ? mL_ : 1.0 / std::log((double)M_);
+    X.assign(X_, X_ + (size_t)n * d);
+    attr.assign(attr_, attr_ + n);
+    std::vector<int64_t> srt(attr);
+    std::sort(srt.begin(), srt.end());
+    bnd.clear();
+    for (int j = 1; j < S; ++j) bnd.push_back(srt[(size_t)((int64_t)j * n / S)]);
+    seg.resize(n);
+    for (int64_t v = 0; v < n; ++v) seg[v] = seg_of(attr[v]);
+    level.assign(n, 0);
+    adj.assign(n, {});
+    marks.assign(n, {});
+    entry.assign(S, -1);
+    maxlev.assign(S, -1);
+    next.assign(n, {});
+    head_next.clear();
+    stamp.assign(n, 0u);
+    cur = 0;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Frozen view: internal ids = rank in (attribute, external id) order.  It is
+// also the content of the index file.
+// ---------------------------------------------------------------------------
+
+struct View {
+  int64_t n = 0;
+  int d = 0, S = 0, M0 = 0, MU = 0, L = -1, gentry = -1, efCons = 0;
+  double mL = 0;
+  uint64_t seed = 0;
+  int64_t R = 0;
+  int W0 = 0, WU = 0;
+  std::vector<int64_t> attr, ext, seg_start;
+  std::vector<int32_t> seg_entry, seg_maxlevel;
+  std::vector<uint8_t> level;
+  std::vector<int32_t> uprow;
+  std::vector<float> X;
+  std::vector<int32_t> adj0, adjU;
+  std::vector<uint32_t> gbits0, gbitsU;
+
+  const float* vec(int v) const { return &X[(size_t)v * d]; }
+  int mcap(int l) const { return l == 0 ? M0 : MU; }
+  // Pointer to chunk j of v on layer l (mcap(l) entries, -1 padded).
+  const int32_t* chunk(int v, int l, int j) const {
+    if (l == 0) return &adj0[((size_t)v * S + j) * M0];
+    int64_t row = (int64_t)uprow[v] + (l - 1);
+    return &adjU[((size_t)row * S + j) * MU];
+  }
+  const uint32_t* bits(int v, int l) const {
+    if (l == 0) return &gbits0[(size_t)v * W0];
+    int64_t row = (int64_t)uprow[v] + (l - 1);
+    return &gbitsU[(size_t)row * WU];
+  }
+  // The global (marked) edges of v on layer l, in bit order.
+  void glist(int v, int l, std::vector<int>& out) const {
+    out.clear();
+    const int mc = mcap(l);
+    const uint32_t* b = bits(v, l);
+    for (int pos = 0; pos < S * mc; ++pos) {
+      if (b[pos >> 5] >> (pos & 31) & 1u) {
+        int t = chunk(v, l, pos / mc)[pos % mc];
+        if (t >= 0) out.push_back(t);
+      }
+    }
+  }
+  // Segment of internal id r (the last j whose start is <= r).
+  int seg_of_rank(int64_t r) const {
+    return (int)(std::upper_bound(seg_start.begin(), seg_start.end(), r) - seg_start.begin()) - 1;
+  }
+};
+
+void freeze(const Builder& B, View& V, uint64_t seed) {
+  const int64_t n = B.n;
+  V.n = n;
+  V.d = B.d;
+  V.S = B.S;
+  V.M0 = B.M0;
+  V.MU = B.M;
+  V.L = B.gmax;
+  V.efCons = B.efCons;
+  V.mL = B.mL;
+  V.seed = seed;
+  std::vector<int> order(n);
+  for (int64_t v = 0; v < n; ++v) order[v] = (int)v;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    return B.attr[a] < B.attr[b] || (B.attr[a] == B.attr[b] && a < b);
+  });
+  std::vector<int> rank(n);
+  for (int64_t r = 0; r < n; ++r) rank[order[r]] = (int)r;
+  V.attr.resize(n);
+  V.ext.resize(n);
+  V.level.resize(n);
+  V.uprow.resize(n);
+  V.X.resize((size_t)n * B.d);
+  int64_t R = 0;
+  for (int64_t r = 0; r < n; ++r) {
+    int v = order[r];
+    V.attr[r] = B.attr[v];
+    V.ext[r] = v;
+    V.level[r] = (uint8_t)B.level[v];
+    V.uprow[r] = B.level[v] > 0 ? (int32_t)R : -1;
+    R += B.level[v];
+    std::memcpy(&V.X[(size_t)r * B.d], B.vec(v), sizeof(float) * B.d);
+  }
+  V.R = R;
+  V.seg_start.assign(B.S + 1, 0);
+  for (int j = 1; j < B.S; ++j)
+    V.seg_start[j] = std::lower_bound(V.attr.begin(), V.attr.end(), B.bnd[j - 1]) - V.attr.begin();
+  V.seg_start[B.S] = n;
+  V.seg_entry.resize(B.S);
+  V.seg_maxlevel.resize(B.S);
+  for (int j = 0; j < B.S; ++j) {
+    V.seg_entry[j] = B.entry[j] >= 0 ? rank[B.entry[j]] : -1;
+    V.seg_maxlevel[j] = B.maxlev[j];
+  }
+  V.gentry = B.gentry >= 0 ? rank[B.gentry] : -1;
+  V.W0 = (B.S * B.M0 + 31) / 32;
+  V.WU = (B.S * B.M + 31) / 32;
+  V.adj0.assign((size_t)n * B.S * B.M0, -1);
+  V.gbits0.assign((size_t)n * V.W0, 0u);
+  V.adjU.assign((size_t)R * B.S * B.M, -1);
+  V.gbitsU.assign((size_t)R * V.WU, 0u);
+  for (int64_t r = 0; r < n; ++r) {
+    int v = order[r];
+    for (int l = 0; l <= B.level[v]; ++l) {
+      int mc = l == 0 ? B.M0 : B.M;
+      int32_t* rowp = l == 0 ? &V.adj0[(size_t)r * B.S * mc]
+                             : &V.adjU[(size_t)(V.uprow[r] + l - 1) * B.S * mc];
+      uint32_t* bp = l == 0 ? &V.gbits0[(size_t)r * V.W0] : &V.gbitsU[(size_t)(V.uprow[r] + l - 1) * V.WU];
+      for (int j = 0; j < B.S; ++j) {
+        const auto& ch = B.adj[v][l][j];
+        for (size_t t = 0; t < ch.size(); ++t) {
+          rowp[j * mc + t] = rank[ch[t].second];
+          if (!B.hnsw_mode && std::binary_search(B.marks[v][l].begin(), B.marks[v][l].end(), ch[t].second)) {
+            int pos = j * mc + (int)t;
+            bp[pos >> 5] |= 1u << (pos & 31);
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Index file (little-endian; 256-byte header; sections 64-byte aligned; CRC-32 footer)
+// ---------------------------------------------------------------------------
+
+uint32_t crc32_update(uint32_t c, const uint8_t* p, size_t len) {
+  static uint32_t table[256];
+  static bool ready = false;
+  if (!ready) {
+    for (uint32_t i = 0; i < 256; ++i) {
+      uint32_t x = i;
+      for (int k = 0; k < 8; ++k) x = (x & 1) ? (0xEDB88320u ^ (x >> 1)) : (x >> 1);
+      table[i] = x;
+    }
+    ready = true;
+  }
+  for (size_t i = 0; i < len; ++i) c = table[(c ^ p[i]) & 0xFFu] ^ (c >> 8);
+  return c;
+}
+
+struct Writer {
+  FILE* f;
+  uint32_t crc = 0xFFFFFFFFu;
+  uint64_t off = 0;
+  bool ok = true;
+  void put(const void* p, size_t len) {
+    if (len == 0) return;
+    if (fwrite(p, 1, len, f) != len) ok = false;
+    crc = crc32_update(crc, (const uint8_t*)p, len);
+    off += len;
+  }
+  void align() {
+    static const uint8_t z[64] = {0};
+    size_t pad = (size_t)((64 - off % 64) % 64);
+    put(z, pad);
+  }
+};
+
+struct Header {
+  char magic[8];
+  uint32_t version, flags;
+  int64_t n;
+  int32_t d, S, M0, MU, L, efCons, gentry, reserved;
+  double mL;
+  uint64_t seed;
+  int64_t R;
+  int32_t W0, WU;
+  uint8_t pad[256 - 8 - 8 - 8 - 32 - 8 - 8 - 8 - 8];
+};
+static_assert(sizeof(Header) == 256, "header is 256 bytes");
+
+int write_view(const View& V, const char* path) {
+  FILE* f = fopen(path, "wb");
+  if (!f) return -5;
+  Writer w{f};
+  Header h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, "UNIFYIX1", 8);
+  h.version = 1;
+  h.n = V.n;
+  h.d = V.d;
+  h.S = V.S;
+  h.M0 = V.M0;
+  h.MU = V.MU;
+  h.L = V.L;
+  h.efCons = V.efCons;
+  h.gentry = V.gentry;
+  h.mL = V.mL;
+  h.seed = V.seed;
+  h.R = V.R;
+  h.W0 = V.W0;
+  h.WU = V.WU;
+  w.put(&h, sizeof h);
+  auto sec = [&](const void* p, size_t len) {
+    w.align();
+    w.put(p, len);
+  };
+  sec(V.attr.data(), 8 * V.n);
+  sec(V.ext.data(), 8 * V.n);
+  sec(V.seg_start.data(), 8 * (V.S + 1));
+  sec(V.seg_entry.data(), 4 * V.S);
+  sec(V.seg_maxlevel.data(), 4 * V.S);
+  sec(V.level.data(), V.n);
+  sec(V.uprow.data(), 4 * V.n);
+  sec(V.X.data(), 4 * V.X.size());
+  sec(V.adj0.data(), 4 * V.adj0.size());
+  sec(V.gbits0.data(), 4 * V.gbits0.size());
+  sec(V.adjU.data(), 4 * V.adjU.size());
+  sec(V.gbitsU.data(), 4 * V.gbitsU.size());
+  w.align();
+  uint32_t crc = w.crc ^ 0xFFFFFFFFu;
+  bool ok = w.ok && fwrite(&crc, 4, 1, f) == 1;
+  ok = (fclose(f) == 0) && ok;
+  return ok ? 0 : -5;
+}
+
+struct Reader {
+  std::vector<uint8_t> buf;
+  size_t pos = 0;
+  bool ok = true;
+  void get(void* p, size_t len) {
+    if (pos + len > buf.size()) {
+      ok = false;
+      return;
+    }
+    if (len) std::memcpy(p, &buf[pos], len);
+    pos += len;
+  }
+  void align() { pos = (pos + 63) / 64 * 64; }
+};
+
+int read_view(const char* path, View& V) {
+  FILE* f = fopen(path, "rb");
+  if (!f) return -5;
+  Reader rd;
+  fseek(f, 0, SEEK_END);
+  long sz = ftell(f);
+  fseek(f, 0, SEEK_SET);
+  if (sz < (long)sizeof(Header) + 4) {
+    fclose(f);
+    return -6;
+  }
+  rd.buf.resize(sz);
+  size_t got = fread(rd.buf.data(), 1, sz, f);
+  fclose(f);
+  if (got != (size_t)sz) return -5;
+  uint32_t stored;
+  std::memcpy(&stored, &rd.buf[sz - 4], 4);
+  uint32_t crc = crc32_update(0xFFFFFFFFu, rd.buf.data(), sz - 4) ^ 0xFFFFFFFFu;
+  Header h;
+  rd.get(&h, sizeof h);
+  if (std::memcmp(h.magic, "UNIFYIX1", 8) != 0 || h.version != 1) return -6;
+  if (crc != stored) return -6;
+  if (h.n < 1 || h.d < 4 || h.d % 4 || h.S < 1 || h.M0 < 1 || h.MU < 1 || h.R < 0) return -6;
+  V.n = h.n;
+  V.d = h.d;
+  V.S = h.S;
+  V.M0 = h.M0;
+  V.MU = h.MU;
+  V.L = h.L;
+  V.efCons = h.efCons;
+  V.gentry = h.gentry;
+  V.mL = h.mL;
+  V.seed = h.seed;
+  V.R = h.R;
+  V.W0 = h.W0;
+  V.WU = h.WU;
+  auto sec = [&](auto& vec, size_t count) {
+    rd.align();
+    vec.resize(count);
+    rd.get(vec.data(), count * sizeof(vec[0]));
+  };
+  sec(V.attr, V.n);
+  sec(V.ext, V.n);
+  sec(V.seg_start, V.S + 1);
+  sec(V.seg_entry, V.S);
+  sec(V.seg_maxlevel, V.S);
+  sec(V.level, V.n);
+  sec(V.uprow, V.n);
+  sec(V.X, (size_t)V.n * V.d);
+  sec(V.adj0, (size_t)V.n * V.S * V.M0);
+  sec(V.gbits0, (size_t)V.n * V.W0);
+  sec(V.adjU, (size_t)V.R * V.S * V.MU);
+  sec(V.gbitsU, (size_t)V.R * V.WU);
+  rd.align();
+  if (!rd.ok || rd.pos + 4 != rd.buf.size()) return -6;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Search (O2) on a view
+// ---------------------------------------------------------------------------
+
+enum { ST_AUTO = 0, ST_PRE = 1, ST_HYBRID = 2, ST_POST = 3 };
+enum { C_NDIST = 0, C_NEXP, C_NVISIT0, C_MAXCAND, C_MAXLIVE, C_STRAT, C_LO, C_HI, C_NCOUNT };
+
+struct Query {
+  const View* V;
+  const float* q;
+  int64_t lo = 0, hi = 0;  // in-range internal ids are [lo, hi)
+  int64_t l = 0, h = 0;    // inclusive attribute range
+  int a = 0, b = -1;       // active segments
+  int c = 0;               // entries per active chunk
+  int64_t* cnt;
+  bool in_range(int v) const { return V->attr[v] >= l && V->attr[v] <= h; }
+  FI key(int v) {
+    ++cnt[C_NDIST];
+    return FI(dist32(q, V->vec(v), V->d), v);
+  }
+};
+
+// Neighbours of o on layer l: the first c entries of each active chunk (hybrid),
+// or the marked global edges (post).
+void neighbours(const Query& Q, bool hybrid, int o, int l, std::vector<int>& out) {
+  out.clear();
+  if (hybrid) {
+    const int mc = Q.V->mcap(l);
+    for (int j = Q.a; j <= Q.b; ++j) {
+      const int32_t* ch = Q.V->chunk(o, l, j);
+      for (int r = 0; r < Q.c && r < mc; ++r)
+        if (ch[r] >= 0) out.push_back(ch[r]);
+    }
+  } else {
+    Q.V->glist(o, l, out);
+  }
+}
+
+// One layer, sequential (Alg. 1 for post and the upper layers; Alg. 7 on layer
+// 0 of the hybrid search).  Returns ann sorted by key.
+std::vector<FI> layer_seq(Query& Q, bool hybrid, bool filter, int ep, int l, int ef,
+                          std::vector<uint32_t>& stamp, uint32_t& cur) {
+  if (++cur == 0) {
+    std::fill(stamp.begin(), stamp.end(), 0u);
+    cur = 1;
+  }
+  std::priority_queue<FI, std::vector<FI>, std::greater<FI>> cand;
+  std::priority_queue<FI> ann;
+  FI e0 = Q.key(ep);
+  stamp[ep] = cur;
+  cand.push(e0);
+  if (!filter || Q.in_range(ep)) ann.push(e0);
+  int64_t nvisit = 1;
+  std::vector<int> nb;
+  while (!cand.empty()) {
+    FI o = cand.top();
+    cand.pop();
+    if ((int)ann.size() == ef && o > ann.top()) break;
+    ++Q.cnt[C_NEXP];
+    neighbours(Q, hybrid, o.second, l, nb);
+    for (int v : nb) {
+      if (stamp[v] == cur) continue;
+      stamp[v] = cur;
+      ++nvisit;
+      FI kv = Q.key(v);
+      if ((int)ann.size() < ef || kv < ann.top()) {
+        cand.push(kv);
+        if (!filter || Q.in_range(v)) {
+          ann.push(kv);
+          if ((int)ann.size() > ef) ann.pop();
+        }
+      }
+    }
+    Q.cnt[C_MAXCAND] = std::max<int64_t>(Q.cnt[C_MAXCAND], (int64_t)cand.size());
+  }
+  if (l == 0) Q.cnt[C_NVISIT0] = nvisit;
+  std::vector<FI> out;
+  while (!ann.empty()) {
+    out.push_back(ann.top());
+    ann.pop();
+  }
+  std::reverse(out.begin(), out.end());
+  return out;
+}
+
+// Layer 0 with beam width p (R13).  For p == 1 the result equals layer_seq.
+std::vector<FI> layer_beam(Query& Q, bool hybrid, bool filter, int ep, int ef, int p,
+                           std::vector<uint32_t>& stamp, uint32_t& cur) {
+  if (++cur == 0) {
+    std::fill(stamp.begin(), stamp.end(), 0u);
+    cur = 1;
+  }
+  std::priority_queue<FI, std::vector<FI>, std::greater<FI>> cand;
+  std::priority_queue<FI> ann;
+  FI e0 = Q.key(ep);
+  stamp[ep] = cur;
+  cand.push(e0);
+  if (!filter || Q.in_range(ep)) ann.push(e0);
+  int64_t nvisit = 1;
+  std::vector<int> nb, batch;
+  std::vector<int> popped;
+  while (!cand.empty()) {
+    popped.clear();
+    while ((int)popped.size() < p && !cand.empty()) {
+      FI o = cand.top();
+      if ((int)ann.size() == ef && o > ann.top()) break;
+      cand.pop();
+      popped.push_back(o.second);
+    }
+    if (popped.empty()) break;
+    const bool full = (int)ann.size() == ef;
+    const FI T = full ? ann.top() : FI(0.f, 0);
+    batch.clear();
+    for (int o : popped) {
+      ++Q.cnt[C_NEXP];
+      neighbours(Q, hybrid, o, 0, nb);
+      for (int v : nb) {
+        if (stamp[v] == cur) continue;
+        stamp[v] = cur;
+        ++nvisit;
+        batch.push_back(v);
+      }
+    }
+    for (int v : batch) {
+      FI kv = Q.key(v);
+      if (!full || kv < T) {
+        cand.push(kv);
+        if (!filter || Q.in_range(v)) ann.push(kv);
+      }
+    }
+    while ((int)ann.size() > ef) ann.pop();
+    Q.cnt[C_MAXCAND] = std::max<int64_t>(Q.cnt[C_MAXCAND], (int64_t)cand.size());
+    // live entries: those the search can still expand
+    if ((int)ann.size() == ef) {
+      int64_t live = 0;
+      auto copy = cand;
+      while (!copy.empty() && !(copy.top() > ann.top())) {
+        ++live;
+        copy.pop();
+      }
+      Q.cnt[C_MAXLIVE] = std::max(Q.cnt[C_MAXLIVE], live);
+    } else {
+      Q.cnt[C_MAXLIVE] = std::max<int64_t>(Q.cnt[C_MAXLIVE], (int64_t)cand.size());
+    }
+  }
+  Q.cnt[C_NVISIT0] = nvisit;
+  std::vector<FI> out;
+  while (!ann.empty()) {
+    out.push_back(ann.top());
+    ann.pop();
+  }
+  std::reverse(out.begin(), out.end());
+  return out;
+}
+
+struct Searcher {
+  const View* V;
+  std::vector<uint32_t> stamp;
+  uint32_t cur = 0;
+  explicit Searcher(const View* v) : V(v), stamp(v->n, 0u) {}
+
+  void plan(Query& Q, int64_t l, int64_t h) const {
+    Q.l = l;
+    Q.h = h;
+    if (l > h) {
+      Q.lo = Q.hi = 0;
+      return;
+    }
+    Q.lo = std::lower_bound(V->attr.begin(), V->attr.end(), l) - V->attr.begin();
+    Q.hi = std::upper_bound(V->attr.begin(), V->attr.end(), h) - V->attr.begin();
+    if (Q.hi < Q.lo) Q.hi = Q.lo;
+    if (Q.hi > Q.lo) {
+      Q.a = V->seg_of_rank(Q.lo);
+      Q.b = V->seg_of_rank(Q.hi - 1);
+    }
+  }
+
+  // Strategy A: the slice of objects in [l, h] (the layer-0 skip list from the
+  // first object >= l), exact top-k by (dist32, id).
+  std::vector<FI> pre(Query& Q, int k) {
+    std::vector<FI> all;
+    for (int64_t v = Q.lo; v < Q.hi; ++v) all.push_back(Q.key((int)v));
+    std::sort(all.begin(), all.end());
+    if ((int)all.size() > k) all.resize(k);
+    return all;
+  }
+
+  // Strategy C: Alg. 2 scheme with Alg. 7 per layer over the active chunks.
+  std::vector<FI> hybrid(Query& Q, int k, int ef, int m, int p, bool batch_form) {
+    const int Sa = Q.b - Q.a + 1;
+    Q.c = (m + Sa - 1) / Sa;
+    int top = -1;
+    for (int j = Q.a; j <= Q.b; ++j)
+      if (V->seg_entry[j] >= 0) top = std::max(top, V->seg_maxlevel[j]);
+    if (top < 0) return {};
+    FI best(std::numeric_limits<float>::infinity(), -1);
+    for (int j = Q.a; j <= Q.b; ++j) {
+      if (V->seg_entry[j] < 0 || V->seg_maxlevel[j] != top) continue;
+      FI kj = Q.key(V->seg_entry[j]);
+      if (best.second < 0 || kj < best) best = kj;
+    }
+    int ep = best.second;
+    for (int l = top; l >= 1; --l) ep = layer_seq(Q, true, false, ep, l, 1, stamp, cur)[0].second;
+    std::vector<FI> ann = (p == 1 && !batch_form) ? layer_seq(Q, true, true, ep, 0, ef, stamp, cur)
+                                                  : layer_beam(Q, true, true, ep, ef, p, stamp, cur);
+    if ((int)ann.size() > k) ann.resize(k);
+    return ann;
+  }
+
+  // Strategy B: Alg. 2 over the marked (global) edges, then the range filter.
+  std::vector<FI> post(Query& Q, int k, int ef, int p, bool batch_form) {
+    if (V->gentry < 0) return {};
+    int ep = V->gentry;
+    for (int l = V->L; l >= 1; --l) ep = layer_seq(Q, false, false, ep, l, 1, stamp, cur)[0].second;
+    std::vector<FI> ann = (p == 1 && !batch_form) ? layer_seq(Q, false, false, ep, 0, ef, stamp, cur)
+                                                  : layer_beam(Q, false, false, ep, ef, p, stamp, cur);
+    std::vector<FI> out;
+    for (const FI& e : ann)
+      if (Q.in_range(e.second) && (int)out.size() < k) out.push_back(e);
+    return out;
+  }
+};
+
+thread_local std::string g_err;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C interface (loaded by the tests through ctypes)
+// ---------------------------------------------------------------------------
+
+struct OrcIndex {
+  Builder B;
+  bool has_builder = false;
+  View V;
+};
+
+extern "C" {
+
+const char* orc_last_error() { return g_err.c_str(); }
+
+float orc_dist32(const float* q, const float* x, int d) { return dist32(q, x, d); }
+int orc_level_of(double u, double mL) { return draw_level(u, mL); }
+double orc_dist64(const float* q, const float* x, int d) { return dist64(q, x, d); }
+
+// Builds an HSIG by inserting objects 0..n-1 in order (Alg. 6).  level_u[v] is
+// the uniform variate of object v's level draw.  M0 <= 0 means M0 = M;
+// mL <= 0 means 1/ln(M).  hnsw != 0 builds a plain HNSW (Alg. 3) instead.
+void* orc_build(const float* X, const int64_t* attr, const double* level_u, int64_t n, int d,
+                int S, int M, int M0, int efCons, double mL, uint64_t seed, int hnsw) {
+  if (n < 1 || d < 4 || d % 4 || S < 1 || M < 1 || efCons < 1) {
+    g_err = "orc_build: bad arguments";
+    return nullptr;
+  }
+  OrcIndex* ix = new OrcIndex();
+  ix->B.hnsw_mode = hnsw != 0;
+  ix->B.init(X, attr, n, d, hnsw ? 1 : S, M, M0, efCons, mL);
+  if (hnsw) {
+    ix->B.bnd.clear();
+    std::fill(ix->B.seg.begin(), ix->B.seg.end(), 0);
+  }
+  for (int64_t v = 0; v < n; ++v) ix->B.insert((int)v, level_u[v]);
+  ix->has_builder = true;
+  freeze(ix->B, ix->V, seed);
+  return ix;
+}
+
+void* orc_read(const char* path) {
+  OrcIndex* ix = new OrcIndex();
+  int rc = read_view(path, ix->V);
+  if (rc != 0) {
+    g_err = rc == -5 ? "orc_read: I/O error" : "orc_read: bad index file";
+    delete ix;
+    return nullptr;
+  }
+  return ix;
+}
+
+int orc_write(void* h, const char* path) { return write_view(((OrcIndex*)h)->V, path); }
+
+void orc_free(void* h) { delete (OrcIndex*)h; }
+
+// info: n, d, S, M0, MU, L, gentry, R, efCons
+void orc_info(void* h, int64_t* out) {
+  const View& V = ((OrcIndex*)h)->V;
+  out[0] = V.n;
+  out[1] = V.d;
+  out[2] = V.S;
+  out[3] = V.M0;
+  out[4] = V.MU;
+  out[5] = V.L;
+  out[6] = V.gentry;
+  out[7] = V.R;
+  out[8] = V.efCons;
+}
+
+// Copies of the view's tables (internal ids).
+void orc_get_attr(void* h, int64_t* out) {
+  const View& V = ((OrcIndex*)h)->V;
+  std::copy(V.attr.begin(), V.attr.end(), out);
+}
+void orc_get_ext(void* h, int64_t* out) {
+  const View& V = ((OrcIndex*)h)->V;
+  std::copy(V.ext.begin(), V.ext.end(), out);
+}
+void orc_get_level(void* h, int32_t* out) {
+  const View& V = ((OrcIndex*)h)->V;
+  for (int64_t i = 0; i < V.n; ++i) out[i] = V.level[i];
+}
+void orc_get_segments(void* h, int64_t* seg_start, int32_t* entry, int32_t* maxlev) {
+  const View& V = ((OrcIndex*)h)->V;
+  std::copy(V.seg_start.begin(), V.seg_start.end(), seg_start);
+  std::copy(V.seg_entry.begin(), V.seg_entry.end(), entry);
+  std::copy(V.seg_maxlevel.begin(), V.seg_maxlevel.end(), maxlev);
+}
+// Chunk rows of layer l for every node that has layer l: out[n][S][mcap] (-1 rows for absent nodes).
+void orc_get_layer(void* h, int l, int32_t* out_adj, int32_t* out_glist) {
+  const View& V = ((OrcIndex*)h)->V;
+  const int mc = V.mcap(l);
+  std::vector<int> g;
+  for (int64_t v = 0; v < V.n; ++v) {
+    int32_t* row = out_adj + (size_t)v * V.S * mc;
+    int32_t* grow = out_glist + (size_t)v * V.S * mc;
+    for (int t = 0; t < V.S * mc; ++t) row[t] = grow[t] = -1;
+    if (V.level[v] < l) continue;
+    for (int j = 0; j < V.S; ++j) std::memcpy(row + j * mc, V.chunk((int)v, l, j), 4 * mc);
+    V.glist((int)v, l, g);
+    for (size_t t = 0; t < g.size(); ++t) grow[t] = g[t];
+  }
+}
+// The real skip list of the builder, walked on layer 0 from the first object
+// with attribute >= l while attribute <= h; writes internal ids (= ranks).
+int64_t orc_skiplist_range(void* h, int64_t l, int64_t hh, int64_t* out, int64_t cap) {
+  OrcIndex* ix = (OrcIndex*)h;
+  if (!ix->has_builder) return -1;
+  const Builder& B = ix->B;
+  int top = (int)B.head_next.size() - 1;
+  int x = -1;
+  for (int lv = top; lv >= 0; --lv) {
+    while (true) {
+      int nx = x < 0 ? B.head_next[lv] : B.next[x][lv];
+      if (nx >= 0 && B.attr[nx] < l) x = nx;
+      else break;
+    }
+  }
+  int v = x < 0 ? B.head_next[0] : B.next[x][0];
+  // map ext -> rank through the view
+  std::vector<int64_t> rank(B.n);
+  for (int64_t r = 0; r < ix->V.n; ++r) rank[ix->V.ext[r]] = r;
+  int64_t cnt = 0;
+  while (v >= 0 && B.attr[v] <= hh) {
+    if (cnt < cap) out[cnt] = rank[v];
+    ++cnt;
+    v = B.next[v][0];
+  }
+  return cnt;
+}
+
+// Build-side structures before freezing, by external id (for reduction tests):
+// chunk j of v on layer l, as external ids.
+int orc_build_chunk(void* h, int64_t v, int l, int j, int64_t* out, int cap) {
+  OrcIndex* ix = (OrcIndex*)h;
+  if (!ix->has_builder) return -1;
+  const Builder& B = ix->B;
+  if (v < 0 || v >= B.n || l > B.level[v] || j < 0 || j >= B.S) return -1;
+  const auto& ch = B.adj[v][l][j];
+  int c = 0;
+  for (const DI& e : ch)
+    if (c < cap) out[c++] = e.second;
+  return (int)ch.size();
+}
+int orc_build_level(void* h, int64_t v) { return ((OrcIndex*)h)->B.level[v]; }
+
+// Prune (Sec. 2.2) of owner point o against candidate points, FP64 distances;
+// writes the indices of the kept candidates in selection order.
+int orc_prune(const float* owner, const float* cands, int nc, int d, int Mcap, int32_t* out) {
+  std::vector<std::pair<double, int>> c;
+  for (int i = 0; i < nc; ++i) c.push_back({dist64(owner, cands + (size_t)i * d, d), i});
+  std::sort(c.begin(), c.end());
+  int cnt = 0;
+  std::vector<int> sel;
+  for (auto& r : c) {
+    if ((int)sel.size() >= Mcap) break;
+    bool keep = true;
+    for (int e : sel)
+      if (dist64(cands + (size_t)e * d, cands + (size_t)r.second * d, d) < r.first) {
+        keep = false;
+        break;
+      }
+    if (keep) {
+      sel.push_back(r.second);
+      out[cnt++] = r.second;
+    }
+  }
+  return cnt;
+}
+
+// Search (O2).  strategy: 0 auto, 1 pre, 2 hybrid, 3 post.  m <= 0 means M0.
+// Outputs external ids and FP32 distances, ascending by (distance, internal id),
+// padded with (-1, +inf).  counters: [nq][C_NCOUNT] or NULL.  batch_form != 0
+// runs layer 0 in the beam form even for p = 1 (and records live-candidate counts).
+int orc_search(void* h, const float* Q, int64_t nq, const int64_t* L, const int64_t* H, int k,
+               int ef, int m, int p, int strategy, double tau_a, double tau_b, int64_t* out_ids,
+               float* out_dist, int64_t* counters, int batch_form) {
+  OrcIndex* ix = (OrcIndex*)h;
+  const View& V = ix->V;
+  if (k < 1 || ef < 1 || p < 1 || strategy < 0 || strategy > 3) {
+    g_err = "orc_search: bad arguments";
+    return -22;
+  }
+  if (m <= 0) m = V.M0;
+  const int64_t tA = (int64_t)std::floor(tau_a * (double)V.n);
+  const int64_t tB = (int64_t)std::ceil(tau_b * (double)V.n);
+  Searcher srch(&V);
+  std::vector<int64_t> dummy(C_NCOUNT);
+  for (int64_t i = 0; i < nq; ++i) {
+    int64_t* cnt = counters ? counters + i * C_NCOUNT : dummy.data();
+    for (int t = 0; t < C_NCOUNT; ++t) cnt[t] = 0;
+    Query qq;
+    qq.V = &V;
+    qq.q = Q + (size_t)i * V.d;
+    qq.cnt = cnt;
+    srch.plan(qq, L[i], H[i]);
+    const int64_t Y = qq.hi - qq.lo;
+    int st = strategy;
+    if (st == ST_AUTO) st = Y <= tA ? ST_PRE : (Y >= tB ? ST_POST : ST_HYBRID);
+    cnt[C_STRAT] = st;
+    cnt[C_LO] = qq.lo;
+    cnt[C_HI] = qq.hi;
+    std::vector<FI> res;
+    if (Y > 0) {
+      if (st == ST_PRE) res = srch.pre(qq, k);
+      else if (st == ST_HYBRID) res = srch.hybrid(qq, k, ef, m, p, batch_form != 0);
+      else res = srch.post(qq, k, ef, p, batch_form != 0);
+    }
+    for (int t = 0; t < k; ++t) {
+      if (t < (int)res.size()) {
+        out_ids[i * k + t] = V.ext[res[t].second];
+        out_dist[i * k + t] = res[t].first;
+      } else {
+        out_ids[i * k + t] = -1;
+        out_dist[i * k + t] = std::numeric_limits<float>::infinity();
+      }
+    }
+  }
+  return 0;
+}
+
+// One layer search from a given entry (for the reachability tests): hybrid
+// (chunk rule with segments [a, b] and c entries each) or post (marked edges);
+// filter applies the [l, h] test to ann.  Returns the count, writes internal ids.
+int orc_layer_search(void* h, const float* q, int ep, int layer, int ef, int hybrid, int a, int b,
+                     int c, int filter, int64_t l, int64_t hh, int32_t* out_ids, float* out_dist) {
+  OrcIndex* ix = (OrcIndex*)h;
+  const View& V = ix->V;
+  Searcher srch(&V);
+  std::vector<int64_t> cnt(C_NCOUNT, 0);
+  Query qq;
+  qq.V = &V;
+  qq.q = q;
+  qq.cnt = cnt.data();
+  qq.l = l;
+  qq.h = hh;
+  qq.a = a;
+  qq.b = b;
+  qq.c = c;
+  std::vector<FI> r = layer_seq(qq, hybrid != 0, filter != 0, ep, layer, ef, srch.stamp, srch.cur);
+  for (size_t t = 0; t < r.size(); ++t) {
+    out_ids[t] = r[t].second;
+    out_dist[t] = r[t].first;
+  }
+  return (int)r.size();
+}
+
+}  // extern "C"
