@@ -1,0 +1,165 @@
+/*
+ * unify.h -- C ABI of the MI355X (gfx950) range-filtered k-NN library.
+ *
+ * The library answers range-filtered k-nearest-neighbour queries over a
+ * Hierarchical Segmented Inclusive Graph (HSIG) kept resident on one GPU.
+ * The method is UNIFY (Liang et al., PVLDB 18(4), 2024):
+ *   - the problem: Definition 1 (Sec. 2.1) -- given q, an inclusive attribute
+ *     range [l, h] and k, return the k objects with l <= attribute <= h nearest
+ *     to q (all of them when fewer than k exist);
+ *   - the index: Sec. 4.1 (segmented chunks per layer, skip-list order,
+ *     global-edge bitmap) and Alg. 4-6 for its construction;
+ *   - the search: Sec. 4.2 -- strategy A (pre-filter scan), B (post-filter search
+ *     on the global edges), C (hybrid search, Alg. 7 inside the scheme of Alg. 2)
+ *     and the range-aware selection rule (pre when Y <= tau_A, post when
+ *     Y >= tau_B, hybrid otherwise, Y = number of objects in range).
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: 0 on success, a negative UNIFY_E* code on failure; on failure
+ *     unify_last_error() describes it.  No C++ exception crosses this boundary.
+ *   - Device pointers are HIP device addresses on the index's device; host
+ *     pointers are ordinary process memory.  Each argument says which it is.
+ *   - The caller owns every buffer it passes; the library owns the index.
+ *   - Work is enqueued on the caller's HIP stream (NULL = the default stream) and
+ *     is not waited for: the caller synchronises that stream before reading outputs.
+ *   - Distances are squared Euclidean distances in FP32.  Identifiers returned
+ *     are the external ids stored with the index (the row numbers the vectors had
+ *     when the index was built).  Each output row is ascending by
+ *     (distance, internal id), internal id = rank in attribute order.
+ *   - Rows with fewer than k results (empty range, l > h, fewer than k objects in
+ *     range, or a post-filter search that met fewer than k in-range objects) are
+ *     padded with id -1 and distance +inf.
+ *   - NaN in a query vector is not checked on the device; results are then unspecified.
+ */
+#ifndef UNIFY_H
+#define UNIFY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct unify_index* unify_index_t;
+
+/* Search strategies (Sec. 4.2). */
+enum {
+  UNIFY_AUTO = 0,   /* range-aware selection rule */
+  UNIFY_PRE = 1,    /* strategy A: exact scan of the objects in range */
+  UNIFY_HYBRID = 2, /* strategy C: Alg. 7 over the chunks of the segments in range */
+  UNIFY_POST = 3    /* strategy B: search on the global edges, then the range filter */
+};
+
+/* Element type of the device vector store used by the graph searches. */
+enum {
+  UNIFY_FP32 = 0,
+  UNIFY_BF16 = 1,    /* bfloat16, round to nearest even; candidates reranked in FP32 */
+  UNIFY_FP8E4M3 = 2  /* OCP FP8 E4M3 with one FP32 scale per vector; reranked in FP32 */
+};
+
+/* Status codes. */
+enum {
+  UNIFY_OK = 0,
+  UNIFY_EINVAL = -22,   /* an argument is out of its documented domain */
+  UNIFY_ENOMEM = -12,   /* device or host allocation failed */
+  UNIFY_EIO = -5,       /* the index file could not be read or written */
+  UNIFY_EFORMAT = -74,  /* bad magic, version, checksum or table contents */
+  UNIFY_EDEVICE = -19   /* a HIP runtime call failed */
+};
+
+/* Search parameters.  Zero in a field selects its default. */
+typedef struct {
+  int32_t m;            /* neighbours examined per expansion in the hybrid search,
+                           ceil(m / S') from each active chunk (Sec. 4.2); default M0 */
+  int32_t beam_p;       /* candidates expanded together per step; default 1 (= Alg. 7) */
+  int32_t rerank_mult;  /* BF16/FP8 stores: FP32 rerank of the best rerank_mult * k
+                           graph results; default 4 */
+  int32_t reserved;
+  double tau_a_frac;    /* tau_A = floor(tau_a_frac * n); default 0.01 (Sec. 6.2) */
+  double tau_b_frac;    /* tau_B = ceil(tau_b_frac * n); default 0.5 (Sec. 6.2) */
+  uint32_t flags;       /* reserved, 0 */
+  uint32_t pad;
+} unify_params;
+
+/*
+ * Reads an index file (format: little-endian; see the package documentation) and
+ * makes it resident on HIP device `device`.  precision selects the store the graph
+ * searches read (UNIFY_FP32, UNIFY_BF16, UNIFY_FP8E4M3); the FP32 store is always
+ * resident for the pre-filter scan and the rerank.  The file's tables are checked
+ * (checksum, sizes, every adjacency entry in range); on any failure *out is left
+ * unchanged.  *out (host) receives a handle owned by the library.
+ */
+int unify_load_index(const char* path, int device, int precision, unify_index_t* out);
+
+/*
+ * Builds an HSIG on device `device` from host arrays and makes it resident.
+ *   vectors   host, [n][d] float32 row-major; row i has external id i
+ *   attr      host, [n] int64 attribute values
+ *   level_u   host, [n] float64 in (0, 1]: the uniform variate of each object's
+ *             level draw (level = floor(-ln(u) / ln(M)), Alg. 6)
+ *   S, M      segments and chunk capacity (Sec. 4.1); ef_cons candidates per chunk
+ * Construction is batched on the GPU (every chunk from exact per-segment
+ * candidates, then the Prune rule and reverse edges of Alg. 4, and the global-edge
+ * marking of Alg. 5); it is not the sequential insertion order of Alg. 6.
+ */
+int unify_build_index(const float* vectors, const int64_t* attr, const double* level_u, int64_t n,
+                      int32_t d, int32_t S, int32_t M, int32_t ef_cons, int device, int precision,
+                      unify_index_t* out);
+
+/*
+ * Reads and checks an index file on the host only (no GPU needed): header,
+ * checksum, section sizes and the range of every adjacency entry.  Outputs are
+ * host pointers, any may be NULL.  Returns UNIFY_EIO or UNIFY_EFORMAT on failure.
+ */
+int unify_validate_index_file(const char* path, int64_t* n, int32_t* d, int32_t* S, int32_t* M);
+
+/* Writes a resident index to `path` in the index file format. */
+int unify_save_index(unify_index_t index, const char* path);
+
+/* Sizes of a resident index (host outputs; any may be NULL).  levels = top layer + 1. */
+int unify_index_info(unify_index_t index, int64_t* n, int32_t* d, int32_t* S, int32_t* M,
+                     int32_t* levels);
+
+/*
+ * Range-filtered k-NN search of nq queries (Definition 1; Sec. 4.2).
+ *   queries       device, [nq][d] float32
+ *   l, h          device, [nq] int64, inclusive attribute range of each query
+ *   k             1 <= k <= 256
+ *   ef            result-list size of the graph searches; k <= ef <= 256 when any
+ *                 query runs the hybrid or post-filter search
+ *   strategy      device, [nq] int8 per-query strategy (UNIFY_AUTO .. UNIFY_POST),
+ *                 or NULL for UNIFY_AUTO on every query
+ *   params        host, or NULL for defaults
+ *   out_ids       device, [nq][k] int64
+ *   out_dist      device, [nq][k] float32
+ *   out_strategy  device, [nq] int8 strategy actually run, or NULL
+ *   hip_stream    hipStream_t to enqueue on, or NULL
+ * nq = 0 is a no-op.  Scratch space is allocated by the library per call.
+ */
+int unify_search(unify_index_t index, const float* queries, int64_t nq, const int64_t* l,
+                 const int64_t* h, int32_t k, int32_t ef, const int8_t* strategy,
+                 const unify_params* params, int64_t* out_ids, float* out_dist,
+                 int8_t* out_strategy, void* hip_stream);
+
+/*
+ * unify_search plus per-query counters:
+ *   out_stats  device, [nq][4] int32: distance evaluations, expansions, visited
+ *              objects on layer 0, and a status (0 = ran in the first pass,
+ *              1 = re-run with larger on-chip lists, 2 = capacity exceeded even then).
+ */
+int unify_search_ex(unify_index_t index, const float* queries, int64_t nq, const int64_t* l,
+                    const int64_t* h, int32_t k, int32_t ef, const int8_t* strategy,
+                    const unify_params* params, int64_t* out_ids, float* out_dist,
+                    int8_t* out_strategy, int32_t* out_stats, void* hip_stream);
+
+/* Frees the index and its device memory.  NULL is accepted. */
+int unify_free_index(unify_index_t index);
+
+/* Message of the last failure on the calling thread (never NULL). */
+const char* unify_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UNIFY_H */

@@ -1,0 +1,182 @@
+"""Range-filtered k-NN search over an HSIG (UNIFY, PVLDB 18(4), 2024) on MI355X.
+
+A thin ctypes binding of ``libunify.so`` (the C ABI declared in
+``include/unify.h``).  Every step of a search runs in the library's HIP kernels;
+this module only marshals arguments: torch tensors supply device memory and the
+current HIP stream.  The library must be built first
+(``python -m paper_2412_02448_amd.build_native``); importing without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = ["Index", "UnifyError", "AUTO", "PRE", "HYBRID", "POST", "FP32", "BF16", "FP8E4M3",
+           "validate_index_file", "library_path", "load_library"]
+
+AUTO, PRE, HYBRID, POST = 0, 1, 2, 3
+FP32, BF16, FP8E4M3 = 0, 1, 2
+_PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8E4M3, "fp8e4m3": FP8E4M3}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libunify.so")
+
+
+class UnifyError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"unify error {code}: {msg}")
+        self.code = code
+
+
+class _Params(C.Structure):
+    _fields_ = [("m", C.c_int32), ("beam_p", C.c_int32), ("rerank_mult", C.c_int32), ("reserved", C.c_int32),
+                ("tau_a_frac", C.c_double), ("tau_b_frac", C.c_double), ("flags", C.c_uint32),
+                ("pad", C.c_uint32)]
+
+
+_lib = None
+
+# name -> (restype, argtypes) of every symbol include/unify.h declares
+_P, _I64, _I32, _S = C.c_void_p, C.c_int64, C.c_int32, C.c_char_p
+SIGNATURES = {
+    "unify_load_index": (_I32, [_S, _I32, _I32, _P]),
+    "unify_build_index": (_I32, [_P, _P, _P, _I64, _I32, _I32, _I32, _I32, _I32, _I32, _P]),
+    "unify_validate_index_file": (_I32, [_S, _P, _P, _P, _P]),
+    "unify_save_index": (_I32, [_P, _S]),
+    "unify_index_info": (_I32, [_P, _P, _P, _P, _P, _P]),
+    "unify_search": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P]),
+    "unify_search_ex": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "unify_free_index": (_I32, [_P]),
+    "unify_last_error": (_S, []),
+}
+
+
+def load_library():
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime; it must be the one in the process before
+        # libunify binds to libamdhip64.so.7, or two runtimes would share the GPU.
+        import torch  # noqa: F401
+        path = library_path()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: run `python -m paper_2412_02448_amd.build_native`")
+        lib = C.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise UnifyError(rc, load_library().unify_last_error().decode(errors="replace"))
+
+
+def validate_index_file(path: str) -> dict:
+    """Host-only check of an index file; returns its sizes."""
+    n, d, S, M = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load_library().unify_validate_index_file(path.encode(), C.byref(n), C.byref(d), C.byref(S),
+                                                    C.byref(M)))
+    return {"n": n.value, "d": d.value, "S": S.value, "M": M.value}
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else None
+
+
+class Index:
+    """An HSIG resident on one GPU."""
+
+    def __init__(self, handle: int, device: int):
+        self._h = C.c_void_p(handle)
+        self.device = device
+        n, d, S, M, L = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load_library().unify_index_info(self._h, C.byref(n), C.byref(d), C.byref(S), C.byref(M),
+                                               C.byref(L)))
+        self.n, self.d, self.S, self.M, self.levels = n.value, d.value, S.value, M.value, L.value
+
+    @staticmethod
+    def _prec(precision) -> int:
+        return _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+    @classmethod
+    def load(cls, path: str, device: int = 0, precision="fp32") -> "Index":
+        h = C.c_void_p()
+        _check(load_library().unify_load_index(path.encode(), device, cls._prec(precision), C.byref(h)))
+        return cls(h.value, device)
+
+    @classmethod
+    def build(cls, vectors: np.ndarray, attr: np.ndarray, level_u: np.ndarray, S: int, M: int,
+              ef_cons: int, device: int = 0, precision="fp32") -> "Index":
+        X = np.ascontiguousarray(vectors, np.float32)
+        a = np.ascontiguousarray(attr, np.int64)
+        u = np.ascontiguousarray(level_u, np.float64)
+        h = C.c_void_p()
+        _check(load_library().unify_build_index(X.ctypes.data, a.ctypes.data, u.ctypes.data, X.shape[0],
+                                                X.shape[1], S, M, ef_cons, device, cls._prec(precision),
+                                                C.byref(h)))
+        return cls(h.value, device)
+
+    def save(self, path: str) -> None:
+        _check(load_library().unify_save_index(self._h, path.encode()))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().unify_free_index(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def search(self, queries, l, h, k: int, ef: int, strategy=None, m: int = 0, beam_p: int = 1,
+               rerank_mult: int = 0, tau_a: float = 0.0, tau_b: float = 0.0, stats: bool = False,
+               out=None, stream=None):
+        """Enqueues a search on the current stream (or `stream`) and returns torch tensors.
+
+        queries: cuda float32 [nq, d]; l, h: cuda int64 [nq] (inclusive); strategy: None (auto),
+        an int for every query, or a cuda int8 [nq] tensor.  Returns (ids, dist, strategy[, stats]).
+        """
+        import torch
+        dev = torch.device("cuda", self.device)
+        nq = queries.shape[0]
+        if queries.dtype != torch.float32 or queries.device != dev or not queries.is_contiguous():
+            raise ValueError("queries must be a contiguous float32 tensor on the index's device")
+        if queries.dim() != 2 or queries.shape[1] != self.d:
+            raise ValueError(f"queries must be [nq, {self.d}]")
+        for t in (l, h):
+            if t.dtype != torch.int64 or t.device != dev or not t.is_contiguous() or t.shape != (nq,):
+                raise ValueError("l and h must be contiguous int64 [nq] tensors on the index's device")
+        st = None
+        if strategy is not None:
+            st = strategy if isinstance(strategy, torch.Tensor) else torch.full((nq,), int(strategy),
+                                                                                 dtype=torch.int8, device=dev)
+            if st.dtype != torch.int8 or st.device != dev or st.shape != (nq,):
+                raise ValueError("strategy must be an int8 [nq] tensor on the index's device")
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
+            dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+            ost = torch.empty((nq,), dtype=torch.int8, device=dev)
+            sts = torch.empty((nq, 4), dtype=torch.int32, device=dev) if stats else None
+        else:
+            ids, dist, ost, sts = out
+        prm = _Params(m, beam_p, rerank_mult, 0, tau_a, tau_b, 0, 0)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        lib = load_library()
+        if stats:
+            rc = lib.unify_search_ex(self._h, _ptr(queries), nq, _ptr(l), _ptr(h), k, ef, _ptr(st), C.byref(prm),
+                                     _ptr(ids), _ptr(dist), _ptr(ost), _ptr(sts), s.cuda_stream)
+        else:
+            rc = lib.unify_search(self._h, _ptr(queries), nq, _ptr(l), _ptr(h), k, ef, _ptr(st), C.byref(prm),
+                                  _ptr(ids), _ptr(dist), _ptr(ost), s.cuda_stream)
+        _check(rc)
+        return (ids, dist, ost, sts) if stats else (ids, dist, ost)

@@ -1,0 +1,323 @@
+// C ABI: index residency (load, upload, free, save) and the search entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "unify_internal.h"
+
+namespace unify {
+
+int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
+                float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream);
+
+namespace {
+thread_local std::string g_error;
+}
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+// Round-to-nearest-even FP32 -> BF16.
+uint16_t f32_to_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(r >> 16);
+}
+
+// Round-to-nearest-even FP32 -> OCP FP8 E4M3 (saturating to +-448; no infinities).
+uint8_t f32_to_e4m3(float x) {
+  uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
+  float a = std::fabs(x);
+  if (std::isnan(x)) return 0x7F;
+  if (a >= 448.0f) return sign | 0x7E;
+  // candidates are k * 2^(e-3) for the binade of a; smallest normal 2^-6
+  int e;
+  std::frexp(a, &e);        // a = f * 2^e, f in [0.5, 1)
+  int ub = e - 1;           // unbiased exponent of a
+  if (ub < -6) ub = -6;     // subnormal spacing 2^-9
+  const float q = std::ldexp(1.0f, ub - 3);   // spacing of representable values
+  float m = a / q;          // exact: division by a power of two
+  float r = std::nearbyint(m);  // ties to even (default rounding mode)
+  float v = r * q;
+  if (v >= 448.0f) return sign | 0x7E;
+  if (v == 0.0f) return sign;
+  int ve;
+  float vf = std::frexp(v, &ve);
+  int vub = ve - 1;
+  if (vub < -6) {  // subnormal: value = mant * 2^-9
+    int mant = (int)std::lround(v / std::ldexp(1.0f, -9));
+    return sign | (uint8_t)mant;
+  }
+  int mant = (int)std::lround((vf * 2.0f - 1.0f) * 8.0f);
+  return sign | (uint8_t)(((vub + 7) << 3) | mant);
+}
+
+namespace {
+
+template <class T>
+int upload(unify_index_t ix, const std::vector<T>& v, const T** out) {
+  if (v.empty()) {
+    *out = nullptr;
+    return UNIFY_OK;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) {
+    set_error("device allocation failed");
+    return UNIFY_ENOMEM;
+  }
+  ix->allocs.push_back(p);
+  if (hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("host-to-device copy failed");
+    return UNIFY_EDEVICE;
+  }
+  *out = static_cast<const T*>(p);
+  return UNIFY_OK;
+}
+
+// Global edges in bit order, -1 padded to GC entries per row.
+void compact_glist(const std::vector<int32_t>& adj, const std::vector<uint32_t>& bits, int64_t rows, int S,
+                   int mc, int W, int GC, std::vector<int32_t>& out) {
+  out.assign((size_t)rows * GC, -1);
+  for (int64_t r = 0; r < rows; ++r) {
+    int c = 0;
+    for (int pos = 0; pos < S * mc && c < GC; ++pos) {
+      if ((bits[(size_t)r * W + (pos >> 5)] >> (pos & 31)) & 1u) {
+        int32_t t = adj[((size_t)r * S) * mc + pos];
+        if (t >= 0) out[(size_t)r * GC + c++] = t;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// Makes HostIndex H resident on `device`; takes ownership of H's tables.
+int make_resident(HostIndex&& H, int device, int precision, unify_index_t* out) {
+  if (precision < UNIFY_FP32 || precision > UNIFY_FP8E4M3) {
+    set_error("unknown precision");
+    return UNIFY_EINVAL;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return UNIFY_EDEVICE;
+  }
+  unify_index_t ix = new unify_index();
+  ix->device = device;
+  DevIndex& dv = ix->dv;
+  dv.n = H.n;
+  dv.d = H.d;
+  dv.S = H.S;
+  dv.M0 = H.M0;
+  dv.MU = H.MU;
+  dv.L = H.L;
+  dv.gentry = H.gentry;
+  dv.R = H.R;
+  dv.precision = precision;
+  // global-edge lists: as wide as the most marks on any row
+  int GC = 1;
+  auto widest = [&](const std::vector<uint32_t>& bits, int W) {
+    size_t rows = W ? bits.size() / W : 0;
+    for (size_t r = 0; r < rows; ++r) {
+      int c = 0;
+      for (int w = 0; w < W; ++w) c += __builtin_popcount(bits[r * W + w]);
+      GC = std::max(GC, c);
+    }
+  };
+  widest(H.gbits0, H.W0);
+  widest(H.gbitsU, H.WU);
+  dv.GC = GC;
+  std::vector<int32_t> g0, gU;
+  compact_glist(H.adj0, H.gbits0, H.n, H.S, H.M0, H.W0, GC, g0);
+  compact_glist(H.adjU, H.gbitsU, H.R, H.S, H.MU, H.WU, GC, gU);
+  int rc = UNIFY_OK;
+  auto up = [&](auto& vec, auto** dst) {
+    if (rc == UNIFY_OK) rc = upload(ix, vec, dst);
+  };
+  up(H.attr, &dv.attr);
+  up(H.ext, &dv.ext);
+  up(H.seg_start, &dv.seg_start);
+  up(H.seg_entry, &dv.seg_entry);
+  up(H.seg_maxlevel, &dv.seg_maxlevel);
+  up(H.uprow, &dv.uprow);
+  up(H.vec, &dv.vec);
+  up(H.adj0, &dv.adj0);
+  up(g0, &dv.glist0);
+  up(H.adjU, &dv.adjU);
+  up(gU, &dv.glistU);
+  if (rc == UNIFY_OK && precision == UNIFY_BF16) {
+    std::vector<uint16_t> b(H.vec.size());
+    for (size_t i = 0; i < b.size(); ++i) b[i] = f32_to_bf16(H.vec[i]);
+    up(b, &dv.vec_bf16);
+  }
+  if (rc == UNIFY_OK && precision == UNIFY_FP8E4M3) {
+    std::vector<uint8_t> c(H.vec.size());
+    std::vector<float> sc(H.n);
+    for (int64_t v = 0; v < H.n; ++v) {
+      float mx = 0.f;
+      for (int t = 0; t < H.d; ++t) mx = std::max(mx, std::fabs(H.vec[(size_t)v * H.d + t]));
+      const float s = mx > 0.f ? mx / 448.0f : 1.0f;
+      sc[v] = s;
+      for (int t = 0; t < H.d; ++t) c[(size_t)v * H.d + t] = f32_to_e4m3(H.vec[(size_t)v * H.d + t] / s);
+    }
+    up(c, &dv.vec_fp8);
+    up(sc, &dv.vec_scale);
+  }
+  if (rc != UNIFY_OK) {
+    for (void* p : ix->allocs) (void)hipFree(p);
+    delete ix;
+    return rc;
+  }
+  // keep the small tables on the host; drop the big ones
+  ix->host = std::move(H);
+  std::vector<float>().swap(ix->host.vec);
+  std::vector<int32_t>().swap(ix->host.adj0);
+  std::vector<int32_t>().swap(ix->host.adjU);
+  std::vector<uint32_t>().swap(ix->host.gbits0);
+  std::vector<uint32_t>().swap(ix->host.gbitsU);
+  *out = ix;
+  return UNIFY_OK;
+}
+
+}  // namespace unify
+
+using namespace unify;
+
+extern "C" {
+
+const char* unify_last_error(void) { return g_error.c_str(); }
+
+int unify_validate_index_file(const char* path, int64_t* n, int32_t* d, int32_t* S, int32_t* M) {
+  if (!path) {
+    set_error("null path");
+    return UNIFY_EINVAL;
+  }
+  HostIndex H;
+  std::string err;
+  int rc = read_index_file(path, H, err);
+  if (rc != UNIFY_OK) {
+    set_error(err);
+    return rc;
+  }
+  if (n) *n = H.n;
+  if (d) *d = H.d;
+  if (S) *S = H.S;
+  if (M) *M = H.M0;
+  return UNIFY_OK;
+}
+
+int unify_load_index(const char* path, int device, int precision, unify_index_t* out) {
+  if (!path || !out) {
+    set_error("null argument");
+    return UNIFY_EINVAL;
+  }
+  HostIndex H;
+  std::string err;
+  int rc = read_index_file(path, H, err);
+  if (rc != UNIFY_OK) {
+    set_error(err);
+    return rc;
+  }
+  return make_resident(std::move(H), device, precision, out);
+}
+
+int unify_save_index(unify_index_t ix, const char* path) {
+  if (!ix || !path) {
+    set_error("null argument");
+    return UNIFY_EINVAL;
+  }
+  if (hipSetDevice(ix->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return UNIFY_EDEVICE;
+  }
+  HostIndex H = ix->host;
+  const DevIndex& dv = ix->dv;
+  H.vec.resize((size_t)dv.n * dv.d);
+  H.adj0.resize((size_t)dv.n * dv.S * dv.M0);
+  H.adjU.resize((size_t)dv.R * dv.S * dv.MU);
+  bool ok = hipMemcpy(H.vec.data(), dv.vec, H.vec.size() * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(H.adj0.data(), dv.adj0, H.adj0.size() * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+            (H.adjU.empty() ||
+             hipMemcpy(H.adjU.data(), dv.adjU, H.adjU.size() * 4, hipMemcpyDeviceToHost) == hipSuccess);
+  if (!ok) {
+    set_error("device-to-host copy failed");
+    return UNIFY_EDEVICE;
+  }
+  // rebuild the bitmaps from the compacted global-edge lists
+  std::vector<int32_t> g0((size_t)dv.n * dv.GC), gU((size_t)dv.R * dv.GC);
+  ok = hipMemcpy(g0.data(), dv.glist0, g0.size() * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+       (gU.empty() || hipMemcpy(gU.data(), dv.glistU, gU.size() * 4, hipMemcpyDeviceToHost) == hipSuccess);
+  if (!ok) {
+    set_error("device-to-host copy failed");
+    return UNIFY_EDEVICE;
+  }
+  auto bits_of = [&](const std::vector<int32_t>& adj, const std::vector<int32_t>& gl, int64_t rows, int mc,
+                     int W, std::vector<uint32_t>& bits) {
+    bits.assign((size_t)rows * W, 0u);
+    for (int64_t r = 0; r < rows; ++r) {
+      for (int t = 0; t < dv.GC; ++t) {
+        int32_t g = gl[(size_t)r * dv.GC + t];
+        if (g < 0) continue;
+        for (int pos = 0; pos < dv.S * mc; ++pos)
+          if (adj[(size_t)r * dv.S * mc + pos] == g) {
+            bits[(size_t)r * W + (pos >> 5)] |= 1u << (pos & 31);
+            break;
+          }
+      }
+    }
+  };
+  bits_of(H.adj0, g0, dv.n, dv.M0, H.W0, H.gbits0);
+  bits_of(H.adjU, gU, dv.R, dv.MU, H.WU, H.gbitsU);
+  std::string err;
+  int rc = write_index_file(path, H, err);
+  if (rc != UNIFY_OK) set_error(err);
+  return rc;
+}
+
+int unify_index_info(unify_index_t ix, int64_t* n, int32_t* d, int32_t* S, int32_t* M, int32_t* levels) {
+  if (!ix) {
+    set_error("null index");
+    return UNIFY_EINVAL;
+  }
+  if (n) *n = ix->dv.n;
+  if (d) *d = ix->dv.d;
+  if (S) *S = ix->dv.S;
+  if (M) *M = ix->dv.M0;
+  if (levels) *levels = ix->dv.L + 1;
+  return UNIFY_OK;
+}
+
+int unify_search(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                 int32_t k, int32_t ef, const int8_t* strategy, const unify_params* params, int64_t* out_ids,
+                 float* out_dist, int8_t* out_strategy, void* hip_stream) {
+  return search_impl(ix, queries, nq, l, h, k, ef, strategy, params, out_ids, out_dist, out_strategy, nullptr,
+                     hip_stream);
+}
+
+int unify_search_ex(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                    int32_t k, int32_t ef, const int8_t* strategy, const unify_params* params, int64_t* out_ids,
+                    float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* hip_stream) {
+  return search_impl(ix, queries, nq, l, h, k, ef, strategy, params, out_ids, out_dist, out_strategy, out_stats,
+                     hip_stream);
+}
+
+int unify_free_index(unify_index_t ix) {
+  if (!ix) return UNIFY_OK;
+  (void)hipSetDevice(ix->device);
+  for (void* p : ix->allocs) (void)hipFree(p);
+  delete ix;
+  return UNIFY_OK;
+}
+
+int unify_build_index(const float* vectors, const int64_t* attr, const double* level_u, int64_t n, int32_t d,
+                      int32_t S, int32_t M, int32_t ef_cons, int device, int precision, unify_index_t* out) {
+  (void)vectors, (void)attr, (void)level_u, (void)n, (void)d, (void)S, (void)M, (void)ef_cons, (void)device,
+      (void)precision, (void)out;
+  set_error("unify_build_index: not available in this build");
+  return UNIFY_EINVAL;
+}
+
+}  // extern "C"

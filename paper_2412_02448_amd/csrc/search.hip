@@ -1,0 +1,732 @@
+// Range-filtered k-NN search over a resident HSIG on gfx950.
+//
+// One 64-lane wavefront runs one query (persistent waves pull queries from a
+// work list).  The strategies follow Sec. 4.2 of the paper:
+//   pre    (strategy A): exact scan of the contiguous id slice [lo, hi);
+//   hybrid (strategy C): the scheme of Alg. 2 with Alg. 7 on each layer, over the
+//          first ceil(m / S') entries of each active chunk;
+//   post   (strategy B): Alg. 2 with Alg. 1 over the global (marked) edges, then
+//          the range filter.
+// The choice between them is the range-aware rule of Sec. 4.2.
+//
+// A layer search keeps three structures in LDS:
+//   visited  an open-addressing hash of ids (exact, never forgets);
+//   cand     an unsorted array of keys with tombstones; pop = wave argmin;
+//   ann      a sorted key list kept by bitonic block merges.
+// One step pops up to p candidates (p = 1 is the sequential loop), gathers
+// their unvisited neighbours, evaluates all distances at once, and admits each
+// neighbour against the threshold taken before the step.  With a strict total
+// order on keys this gives the same ann and the same stopping point as
+// evaluating the neighbours one at a time; see DESIGN notes on batch admission.
+// If a query's visited set or candidate array outgrows its LDS capacity, the
+// query is abandoned and re-run by a second launch with larger capacities.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "unify_internal.h"
+#include "wave.h"
+
+namespace unify {
+
+struct QPlan {
+  int32_t lo, hi;   // in-range internal ids [lo, hi)
+  int32_t a, b;     // active segments a..b (segments holding an in-range object)
+  int32_t strat;    // UNIFY_PRE / HYBRID / POST; -1 when the range is empty
+  int32_t pad;
+};
+
+struct SearchArgs {
+  DevIndex ix;
+  const float* Q;
+  int64_t nq;
+  int32_t k, ef, m, p, rerank;
+  int32_t ccap, hcap, ef_blocks, nbr_cap;
+  int32_t pass;  // 0: first pass, 1: larger-capacity re-run
+  int64_t* out_ids;
+  float* out_dist;
+  int32_t* out_stats;
+  const QPlan* plan;
+  const int32_t* work;    // query indices to run
+  const int32_t* nwork;   // number of entries in work
+  int32_t* next;          // work counter
+  int32_t* fb_list;       // queries abandoned by the first pass
+  int32_t* fb_count;
+};
+
+constexpr uint32_t HASH_EMPTY = 0xFFFFFFFFu;
+constexpr int MAX_PROBE = 128;
+
+// ---------------------------------------------------------------------------
+// Plan: the range becomes an id interval [lo, hi) (the skip-list walk of
+// strategy A reduces to two binary searches over the sorted attributes), Y =
+// hi - lo, the active segments are those of lo and hi - 1, and the strategy
+// follows the range-aware rule unless the caller forces one.
+// ---------------------------------------------------------------------------
+__device__ int64_t lower_bound_i64(const int64_t* a, int64_t n, int64_t x) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+__device__ int64_t upper_bound_i64(const int64_t* a, int64_t n, int64_t x) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a[mid] <= x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t* __restrict__ h,
+                       const int8_t* __restrict__ strat_in, int64_t nq, int64_t tauA, int64_t tauB,
+                       int32_t k, QPlan* __restrict__ plan, int8_t* __restrict__ out_strat,
+                       int64_t* __restrict__ out_ids, float* __restrict__ out_dist,
+                       int32_t* __restrict__ out_stats) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const int64_t lq = l[q], hq = h[q];
+  int64_t lo = 0, hi = 0;
+  if (lq <= hq) {
+    lo = lower_bound_i64(ix.attr, ix.n, lq);
+    hi = upper_bound_i64(ix.attr, ix.n, hq);
+    if (hi < lo) hi = lo;
+  }
+  const int64_t Y = hi - lo;
+  int s = strat_in ? (int)strat_in[q] : UNIFY_AUTO;
+  if (s < UNIFY_AUTO || s > UNIFY_POST) s = UNIFY_AUTO;
+  if (s == UNIFY_AUTO) s = Y <= tauA ? UNIFY_PRE : (Y >= tauB ? UNIFY_POST : UNIFY_HYBRID);
+  QPlan P;
+  P.lo = (int32_t)lo;
+  P.hi = (int32_t)hi;
+  P.a = P.b = 0;
+  P.pad = 0;
+  if (Y > 0) {
+    P.a = (int32_t)(upper_bound_i64(ix.seg_start, ix.S + 1, lo) - 1);
+    P.b = (int32_t)(upper_bound_i64(ix.seg_start, ix.S + 1, hi - 1) - 1);
+    P.strat = s;
+  } else {
+    P.strat = -1;
+    for (int t = 0; t < k; ++t) {
+      out_ids[q * k + t] = -1;
+      out_dist[q * k + t] = __builtin_inff();
+    }
+    if (out_stats) {
+      for (int t = 0; t < 4; ++t) out_stats[q * 4 + t] = 0;
+    }
+  }
+  plan[q] = P;
+  if (out_strat) out_strat[q] = (int8_t)s;
+}
+
+// Work list: queries with a non-empty range, in query order; resets counters.
+__global__ void k_worklist(const QPlan* __restrict__ plan, int64_t nq, int32_t* __restrict__ work,
+                           int32_t* __restrict__ counters /* nwork, next, fb_count, fb_next */) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x, T = blockDim.x;
+  const int64_t per = (nq + T - 1) / T;
+  const int64_t s0 = std::min<int64_t>(nq, t * per), s1 = std::min<int64_t>(nq, s0 + per);
+  int32_t c = 0;
+  for (int64_t q = s0; q < s1; ++q) c += plan[q].strat >= 0;
+  part[t] = c;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {
+    int32_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t pos = part[t] - c;
+  for (int64_t q = s0; q < s1; ++q)
+    if (plan[q].strat >= 0) work[pos++] = (int32_t)q;
+  if (t == T - 1) {
+    counters[0] = part[T - 1];
+    counters[1] = 0;
+    counters[2] = 0;
+    counters[3] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Vector loads: 4 consecutive elements of row v, group g, as FP32.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+// OCP FP8 E4M3 (no infinities; 0x7F/0xFF are NaN): value = (-1)^s 2^(e-7) (1 + m/8),
+// subnormals 2^-6 m/8.
+__device__ __forceinline__ float e4m3_to_f32(uint32_t c) {
+  const uint32_t s = (c >> 7) & 1u, e = (c >> 3) & 15u, m = c & 7u;
+  float mag;
+  if (e == 0) mag = (float)m * 0.001953125f;  // m * 2^-9
+  else if (e == 15 && m == 7) mag = __builtin_nanf("");
+  else mag = __uint_as_float(((e + 120u) << 23) | (m << 20));
+  return s ? -mag : mag;
+}
+
+template <int PREC>
+__device__ __forceinline__ float4 load4(const DevIndex& ix, int64_t v, int g) {
+  const int64_t off = v * ix.d + 4 * g;
+  if constexpr (PREC == UNIFY_FP32) {
+    return *reinterpret_cast<const float4*>(ix.vec + off);
+  } else if constexpr (PREC == UNIFY_BF16) {
+    uint2 w = *reinterpret_cast<const uint2*>(ix.vec_bf16 + off);
+    return make_float4(bf16_to_f32(w.x & 0xFFFFu), bf16_to_f32(w.x >> 16), bf16_to_f32(w.y & 0xFFFFu),
+                       bf16_to_f32(w.y >> 16));
+  } else {
+    uint32_t w = *reinterpret_cast<const uint32_t*>(ix.vec_fp8 + off);
+    const float sc = ix.vec_scale[v];
+    return make_float4(e4m3_to_f32(w & 0xFFu) * sc, e4m3_to_f32((w >> 8) & 0xFFu) * sc,
+                       e4m3_to_f32((w >> 16) & 0xFFu) * sc, e4m3_to_f32(w >> 24) * sc);
+  }
+}
+
+// Keys of cnt vectors: id_of(i) gives the id of the i-th; the key of the i-th
+// is written to keys[i] (LDS).  Four vectors per round, RB rounds per batch of loads.
+template <int NG, int PREC, class IdOf>
+__device__ __forceinline__ void eval_keys(const DevIndex& ix, const float4 (&qv)[NG], int cnt,
+                                          IdOf id_of, u64* keys) {
+  constexpr int RB = NG <= 2 ? 4 : (NG <= 4 ? 2 : 1);
+  const int lane = lane_id();
+  const int s = lane & 15, g4 = lane >> 4;
+  const int G = ix.d >> 2;
+  for (int base = 0; base < cnt; base += 4 * RB) {
+    float4 x[RB][NG];
+    int32_t vid[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int idx = base + 4 * r + g4;
+      vid[r] = idx < cnt ? id_of(idx) : -1;
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+        const int g = s + 16 * i;
+        x[r][i] = (vid[r] >= 0 && g < G) ? load4<PREC>(ix, vid[r], g) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+        if (s + 16 * i < G) acc = fma_sq4(x[r][i], qv[i], acc);
+      }
+      acc = group_reduce16(acc);
+      const int idx = base + 4 * r + g4;
+      if (s == 0 && idx < cnt) keys[idx] = make_key(acc, vid[r]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-wave LDS state
+// ---------------------------------------------------------------------------
+struct Lds {
+  u64* ann;
+  u64* cand;
+  uint32_t* hash;
+  int32_t* nbr;
+  u64* bkeys;
+};
+
+__device__ __forceinline__ bool hash_insert(uint32_t* hash, uint32_t hmask, int hbits, int32_t v,
+                                            bool& overflow) {
+  uint32_t hpos = ((uint32_t)v * 2654435761u) >> (32 - hbits);
+  for (int probe = 0; probe < MAX_PROBE; ++probe) {
+    uint32_t old = atomicCAS(&hash[hpos], HASH_EMPTY, (uint32_t)v);
+    if (old == HASH_EMPTY) return true;
+    if (old == (uint32_t)v) return false;
+    hpos = (hpos + 1) & hmask;
+  }
+  overflow = true;
+  return false;
+}
+
+struct Counters {
+  int32_t ndist = 0, nexp = 0, nvisit0 = 0;
+};
+
+// One layer of the search (Alg. 1 / Alg. 7 with beam width p).  On return, the
+// ann list holds `al` keys ascending.  Returns false on capacity overflow.
+template <int NG, int PREC>
+__device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
+                             bool hybrid, bool filter, int c, int32_t ep, u64 ep_key, int layer, int efl,
+                             int p, int& al, Counters& cnt) {
+  const DevIndex& ix = A.ix;
+  const int lane = lane_id();
+  int hbits = 0;
+  while ((1 << hbits) < A.hcap) ++hbits;
+  const uint32_t hmask = (uint32_t)A.hcap - 1;
+  for (int i = lane; i < A.hcap; i += WAVE) L.hash[i] = HASH_EMPTY;
+  __syncthreads();
+  bool overflow = false;
+  if (lane == 0) hash_insert(L.hash, hmask, hbits, ep, overflow);
+  int hcount = 1;
+  // cand = {ep}; ann = {ep} unless filtered out
+  if (lane == 0) L.cand[0] = ep_key;
+  int cl = 1;
+  const bool ep_in = !filter || (ep >= P.lo && ep < P.hi);
+  L.ann[lane] = (ep_in && lane == 0) ? ep_key : KEY_MAX;
+  al = ep_in ? 1 : 0;
+  __syncthreads();
+
+  const int mc = layer == 0 ? ix.M0 : ix.MU;
+  const int Sa = P.b - P.a + 1;
+  const int per_node = hybrid ? Sa * min(c, mc) : ix.GC;
+  const int64_t max_steps = ix.n + 2;
+  int64_t steps = 0;
+  int32_t popped[8];
+
+  while (true) {
+    if (++steps > max_steps) {
+      overflow = true;
+      break;
+    }
+    const bool full = al == efl;
+    const u64 T = full ? L.ann[efl - 1] : KEY_MAX;
+    // pop up to p candidates that pass the stopping test
+    int npop = 0;
+    for (int t = 0; t < p; ++t) {
+      u64 best = KEY_MAX;
+      int bidx = -1;
+      for (int i = lane; i < cl; i += WAVE) {
+        u64 kk = L.cand[i];
+        if (kk < best) {
+          best = kk;
+          bidx = i;
+        }
+      }
+      const u64 mn = wave_min64(best);
+      if (mn == KEY_MAX || (full && mn > T)) break;
+      const u64 who = ballot(best == mn);
+      const int src = __ffsll((unsigned long long)who) - 1;
+      const int idx = __shfl(bidx, src, WAVE);
+      if (lane == src) L.cand[idx] = KEY_MAX;
+      popped[t] = key_id(mn);
+      ++npop;
+      __syncthreads();
+    }
+    if (npop == 0) break;
+    cnt.nexp += npop;
+    // unvisited neighbours of the popped candidates
+    int nn = 0;
+    for (int t = 0; t < npop; ++t) {
+      const int32_t o = popped[t];
+      const int32_t* row;
+      if (hybrid) {
+        row = layer == 0 ? ix.adj0 + (int64_t)o * ix.S * mc
+                         : ix.adjU + ((int64_t)ix.uprow[o] + layer - 1) * ix.S * mc;
+      } else {
+        row = layer == 0 ? ix.glist0 + (int64_t)o * ix.GC
+                         : ix.glistU + ((int64_t)ix.uprow[o] + layer - 1) * ix.GC;
+      }
+      for (int base = 0; base < per_node; base += WAVE) {
+        const int tt = base + lane;
+        int32_t v = -1;
+        if (tt < per_node) {
+          if (hybrid) {
+            const int cc = min(c, mc);
+            const int j = P.a + tt / cc, r = tt % cc;
+            v = row[j * mc + r];
+          } else {
+            v = row[tt];
+          }
+        }
+        bool isnew = v >= 0 && hash_insert(L.hash, hmask, hbits, v, overflow);
+        const u64 nm = ballot(isnew);
+        if (isnew) L.nbr[nn + rank_in(nm)] = v;
+        nn += __popcll(nm);
+      }
+    }
+    hcount += nn;
+    if (__any(overflow) || hcount * 4 > A.hcap * 3) {
+      overflow = true;
+      break;
+    }
+    if (nn == 0) continue;
+    __syncthreads();
+    cnt.ndist += nn;
+    eval_keys<NG, PREC>(ix, qv, nn, [&](int i) { return L.nbr[i]; }, L.bkeys);
+    __syncthreads();
+    // admission against the threshold from before this step
+    for (int base = 0; base < nn; base += WAVE) {
+      const int tt = base + lane;
+      const u64 key = tt < nn ? L.bkeys[tt] : KEY_MAX;
+      const bool adm = key != KEY_MAX && key < T;
+      const u64 am = ballot(adm);
+      const int na = __popcll(am);
+      if (na == 0) continue;
+      if (cl + na > A.ccap) {
+        // compact: drop tombstones and keys that can no longer be expanded
+        const u64 W = al == efl ? L.ann[efl - 1] : KEY_MAX;
+        int ncl = 0;
+        for (int i0 = 0; i0 < cl; i0 += WAVE) {
+          const int i = i0 + lane;
+          const u64 kk = i < cl ? L.cand[i] : KEY_MAX;
+          const bool keep = kk != KEY_MAX && kk <= W;
+          const u64 km = ballot(keep);
+          __syncthreads();
+          if (keep) L.cand[ncl + rank_in(km)] = kk;
+          ncl += __popcll(km);
+          __syncthreads();
+        }
+        cl = ncl;
+        if (cl + na > A.ccap) {
+          overflow = true;
+          break;
+        }
+      }
+      if (adm) L.cand[cl + rank_in(am)] = key;
+      cl += na;
+      const int32_t id = key_id(key);
+      const bool in_r = adm && (!filter || (id >= P.lo && id < P.hi));
+      list_insert(L.ann, al, efl, in_r ? key : KEY_MAX);
+      __syncthreads();
+    }
+    if (overflow) break;
+  }
+  if (layer == 0) cnt.nvisit0 = hcount;
+  return !__any(overflow);
+}
+
+// Strategy A: exact top-k over the id slice [lo, hi).
+template <int NG>
+__device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
+                         int& al, Counters& cnt) {
+  const int lane = lane_id();
+  const int k = A.k;
+  al = 0;
+  for (int blk = 0; blk * WAVE < k; ++blk) L.ann[blk * WAVE + lane] = KEY_MAX;
+  __syncthreads();
+  for (int base = P.lo; base < P.hi; base += WAVE) {
+    const int cntv = min(WAVE, P.hi - base);
+    eval_keys<NG, UNIFY_FP32>(A.ix, qv, cntv, [&](int i) { return base + i; }, L.bkeys);
+    __syncthreads();
+    const u64 key = lane < cntv ? L.bkeys[lane] : KEY_MAX;
+    const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
+    list_insert(L.ann, al, k, key < T ? key : KEY_MAX);
+    __syncthreads();
+  }
+  cnt.ndist += P.hi - P.lo;
+}
+
+__device__ __forceinline__ bool ne_missing(int top) { return top < 0; }
+
+template <int NG, int PREC>
+__device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q) {
+  const DevIndex& ix = A.ix;
+  const int lane = lane_id();
+  const QPlan P = A.plan[q];
+  float4 qv[NG];
+  {
+    const int s = lane & 15, G = ix.d >> 2;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const int g = s + 16 * i;
+      qv[i] = g < G ? *reinterpret_cast<const float4*>(A.Q + (int64_t)q * ix.d + 4 * g)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  Counters cnt;
+  int al = 0;
+  bool ok = true;
+  const bool hybrid = P.strat == UNIFY_HYBRID;
+  int kout = A.k;
+  if (P.strat == UNIFY_PRE) {
+    pre_scan<NG>(A, L, qv, P, al, cnt);
+  } else {
+    const int Sa = P.b - P.a + 1;
+    const int c = (A.m + Sa - 1) / Sa;
+    int32_t ep;
+    int top;
+    u64 ep_key;
+    if (hybrid) {
+      // entry of the active segment with the highest top level; ties: nearer, then smaller id
+      top = -1;
+      for (int j = P.a; j <= P.b; ++j)
+        if (ix.seg_entry[j] >= 0) top = max(top, ix.seg_maxlevel[j]);
+      int ne = 0;
+      for (int j0 = P.a; j0 <= P.b; j0 += WAVE) {
+        const int j = j0 + lane;
+        const bool is = j <= P.b && ix.seg_entry[j] >= 0 && ix.seg_maxlevel[j] == top;
+        const u64 mk = ballot(is);
+        if (is) L.nbr[ne + rank_in(mk)] = ix.seg_entry[j];
+        ne += __popcll(mk);
+      }
+      __syncthreads();
+      eval_keys<NG, PREC>(ix, qv, ne, [&](int i) { return L.nbr[i]; }, L.bkeys);
+      __syncthreads();
+      cnt.ndist += ne;
+      const u64 kk = lane < ne ? L.bkeys[lane] : KEY_MAX;
+      ep_key = wave_min64(kk);
+      ep = key_id(ep_key);
+      __syncthreads();
+      if (ne == 0) {  // no entry among the active segments: nothing to search
+        top = -1;
+        ok = false;
+      }
+    } else {
+      top = ix.L;
+      ep = ix.gentry;
+      L.nbr[0] = ep;
+      __syncthreads();
+      eval_keys<NG, PREC>(ix, qv, 1, [&](int i) { return L.nbr[i]; }, L.bkeys);
+      __syncthreads();
+      ep_key = L.bkeys[0];
+      cnt.ndist += 1;
+      __syncthreads();
+    }
+    for (int layer = top; layer >= 1 && ok; --layer) {
+      ok = layer_search<NG, PREC>(A, L, qv, P, hybrid, false, c, ep, ep_key, layer, 1, 1, al, cnt);
+      ep_key = L.ann[0];
+      ep = key_id(ep_key);
+      __syncthreads();
+    }
+    if (ok) ok = layer_search<NG, PREC>(A, L, qv, P, hybrid, hybrid, c, ep, ep_key, 0, A.ef, A.p, al, cnt);
+    if (ne_missing(top)) {
+      al = 0;
+      ok = true;
+    }
+  }
+  if (!ok) {
+    if (A.pass == 0) {
+      if (lane == 0) {
+        const int32_t slot = atomicAdd(A.fb_count, 1);
+        A.fb_list[slot] = q;
+      }
+      return;
+    }
+  }
+  // outputs: hybrid / pre take the first k; post keeps in-range entries in order
+  int written = 0;
+  for (int base = 0; base < al && written < kout; base += WAVE) {
+    const int t = base + lane;
+    const u64 key = t < al ? L.ann[t] : KEY_MAX;
+    const int32_t id = key_id(key);
+    const bool keep = key != KEY_MAX && (P.strat != UNIFY_POST || (id >= P.lo && id < P.hi));
+    const u64 km = ballot(keep);
+    const int pos = written + rank_in(km);
+    if (keep && pos < kout) {
+      A.out_ids[(int64_t)q * kout + pos] = ix.ext[id];
+      A.out_dist[(int64_t)q * kout + pos] = key_dist(key);
+    }
+    written += __popcll(km);
+  }
+  written = min(written, kout);
+  if (!ok) written = 0;
+  for (int t = written + lane; t < kout; t += WAVE) {
+    A.out_ids[(int64_t)q * kout + t] = -1;
+    A.out_dist[(int64_t)q * kout + t] = __builtin_inff();
+  }
+  if (A.out_stats && lane == 0) {
+    A.out_stats[q * 4 + 0] = cnt.ndist;
+    A.out_stats[q * 4 + 1] = cnt.nexp;
+    A.out_stats[q * 4 + 2] = cnt.nvisit0;
+    A.out_stats[q * 4 + 3] = ok ? A.pass : 2;
+  }
+}
+
+template <int NG, int PREC>
+__global__ void __launch_bounds__(64) k_search(SearchArgs A) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  Lds L;
+  unsigned char* p = lds_raw;
+  L.ann = reinterpret_cast<u64*>(p);
+  p += sizeof(u64) * A.ef_blocks * WAVE;
+  L.cand = reinterpret_cast<u64*>(p);
+  p += sizeof(u64) * A.ccap;
+  L.bkeys = reinterpret_cast<u64*>(p);
+  p += sizeof(u64) * A.nbr_cap;
+  L.hash = reinterpret_cast<uint32_t*>(p);
+  p += sizeof(uint32_t) * A.hcap;
+  L.nbr = reinterpret_cast<int32_t*>(p);
+  const int32_t nwork = *A.nwork;
+  while (true) {
+    int32_t w = 0;
+    if (lane_id() == 0) w = atomicAdd(A.next, 1);
+    w = __shfl(w, 0, WAVE);
+    if (w >= nwork) break;
+    run_query<NG, PREC>(A, L, A.work[w]);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+namespace {
+
+size_t lds_bytes(int ef_blocks, int ccap, int hcap, int nbr_cap) {
+  return sizeof(u64) * ((size_t)ef_blocks * WAVE + ccap + nbr_cap) + sizeof(uint32_t) * hcap +
+         sizeof(int32_t) * nbr_cap;
+}
+
+typedef void (*KernelFn)(SearchArgs);
+
+template <int PREC>
+KernelFn pick_kernel(int d) {
+  const int ng = (d + 63) / 64;
+  if (ng <= 2) return k_search<2, PREC>;
+  if (ng <= 4) return k_search<4, PREC>;
+  if (ng <= 8) return k_search<8, PREC>;
+  if (ng <= 15) return k_search<15, PREC>;
+  if (ng <= 32) return k_search<32, PREC>;
+  return nullptr;
+}
+
+KernelFn kernel_for(int d, int prec) {
+  if (prec == UNIFY_BF16) return pick_kernel<UNIFY_BF16>(d);
+  if (prec == UNIFY_FP8E4M3) return pick_kernel<UNIFY_FP8E4M3>(d);
+  return pick_kernel<UNIFY_FP32>(d);
+}
+
+#define HIP_OK(x)                                                            \
+  do {                                                                       \
+    hipError_t e_ = (x);                                                     \
+    if (e_ != hipSuccess) {                                                  \
+      set_error(std::string(#x) + ": " + hipGetErrorString(e_));             \
+      return UNIFY_EDEVICE;                                                  \
+    }                                                                        \
+  } while (0)
+
+int launch_pass(KernelFn fn, SearchArgs A, int device, hipStream_t st, size_t lds) {
+  HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per_cu = 0;
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), 64, lds));
+  int cus = 0;
+  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  if (per_cu < 1) {
+    set_error("search kernel does not fit on a compute unit");
+    return UNIFY_EDEVICE;
+  }
+  int64_t grid = (int64_t)per_cu * cus;
+  if (grid > A.nq) grid = A.nq;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), lds, st, A);
+  HIP_OK(hipGetLastError());
+  return UNIFY_OK;
+}
+
+}  // namespace
+
+int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
+                float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream) {
+  if (!ix) {
+    set_error("null index");
+    return UNIFY_EINVAL;
+  }
+  if (nq < 0 || nq >= (int64_t(1) << 31)) {
+    set_error("nq out of range");
+    return UNIFY_EINVAL;
+  }
+  if (k < 1 || k > 256) {
+    set_error("k must be in [1, 256]");
+    return UNIFY_EINVAL;
+  }
+  if (ef < k || ef > 256) {
+    set_error("ef must be in [k, 256]");
+    return UNIFY_EINVAL;
+  }
+  unify_params P{};
+  if (prm) P = *prm;
+  const DevIndex& dv = ix->dv;
+  const int m = P.m > 0 ? P.m : dv.M0;
+  const int p = P.beam_p > 0 ? P.beam_p : 1;
+  const double ta = P.tau_a_frac > 0 ? P.tau_a_frac : 0.01;
+  const double tb = P.tau_b_frac > 0 ? P.tau_b_frac : 0.5;
+  if (m > dv.S * dv.M0 || p > 8 || ta > 1.0 || tb > 1.0) {
+    set_error("params out of range (m <= S*M0, beam_p <= 8, tau fractions <= 1)");
+    return UNIFY_EINVAL;
+  }
+  if (!queries || !l || !h || !out_ids || !out_dist) {
+    if (nq == 0) return UNIFY_OK;
+    set_error("null buffer");
+    return UNIFY_EINVAL;
+  }
+  if (nq == 0) return UNIFY_OK;
+  HIP_OK(hipSetDevice(ix->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t tauA = (int64_t)std::floor(ta * (double)dv.n);
+  const int64_t tauB = (int64_t)std::ceil(tb * (double)dv.n);
+
+  // scratch: plans, work list, fallback list, counters
+  const size_t plan_b = sizeof(QPlan) * nq, list_b = sizeof(int32_t) * nq;
+  void* scratch = nullptr;
+  HIP_OK(hipMallocAsync(&scratch, plan_b + 2 * list_b + 64, st));
+  QPlan* plan = reinterpret_cast<QPlan*>(scratch);
+  int32_t* work = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(scratch) + plan_b);
+  int32_t* fb = work + nq;
+  int32_t* counters = fb + nq;  // nwork, next, fb_count, fb_next
+
+  int rc = UNIFY_OK;
+  const unsigned pb = 256;
+  hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, dv, l, h, strategy, nq,
+                     tauA, tauB, k, plan, out_strategy, out_ids, out_dist, out_stats);
+  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, plan, nq, work, counters);
+  if (hipGetLastError() != hipSuccess) rc = UNIFY_EDEVICE;
+
+  KernelFn fn = kernel_for(dv.d, dv.precision);
+  if (rc == UNIFY_OK && !fn) {
+    set_error("unsupported dimension");
+    rc = UNIFY_EINVAL;
+  }
+  if (rc == UNIFY_OK) {
+    const int S = dv.S;
+    const int per_node = std::max(std::min(m + S - 1, S * std::max(dv.M0, dv.MU)), dv.GC);
+    const int nb1 = (per_node + WAVE - 1) / WAVE * WAVE;
+    SearchArgs A{};
+    A.ix = dv;
+    A.Q = queries;
+    A.nq = nq;
+    A.k = k;
+    A.ef = ef;
+    A.m = m;
+    A.p = p;
+    A.rerank = P.rerank_mult > 0 ? P.rerank_mult : 4;
+    A.ef_blocks = (std::max(ef, k) + WAVE - 1) / WAVE;
+    A.nbr_cap = std::max(p * nb1, WAVE);
+    A.out_ids = out_ids;
+    A.out_dist = out_dist;
+    A.out_stats = out_stats;
+    A.plan = plan;
+    // first pass: modest LDS per wave for occupancy
+    A.ccap = 512;
+    A.hcap = 2048;
+    A.pass = 0;
+    A.work = work;
+    A.nwork = counters + 0;
+    A.next = counters + 1;
+    A.fb_list = fb;
+    A.fb_count = counters + 2;
+    rc = launch_pass(fn, A, ix->device, st, lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap));
+    if (rc == UNIFY_OK) {
+      // second pass over the abandoned queries with the largest LDS that fits
+      int maxlds = 0;
+      if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) != hipSuccess)
+        maxlds = 65536;
+      int cc = 8192, hc = 32768;
+      while (lds_bytes(A.ef_blocks, cc, hc, A.nbr_cap) > (size_t)maxlds && cc > 1024) {
+        cc /= 2;
+        hc /= 2;
+      }
+      SearchArgs B = A;
+      B.ccap = cc;
+      B.hcap = hc;
+      B.pass = 1;
+      B.work = fb;
+      B.nwork = counters + 2;
+      B.next = counters + 3;
+      rc = launch_pass(fn, B, ix->device, st, lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap));
+    }
+  }
+  if (hipFreeAsync(scratch, st) != hipSuccess && rc == UNIFY_OK) rc = UNIFY_EDEVICE;
+  return rc;
+}
+
+}  // namespace unify

@@ -1,0 +1,69 @@
+// Internal declarations shared by the HIP translation units of libunify.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/unify.h"
+
+namespace unify {
+
+// Device-resident index.  Internal ids are ranks in (attribute, external id)
+// order, so the objects in an attribute range are one contiguous id interval
+// (the layer-0 skip list of Sec. 4.1 becomes "next = id + 1").
+struct DevIndex {
+  int64_t n;
+  int32_t d, S, M0, MU, GC, L, gentry;
+  int64_t R;            // rows of the upper-layer tables
+  int32_t precision;    // UNIFY_FP32 / BF16 / FP8E4M3 store read by the graph searches
+  int32_t pad;
+  const int64_t* attr;       // [n] sorted attributes
+  const int64_t* ext;        // [n] external id of each internal id
+  const int64_t* seg_start;  // [S+1] first internal id of each segment
+  const int32_t* seg_entry;  // [S] entry (internal id) of each segment's HNSW, -1 if empty
+  const int32_t* seg_maxlevel;  // [S]
+  const int32_t* uprow;      // [n] row of (v, layer 1) in the upper tables; rows of layers 2.. follow
+  const float* vec;          // [n][d] FP32 store
+  const uint16_t* vec_bf16;  // [n][d] BF16 store or null
+  const uint8_t* vec_fp8;    // [n][d] FP8 E4M3 store or null
+  const float* vec_scale;    // [n] FP8 scale or null
+  const int32_t* adj0;       // [n][S][M0] layer-0 chunks, -1 padded
+  const int32_t* glist0;     // [n][GC] layer-0 global (marked) edges, -1 padded
+  const int32_t* adjU;       // [R][S][MU]
+  const int32_t* glistU;     // [R][GC]
+};
+
+// Host-side tables of an index (the index file content), internal ids.
+struct HostIndex {
+  int64_t n = 0;
+  int32_t d = 0, S = 0, M0 = 0, MU = 0, L = -1, gentry = -1, ef_cons = 0;
+  double mL = 0;
+  uint64_t seed = 0;
+  int64_t R = 0;
+  int32_t W0 = 0, WU = 0;
+  std::vector<int64_t> attr, ext, seg_start;
+  std::vector<int32_t> seg_entry, seg_maxlevel;
+  std::vector<uint8_t> level;
+  std::vector<int32_t> uprow;
+  std::vector<float> vec;
+  std::vector<int32_t> adj0, adjU;
+  std::vector<uint32_t> gbits0, gbitsU;
+};
+
+int read_index_file(const char* path, HostIndex& H, std::string& err);
+int write_index_file(const char* path, const HostIndex& H, std::string& err);
+int validate_index(const HostIndex& H, std::string& err);
+
+void set_error(const std::string& msg);
+
+}  // namespace unify
+
+struct unify_index {
+  int device = 0;
+  unify::DevIndex dv{};
+  unify::HostIndex host;  // small tables kept on the host; large ones released after upload
+  std::vector<void*> allocs;
+};

@@ -1,0 +1,133 @@
+// Wavefront-level building blocks for gfx950 (64 lanes): 64-bit key shuffles,
+// bitonic sort / merge across lanes, ballot-based compaction, and the
+// canonical FP32 squared distance evaluated by 16 lanes per vector.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace unify {
+
+typedef unsigned long long u64;
+constexpr u64 KEY_MAX = ~0ull;
+constexpr int WAVE = 64;
+
+// Key = (FP32 distance bits, id).  Distances are >= +0, so comparing the keys
+// as unsigned 64-bit integers orders by (distance, id).
+__device__ __forceinline__ u64 make_key(float d, int32_t id) {
+  return ((u64)__float_as_uint(d) << 32) | (uint32_t)id;
+}
+__device__ __forceinline__ float key_dist(u64 k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ __forceinline__ int32_t key_id(u64 k) { return (int32_t)(uint32_t)k; }
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ u64 shfl64(u64 v, int src) {
+  uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, WAVE);
+  uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, WAVE);
+  return ((u64)hi << 32) | lo;
+}
+__device__ __forceinline__ u64 shfl_xor64(u64 v, int m) {
+  uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, WAVE);
+  uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);
+  return ((u64)hi << 32) | lo;
+}
+__device__ __forceinline__ u64 umin64(u64 a, u64 b) { return a < b ? a : b; }
+__device__ __forceinline__ u64 umax64(u64 a, u64 b) { return a < b ? b : a; }
+
+// Lanes below this one whose bit is set in mask.
+__device__ __forceinline__ int rank_in(u64 mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+__device__ __forceinline__ u64 ballot(bool p) { return __ballot(p); }
+
+// Wave-wide minimum of a 64-bit key.
+__device__ __forceinline__ u64 wave_min64(u64 v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = umin64(v, shfl_xor64(v, m));
+  return v;
+}
+
+// Bitonic sort of one key per lane, ascending by lane index.
+__device__ __forceinline__ u64 sort64(u64 x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= WAVE; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      u64 y = shfl_xor64(x, j);
+      bool asc = (lane & k) == 0;
+      bool low = (lane & j) == 0;
+      x = (low == asc) ? umin64(x, y) : umax64(x, y);
+    }
+  }
+  return x;
+}
+
+// a, b ascending across lanes -> a = 64 smallest of both (ascending),
+// b = 64 largest (ascending).
+__device__ __forceinline__ void merge64(u64& a, u64& b) {
+  const int lane = lane_id();
+  u64 br = shfl64(b, WAVE - 1 - lane);
+  u64 lo = umin64(a, br), hi = umax64(a, br);
+#pragma unroll
+  for (int j = 32; j > 0; j >>= 1) {
+    u64 y = shfl_xor64(lo, j);
+    u64 z = shfl_xor64(hi, j);
+    bool low = (lane & j) == 0;
+    lo = low ? umin64(lo, y) : umax64(lo, y);
+    hi = low ? umin64(hi, z) : umax64(hi, z);
+  }
+  a = lo;
+  b = hi;
+}
+
+// Sorted list of keys in LDS, `cap` entries used at most, `len` valid.
+// Inserts a batch (one key per lane, KEY_MAX = none; need not be sorted);
+// keeps the `cap` smallest.  len is wave-uniform.
+__device__ __forceinline__ void list_insert(u64* lst, int& len, int cap, u64 key) {
+  const int lane = lane_id();
+  const int add = __popcll(ballot(key != KEY_MAX));
+  if (add == 0) return;
+  u64 carry = sort64(key);
+  const int total = min(len + add, cap);
+  const int used_blocks = (len + WAVE - 1) / WAVE;
+  const int new_blocks = (total + WAVE - 1) / WAVE;
+  for (int blk = 0; blk < new_blocks; ++blk) {
+    u64 a = blk < used_blocks ? lst[blk * WAVE + lane] : KEY_MAX;
+    merge64(a, carry);
+    const int pos = blk * WAVE + lane;
+    lst[pos] = pos < total ? a : KEY_MAX;
+  }
+  len = total;
+}
+
+// Canonical FP32 squared distance of 4 vectors per wave (16 lanes each).
+// Lane s = lane & 15 owns the 4-element groups g = s, s + 16, ... (< d / 4) and
+// accumulates them in increasing order with fused multiply-adds; the 16
+// partials are then combined by the butterfly s ^ 8, s ^ 4, s ^ 2, s ^ 1.  Every
+// lane of the 16-lane group ends with the same value.
+__device__ __forceinline__ float group_reduce16(float p) {
+  p = p + __shfl_xor(p, 8, WAVE);
+  p = p + __shfl_xor(p, 4, WAVE);
+  p = p + __shfl_xor(p, 2, WAVE);
+  p = p + __shfl_xor(p, 1, WAVE);
+  return p;
+}
+
+__device__ __forceinline__ float fma_sq4(float4 x, float4 q, float acc) {
+#pragma clang fp contract(off)
+  float e0 = x.x - q.x;
+  acc = __builtin_fmaf(e0, e0, acc);
+  float e1 = x.y - q.y;
+  acc = __builtin_fmaf(e1, e1, acc);
+  float e2 = x.z - q.z;
+  acc = __builtin_fmaf(e2, e2, acc);
+  float e3 = x.w - q.w;
+  acc = __builtin_fmaf(e3, e3, acc);
+  return acc;
+}
+
+}  // namespace unify

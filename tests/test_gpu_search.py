@@ -1,0 +1,156 @@
+"""GPU parity: the HIP search against the CPU oracle on the same index file.
+
+The oracle builds the index (Alg. 6) and writes it; the library loads that file.
+Both then search the same graph with the same parameters.  The bar: identical
+ids and bit-identical FP32 distances (canonical summation order on both sides)
+for every query; pre-filter results additionally within 1e-5 relative of the
+FP64 exact answer.
+"""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import exact, hsig
+from synth import workloads as w
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def gpu_search(g, W, k, ef, strategy=None, **kw):
+    torch = _torch()
+    dev = torch.device("cuda", 0)
+    Q = torch.from_numpy(W.queries).to(dev)
+    l = torch.from_numpy(W.l).to(dev)
+    h = torch.from_numpy(W.h).to(dev)
+    out = g.search(Q, l, h, k, ef, strategy=strategy, stats=True, **kw)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in out]
+
+
+def _build(spec, seed, path):
+    W = w.make(spec, base_seed=seed)
+    print(f"[fixture] oracle build {spec.name} n={spec.n} d={spec.d}", flush=True)
+    ix = hsig.Index.build(W.base, W.attr, W.level_u, spec.S, spec.M, spec.ef_cons, seed=seed)
+    ix.write(path)
+    import paper_2412_02448_amd as u
+    g = u.Index.load(path, device=0)
+    return W, ix, g
+
+
+@pytest.fixture(scope="module")
+def c1(tmp_path_factory):
+    path = str(tmp_path_factory.mktemp("c1") / "hybrid10k.uix")
+    return _build(w.SPECS["hybrid10k"], 0, path)
+
+
+def assert_parity(ref, got, what):
+    rid, rd = ref
+    gid, gd, gst, gstats = got
+    bad = np.nonzero((rid != gid).any(1) | (rd.view(np.uint32) != gd.view(np.uint32)).any(1))[0]
+    assert (gstats[:, 3] != 2).all(), f"{what}: capacity overflow on {np.nonzero(gstats[:, 3] == 2)[0][:5]}"
+    assert bad.size == 0, f"{what}: {bad.size} queries differ, first {bad[:5]}: ref {rid[bad[0]]} got {gid[bad[0]]}"
+
+
+@pytest.mark.parametrize("strategy", [hsig.AUTO, hsig.PRE, hsig.HYBRID, hsig.POST])
+def test_parity_hybrid10k(c1, strategy):
+    W, ix, g = c1
+    k, ef = 10, 64
+    print(f"[case] hybrid10k strategy={strategy} k={k} ef={ef}", flush=True)
+    ref = ix.search(W.queries, W.l, W.h, k, ef, strategy=strategy)
+    got = gpu_search(g, W, k, ef, strategy=None if strategy == hsig.AUTO else strategy)
+    assert_parity(ref, got, f"strategy {strategy}")
+    if strategy == hsig.AUTO:
+        _, _, cnt = ix.search(W.queries, W.l, W.h, k, ef, strategy=strategy, counters=True)
+        assert (got[2] == cnt[:, hsig.STRAT]).all()
+
+
+@pytest.mark.parametrize("p", [2, 4])
+@pytest.mark.parametrize("strategy", [hsig.HYBRID, hsig.POST])
+def test_parity_beam_width(c1, strategy, p):
+    W, ix, g = c1
+    print(f"[case] hybrid10k beam p={p} strategy={strategy}", flush=True)
+    ref = ix.search(W.queries, W.l, W.h, 10, 48, p=p, strategy=strategy)
+    got = gpu_search(g, W, 10, 48, strategy=strategy, beam_p=p)
+    assert_parity(ref, got, f"p={p}")
+
+
+@pytest.mark.parametrize("m", [4, 8, 64])
+def test_parity_neighbour_budget(c1, m):
+    W, ix, g = c1
+    print(f"[case] hybrid10k m={m}", flush=True)
+    ref = ix.search(W.queries, W.l, W.h, 10, 32, m=m, strategy=hsig.HYBRID)
+    got = gpu_search(g, W, 10, 32, strategy=hsig.HYBRID, m=m)
+    assert_parity(ref, got, f"m={m}")
+
+
+def test_pre_filter_matches_fp64_exact(c1):
+    W, ix, g = c1
+    print("[case] pre vs FP64 exact", flush=True)
+    gid, gd, _, _ = gpu_search(g, W, 10, 10, strategy=hsig.PRE)
+    for i in range(len(W.queries)):
+        tid, td = exact.rfknn(W.base, W.attr, W.queries[i], W.l[i], W.h[i], 10)
+        assert gid[i, : len(tid)].tolist() == tid.tolist()
+        np.testing.assert_allclose(gd[i, : len(tid)], td, rtol=1e-5)
+
+
+def test_edge_cases_and_large_k(c1):
+    W, ix, g = c1
+    torch = _torch()
+    print("[case] edge cases", flush=True)
+    a = ix.attr_sorted()
+    n = len(a)
+    Q = W.queries[:6]
+    l = np.array([10, a[-1] + 1, a[7], a[0], a[100], a[0]], np.int64)
+    h = np.array([5, a[-1] + 50, a[7], a[-1], a[130], a[n // 3]], np.int64)
+    Wc = w.Workload(W.spec, W.base, W.attr, Q, l, h, None, None)
+    for strategy in (hsig.AUTO, hsig.PRE, hsig.HYBRID, hsig.POST):
+        for k, ef in ((1, 1), (10, 10), (256, 256), (37, 100)):
+            ref = ix.search(Q, l, h, k, ef, strategy=strategy)
+            got = gpu_search(g, Wc, k, ef, strategy=None if strategy == hsig.AUTO else strategy)
+            assert_parity(ref, got, f"edge strategy={strategy} k={k} ef={ef}")
+            assert (got[0][0] == -1).all() and (got[0][1] == -1).all()
+
+
+def test_invalid_arguments(c1):
+    W, ix, g = c1
+    torch = _torch()
+    import paper_2412_02448_amd as u
+    dev = torch.device("cuda", 0)
+    Q = torch.from_numpy(W.queries[:4]).to(dev)
+    l = torch.from_numpy(W.l[:4]).to(dev)
+    h = torch.from_numpy(W.h[:4]).to(dev)
+    for k, ef in ((0, 10), (257, 300), (10, 5), (10, 257)):
+        with pytest.raises(u.UnifyError) as e:
+            g.search(Q, l, h, k, ef)
+        assert e.value.code == -22
+    with pytest.raises(u.UnifyError):
+        g.search(Q, l, h, 10, 10, beam_p=9)
+    # nq = 0 is a no-op
+    ids, dist, st = g.search(Q[:0], l[:0], h[:0], 10, 10)
+    assert ids.shape == (0, 10)
+
+
+def test_deterministic(c1):
+    W, ix, g = c1
+    a = gpu_search(g, W, 10, 64)
+    b = gpu_search(g, W, 10, 64)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("d", [96, 960])
+def test_parity_other_dimensions(tmp_path, d):
+    spec = w.scaled(w.SPECS["hybrid10k"], n=3000, nq=40, d=d, S=4, M=8, ef_cons=40)
+    W, ix, g = _build(spec, 3, str(tmp_path / f"d{d}.uix"))
+    print(f"[case] d={d}", flush=True)
+    for strategy in (hsig.AUTO, hsig.PRE, hsig.HYBRID, hsig.POST):
+        ref = ix.search(W.queries, W.l, W.h, 10, 32, strategy=strategy)
+        got = gpu_search(g, W, 10, 32, strategy=None if strategy == hsig.AUTO else strategy)
+        assert_parity(ref, got, f"d={d} strategy={strategy}")
