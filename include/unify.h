@@ -67,6 +67,11 @@ enum {
   UNIFY_EDEVICE = -19   /* a HIP runtime call failed */
 };
 
+/* Bits of unify_params.flags. */
+enum {
+  UNIFY_FLAG_TIMING = 1  /* record HIP events around the search kernels; see unify_last_timing */
+};
+
 /* Search parameters.  Zero in a field selects its default. */
 typedef struct {
   int32_t m;            /* neighbours examined per expansion in the hybrid search,
@@ -77,7 +82,7 @@ typedef struct {
   int32_t reserved;
   double tau_a_frac;    /* tau_A = floor(tau_a_frac * n); default 0.01 (Sec. 6.2) */
   double tau_b_frac;    /* tau_B = ceil(tau_b_frac * n); default 0.5 (Sec. 6.2) */
-  uint32_t flags;       /* reserved, 0 */
+  uint32_t flags;       /* UNIFY_FLAG_* bits, 0 for none */
   uint32_t pad;
 } unify_params;
 
@@ -143,14 +148,27 @@ int unify_search(unify_index_t index, const float* queries, int64_t nq, const in
 
 /*
  * unify_search plus per-query counters:
- *   out_stats  device, [nq][4] int32: distance evaluations, expansions, visited
- *              objects on layer 0, and a status (0 = ran in the first pass,
- *              1 = re-run with larger on-chip lists, 2 = capacity exceeded even then).
+ *   out_stats  device, [nq][8] int32: [0] distance evaluations, [1] expansions,
+ *              [2] objects visited on layer 0, [3] status (0 = ran in the first
+ *              pass, 1 = re-run with larger on-chip lists, 2 = capacity exceeded even
+ *              then: the row is padded), [4] adjacency entries read, [5] strategy run
+ *              (-1 for an empty range), [6] Y = objects in range, [7] active segments
+ *              (hybrid only, else 0).
  */
 int unify_search_ex(unify_index_t index, const float* queries, int64_t nq, const int64_t* l,
                     const int64_t* h, int32_t k, int32_t ef, const int8_t* strategy,
                     const unify_params* params, int64_t* out_ids, float* out_dist,
                     int8_t* out_strategy, int32_t* out_stats, void* hip_stream);
+
+/*
+ * Durations of the search kernels of the last unify_search* call on this index
+ * that set UNIFY_FLAG_TIMING, from HIP events recorded on that call's stream:
+ *   search_ms  the main search launch (all queries);
+ *   rerun_ms   the launch that re-runs queries whose on-chip lists overflowed.
+ * Waits for the events to complete.  Outputs are host pointers, any may be NULL.
+ * Returns UNIFY_EINVAL when no timed search has been issued.
+ */
+int unify_last_timing(unify_index_t index, float* search_ms, float* rerun_ms);
 
 /* Frees the index and its device memory.  NULL is accepted. */
 int unify_free_index(unify_index_t index);

@@ -136,8 +136,11 @@ class Index:
             raise OSError(f"orc_write failed ({rc})")
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().orc_free(self._h)
+        if getattr(self, "_h", None) and _lib is not None:
+            try:
+                _lib.orc_free(self._h)
+            except Exception:
+                pass
             self._h = None
 
     # --- tables of the frozen view (internal ids = attribute rank) ---

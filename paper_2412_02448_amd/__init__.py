@@ -17,6 +17,7 @@ __all__ = ["Index", "UnifyError", "AUTO", "PRE", "HYBRID", "POST", "FP32", "BF16
            "validate_index_file", "library_path", "load_library"]
 
 AUTO, PRE, HYBRID, POST = 0, 1, 2, 3
+FLAG_TIMING = 1
 FP32, BF16, FP8E4M3 = 0, 1, 2
 _PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8E4M3, "fp8e4m3": FP8E4M3}
 
@@ -51,6 +52,7 @@ SIGNATURES = {
     "unify_index_info": (_I32, [_P, _P, _P, _P, _P, _P]),
     "unify_search": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P]),
     "unify_search_ex": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "unify_last_timing": (_I32, [_P, _P, _P]),
     "unify_free_index": (_I32, [_P]),
     "unify_last_error": (_S, []),
 }
@@ -138,9 +140,15 @@ class Index:
         except Exception:
             pass
 
+    def last_timing(self):
+        """(search_ms, rerun_ms) of the last search issued with timing=True (waits for it)."""
+        a, b = C.c_float(), C.c_float()
+        _check(load_library().unify_last_timing(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def search(self, queries, l, h, k: int, ef: int, strategy=None, m: int = 0, beam_p: int = 1,
                rerank_mult: int = 0, tau_a: float = 0.0, tau_b: float = 0.0, stats: bool = False,
-               out=None, stream=None):
+               out=None, stream=None, timing: bool = False):
         """Enqueues a search on the current stream (or `stream`) and returns torch tensors.
 
         queries: cuda float32 [nq, d]; l, h: cuda int64 [nq] (inclusive); strategy: None (auto),
@@ -166,10 +174,10 @@ class Index:
             ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
             dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
             ost = torch.empty((nq,), dtype=torch.int8, device=dev)
-            sts = torch.empty((nq, 4), dtype=torch.int32, device=dev) if stats else None
+            sts = torch.empty((nq, 8), dtype=torch.int32, device=dev) if stats else None
         else:
             ids, dist, ost, sts = out
-        prm = _Params(m, beam_p, rerank_mult, 0, tau_a, tau_b, 0, 0)
+        prm = _Params(m, beam_p, rerank_mult, 0, tau_a, tau_b, FLAG_TIMING if timing else 0, 0)
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         lib = load_library()
         if stats:

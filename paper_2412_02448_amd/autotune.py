@@ -1,0 +1,88 @@
+"""Search-parameter tuning for a resident index.
+
+The paper sets its search parameters by sweeping them (Sec. 6.6: ef and m trade
+recall for speed; Sec. 4.2: tau_A and tau_B come from sample queries).  This
+tuner does the same on the GPU: for sample queries with known exact answers
+(the pre-filter scan forced on every sample query gives them), it measures
+recall@k and throughput of the range-aware search over a grid of
+(m, ef, beam width p) and returns the fastest setting whose recall reaches the
+target.  Every measurement runs the library's kernels; this module only
+orchestrates calls and computes recall.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Setting:
+    m: int
+    ef: int
+    beam_p: int
+    recall: float
+    qps: float
+
+
+def recall_at_k(ids: np.ndarray, truth: np.ndarray) -> float:
+    """Mean over queries of |found & exact| / |exact| (Eq. 1; |exact| = min(k, |R|))."""
+    r = np.empty(len(ids))
+    for i in range(len(ids)):
+        t = truth[i][truth[i] >= 0]
+        if t.size == 0:
+            r[i] = 1.0
+            continue
+        f = ids[i][ids[i] >= 0]
+        r[i] = np.intersect1d(f, t, assume_unique=True).size / t.size
+    return float(r.mean())
+
+
+def exact_answers(index, Q, L, H, k):
+    """Exact range-filtered k-NN ids of every query (strategy A on all of them)."""
+    import torch
+    from . import PRE
+    ids, _, _ = index.search(Q, L, H, k, k, strategy=PRE)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy()
+
+
+def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256), ps=(1, 2, 4),
+         reps: int = 3, log=None):
+    """Fastest (m, ef, p) reaching recall@k >= target on the given sample queries.
+
+    Returns (best Setting or None, list of every Setting measured)."""
+    import torch
+    if ms is None:
+        M = index.M
+        ms = (M, (3 * M) // 2, 2 * M, 3 * M)
+    truth = exact_answers(index, Q, L, H, k)
+    table = []
+    for m in ms:
+        if m > index.S * index.M:
+            continue
+        for ef in efs:
+            if ef < k:
+                continue
+            ids, _, _ = index.search(Q, L, H, k, ef, m=m)
+            torch.cuda.synchronize()
+            rec = recall_at_k(ids.cpu().numpy(), truth)
+            if rec < target:
+                table.append(Setting(m, ef, 1, rec, 0.0))
+                continue
+            for p in ps:
+                index.search(Q, L, H, k, ef, m=m, beam_p=p)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(reps):
+                    index.search(Q, L, H, k, ef, m=m, beam_p=p)
+                torch.cuda.synchronize()
+                qps = Q.shape[0] * reps / (time.perf_counter() - t)
+                table.append(Setting(m, ef, p, rec, qps))
+                if log:
+                    log(f"tune m={m} ef={ef} p={p}: recall {rec:.4f}, {qps:,.0f} QPS")
+            break  # larger ef only costs more once the target is met
+    ok = [s for s in table if s.recall >= target and s.qps > 0]
+    best = max(ok, key=lambda s: s.qps) if ok else None
+    return best, table

@@ -9,6 +9,8 @@
 
 namespace unify {
 
+int build_impl(const float* vectors, const int64_t* attr, const double* level_u, int64_t n, int32_t d, int32_t S,
+               int32_t M, int32_t ef_cons, int device, int precision, unify_index_t* out);
 int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
                 int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
                 float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream);
@@ -304,9 +306,31 @@ int unify_search_ex(unify_index_t ix, const float* queries, int64_t nq, const in
                      hip_stream);
 }
 
+int unify_last_timing(unify_index_t ix, float* search_ms, float* rerun_ms) {
+  if (!ix || !ix->timed) {
+    set_error("no timed search on this index");
+    return UNIFY_EINVAL;
+  }
+  if (hipSetDevice(ix->device) != hipSuccess || hipEventSynchronize(ix->ev[2]) != hipSuccess) {
+    set_error("hipEventSynchronize failed");
+    return UNIFY_EDEVICE;
+  }
+  float a = 0.f, b = 0.f;
+  if (hipEventElapsedTime(&a, ix->ev[0], ix->ev[1]) != hipSuccess ||
+      hipEventElapsedTime(&b, ix->ev[1], ix->ev[2]) != hipSuccess) {
+    set_error("hipEventElapsedTime failed");
+    return UNIFY_EDEVICE;
+  }
+  if (search_ms) *search_ms = a;
+  if (rerun_ms) *rerun_ms = b;
+  return UNIFY_OK;
+}
+
 int unify_free_index(unify_index_t ix) {
   if (!ix) return UNIFY_OK;
   (void)hipSetDevice(ix->device);
+  for (hipEvent_t e : ix->ev)
+    if (e) (void)hipEventDestroy(e);
   for (void* p : ix->allocs) (void)hipFree(p);
   delete ix;
   return UNIFY_OK;
@@ -314,10 +338,7 @@ int unify_free_index(unify_index_t ix) {
 
 int unify_build_index(const float* vectors, const int64_t* attr, const double* level_u, int64_t n, int32_t d,
                       int32_t S, int32_t M, int32_t ef_cons, int device, int precision, unify_index_t* out) {
-  (void)vectors, (void)attr, (void)level_u, (void)n, (void)d, (void)S, (void)M, (void)ef_cons, (void)device,
-      (void)precision, (void)out;
-  set_error("unify_build_index: not available in this build");
-  return UNIFY_EINVAL;
+  return build_impl(vectors, attr, level_u, n, d, S, M, ef_cons, device, precision, out);
 }
 
 }  // extern "C"

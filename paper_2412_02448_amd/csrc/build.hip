@@ -1,0 +1,864 @@
+// Batched HSIG construction on the GPU.
+//
+// The paper builds HSIG by inserting objects one at a time (Alg. 6): for every
+// segment j, ANNSearch finds the new object's efCons nearest objects of segment
+// j, Prune keeps at most M of them as chunk j, and each kept neighbour o gets
+// the reverse edge in its chunk for the new object's segment, re-pruned when
+// that chunk overflows (Alg. 4); GlobalEdgeMasking (Alg. 5) then marks at most
+// M of the node's chunk edges as the global HNSW edges used by post-filtering.
+//
+// This builder produces the same structure for all objects at once, layer by
+// layer:
+//   1. candidates: the exact K nearest objects of segment j for every object
+//      (one tiled distance pass per segment, K = min(efCons, 128));
+//   2. forward chunks: Prune(v, candidates, M);
+//   3. reverse edges: every forward edge v -> o (v in segment i) offers v to
+//      chunk i of o; a chunk that then holds more than M objects is re-pruned;
+//   4. global edges: Prune(v, all chunks of v, M) per object, then each object
+//      o receives the marks of the objects v that marked o while o links back
+//      to v, in insertion (external id) order, falling back to its own pruned
+//      set whenever the marks exceed M -- Alg. 5 applied to the final graph.
+// Chunks are sorted by (distance to owner, id), as the hybrid search expects.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "unify_internal.h"
+#include "wave.h"
+
+namespace unify {
+
+int make_resident(HostIndex&& H, int device, int precision, unify_index_t* out);
+
+namespace {
+
+constexpr int KT_R = 128;  // rows per candidate block
+constexpr int KT_C = 64;   // candidate columns per tile
+constexpr int KT_D = 64;   // dimensions per staged slice
+constexpr int KC = 128;    // candidate list capacity per (object, segment)
+constexpr int CAPR = 256;  // nearest candidates kept before a prune
+
+__global__ void b_gather(const float* __restrict__ X, int d, const int32_t* __restrict__ nodes, int64_t nl,
+                         float* __restrict__ out) {
+  const int64_t G = (int64_t)d / 4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nl * G; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / G, g = i % G;
+    reinterpret_cast<float4*>(out)[i] = reinterpret_cast<const float4*>(X + (int64_t)nodes[r] * d)[g];
+  }
+}
+
+__global__ void b_norms(const float* __restrict__ X, int d, int64_t nl, float* __restrict__ xn) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nl; r += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int t = 0; t < d; ++t) {
+      const float x = X[r * d + t];
+      s = __builtin_fmaf(x, x, s);
+    }
+    xn[r] = s;
+  }
+}
+
+// Inserts a batch into a sorted list held in global memory; returns the worst
+// kept key when the list is full (KEY_MAX otherwise).
+__device__ u64 glist_insert(u64* lst, int& len, int cap, u64 key) {
+  const int lane = lane_id();
+  const int add = __popcll(ballot(key != KEY_MAX));
+  if (add == 0) return len == cap ? lst[cap - 1] : KEY_MAX;
+  u64 carry = sort64(key);
+  const int total = min(len + add, cap);
+  const int used = (len + WAVE - 1) / WAVE, nb = (total + WAVE - 1) / WAVE;
+  u64 worst = KEY_MAX;
+  for (int blk = 0; blk < nb; ++blk) {
+    u64 a = blk < used ? lst[blk * WAVE + lane] : KEY_MAX;
+    merge64(a, carry);
+    const int pos = blk * WAVE + lane;
+    lst[pos] = pos < total ? a : KEY_MAX;
+    if (blk == (cap - 1) / WAVE) {
+      uint32_t lo = (uint32_t)__shfl((int)(uint32_t)a, (cap - 1) % WAVE, WAVE);
+      uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(a >> 32), (cap - 1) % WAVE, WAVE);
+      worst = ((u64)hi << 32) | lo;
+    }
+  }
+  len = total;
+  return total == cap ? worst : KEY_MAX;
+}
+
+// Exact K nearest candidates of segment j for rows [row0, row0 + nrows) of a layer.
+struct KnnArgs {
+  const float* X;
+  const float* xn;
+  int d, S, K;
+  int64_t row0, nrows;
+  const int64_t* sstart;  // [S+1] compact id ranges of the segments
+  u64* lists;             // [nrows][S][KC]
+  int32_t* lens;          // [nrows][S]
+  u64* pend;              // [nrows][S][KT_C]
+};
+
+__global__ void __launch_bounds__(256) b_knn(KnnArgs A) {
+  __shared__ float qT[KT_D][KT_R];
+  __shared__ float xT[KT_D][KT_C + 4];
+  __shared__ u64 tau[KT_R];
+  __shared__ int pcnt[KT_R];
+  __shared__ int lenr[KT_R];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int j = blockIdx.y;
+  const int64_t lr0 = (int64_t)blockIdx.x * KT_R;  // first local row
+  const int64_t c_begin = A.sstart[j], c_end = A.sstart[j + 1];
+  const int d = A.d, S = A.S;
+  if (tid < KT_R) {
+    tau[tid] = KEY_MAX;
+    pcnt[tid] = 0;
+    lenr[tid] = 0;
+  }
+  const int rg = tid >> 4, cg = tid & 15;
+  for (int64_t c0 = c_begin; c0 < c_end; c0 += KT_C) {
+    float acc[8][4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[i][t] = 0.f;
+    for (int k0 = 0; k0 < d; k0 += KT_D) {
+      __syncthreads();
+      // rows: lanes take consecutive rows so that the transposed stores do not conflict
+      for (int it = 0; it < (KT_R * KT_D / 4) / 256; ++it) {
+        const int idx = tid + 256 * it;
+        const int r = idx % KT_R, g = idx / KT_R;
+        const int64_t lr = lr0 + r;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lr < A.nrows && k0 + 4 * g < d)
+          v = *reinterpret_cast<const float4*>(A.X + (A.row0 + lr) * d + k0 + 4 * g);
+        qT[4 * g + 0][r] = v.x;
+        qT[4 * g + 1][r] = v.y;
+        qT[4 * g + 2][r] = v.z;
+        qT[4 * g + 3][r] = v.w;
+      }
+      for (int it = 0; it < (KT_C * KT_D / 4) / 256; ++it) {
+        const int idx = tid + 256 * it;
+        const int c = idx / (KT_D / 4), g = idx % (KT_D / 4);
+        const int64_t col = c0 + c;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (col < c_end && k0 + 4 * g < d) v = *reinterpret_cast<const float4*>(A.X + col * d + k0 + 4 * g);
+        xT[4 * g + 0][c] = v.x;
+        xT[4 * g + 1][c] = v.y;
+        xT[4 * g + 2][c] = v.z;
+        xT[4 * g + 3][c] = v.w;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < KT_D; ++kk) {
+        const float4 qa = *reinterpret_cast<const float4*>(&qT[kk][rg * 8]);
+        const float4 qb = *reinterpret_cast<const float4*>(&qT[kk][rg * 8 + 4]);
+        const float4 xa = *reinterpret_cast<const float4*>(&xT[kk][cg * 4]);
+        const float q[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
+        const float x[4] = {xa.x, xa.y, xa.z, xa.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[i][t] = __builtin_fmaf(q[i], x[t], acc[i][t]);
+      }
+    }
+    // distances, filtered against each row's current K-th key
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int r = rg * 8 + i;
+      const int64_t lr = lr0 + r;
+      if (lr >= A.nrows) continue;
+      const int64_t row = A.row0 + lr;
+      const float qn = A.xn[row];
+      const u64 tr = tau[r];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t col = c0 + cg * 4 + t;
+        if (col >= c_end || col == row) continue;
+        float dist = qn + A.xn[col] - 2.0f * acc[i][t];
+        dist = dist > 0.f ? dist : 0.f;
+        const u64 key = make_key(dist, (int32_t)col);
+        if (key < tr) {
+          const int slot = atomicAdd(&pcnt[r], 1);
+          A.pend[(lr * S + j) * KT_C + slot] = key;
+        }
+      }
+    }
+    __syncthreads();
+    // merge the pending candidates of each row into its list (wave w owns 32 rows)
+    for (int rr = 0; rr < KT_R / 4; ++rr) {
+      const int r = wv * (KT_R / 4) + rr;
+      const int cnt = pcnt[r];
+      if (cnt == 0) continue;
+      const int64_t lr = lr0 + r;
+      const int64_t base = lr * S + j;
+      const u64 key = lane < cnt ? A.pend[base * KT_C + lane] : KEY_MAX;
+      int len = lenr[r];
+      const u64 worst = glist_insert(A.lists + base * KC, len, A.K, key);
+      if (lane == 0) {
+        lenr[r] = len;
+        tau[r] = worst;
+        pcnt[r] = 0;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < KT_R && lr0 + tid < A.nrows) A.lens[(lr0 + tid) * S + j] = lenr[tid];
+}
+
+// Generic Prune (Sec. 2.2) of one owner per task, one wavefront per task.
+// Candidates: a_cnt[t] (or a_stride) keys at a + t * a_stride, then b_cnt[t]
+// keys at b + b_off[t]; only the id half of a key is used.  Distances are
+// recomputed from the vectors, duplicates removed, the nearest CAPR kept; if
+// more than Mcap remain (or always, when !only_if_over), the greedy rule keeps
+// a candidate unless an already kept one is nearer to it than the owner is.
+struct PruneArgs {
+  const float* X;
+  int d;
+  int64_t ntask;
+  int64_t owner0;
+  int32_t owner_div;
+  const u64* a;
+  int32_t a_stride;
+  const int32_t* a_cnt;
+  const u64* b;
+  const int64_t* b_off;
+  const int32_t* b_cnt;
+  int32_t Mcap;
+  int32_t only_if_over;
+  u64* out;  // [ntask][Mcap]
+};
+
+template <int NG>
+__device__ __forceinline__ void load_row(const float* X, int d, int64_t v, float4 (&x)[NG]) {
+  const int s = lane_id() & 15, G = d >> 2;
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    const int g = s + 16 * i;
+    x[i] = g < G ? *reinterpret_cast<const float4*>(X + v * d + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+template <int NG>
+__device__ __forceinline__ float group_dist(const float4 (&a)[NG], const float4 (&b)[NG]) {
+  float acc = 0.f;
+#pragma unroll
+  for (int i = 0; i < NG; ++i) acc = fma_sq4(a[i], b[i], acc);
+  return group_reduce16(acc);
+}
+
+template <int NG, int SG>
+__global__ void __launch_bounds__(64) b_prune(PruneArgs A) {
+  __shared__ u64 lst[CAPR];
+  __shared__ u64 bk[WAVE];
+  __shared__ int32_t ids[WAVE];
+  const int lane = lane_id(), g4 = lane >> 4;
+  for (int64_t t = blockIdx.x; t < A.ntask; t += gridDim.x) {
+    const int64_t owner = A.owner0 + t / A.owner_div;
+    float4 qv[NG];
+    load_row<NG>(A.X, A.d, owner, qv);
+    int len = 0;
+    for (int i = lane; i < CAPR; i += WAVE) lst[i] = KEY_MAX;
+    __syncthreads();
+    const int na = A.a_cnt ? A.a_cnt[t] : A.a_stride;
+    const int nb = A.b ? A.b_cnt[t] : 0;
+    const int64_t boff = A.b ? A.b_off[t] : 0;
+    for (int base = 0; base < na + nb; base += WAVE) {
+      const int i = base + lane;
+      int32_t v = -1;
+      if (i < na) {
+        const u64 kk = A.a[t * A.a_stride + i];
+        if (kk != KEY_MAX) v = key_id(kk);
+      } else if (i < na + nb) {
+        const u64 kk = A.b[boff + (i - na)];
+        if (kk != KEY_MAX) v = key_id(kk);
+      }
+      if (v == (int32_t)owner) v = -1;
+      const u64 m = ballot(v >= 0);
+      if (v >= 0) ids[rank_in(m)] = v;
+      const int cnt = __popcll(m);
+      __syncthreads();
+      eval_keys_generic<NG>(
+          A.d >> 2, qv, cnt, [&](int i) { return ids[i]; },
+          [&](int64_t v, int g) { return *reinterpret_cast<const float4*>(A.X + v * A.d + 4 * g); }, bk);
+      __syncthreads();
+      list_insert(lst, len, CAPR, lane < cnt ? bk[lane] : KEY_MAX);
+      __syncthreads();
+    }
+    // drop duplicates (equal keys are adjacent)
+    {
+      u64 prev_last = KEY_MAX;
+      int w = 0;
+      for (int b0 = 0; b0 < len; b0 += WAVE) {
+        const int i = b0 + lane;
+        const u64 kk = i < len ? lst[i] : KEY_MAX;
+        u64 prev = shfl64(kk, lane > 0 ? lane - 1 : 0);
+        if (lane == 0) prev = prev_last;
+        prev_last = shfl64(kk, WAVE - 1);
+        const bool keep = i < len && kk != prev;
+        const u64 km = ballot(keep);
+        __syncthreads();
+        if (keep) lst[w + rank_in(km)] = kk;
+        w += __popcll(km);
+        __syncthreads();
+      }
+      len = w;
+    }
+    u64* out = A.out + t * A.Mcap;
+    if (A.only_if_over && len <= A.Mcap) {
+      for (int i = lane; i < A.Mcap; i += WAVE) out[i] = i < len ? lst[i] : KEY_MAX;
+      __syncthreads();
+      continue;
+    }
+    // greedy selection; kept vectors stay in registers (group g keeps numbers 4s+g)
+    float4 sel[SG][NG];
+#pragma unroll
+    for (int s = 0; s < SG; ++s)
+#pragma unroll
+      for (int i = 0; i < NG; ++i) sel[s][i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    int nsel = 0;
+    for (int pos = 0; pos < len && nsel < A.Mcap; ++pos) {
+      const u64 key = lst[pos];
+      const int32_t r = key_id(key);
+      const float dvr = key_dist(key);
+      float4 xr[NG];
+      load_row<NG>(A.X, A.d, r, xr);
+      bool bad = false;
+#pragma unroll
+      for (int s = 0; s < SG; ++s) {
+        if (4 * s < nsel) {
+          const float de = group_dist<NG>(sel[s], xr);
+          if (4 * s + g4 < nsel && de < dvr) bad = true;
+        }
+      }
+      if (__any(bad)) continue;
+#pragma unroll
+      for (int s = 0; s < SG; ++s)
+        if (s == nsel / 4 && g4 == nsel % 4) {
+#pragma unroll
+          for (int i = 0; i < NG; ++i) sel[s][i] = xr[i];
+        }
+      if (lane == 0) out[nsel] = key;
+      ++nsel;
+    }
+    for (int i = nsel + lane; i < A.Mcap; i += WAVE) out[i] = KEY_MAX;
+    __syncthreads();
+  }
+}
+
+// Reverse edges: every forward edge row -> o (row in segment si) is offered to chunk si of o.
+__global__ void b_rev(const u64* __restrict__ fwd, int64_t nrows, int S, int M, const int32_t* __restrict__ segc,
+                      int32_t* __restrict__ cnt, const int64_t* __restrict__ off, u64* __restrict__ rev) {
+  const int64_t total = nrows * S * M;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const u64 kk = fwd[e];
+    if (kk == KEY_MAX) continue;
+    const int64_t row = e / ((int64_t)S * M);
+    const int32_t o = key_id(kk);
+    const int64_t slot = (int64_t)o * S + segc[row];
+    const int32_t p = atomicAdd(&cnt[slot], 1);
+    if (rev) rev[off[slot] + p] = make_key(0.f, (int32_t)row);
+  }
+}
+
+// Exclusive prefix sum of n int32 counts into int64 offsets (off[n] = total).
+__global__ void b_scan_blocks(const int32_t* __restrict__ cnt, int64_t n, int64_t* __restrict__ off,
+                              int64_t* __restrict__ bsum) {
+  __shared__ int64_t s[1024];
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  const int64_t v = i < n ? cnt[i] : 0;
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int64_t t = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (i < n) off[i] = s[threadIdx.x] - v;
+  if (threadIdx.x == 1023) bsum[blockIdx.x] = s[1023];
+}
+__global__ void b_scan_top(int64_t* bsum, int64_t nb) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t run = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      const int64_t v = bsum[b];
+      bsum[b] = run;
+      run += v;
+    }
+    bsum[nb] = run;
+  }
+}
+__global__ void b_scan_add(int64_t* off, int64_t n, const int64_t* bsum, int64_t nb) {
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  if (i < n) off[i] += bsum[blockIdx.x];
+  if (i == 0) off[n] = bsum[nb];
+}
+
+// Global-edge marks, reverse part: v marked o (o in P(v)) and o links back to v.
+__global__ void b_mask_rev(const u64* __restrict__ P, const u64* __restrict__ chunks, int64_t nrows, int S, int M,
+                           const int32_t* __restrict__ segc, int32_t* __restrict__ cnt,
+                           const int64_t* __restrict__ off, int32_t* __restrict__ rev) {
+  const int64_t total = nrows * M;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const u64 kk = P[e];
+    if (kk == KEY_MAX) continue;
+    const int64_t v = e / M;
+    const int32_t o = key_id(kk);
+    const u64* ch = chunks + ((int64_t)o * S + segc[v]) * M;
+    bool back = false;
+    for (int t = 0; t < M; ++t)
+      if (ch[t] != KEY_MAX && key_id(ch[t]) == (int32_t)v) back = true;
+    if (!back) continue;
+    const int32_t p = atomicAdd(&cnt[o], 1);
+    if (rev) rev[off[o] + p] = (int32_t)v;
+  }
+}
+
+// Final marks of each object: its own pruned set P(o), then the reverse marks in
+// ascending external id, restarting from P(o) whenever more than M are marked.
+__global__ void b_mask_final(const u64* __restrict__ P, int64_t nrows, int M, const int64_t* __restrict__ off,
+                             const int32_t* __restrict__ rev, const int64_t* __restrict__ ext_of,
+                             int32_t* __restrict__ glist) {
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < nrows; o += (int64_t)gridDim.x * blockDim.x) {
+    int32_t marks[65];
+    int np = 0;
+    for (int t = 0; t < M; ++t)
+      if (P[o * M + t] != KEY_MAX) marks[np++] = key_id(P[o * M + t]);
+    int nm = np;
+    const int64_t b = off[o], e = off[o + 1];
+    int64_t last = -1;
+    for (int64_t step = b; step < e; ++step) {
+      // next reverse mark in ascending external id
+      int32_t best = -1;
+      int64_t bx = INT64_MAX;
+      for (int64_t q = b; q < e; ++q) {
+        const int64_t x = ext_of[rev[q]];
+        if (x > last && x < bx) {
+          bx = x;
+          best = rev[q];
+        }
+      }
+      last = bx;
+      bool have = false;
+      for (int t = 0; t < nm; ++t) have |= marks[t] == best;
+      if (have) continue;
+      marks[nm++] = best;
+      if (nm > M) {
+        nm = np;
+        for (int t = 0; t < M; ++t)
+          if (P[o * M + t] != KEY_MAX) marks[t] = key_id(P[o * M + t]);
+      }
+    }
+    for (int t = 0; t < M; ++t) glist[o * M + t] = t < nm ? marks[t] : -1;
+  }
+}
+
+#define BHIP(x)                                                       \
+  do {                                                                \
+    hipError_t e_ = (x);                                              \
+    if (e_ != hipSuccess) {                                           \
+      set_error(std::string("build: ") + #x + ": " + hipGetErrorString(e_)); \
+      return UNIFY_EDEVICE;                                           \
+    }                                                                 \
+  } while (0)
+
+struct DevBuf {
+  std::vector<void*> ptrs;
+  ~DevBuf() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  void release(void* p) {
+    for (auto& q : ptrs)
+      if (q == p) {
+        (void)hipFree(q);
+        q = nullptr;
+      }
+  }
+};
+
+int scan(DevBuf& buf, const int32_t* cnt, int64_t n, int64_t* off) {
+  const int64_t nb = (n + 1023) / 1024;
+  int64_t* bsum = buf.alloc<int64_t>(nb + 1);
+  if (!bsum) {
+    set_error("build: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  hipLaunchKernelGGL(b_scan_blocks, dim3((unsigned)nb), dim3(1024), 0, 0, cnt, n, off, bsum);
+  hipLaunchKernelGGL(b_scan_top, dim3(1), dim3(1), 0, 0, bsum, nb);
+  hipLaunchKernelGGL(b_scan_add, dim3((unsigned)nb), dim3(1024), 0, 0, off, n, bsum, nb);
+  BHIP(hipGetLastError());
+  buf.release(bsum);
+  return UNIFY_OK;
+}
+
+typedef void (*PruneFn)(PruneArgs);
+PruneFn prune_kernel(int d, int Mcap) {
+  const int ng = (d + 63) / 64;
+  if (Mcap <= 32) {
+    if (ng <= 2) return b_prune<2, 8>;
+    if (ng <= 4) return b_prune<4, 8>;
+  } else if (Mcap <= 64) {
+    if (ng <= 2) return b_prune<2, 16>;
+  }
+  return nullptr;
+}
+
+int run_prune(PruneArgs A) {
+  PruneFn fn = prune_kernel(A.d, A.Mcap);
+  if (!fn) {
+    set_error("build: unsupported (d, M) for the GPU builder (d <= 256 with M <= 32, or d <= 128 with M <= 64)");
+    return UNIFY_EINVAL;
+  }
+  const int64_t grid = std::min<int64_t>(A.ntask, 1 << 20);
+  hipLaunchKernelGGL(fn, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(64), 0, 0, A);
+  BHIP(hipGetLastError());
+  return UNIFY_OK;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Builds one layer over `nodes` (internal ids, ascending).  Outputs, on the
+// host: chunks [nl][S][M] and marks [nl][M] as internal ids (-1 padded).
+int build_layer(const float* dX, int d, int S, int M, int K, const std::vector<int32_t>& nodes,
+                const std::vector<int64_t>& seg_start, const std::vector<int64_t>& ext,
+                std::vector<int32_t>& chunks_out, std::vector<int32_t>& glist_out, bool verbose) {
+  const int64_t nl = (int64_t)nodes.size();
+  DevBuf buf;
+  // compact vectors of this layer
+  const float* X = dX;
+  std::vector<int64_t> sst(S + 1, 0);
+  std::vector<int32_t> segc(nl);
+  {
+    int j = 0;
+    for (int64_t c = 0; c < nl; ++c) {
+      while (j + 1 <= S && nodes[c] >= seg_start[j + 1]) ++j;
+      segc[c] = j;
+    }
+    for (int jj = 0; jj <= S; ++jj)
+      sst[jj] = std::lower_bound(nodes.begin(), nodes.end(), (int32_t)std::min<int64_t>(seg_start[jj], INT32_MAX)) -
+                nodes.begin();
+    sst[S] = nl;
+  }
+  const bool identity = nl > 0 && nodes.back() == nl - 1;
+  if (!identity) {
+    int32_t* dnodes = buf.alloc<int32_t>(nl);
+    float* Xl = buf.alloc<float>((size_t)nl * d);
+    if (!dnodes || !Xl) {
+      set_error("build: out of device memory");
+      return UNIFY_ENOMEM;
+    }
+    BHIP(hipMemcpy(dnodes, nodes.data(), 4 * nl, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(b_gather, dim3(1024), dim3(256), 0, 0, dX, d, dnodes, nl, Xl);
+    X = Xl;
+  }
+  float* xn = buf.alloc<float>(nl);
+  int64_t* dsst = buf.alloc<int64_t>(S + 1);
+  int32_t* dsegc = buf.alloc<int32_t>(nl);
+  int64_t* dext = buf.alloc<int64_t>(nl);
+  u64* fwd = buf.alloc<u64>((size_t)nl * S * M);
+  if (!xn || !dsst || !dsegc || !dext || !fwd) {
+    set_error("build: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  {
+    std::vector<int64_t> ext_c(nl);
+    for (int64_t c = 0; c < nl; ++c) ext_c[c] = ext[nodes[c]];
+    BHIP(hipMemcpy(dext, ext_c.data(), 8 * nl, hipMemcpyHostToDevice));
+  }
+  BHIP(hipMemcpy(dsst, sst.data(), 8 * (S + 1), hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(dsegc, segc.data(), 4 * nl, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(b_norms, dim3(1024), dim3(256), 0, 0, X, d, nl, xn);
+  BHIP(hipGetLastError());
+
+  // 1-2: candidates and forward chunks, in row chunks
+  const int64_t rows_per = std::min<int64_t>(nl, 131072);
+  u64* lists = buf.alloc<u64>((size_t)rows_per * S * KC);
+  int32_t* lens = buf.alloc<int32_t>((size_t)rows_per * S);
+  u64* pend = buf.alloc<u64>((size_t)rows_per * S * KT_C);
+  if (!lists || !lens || !pend) {
+    set_error("build: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  double t0 = now_s();
+  for (int64_t r0 = 0; r0 < nl; r0 += rows_per) {
+    const int64_t nr = std::min(rows_per, nl - r0);
+    KnnArgs ka{X, xn, d, S, K, r0, nr, dsst, lists, lens, pend};
+    hipLaunchKernelGGL(b_knn, dim3((unsigned)((nr + KT_R - 1) / KT_R), (unsigned)S), dim3(256), 0, 0, ka);
+    BHIP(hipGetLastError());
+    PruneArgs pa{};
+    pa.X = X;
+    pa.d = d;
+    pa.ntask = nr * S;
+    pa.owner0 = r0;
+    pa.owner_div = S;
+    pa.a = lists;
+    pa.a_stride = KC;
+    pa.a_cnt = lens;
+    pa.Mcap = M;
+    pa.only_if_over = 0;
+    pa.out = fwd + (size_t)r0 * S * M;
+    int rc = run_prune(pa);
+    if (rc) return rc;
+    BHIP(hipDeviceSynchronize());
+    if (verbose)
+      std::fprintf(stderr, "[build] layer n=%lld: candidates+prune rows %lld/%lld (%.1fs)\n", (long long)nl,
+                   (long long)(r0 + nr), (long long)nl, now_s() - t0);
+  }
+  buf.release(lists);
+  buf.release(lens);
+  buf.release(pend);
+
+  // 3: reverse edges and re-prune
+  int32_t* rcnt = buf.alloc<int32_t>((size_t)nl * S);
+  int64_t* roff = buf.alloc<int64_t>((size_t)nl * S + 1);
+  if (!rcnt || !roff) {
+    set_error("build: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  BHIP(hipMemset(rcnt, 0, 4 * (size_t)nl * S));
+  hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nl, S, M, dsegc, rcnt, nullptr, nullptr);
+  int rc = scan(buf, rcnt, nl * S, roff);
+  if (rc) return rc;
+  int64_t total = 0;
+  BHIP(hipMemcpy(&total, roff + (size_t)nl * S, 8, hipMemcpyDeviceToHost));
+  u64* rev = buf.alloc<u64>((size_t)std::max<int64_t>(total, 1));
+  if (!rev) {
+    set_error("build: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  BHIP(hipMemset(rcnt, 0, 4 * (size_t)nl * S));
+  hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nl, S, M, dsegc, rcnt, roff, rev);
+  {
+    PruneArgs pa{};
+    pa.X = X;
+    pa.d = d;
+    pa.ntask = nl * S;
+    pa.owner0 = 0;
+    pa.owner_div = S;
+    pa.a = fwd;
+    pa.a_stride = M;
+    pa.b = rev;
+    pa.b_off = roff;
+    pa.b_cnt = rcnt;
+    pa.Mcap = M;
+    pa.only_if_over = 1;
+    pa.out = fwd;  // each task reads its own row before writing it
+    rc = run_prune(pa);
+    if (rc) return rc;
+  }
+  BHIP(hipDeviceSynchronize());
+  buf.release(rev);
+  if (verbose)
+    std::fprintf(stderr, "[build] layer n=%lld: reverse edges %lld (%.1fs)\n", (long long)nl, (long long)total,
+                 now_s() - t0);
+
+  // 4: global-edge marks
+  u64* P = buf.alloc<u64>((size_t)nl * M);
+  int32_t* mcnt = buf.alloc<int32_t>(nl);
+  int64_t* moff = buf.alloc<int64_t>(nl + 1);
+  int32_t* glist = buf.alloc<int32_t>((size_t)nl * M);
+  if (!P || !mcnt || !moff || !glist) {
+    set_error("build: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  {
+    PruneArgs pa{};
+    pa.X = X;
+    pa.d = d;
+    pa.ntask = nl;
+    pa.owner0 = 0;
+    pa.owner_div = 1;
+    pa.a = fwd;
+    pa.a_stride = S * M;
+    pa.Mcap = M;
+    pa.only_if_over = 1;
+    pa.out = P;
+    rc = run_prune(pa);
+    if (rc) return rc;
+  }
+  BHIP(hipMemset(mcnt, 0, 4 * nl));
+  hipLaunchKernelGGL(b_mask_rev, dim3(4096), dim3(256), 0, 0, P, fwd, nl, S, M, dsegc, mcnt, nullptr, nullptr);
+  rc = scan(buf, mcnt, nl, moff);
+  if (rc) return rc;
+  int64_t mtotal = 0;
+  BHIP(hipMemcpy(&mtotal, moff + nl, 8, hipMemcpyDeviceToHost));
+  int32_t* mrev = buf.alloc<int32_t>((size_t)std::max<int64_t>(mtotal, 1));
+  if (!mrev) {
+    set_error("build: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  BHIP(hipMemset(mcnt, 0, 4 * nl));
+  hipLaunchKernelGGL(b_mask_rev, dim3(4096), dim3(256), 0, 0, P, fwd, nl, S, M, dsegc, mcnt, moff, mrev);
+  hipLaunchKernelGGL(b_mask_final, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, 0, P, nl, M, moff, mrev, dext,
+                     glist);
+  BHIP(hipGetLastError());
+  BHIP(hipDeviceSynchronize());
+  if (verbose)
+    std::fprintf(stderr, "[build] layer n=%lld: global marks (%.1fs)\n", (long long)nl, now_s() - t0);
+
+  // to the host, as internal ids
+  std::vector<u64> hk((size_t)nl * S * M);
+  BHIP(hipMemcpy(hk.data(), fwd, 8 * hk.size(), hipMemcpyDeviceToHost));
+  chunks_out.resize(hk.size());
+  for (size_t i = 0; i < hk.size(); ++i) chunks_out[i] = hk[i] == KEY_MAX ? -1 : nodes[(int32_t)(uint32_t)hk[i]];
+  glist_out.resize((size_t)nl * M);
+  BHIP(hipMemcpy(glist_out.data(), glist, 4 * glist_out.size(), hipMemcpyDeviceToHost));
+  for (auto& g : glist_out)
+    if (g >= 0) g = nodes[g];
+  return UNIFY_OK;
+}
+
+}  // namespace
+
+int build_impl(const float* vectors, const int64_t* attr, const double* level_u, int64_t n, int32_t d, int32_t S,
+               int32_t M, int32_t ef_cons, int device, int precision, unify_index_t* out) {
+  if (!vectors || !attr || !level_u || !out) {
+    set_error("build: null argument");
+    return UNIFY_EINVAL;
+  }
+  if (n < 2 || n >= (int64_t(1) << 31) || d < 4 || d % 4 || d > 256 || S < 1 || S > 64 || M < 2 || M > 64 ||
+      ef_cons < 1) {
+    set_error("build: arguments out of range (2 <= n < 2^31, d % 4 == 0, d <= 256, 1 <= S <= 64, 2 <= M <= 64)");
+    return UNIFY_EINVAL;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (!(level_u[i] > 0.0 && level_u[i] <= 1.0)) {
+      set_error("build: level variates must lie in (0, 1]");
+      return UNIFY_EINVAL;
+    }
+  if (hipSetDevice(device) != hipSuccess) {
+    set_error("build: hipSetDevice failed");
+    return UNIFY_EDEVICE;
+  }
+  const bool verbose = std::getenv("UNIFY_BUILD_VERBOSE") != nullptr;
+  const int K = std::min(ef_cons, KC);
+  HostIndex H;
+  H.n = n;
+  H.d = d;
+  H.S = S;
+  H.M0 = M;
+  H.MU = M;
+  H.ef_cons = ef_cons;
+  H.mL = 1.0 / std::log((double)M);
+  // attribute order: internal id = rank by (attribute, external id)
+  std::vector<int64_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(),
+            [&](int64_t a, int64_t b) { return attr[a] < attr[b] || (attr[a] == attr[b] && a < b); });
+  H.attr.resize(n);
+  H.ext.resize(n);
+  H.level.resize(n);
+  H.uprow.resize(n);
+  H.vec.resize((size_t)n * d);
+  for (int64_t r = 0; r < n; ++r) {
+    const int64_t v = order[r];
+    H.attr[r] = attr[v];
+    H.ext[r] = v;
+    const double lv = std::floor(-std::log(level_u[v]) * H.mL);
+    H.level[r] = (uint8_t)std::min(lv, 30.0);
+    std::memcpy(&H.vec[(size_t)r * d], vectors + (size_t)v * d, 4 * (size_t)d);
+  }
+  // segments: equi-depth boundaries over all objects; a boundary value opens its segment
+  H.seg_start.assign(S + 1, 0);
+  for (int j = 1; j < S; ++j) {
+    const int64_t b = H.attr[(size_t)((int64_t)j * n / S)];
+    H.seg_start[j] = std::lower_bound(H.attr.begin(), H.attr.end(), b) - H.attr.begin();
+  }
+  H.seg_start[S] = n;
+  int L = 0;
+  int64_t R = 0;
+  for (int64_t r = 0; r < n; ++r) {
+    L = std::max<int>(L, H.level[r]);
+    H.uprow[r] = H.level[r] > 0 ? (int32_t)R : -1;
+    R += H.level[r];
+  }
+  H.L = L;
+  H.R = R;
+  // entries: the first object (smallest external id) at each segment's top level
+  H.seg_entry.assign(S, -1);
+  H.seg_maxlevel.assign(S, -1);
+  for (int j = 0; j < S; ++j) {
+    for (int64_t r = H.seg_start[j]; r < H.seg_start[j + 1]; ++r) {
+      const int lv = H.level[r];
+      if (lv > H.seg_maxlevel[j] || (lv == H.seg_maxlevel[j] && H.ext[r] < H.ext[H.seg_entry[j]])) {
+        H.seg_maxlevel[j] = lv;
+        H.seg_entry[j] = (int32_t)r;
+      }
+    }
+  }
+  H.gentry = -1;
+  for (int64_t r = 0; r < n; ++r)
+    if (H.level[r] == L && (H.gentry < 0 || H.ext[r] < H.ext[H.gentry])) H.gentry = (int32_t)r;
+  H.W0 = (S * M + 31) / 32;
+  H.WU = H.W0;
+  H.adj0.assign((size_t)n * S * M, -1);
+  H.gbits0.assign((size_t)n * H.W0, 0u);
+  H.adjU.assign((size_t)R * S * M, -1);
+  H.gbitsU.assign((size_t)R * H.WU, 0u);
+
+  float* dX = nullptr;
+  if (hipMalloc(&dX, H.vec.size() * 4) != hipSuccess) {
+    set_error("build: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  struct Free {
+    float* p;
+    ~Free() { (void)hipFree(p); }
+  } free_dx{dX};
+  BHIP(hipMemcpy(dX, H.vec.data(), H.vec.size() * 4, hipMemcpyHostToDevice));
+
+  auto set_bits = [&](const int32_t* row, const int32_t* marks, uint32_t* bits) {
+    for (int t = 0; t < M; ++t) {
+      if (marks[t] < 0) continue;
+      for (int pos = 0; pos < S * M; ++pos)
+        if (row[pos] == marks[t]) {
+          bits[pos >> 5] |= 1u << (pos & 31);
+          break;
+        }
+    }
+  };
+  for (int l = L; l >= 0; --l) {
+    std::vector<int32_t> nodes;
+    for (int64_t r = 0; r < n; ++r)
+      if (H.level[r] >= l) nodes.push_back((int32_t)r);
+    if (nodes.size() < 2) continue;
+    std::vector<int32_t> ch, gl;
+    int rc = build_layer(dX, d, S, M, K, nodes, H.seg_start, H.ext, ch, gl, verbose);
+    if (rc) return rc;
+    for (size_t c = 0; c < nodes.size(); ++c) {
+      const int64_t v = nodes[c];
+      int32_t* row;
+      uint32_t* bits;
+      if (l == 0) {
+        row = &H.adj0[(size_t)v * S * M];
+        bits = &H.gbits0[(size_t)v * H.W0];
+      } else {
+        const int64_t ur = H.uprow[v] + l - 1;
+        row = &H.adjU[(size_t)ur * S * M];
+        bits = &H.gbitsU[(size_t)ur * H.WU];
+      }
+      std::memcpy(row, &ch[c * S * M], 4 * (size_t)S * M);
+      set_bits(row, &gl[c * M], bits);
+    }
+  }
+  std::string err;
+  int rc = validate_index(H, err);
+  if (rc) {
+    set_error("build produced an invalid index: " + err);
+    return rc;
+  }
+  return make_resident(std::move(H), device, precision, out);
+}
+
+}  // namespace unify

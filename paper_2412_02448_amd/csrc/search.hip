@@ -10,7 +10,8 @@
 // The choice between them is the range-aware rule of Sec. 4.2.
 //
 // A layer search keeps three structures in LDS:
-//   visited  an open-addressing hash of ids (exact, never forgets);
+//   visited  per-wave epoch tags in HBM (one u32 per object; exact and
+//            unbounded), fronted by a direct-mapped LDS cache of recent ids;
 //   cand     an unsorted array of keys with tombstones; pop = wave argmin;
 //   ann      a sorted key list kept by bitonic block merges.
 // One step pops up to p candidates (p = 1 is the sequential loop), gathers
@@ -18,8 +19,8 @@
 // neighbour against the threshold taken before the step.  With a strict total
 // order on keys this gives the same ann and the same stopping point as
 // evaluating the neighbours one at a time; see DESIGN notes on batch admission.
-// If a query's visited set or candidate array outgrows its LDS capacity, the
-// query is abandoned and re-run by a second launch with larger capacities.
+// If a query's candidate array outgrows its LDS capacity, the query is
+// abandoned and re-run by a second launch with a larger array.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,10 +55,12 @@ struct SearchArgs {
   int32_t* next;          // work counter
   int32_t* fb_list;       // queries abandoned by the first pass
   int32_t* fb_count;
+  uint32_t* tags;         // [nslots][n] visited epochs, one row per persistent wave
+  uint32_t* epochs;       // [nslots] last epoch used by each row
+  int64_t nslots;
 };
 
 constexpr uint32_t HASH_EMPTY = 0xFFFFFFFFu;
-constexpr int MAX_PROBE = 128;
 
 // ---------------------------------------------------------------------------
 // Plan: the range becomes an id interval [lo, hi) (the skip-list walk of
@@ -118,7 +121,7 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
       out_dist[q * k + t] = __builtin_inff();
     }
     if (out_stats) {
-      for (int t = 0; t < 4; ++t) out_stats[q * 4 + t] = 0;
+      for (int t = 0; t < 8; ++t) out_stats[q * 8 + t] = 0;
     }
   }
   plan[q] = P;
@@ -186,40 +189,12 @@ __device__ __forceinline__ float4 load4(const DevIndex& ix, int64_t v, int g) {
   }
 }
 
-// Keys of cnt vectors: id_of(i) gives the id of the i-th; the key of the i-th
-// is written to keys[i] (LDS).  Four vectors per round, RB rounds per batch of loads.
+// Keys of cnt vectors of the store selected by PREC (see eval_keys_generic).
 template <int NG, int PREC, class IdOf>
-__device__ __forceinline__ void eval_keys(const DevIndex& ix, const float4 (&qv)[NG], int cnt,
-                                          IdOf id_of, u64* keys) {
-  constexpr int RB = NG <= 2 ? 4 : (NG <= 4 ? 2 : 1);
-  const int lane = lane_id();
-  const int s = lane & 15, g4 = lane >> 4;
-  const int G = ix.d >> 2;
-  for (int base = 0; base < cnt; base += 4 * RB) {
-    float4 x[RB][NG];
-    int32_t vid[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int idx = base + 4 * r + g4;
-      vid[r] = idx < cnt ? id_of(idx) : -1;
-#pragma unroll
-      for (int i = 0; i < NG; ++i) {
-        const int g = s + 16 * i;
-        x[r][i] = (vid[r] >= 0 && g < G) ? load4<PREC>(ix, vid[r], g) : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      float acc = 0.0f;
-#pragma unroll
-      for (int i = 0; i < NG; ++i) {
-        if (s + 16 * i < G) acc = fma_sq4(x[r][i], qv[i], acc);
-      }
-      acc = group_reduce16(acc);
-      const int idx = base + 4 * r + g4;
-      if (s == 0 && idx < cnt) keys[idx] = make_key(acc, vid[r]);
-    }
-  }
+__device__ __forceinline__ void eval_keys(const DevIndex& ix, const float4 (&qv)[NG], int cnt, IdOf id_of,
+                                          u64* keys) {
+  eval_keys_generic<NG>(ix.d >> 2, qv, cnt, id_of, [&](int64_t v, int g) { return load4<PREC>(ix, v, g); },
+                        keys);
 }
 
 // ---------------------------------------------------------------------------
@@ -233,21 +208,24 @@ struct Lds {
   u64* bkeys;
 };
 
-__device__ __forceinline__ bool hash_insert(uint32_t* hash, uint32_t hmask, int hbits, int32_t v,
-                                            bool& overflow) {
-  uint32_t hpos = ((uint32_t)v * 2654435761u) >> (32 - hbits);
-  for (int probe = 0; probe < MAX_PROBE; ++probe) {
-    uint32_t old = atomicCAS(&hash[hpos], HASH_EMPTY, (uint32_t)v);
-    if (old == HASH_EMPTY) return true;
-    if (old == (uint32_t)v) return false;
-    hpos = (hpos + 1) & hmask;
-  }
-  overflow = true;
-  return false;
+__device__ __forceinline__ uint32_t cache_slot(int32_t v, int hbits) {
+  return ((uint32_t)v * 2654435761u) >> (32 - hbits);
+}
+
+// Marks v visited; true when it was not yet visited in this layer search.
+// A hit in the LDS cache proves an earlier visit; otherwise the wave's tag for
+// v in HBM decides (exchanging in the current epoch).  Only this wave uses
+// its tag row, so workgroup scope suffices.
+__device__ __forceinline__ bool visit(uint32_t* cache, int hbits, uint32_t* tags, uint32_t epoch, int32_t v) {
+  const uint32_t hs = cache_slot(v, hbits);
+  if (cache[hs] == (uint32_t)v) return false;
+  const uint32_t old = __hip_atomic_exchange(&tags[v], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  cache[hs] = (uint32_t)v;
+  return old != epoch;
 }
 
 struct Counters {
-  int32_t ndist = 0, nexp = 0, nvisit0 = 0;
+  int32_t ndist = 0, nexp = 0, nvisit0 = 0, nadj = 0;
 };
 
 // One layer of the search (Alg. 1 / Alg. 7 with beam width p).  On return, the
@@ -255,16 +233,21 @@ struct Counters {
 template <int NG, int PREC>
 __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
                              bool hybrid, bool filter, int c, int32_t ep, u64 ep_key, int layer, int efl,
-                             int p, int& al, Counters& cnt) {
+                             int p, int& al, Counters& cnt, uint32_t* tags, uint32_t& epoch) {
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
   int hbits = 0;
   while ((1 << hbits) < A.hcap) ++hbits;
-  const uint32_t hmask = (uint32_t)A.hcap - 1;
+  // a fresh epoch per layer search; the row is cleared if the counter wraps
+  if (++epoch == 0) {
+    for (int64_t i = lane; i < ix.n; i += WAVE) tags[i] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    epoch = 1;
+  }
   for (int i = lane; i < A.hcap; i += WAVE) L.hash[i] = HASH_EMPTY;
   __syncthreads();
   bool overflow = false;
-  if (lane == 0) hash_insert(L.hash, hmask, hbits, ep, overflow);
+  if (lane == 0) visit(L.hash, hbits, tags, epoch, ep);
   int hcount = 1;
   // cand = {ep}; ann = {ep} unless filtered out
   if (lane == 0) L.cand[0] = ep_key;
@@ -312,6 +295,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
     }
     if (npop == 0) break;
     cnt.nexp += npop;
+    cnt.nadj += npop * per_node;
     // unvisited neighbours of the popped candidates
     int nn = 0;
     for (int t = 0; t < npop; ++t) {
@@ -336,17 +320,13 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
             v = row[tt];
           }
         }
-        bool isnew = v >= 0 && hash_insert(L.hash, hmask, hbits, v, overflow);
+        const bool isnew = v >= 0 && visit(L.hash, hbits, tags, epoch, v);
         const u64 nm = ballot(isnew);
         if (isnew) L.nbr[nn + rank_in(nm)] = v;
         nn += __popcll(nm);
       }
     }
     hcount += nn;
-    if (__any(overflow) || hcount * 4 > A.hcap * 3) {
-      overflow = true;
-      break;
-    }
     if (nn == 0) continue;
     __syncthreads();
     cnt.ndist += nn;
@@ -417,7 +397,7 @@ __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[N
 __device__ __forceinline__ bool ne_missing(int top) { return top < 0; }
 
 template <int NG, int PREC>
-__device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q) {
+__device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, uint32_t* tags, uint32_t& epoch) {
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
   const QPlan P = A.plan[q];
@@ -481,12 +461,13 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q) {
       __syncthreads();
     }
     for (int layer = top; layer >= 1 && ok; --layer) {
-      ok = layer_search<NG, PREC>(A, L, qv, P, hybrid, false, c, ep, ep_key, layer, 1, 1, al, cnt);
+      ok = layer_search<NG, PREC>(A, L, qv, P, hybrid, false, c, ep, ep_key, layer, 1, 1, al, cnt, tags, epoch);
       ep_key = L.ann[0];
       ep = key_id(ep_key);
       __syncthreads();
     }
-    if (ok) ok = layer_search<NG, PREC>(A, L, qv, P, hybrid, hybrid, c, ep, ep_key, 0, A.ef, A.p, al, cnt);
+    if (ok)
+      ok = layer_search<NG, PREC>(A, L, qv, P, hybrid, hybrid, c, ep, ep_key, 0, A.ef, A.p, al, cnt, tags, epoch);
     if (ne_missing(top)) {
       al = 0;
       ok = true;
@@ -523,14 +504,19 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q) {
     A.out_dist[(int64_t)q * kout + t] = __builtin_inff();
   }
   if (A.out_stats && lane == 0) {
-    A.out_stats[q * 4 + 0] = cnt.ndist;
-    A.out_stats[q * 4 + 1] = cnt.nexp;
-    A.out_stats[q * 4 + 2] = cnt.nvisit0;
-    A.out_stats[q * 4 + 3] = ok ? A.pass : 2;
+    int32_t* st = A.out_stats + (int64_t)q * 8;
+    st[0] = cnt.ndist;
+    st[1] = cnt.nexp;
+    st[2] = cnt.nvisit0;
+    st[3] = ok ? A.pass : 2;
+    st[4] = cnt.nadj;
+    st[5] = P.strat;
+    st[6] = P.hi - P.lo;
+    st[7] = hybrid ? P.b - P.a + 1 : 0;
   }
 }
 
-template <int NG, int PREC>
+template <int NG, int PREC, int PASS>
 __global__ void __launch_bounds__(64) k_search(SearchArgs A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   Lds L;
@@ -545,14 +531,19 @@ __global__ void __launch_bounds__(64) k_search(SearchArgs A) {
   p += sizeof(uint32_t) * A.hcap;
   L.nbr = reinterpret_cast<int32_t*>(p);
   const int32_t nwork = *A.nwork;
+  // this wave's visited tags; the epoch persists across launches in A.epochs
+  const int64_t slot = blockIdx.x;
+  uint32_t* tags = A.tags + slot * A.ix.n;
+  uint32_t epoch = __hip_atomic_load(&A.epochs[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   while (true) {
     int32_t w = 0;
     if (lane_id() == 0) w = atomicAdd(A.next, 1);
     w = __shfl(w, 0, WAVE);
     if (w >= nwork) break;
-    run_query<NG, PREC>(A, L, A.work[w]);
+    run_query<NG, PREC>(A, L, A.work[w], tags, epoch);
     __syncthreads();
   }
+  if (lane_id() == 0) __hip_atomic_store(&A.epochs[slot], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -567,21 +558,22 @@ size_t lds_bytes(int ef_blocks, int ccap, int hcap, int nbr_cap) {
 
 typedef void (*KernelFn)(SearchArgs);
 
-template <int PREC>
+template <int PREC, int PASS>
 KernelFn pick_kernel(int d) {
   const int ng = (d + 63) / 64;
-  if (ng <= 2) return k_search<2, PREC>;
-  if (ng <= 4) return k_search<4, PREC>;
-  if (ng <= 8) return k_search<8, PREC>;
-  if (ng <= 15) return k_search<15, PREC>;
-  if (ng <= 32) return k_search<32, PREC>;
+  if (ng <= 2) return k_search<2, PREC, PASS>;
+  if (ng <= 4) return k_search<4, PREC, PASS>;
+  if (ng <= 8) return k_search<8, PREC, PASS>;
+  if (ng <= 15) return k_search<15, PREC, PASS>;
+  if (ng <= 32) return k_search<32, PREC, PASS>;
   return nullptr;
 }
 
+template <int PASS>
 KernelFn kernel_for(int d, int prec) {
-  if (prec == UNIFY_BF16) return pick_kernel<UNIFY_BF16>(d);
-  if (prec == UNIFY_FP8E4M3) return pick_kernel<UNIFY_FP8E4M3>(d);
-  return pick_kernel<UNIFY_FP32>(d);
+  if (prec == UNIFY_BF16) return pick_kernel<UNIFY_BF16, PASS>(d);
+  if (prec == UNIFY_FP8E4M3) return pick_kernel<UNIFY_FP8E4M3, PASS>(d);
+  return pick_kernel<UNIFY_FP32, PASS>(d);
 }
 
 #define HIP_OK(x)                                                            \
@@ -605,6 +597,7 @@ int launch_pass(KernelFn fn, SearchArgs A, int device, hipStream_t st, size_t ld
     return UNIFY_EDEVICE;
   }
   int64_t grid = (int64_t)per_cu * cus;
+  if (grid > A.nslots) grid = A.nslots;
   if (grid > A.nq) grid = A.nq;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), lds, st, A);
@@ -655,6 +648,37 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
   const int64_t tauA = (int64_t)std::floor(ta * (double)dv.n);
   const int64_t tauB = (int64_t)std::ceil(tb * (double)dv.n);
 
+  // visited tags: one row of n epochs per persistent wave, kept with the index
+  if (!ix->tags) {
+    int cus = 0;
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ix->device));
+    size_t free_b = 0, total_b = 0;
+    HIP_OK(hipMemGetInfo(&free_b, &total_b));
+    int64_t slots = (int64_t)cus * 16;
+    const int64_t fit = (int64_t)(free_b / 4 / (sizeof(uint32_t) * (size_t)dv.n));
+    if (slots > fit) slots = fit;
+    if (slots < 1) {
+      set_error("no device memory for the visited tags");
+      return UNIFY_ENOMEM;
+    }
+    void* t = nullptr;
+    void* e = nullptr;
+    if (hipMalloc(&t, sizeof(uint32_t) * (size_t)dv.n * slots) != hipSuccess ||
+        hipMalloc(&e, sizeof(uint32_t) * slots) != hipSuccess) {
+      if (t) (void)hipFree(t);
+      set_error("no device memory for the visited tags");
+      return UNIFY_ENOMEM;
+    }
+    HIP_OK(hipMemset(t, 0, sizeof(uint32_t) * (size_t)dv.n * slots));
+    HIP_OK(hipMemset(e, 0, sizeof(uint32_t) * slots));
+    HIP_OK(hipDeviceSynchronize());
+    ix->tags = static_cast<uint32_t*>(t);
+    ix->epochs = static_cast<uint32_t*>(e);
+    ix->nslots = slots;
+    ix->allocs.push_back(t);
+    ix->allocs.push_back(e);
+  }
+
   // scratch: plans, work list, fallback list, counters
   const size_t plan_b = sizeof(QPlan) * nq, list_b = sizeof(int32_t) * nq;
   void* scratch = nullptr;
@@ -671,8 +695,9 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
   hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, plan, nq, work, counters);
   if (hipGetLastError() != hipSuccess) rc = UNIFY_EDEVICE;
 
-  KernelFn fn = kernel_for(dv.d, dv.precision);
-  if (rc == UNIFY_OK && !fn) {
+  KernelFn fn = kernel_for<0>(dv.d, dv.precision);
+  KernelFn fn_rerun = kernel_for<1>(dv.d, dv.precision);
+  if (rc == UNIFY_OK && (!fn || !fn_rerun)) {
     set_error("unsupported dimension");
     rc = UNIFY_EINVAL;
   }
@@ -695,8 +720,11 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
     A.out_dist = out_dist;
     A.out_stats = out_stats;
     A.plan = plan;
+    A.tags = ix->tags;
+    A.epochs = ix->epochs;
+    A.nslots = ix->nslots;
     // first pass: modest LDS per wave for occupancy
-    A.ccap = 512;
+    A.ccap = 1024;
     A.hcap = 2048;
     A.pass = 0;
     A.work = work;
@@ -704,17 +732,22 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
     A.next = counters + 1;
     A.fb_list = fb;
     A.fb_count = counters + 2;
-    rc = launch_pass(fn, A, ix->device, st, lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap));
+    const bool timing = (P.flags & UNIFY_FLAG_TIMING) != 0;
+    if (timing) {
+      for (int e = 0; e < 3 && rc == UNIFY_OK; ++e)
+        if (!ix->ev[e] && hipEventCreate(&ix->ev[e]) != hipSuccess) rc = UNIFY_EDEVICE;
+      if (rc == UNIFY_OK && hipEventRecord(ix->ev[0], st) != hipSuccess) rc = UNIFY_EDEVICE;
+      ix->timed = rc == UNIFY_OK;
+    }
+    if (rc == UNIFY_OK) rc = launch_pass(fn, A, ix->device, st, lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap));
+    if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[1], st) != hipSuccess) rc = UNIFY_EDEVICE;
     if (rc == UNIFY_OK) {
       // second pass over the abandoned queries with the largest LDS that fits
       int maxlds = 0;
       if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) != hipSuccess)
         maxlds = 65536;
-      int cc = 8192, hc = 32768;
-      while (lds_bytes(A.ef_blocks, cc, hc, A.nbr_cap) > (size_t)maxlds && cc > 1024) {
-        cc /= 2;
-        hc /= 2;
-      }
+      int cc = 16384, hc = 2048;
+      while (lds_bytes(A.ef_blocks, cc, hc, A.nbr_cap) > (size_t)maxlds && cc > 1024) cc /= 2;
       SearchArgs B = A;
       B.ccap = cc;
       B.hcap = hc;
@@ -722,7 +755,8 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
       B.work = fb;
       B.nwork = counters + 2;
       B.next = counters + 3;
-      rc = launch_pass(fn, B, ix->device, st, lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap));
+      rc = launch_pass(fn_rerun, B, ix->device, st, lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap));
+      if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[2], st) != hipSuccess) rc = UNIFY_EDEVICE;
     }
   }
   if (hipFreeAsync(scratch, st) != hipSuccess && rc == UNIFY_OK) rc = UNIFY_EDEVICE;

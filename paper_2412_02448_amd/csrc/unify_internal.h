@@ -63,6 +63,11 @@ void set_error(const std::string& msg);
 
 struct unify_index {
   int device = 0;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // timing: before search, after search, after re-run
+  bool timed = false;
+  uint32_t* tags = nullptr;    // visited epochs [nslots][n], allocated at the first search
+  uint32_t* epochs = nullptr;  // [nslots]
+  int64_t nslots = 0;
   unify::DevIndex dv{};
   unify::HostIndex host;  // small tables kept on the host; large ones released after upload
   std::vector<void*> allocs;

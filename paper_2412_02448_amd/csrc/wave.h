@@ -130,4 +130,40 @@ __device__ __forceinline__ float fma_sq4(float4 x, float4 q, float acc) {
   return acc;
 }
 
+// Keys of cnt vectors, four per round (16 lanes each), RB rounds of loads in
+// flight: id_of(i) names the i-th vector, load(v, g) returns its 4-element group
+// g as FP32; the key of the i-th lands in keys[i] (LDS).
+template <int NG, class IdOf, class Load4>
+__device__ __forceinline__ void eval_keys_generic(int G, const float4 (&qv)[NG], int cnt, IdOf id_of,
+                                                  Load4 load, u64* keys) {
+  constexpr int RB = NG <= 2 ? 4 : (NG <= 4 ? 2 : 1);
+  const int lane = lane_id();
+  const int s = lane & 15, g4 = lane >> 4;
+  for (int base = 0; base < cnt; base += 4 * RB) {
+    float4 x[RB][NG];
+    int32_t vid[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int idx = base + 4 * r + g4;
+      vid[r] = idx < cnt ? id_of(idx) : -1;
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+        const int g = s + 16 * i;
+        x[r][i] = (vid[r] >= 0 && g < G) ? load((int64_t)vid[r], g) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+        if (s + 16 * i < G) acc = fma_sq4(x[r][i], qv[i], acc);
+      }
+      acc = group_reduce16(acc);
+      const int idx = base + 4 * r + g4;
+      if (s == 0 && idx < cnt) keys[idx] = make_key(acc, vid[r]);
+    }
+  }
+}
+
 }  // namespace unify

@@ -158,6 +158,20 @@ class Workload:
     level_u: np.ndarray       # [n] float64 in (0, 1]
 
 
+def more_queries(spec: WorkloadSpec, attr: np.ndarray, nq: int, base_seed: int = 0, stream: int = 1):
+    """Another query set of the same recipe over the same data (e.g. held-out tuning queries).
+
+    Query vectors come from the same mixture (same centres); vectors, range
+    fractions and placements use their own streams.  Returns (queries, l, h, fractions)."""
+    sub = dataclasses.replace(spec, nq=nq)
+    q = mixture(nq, spec.d, spec.centers, spec.sigma, base_seed, SEED_QUERY + 1000 * stream)
+    fr = range_fractions(sub, base_seed + 7919 * stream)
+    if spec.ranges == "fixed":
+        q = np.repeat(q, len(spec.fractions), axis=0)
+    l, h = ranges_for(attr, fr, base_seed, stream_offset=104729 * stream)
+    return np.ascontiguousarray(q), l, h, fr
+
+
 def make(spec: WorkloadSpec, base_seed: int = 0) -> Workload:
     base = mixture(spec.n, spec.d, spec.centers, spec.sigma, base_seed, SEED_DATA)
     attr = attributes(spec, base_seed)
