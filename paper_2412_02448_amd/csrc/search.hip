@@ -128,28 +128,53 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
   if (out_strat) out_strat[q] = (int8_t)s;
 }
 
-// Work list: queries with a non-empty range, in query order; resets counters.
-__global__ void k_worklist(const QPlan* __restrict__ plan, int64_t nq, int32_t* __restrict__ work,
+// Work list: the graph-search queries (hybrid, post) in query order, then the
+// pre-filter queries bucketed by the start of their slice, so that waves that
+// scan at the same time read overlapping slices.  Resets the counters.
+__global__ void k_worklist(const QPlan* __restrict__ plan, int64_t nq, int64_t n, int32_t* __restrict__ work,
                            int32_t* __restrict__ counters /* nwork, next, fb_count, fb_next */) {
+  constexpr int NB = 1024;
   __shared__ int32_t part[1024];
+  __shared__ int32_t bucket[NB];
   const int t = threadIdx.x, T = blockDim.x;
   const int64_t per = (nq + T - 1) / T;
   const int64_t s0 = std::min<int64_t>(nq, t * per), s1 = std::min<int64_t>(nq, s0 + per);
+  for (int b = t; b < NB; b += T) bucket[b] = 0;
+  __syncthreads();
   int32_t c = 0;
-  for (int64_t q = s0; q < s1; ++q) c += plan[q].strat >= 0;
+  for (int64_t q = s0; q < s1; ++q) {
+    const QPlan P = plan[q];
+    if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) ++c;
+    else if (P.strat == UNIFY_PRE) atomicAdd(&bucket[(int)((int64_t)P.lo * NB / n)], 1);
+  }
   part[t] = c;
   __syncthreads();
   for (int off = 1; off < T; off <<= 1) {
     int32_t v = t >= off ? part[t - off] : 0;
+    int32_t bv = (t >= off && t < NB) ? bucket[t - off] : 0;
     __syncthreads();
     part[t] += v;
+    if (t < NB) bucket[t] += bv;
     __syncthreads();
   }
+  const int32_t nbeam = part[T - 1];
+  const int32_t npre = bucket[NB - 1];
+  const int32_t my_end = t < NB ? bucket[t] : 0;  // inclusive prefix count of pre queries
+  __syncthreads();
+  if (t < NB) bucket[t] = nbeam + my_end;  // one past the last slot of bucket t
+  __syncthreads();
   int32_t pos = part[t] - c;
-  for (int64_t q = s0; q < s1; ++q)
-    if (plan[q].strat >= 0) work[pos++] = (int32_t)q;
-  if (t == T - 1) {
-    counters[0] = part[T - 1];
+  for (int64_t q = s0; q < s1; ++q) {
+    const QPlan P = plan[q];
+    if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) {
+      work[pos++] = (int32_t)q;
+    } else if (P.strat == UNIFY_PRE) {
+      const int b = (int)((int64_t)P.lo * NB / n);
+      work[atomicSub(&bucket[b], 1) - 1] = (int32_t)q;
+    }
+  }
+  if (t == 0) {
+    counters[0] = nbeam + npre;
     counters[1] = 0;
     counters[2] = 0;
     counters[3] = 0;
@@ -208,20 +233,52 @@ struct Lds {
   u64* bkeys;
 };
 
-__device__ __forceinline__ uint32_t cache_slot(int32_t v, int hbits) {
-  return ((uint32_t)v * 2654435761u) >> (32 - hbits);
+// Visited set of one layer search.  An 8-way set-associative cache of ids in
+// LDS is exact while no set has overflowed ("local" mode: a miss proves the id
+// new).  When an insert finds its set full, the wave writes every cached id and
+// the overflowing ones to its HBM tag row (tag == epoch means visited) and
+// switches to "tagged" mode: a cache miss then reads the tag.  Only this wave
+// uses its tag row; workgroup-scope fences order its own stores and loads.
+constexpr int VWAYS = 8;
+
+__device__ __forceinline__ uint32_t* cache_set(uint32_t* cache, int setbits, int32_t v) {
+  const uint32_t set = ((uint32_t)v * 2654435761u) >> (32 - setbits);
+  return cache + set * VWAYS;
 }
 
-// Marks v visited; true when it was not yet visited in this layer search.
-// A hit in the LDS cache proves an earlier visit; otherwise the wave's tag for
-// v in HBM decides (exchanging in the current epoch).  Only this wave uses
-// its tag row, so workgroup scope suffices.
-__device__ __forceinline__ bool visit(uint32_t* cache, int hbits, uint32_t* tags, uint32_t epoch, int32_t v) {
-  const uint32_t hs = cache_slot(v, hbits);
-  if (cache[hs] == (uint32_t)v) return false;
-  const uint32_t old = __hip_atomic_exchange(&tags[v], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  cache[hs] = (uint32_t)v;
-  return old != epoch;
+__device__ __forceinline__ bool cache_hit(const uint32_t* base, int32_t v) {
+  const uint4 a = *reinterpret_cast<const uint4*>(base);
+  const uint4 b = *reinterpret_cast<const uint4*>(base + 4);
+  const uint32_t u = (uint32_t)v;
+  return a.x == u || a.y == u || a.z == u || a.w == u || b.x == u || b.y == u || b.z == u || b.w == u;
+}
+
+// Local mode: true when v is new; `full` when it could not be recorded.
+__device__ __forceinline__ bool visit_local(uint32_t* cache, int setbits, int32_t v, bool& full) {
+  uint32_t* base = cache_set(cache, setbits, v);
+  if (cache_hit(base, v)) return false;
+#pragma unroll
+  for (int w = 0; w < VWAYS; ++w) {
+    if (atomicCAS(base + w, HASH_EMPTY, (uint32_t)v) == HASH_EMPTY) return true;
+  }
+  full = true;
+  return true;
+}
+
+// Tagged mode: the tag row is authoritative, the cache only saves reads.
+__device__ __forceinline__ bool visit_tagged(uint32_t* cache, int setbits, uint32_t* tags, uint32_t epoch,
+                                             int32_t v) {
+  uint32_t* base = cache_set(cache, setbits, v);
+  if (cache_hit(base, v)) return false;
+  if (tags[v] == epoch) return false;
+  tags[v] = epoch;
+  base[(uint32_t)v & (VWAYS - 1)] = (uint32_t)v;
+  return true;
+}
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 struct Counters {
@@ -246,8 +303,10 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
   }
   for (int i = lane; i < A.hcap; i += WAVE) L.hash[i] = HASH_EMPTY;
   __syncthreads();
+  const int setbits = hbits - 3;  // hcap / VWAYS sets
+  bool tagged = false;
   bool overflow = false;
-  if (lane == 0) visit(L.hash, hbits, tags, epoch, ep);
+  if (lane == 0) L.hash[(cache_set(L.hash, setbits, ep) - L.hash)] = (uint32_t)ep;
   int hcount = 1;
   // cand = {ep}; ann = {ep} unless filtered out
   if (lane == 0) L.cand[0] = ep_key;
@@ -320,7 +379,21 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
             v = row[tt];
           }
         }
-        const bool isnew = v >= 0 && visit(L.hash, hbits, tags, epoch, v);
+        bool isnew = false, full = false;
+        if (v >= 0) {
+          isnew = tagged ? visit_tagged(L.hash, setbits, tags, epoch, v)
+                         : visit_local(L.hash, setbits, v, full);
+        }
+        if (!tagged && __any(full)) {
+          // switch to tagged mode: record every visited id in the tag row
+          for (int i = lane; i < A.hcap; i += WAVE) {
+            const uint32_t id = L.hash[i];
+            if (id != HASH_EMPTY) tags[id] = epoch;
+          }
+          if (full) tags[v] = epoch;
+          tagged = true;
+        }
+        if (tagged) wave_fence();
         const u64 nm = ballot(isnew);
         if (isnew) L.nbr[nn + rank_in(nm)] = v;
         nn += __popcll(nm);
@@ -692,7 +765,7 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
   const unsigned pb = 256;
   hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, dv, l, h, strategy, nq,
                      tauA, tauB, k, plan, out_strategy, out_ids, out_dist, out_stats);
-  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, plan, nq, work, counters);
+  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, plan, nq, dv.n, work, counters);
   if (hipGetLastError() != hipSuccess) rc = UNIFY_EDEVICE;
 
   KernelFn fn = kernel_for<0>(dv.d, dv.precision);

@@ -33,6 +33,16 @@ __device__ __forceinline__ u64 shfl_xor64(u64 v, int m) {
   uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);
   return ((u64)hi << 32) | lo;
 }
+// Value of lane (i - n) mod 16 within each 16-lane row (DPP row rotate right).
+template <int N>
+__device__ __forceinline__ float row_ror(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x120 + N, 0xF, 0xF, false));
+}
+template <int N>
+__device__ __forceinline__ uint32_t row_ror_u(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x120 + N, 0xF, 0xF, false);
+}
+
 __device__ __forceinline__ u64 umin64(u64 a, u64 b) { return a < b ? a : b; }
 __device__ __forceinline__ u64 umax64(u64 a, u64 b) { return a < b ? b : a; }
 
@@ -43,10 +53,19 @@ __device__ __forceinline__ int rank_in(u64 mask) {
 }
 __device__ __forceinline__ u64 ballot(bool p) { return __ballot(p); }
 
-// Wave-wide minimum of a 64-bit key.
+// Wave-wide minimum of a 64-bit key (rows by DPP rotation, then across rows).
 __device__ __forceinline__ u64 wave_min64(u64 v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = umin64(v, shfl_xor64(v, m));
+  u64 o;
+  o = ((u64)row_ror_u<8>((uint32_t)(v >> 32)) << 32) | row_ror_u<8>((uint32_t)v);
+  v = umin64(v, o);
+  o = ((u64)row_ror_u<4>((uint32_t)(v >> 32)) << 32) | row_ror_u<4>((uint32_t)v);
+  v = umin64(v, o);
+  o = ((u64)row_ror_u<2>((uint32_t)(v >> 32)) << 32) | row_ror_u<2>((uint32_t)v);
+  v = umin64(v, o);
+  o = ((u64)row_ror_u<1>((uint32_t)(v >> 32)) << 32) | row_ror_u<1>((uint32_t)v);
+  v = umin64(v, o);
+  v = umin64(v, shfl_xor64(v, 16));
+  v = umin64(v, shfl_xor64(v, 32));
   return v;
 }
 
@@ -107,13 +126,16 @@ __device__ __forceinline__ void list_insert(u64* lst, int& len, int cap, u64 key
 // Canonical FP32 squared distance of 4 vectors per wave (16 lanes each).
 // Lane s = lane & 15 owns the 4-element groups g = s, s + 16, ... (< d / 4) and
 // accumulates them in increasing order with fused multiply-adds; the 16
-// partials are then combined by the butterfly s ^ 8, s ^ 4, s ^ 2, s ^ 1.  Every
-// lane of the 16-lane group ends with the same value.
+// partials are then combined by the butterfly P[s] + P[s ^ 8], then ^ 4, ^ 2,
+// ^ 1.  Rotating by 8, 4, 2, 1 within the row computes exactly that tree: after
+// the step for t, every partial is unchanged by xor-ing bits >= log2(t) of its
+// lane, and (s - t) mod 16 differs from s ^ t only in those bits.  Every lane of
+// the row ends with the same value.
 __device__ __forceinline__ float group_reduce16(float p) {
-  p = p + __shfl_xor(p, 8, WAVE);
-  p = p + __shfl_xor(p, 4, WAVE);
-  p = p + __shfl_xor(p, 2, WAVE);
-  p = p + __shfl_xor(p, 1, WAVE);
+  p = p + row_ror<8>(p);
+  p = p + row_ror<4>(p);
+  p = p + row_ror<2>(p);
+  p = p + row_ror<1>(p);
   return p;
 }
 
