@@ -132,14 +132,14 @@ def main():
     rec = recalls[ef]
     log(f"recall@10 on the benchmark queries at m={m}: " + ", ".join(f"ef={e}: {r:.4f}" for e, r in recalls.items()))
 
-    def timed(strategy=None, steps=args.steps, warmup=args.warmup):
+    def timed(strategy=None, steps=args.steps, warmup=args.warmup, **kw):
         out = None
         for _ in range(warmup):
-            out = index.search(Q, L, H, k, ef, strategy=strategy, m=m, beam_p=bp)
+            out = index.search(Q, L, H, k, ef, strategy=strategy, m=m, beam_p=bp, **kw)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
-            out = index.search(Q, L, H, k, ef, strategy=strategy, m=m, beam_p=bp)
+            out = index.search(Q, L, H, k, ef, strategy=strategy, m=m, beam_p=bp, **kw)
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / steps, out
 
@@ -153,10 +153,22 @@ def main():
         per_strategy[name] = {"qps": round(nq / s, 1), "recall@10": round(recall_of(o[0]), 4)}
         log(f"{name}: {nq / s:,.0f} QPS recall {per_strategy[name]['recall@10']}")
 
+    # the same step with narrow pre-filter queries answered by the tile-shared scan
+    s, o = timed(steps=max(1, args.steps // 2 + 1), warmup=1, tiled_prescan=True)
+    same = bool((o[0] == out[0]).all().item())
+    _, _, _, tst = index.search(Q, L, H, k, ef, m=m, beam_p=bp, stats=True, timing=True, tiled_prescan=True)
+    torch.cuda.synchronize()
+    tpre_ms = index.last_timing()[0]
+    ntiled = int((tst[:, 3] == 3).sum().item())
+    tiled_alt = {"qps": round(nq / s, 1), "same_ids_as_default": same, "tiled_queries": ntiled,
+                 "prescan_ms": round(tpre_ms, 4)}
+    log(f"auto with tiled pre-filter scan: {nq / s:,.0f} QPS ({ntiled} tiled queries, "
+        f"{tpre_ms:.3f} ms), same ids: {same}")
+
     # ---- roofline of the search kernel: counters of one more (identical) call ----
     ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, stats=True, timing=True)
     torch.cuda.synchronize()
-    search_ms, rerun_ms = index.last_timing()
+    pre_ms, search_ms, rerun_ms = index.last_timing()
     st = stats.cpu().numpy().astype(np.int64)
     d = spec.d
     first = st[:, 3] == 0
@@ -179,7 +191,8 @@ def main():
             r = [len(set(ids_np[i][ids_np[i] >= 0].tolist()) & set(truth[i][truth[i] >= 0].tolist()))
                  / max(1, int((truth[i] >= 0).sum())) for i in sel]
             per_strategy.setdefault(sname, {})["recall@10_in_auto"] = round(float(np.mean(r)), 4)
-    log(f"search kernel {search_ms:.3f} ms, rerun {rerun_ms:.3f} ms, {achieved:.1f} GB/s algorithmic")
+    log(f"work list {pre_ms:.3f} ms; search kernel {search_ms:.3f} ms, "
+        f"rerun {rerun_ms:.3f} ms, {achieved:.1f} GB/s algorithmic")
 
     # ---- CPU baseline: the oracle's HSIG search on the same index file ----
     cpu = None
@@ -203,6 +216,7 @@ def main():
                    "build_s": round(build_s, 1)},
         "per_strategy": per_strategy,
         "roofline": roofline,
+        "alt_tiled_prescan": tiled_alt,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -277,7 +291,7 @@ def profile_run(args, index, Q, L, H, k, spec, nq, build_s):
     sec = (time.perf_counter() - t) / args.steps
     ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, stats=True, timing=True)
     torch.cuda.synchronize()
-    search_ms, rerun_ms = index.last_timing()
+    pre_ms, search_ms, rerun_ms = index.last_timing()
     st = stats.cpu().numpy().astype(np.int64)
     per_q = st[:, 0] * spec.d * 4 + st[:, 4] * 4 + (st[:, 5] >= 0) * (spec.d * 4 + k * 12)
     b = int(per_q[st[:, 3] == 0].sum())

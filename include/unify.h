@@ -69,21 +69,28 @@ enum {
 
 /* Bits of unify_params.flags. */
 enum {
-  UNIFY_FLAG_TIMING = 1  /* record HIP events around the search kernels; see unify_last_timing */
+  UNIFY_FLAG_TIMING = 1,         /* record HIP events around the search kernels; see unify_last_timing */
+  UNIFY_FLAG_TILED_PRESCAN = 2   /* answer narrow pre-filter queries with the tile-shared scan
+                                    (reads each tile once per group of 16 queries) instead of
+                                    one wavefront per query; same results */
 };
 
 /* Search parameters.  Zero in a field selects its default. */
 typedef struct {
   int32_t m;            /* neighbours examined per expansion in the hybrid search,
                            ceil(m / S') from each active chunk (Sec. 4.2); default M0 */
-  int32_t beam_p;       /* candidates expanded together per step; default 1 (= Alg. 7) */
+  int32_t beam_p;       /* candidates expanded together per step, 1..8; default 1 (= Alg. 7) */
   int32_t rerank_mult;  /* BF16/FP8 stores: FP32 rerank of the best rerank_mult * k
                            graph results; default 4 */
-  int32_t reserved;
+  int32_t cand_cap;     /* on-chip candidate entries per query, a power of two in
+                           [64, 4096]; default 512.  Queries that need more are re-run
+                           with a larger array (same results). */
   double tau_a_frac;    /* tau_A = floor(tau_a_frac * n); default 0.01 (Sec. 6.2) */
   double tau_b_frac;    /* tau_B = ceil(tau_b_frac * n); default 0.5 (Sec. 6.2) */
   uint32_t flags;       /* UNIFY_FLAG_* bits, 0 for none */
-  uint32_t pad;
+  int32_t visit_cap;    /* on-chip visited-cache entries per query, a power of two in
+                           [256, 16384]; default 1024 (larger visited sets spill to HBM,
+                           same results) */
 } unify_params;
 
 /*
@@ -150,8 +157,8 @@ int unify_search(unify_index_t index, const float* queries, int64_t nq, const in
  * unify_search plus per-query counters:
  *   out_stats  device, [nq][8] int32: [0] distance evaluations, [1] expansions,
  *              [2] objects visited on layer 0, [3] status (0 = ran in the first
- *              pass, 1 = re-run with larger on-chip lists, 2 = capacity exceeded even
- *              then: the row is padded), [4] adjacency entries read, [5] strategy run
+ *              search pass, 1 = re-run with larger on-chip lists, 2 = capacity exceeded
+ *              even then: the row is padded, 3 = answered by the tiled pre-filter scan), [4] adjacency entries read, [5] strategy run
  *              (-1 for an empty range), [6] Y = objects in range, [7] active segments
  *              (hybrid only, else 0).
  */
@@ -161,14 +168,15 @@ int unify_search_ex(unify_index_t index, const float* queries, int64_t nq, const
                     int8_t* out_strategy, int32_t* out_stats, void* hip_stream);
 
 /*
- * Durations of the search kernels of the last unify_search* call on this index
- * that set UNIFY_FLAG_TIMING, from HIP events recorded on that call's stream:
- *   search_ms  the main search launch (all queries);
- *   rerun_ms   the launch that re-runs queries whose on-chip lists overflowed.
+ * Durations of the kernels of the last unify_search* call on this index that set
+ * UNIFY_FLAG_TIMING, from HIP events recorded on that call's stream:
+ *   prescan_ms  the tiled pre-filter scan (pre-filter queries of narrow ranges);
+ *   search_ms   the main search launch (graph searches and the remaining scans);
+ *   rerun_ms    the launch that re-runs queries whose on-chip lists overflowed.
  * Waits for the events to complete.  Outputs are host pointers, any may be NULL.
  * Returns UNIFY_EINVAL when no timed search has been issued.
  */
-int unify_last_timing(unify_index_t index, float* search_ms, float* rerun_ms);
+int unify_last_timing(unify_index_t index, float* prescan_ms, float* search_ms, float* rerun_ms);
 
 /* Frees the index and its device memory.  NULL is accepted. */
 int unify_free_index(unify_index_t index);

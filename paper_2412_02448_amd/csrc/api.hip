@@ -306,23 +306,25 @@ int unify_search_ex(unify_index_t ix, const float* queries, int64_t nq, const in
                      hip_stream);
 }
 
-int unify_last_timing(unify_index_t ix, float* search_ms, float* rerun_ms) {
+int unify_last_timing(unify_index_t ix, float* prescan_ms, float* search_ms, float* rerun_ms) {
   if (!ix || !ix->timed) {
     set_error("no timed search on this index");
     return UNIFY_EINVAL;
   }
-  if (hipSetDevice(ix->device) != hipSuccess || hipEventSynchronize(ix->ev[2]) != hipSuccess) {
+  if (hipSetDevice(ix->device) != hipSuccess || hipEventSynchronize(ix->ev[3]) != hipSuccess) {
     set_error("hipEventSynchronize failed");
     return UNIFY_EDEVICE;
   }
-  float a = 0.f, b = 0.f;
+  float a = 0.f, b = 0.f, c = 0.f;
   if (hipEventElapsedTime(&a, ix->ev[0], ix->ev[1]) != hipSuccess ||
-      hipEventElapsedTime(&b, ix->ev[1], ix->ev[2]) != hipSuccess) {
+      hipEventElapsedTime(&b, ix->ev[1], ix->ev[2]) != hipSuccess ||
+      hipEventElapsedTime(&c, ix->ev[2], ix->ev[3]) != hipSuccess) {
     set_error("hipEventElapsedTime failed");
     return UNIFY_EDEVICE;
   }
-  if (search_ms) *search_ms = a;
-  if (rerun_ms) *rerun_ms = b;
+  if (prescan_ms) *prescan_ms = a;
+  if (search_ms) *search_ms = b;
+  if (rerun_ms) *rerun_ms = c;
   return UNIFY_OK;
 }
 

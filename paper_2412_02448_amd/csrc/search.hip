@@ -32,13 +32,6 @@
 
 namespace unify {
 
-struct QPlan {
-  int32_t lo, hi;   // in-range internal ids [lo, hi)
-  int32_t a, b;     // active segments a..b (segments holding an in-range object)
-  int32_t strat;    // UNIFY_PRE / HYBRID / POST; -1 when the range is empty
-  int32_t pad;
-};
-
 struct SearchArgs {
   DevIndex ix;
   const float* Q;
@@ -109,7 +102,7 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
   P.lo = (int32_t)lo;
   P.hi = (int32_t)hi;
   P.a = P.b = 0;
-  P.pad = 0;
+  P.tiled = 0;
   if (Y > 0) {
     P.a = (int32_t)(upper_bound_i64(ix.seg_start, ix.S + 1, lo) - 1);
     P.b = (int32_t)(upper_bound_i64(ix.seg_start, ix.S + 1, hi - 1) - 1);
@@ -145,7 +138,7 @@ __global__ void k_worklist(const QPlan* __restrict__ plan, int64_t nq, int64_t n
   for (int64_t q = s0; q < s1; ++q) {
     const QPlan P = plan[q];
     if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) ++c;
-    else if (P.strat == UNIFY_PRE) atomicAdd(&bucket[(int)((int64_t)P.lo * NB / n)], 1);
+    else if (P.strat == UNIFY_PRE && !P.tiled) atomicAdd(&bucket[(int)((int64_t)P.lo * NB / n)], 1);
   }
   part[t] = c;
   __syncthreads();
@@ -168,7 +161,7 @@ __global__ void k_worklist(const QPlan* __restrict__ plan, int64_t nq, int64_t n
     const QPlan P = plan[q];
     if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) {
       work[pos++] = (int32_t)q;
-    } else if (P.strat == UNIFY_PRE) {
+    } else if (P.strat == UNIFY_PRE && !P.tiled) {
       const int b = (int)((int64_t)P.lo * NB / n);
       work[atomicSub(&bucket[b], 1) - 1] = (int32_t)q;
     }
@@ -229,8 +222,7 @@ struct Lds {
   u64* ann;
   u64* cand;
   uint32_t* hash;
-  int32_t* nbr;
-  u64* bkeys;
+  u64* bkeys;  // neighbour ids (low 32 bits) before evaluation, their keys after
 };
 
 // Visited set of one layer search.  An 8-way set-associative cache of ids in
@@ -395,7 +387,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
         }
         if (tagged) wave_fence();
         const u64 nm = ballot(isnew);
-        if (isnew) L.nbr[nn + rank_in(nm)] = v;
+        if (isnew) L.bkeys[nn + rank_in(nm)] = (uint32_t)v;
         nn += __popcll(nm);
       }
     }
@@ -403,7 +395,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
     if (nn == 0) continue;
     __syncthreads();
     cnt.ndist += nn;
-    eval_keys<NG, PREC>(ix, qv, nn, [&](int i) { return L.nbr[i]; }, L.bkeys);
+    eval_keys<NG, PREC>(ix, qv, nn, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
     __syncthreads();
     // admission against the threshold from before this step
     for (int base = 0; base < nn; base += WAVE) {
@@ -507,11 +499,11 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, uint32_t
         const int j = j0 + lane;
         const bool is = j <= P.b && ix.seg_entry[j] >= 0 && ix.seg_maxlevel[j] == top;
         const u64 mk = ballot(is);
-        if (is) L.nbr[ne + rank_in(mk)] = ix.seg_entry[j];
+        if (is) L.bkeys[ne + rank_in(mk)] = (uint32_t)ix.seg_entry[j];
         ne += __popcll(mk);
       }
       __syncthreads();
-      eval_keys<NG, PREC>(ix, qv, ne, [&](int i) { return L.nbr[i]; }, L.bkeys);
+      eval_keys<NG, PREC>(ix, qv, ne, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
       __syncthreads();
       cnt.ndist += ne;
       const u64 kk = lane < ne ? L.bkeys[lane] : KEY_MAX;
@@ -525,9 +517,9 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, uint32_t
     } else {
       top = ix.L;
       ep = ix.gentry;
-      L.nbr[0] = ep;
+      L.bkeys[0] = (uint32_t)ep;
       __syncthreads();
-      eval_keys<NG, PREC>(ix, qv, 1, [&](int i) { return L.nbr[i]; }, L.bkeys);
+      eval_keys<NG, PREC>(ix, qv, 1, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
       __syncthreads();
       ep_key = L.bkeys[0];
       cnt.ndist += 1;
@@ -601,8 +593,6 @@ __global__ void __launch_bounds__(64) k_search(SearchArgs A) {
   L.bkeys = reinterpret_cast<u64*>(p);
   p += sizeof(u64) * A.nbr_cap;
   L.hash = reinterpret_cast<uint32_t*>(p);
-  p += sizeof(uint32_t) * A.hcap;
-  L.nbr = reinterpret_cast<int32_t*>(p);
   const int32_t nwork = *A.nwork;
   // this wave's visited tags; the epoch persists across launches in A.epochs
   const int64_t slot = blockIdx.x;
@@ -622,11 +612,15 @@ __global__ void __launch_bounds__(64) k_search(SearchArgs A) {
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+size_t prescan_scratch_bytes(const DevIndex& dv, int64_t nq, int k, int span_cap);
+int span_cap_for(const DevIndex& dv, int64_t tauA);
+int launch_prescan(const DevIndex& dv, const float* Q, int64_t nq, int k, int span_cap, QPlan* plan, void* scratch,
+                   int64_t* out_ids, float* out_dist, int32_t* out_stats, int device, hipStream_t st);
+
 namespace {
 
 size_t lds_bytes(int ef_blocks, int ccap, int hcap, int nbr_cap) {
-  return sizeof(u64) * ((size_t)ef_blocks * WAVE + ccap + nbr_cap) + sizeof(uint32_t) * hcap +
-         sizeof(int32_t) * nbr_cap;
+  return sizeof(u64) * ((size_t)ef_blocks * WAVE + ccap + nbr_cap) + sizeof(uint32_t) * hcap;
 }
 
 typedef void (*KernelFn)(SearchArgs);
@@ -706,8 +700,12 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
   const int p = P.beam_p > 0 ? P.beam_p : 1;
   const double ta = P.tau_a_frac > 0 ? P.tau_a_frac : 0.01;
   const double tb = P.tau_b_frac > 0 ? P.tau_b_frac : 0.5;
-  if (m > dv.S * dv.M0 || p > 8 || ta > 1.0 || tb > 1.0) {
-    set_error("params out of range (m <= S*M0, beam_p <= 8, tau fractions <= 1)");
+  const int ccap = P.cand_cap > 0 ? P.cand_cap : 512;
+  const int hcap = P.visit_cap > 0 ? P.visit_cap : 1024;
+  if (m > dv.S * dv.M0 || p > 8 || ta > 1.0 || tb > 1.0 || ccap < 64 || ccap > 4096 || (ccap & (ccap - 1)) ||
+      hcap < 256 || hcap > 16384 || (hcap & (hcap - 1))) {
+    set_error("params out of range (m <= S*M0, beam_p <= 8, tau fractions <= 1, cand_cap and visit_cap powers "
+              "of two in [64, 4096] and [256, 16384])");
     return UNIFY_EINVAL;
   }
   if (!queries || !l || !h || !out_ids || !out_dist) {
@@ -752,19 +750,32 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
     ix->allocs.push_back(e);
   }
 
-  // scratch: plans, work list, fallback list, counters
-  const size_t plan_b = sizeof(QPlan) * nq, list_b = sizeof(int32_t) * nq;
+  // scratch: plans, work list, fallback list, counters, tiled pre-filter scan
+  const int span_cap = span_cap_for(dv, tauA);
+  const size_t plan_b = (sizeof(QPlan) * nq + 255) / 256 * 256, list_b = (sizeof(int32_t) * nq + 255) / 256 * 256;
+  const size_t pre_b = (P.flags & UNIFY_FLAG_TILED_PRESCAN) ? prescan_scratch_bytes(dv, nq, k, span_cap) : 0;
   void* scratch = nullptr;
-  HIP_OK(hipMallocAsync(&scratch, plan_b + 2 * list_b + 64, st));
+  HIP_OK(hipMallocAsync(&scratch, plan_b + 2 * list_b + 256 + pre_b, st));
   QPlan* plan = reinterpret_cast<QPlan*>(scratch);
   int32_t* work = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(scratch) + plan_b);
-  int32_t* fb = work + nq;
-  int32_t* counters = fb + nq;  // nwork, next, fb_count, fb_next
+  int32_t* fb = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(work) + list_b);
+  int32_t* counters = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(fb) + list_b);  // nwork, next, fb_count, fb_next
+  void* pre_scratch = reinterpret_cast<char*>(counters) + 256;
 
+  const bool timing = (P.flags & UNIFY_FLAG_TIMING) != 0;
   int rc = UNIFY_OK;
+  if (timing) {
+    for (int e = 0; e < 4 && rc == UNIFY_OK; ++e)
+      if (!ix->ev[e] && hipEventCreate(&ix->ev[e]) != hipSuccess) rc = UNIFY_EDEVICE;
+    ix->timed = rc == UNIFY_OK;
+  }
   const unsigned pb = 256;
   hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, dv, l, h, strategy, nq,
                      tauA, tauB, k, plan, out_strategy, out_ids, out_dist, out_stats);
+  if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[0], st) != hipSuccess) rc = UNIFY_EDEVICE;
+  if (rc == UNIFY_OK && (P.flags & UNIFY_FLAG_TILED_PRESCAN))
+    rc = launch_prescan(dv, queries, nq, k, span_cap, plan, pre_scratch, out_ids, out_dist, out_stats, ix->device,
+                        st);
   hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, plan, nq, dv.n, work, counters);
   if (hipGetLastError() != hipSuccess) rc = UNIFY_EDEVICE;
 
@@ -797,30 +808,24 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
     A.epochs = ix->epochs;
     A.nslots = ix->nslots;
     // first pass: modest LDS per wave for occupancy
-    A.ccap = 1024;
-    A.hcap = 2048;
+    A.ccap = ccap;
+    A.hcap = hcap;
     A.pass = 0;
     A.work = work;
     A.nwork = counters + 0;
     A.next = counters + 1;
     A.fb_list = fb;
     A.fb_count = counters + 2;
-    const bool timing = (P.flags & UNIFY_FLAG_TIMING) != 0;
-    if (timing) {
-      for (int e = 0; e < 3 && rc == UNIFY_OK; ++e)
-        if (!ix->ev[e] && hipEventCreate(&ix->ev[e]) != hipSuccess) rc = UNIFY_EDEVICE;
-      if (rc == UNIFY_OK && hipEventRecord(ix->ev[0], st) != hipSuccess) rc = UNIFY_EDEVICE;
-      ix->timed = rc == UNIFY_OK;
-    }
-    if (rc == UNIFY_OK) rc = launch_pass(fn, A, ix->device, st, lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap));
     if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[1], st) != hipSuccess) rc = UNIFY_EDEVICE;
+    if (rc == UNIFY_OK) rc = launch_pass(fn, A, ix->device, st, lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap));
+    if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[2], st) != hipSuccess) rc = UNIFY_EDEVICE;
     if (rc == UNIFY_OK) {
       // second pass over the abandoned queries with the largest LDS that fits
       int maxlds = 0;
       if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) != hipSuccess)
         maxlds = 65536;
-      int cc = 16384, hc = 2048;
-      while (lds_bytes(A.ef_blocks, cc, hc, A.nbr_cap) > (size_t)maxlds && cc > 1024) cc /= 2;
+      int cc = 16384, hc = std::max(hcap, 2048);
+      while (lds_bytes(A.ef_blocks, cc, hc, A.nbr_cap) > (size_t)maxlds && cc > 2 * ccap) cc /= 2;
       SearchArgs B = A;
       B.ccap = cc;
       B.hcap = hc;
@@ -829,7 +834,7 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
       B.nwork = counters + 2;
       B.next = counters + 3;
       rc = launch_pass(fn_rerun, B, ix->device, st, lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap));
-      if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[2], st) != hipSuccess) rc = UNIFY_EDEVICE;
+      if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[3], st) != hipSuccess) rc = UNIFY_EDEVICE;
     }
   }
   if (hipFreeAsync(scratch, st) != hipSuccess && rc == UNIFY_OK) rc = UNIFY_EDEVICE;

@@ -36,6 +36,14 @@ struct DevIndex {
   const int32_t* glistU;     // [R][GC]
 };
 
+// Per-query plan written by the plan kernel.
+struct QPlan {
+  int32_t lo, hi;   // in-range internal ids [lo, hi)
+  int32_t a, b;     // active segments a..b (segments holding an in-range object)
+  int32_t strat;    // UNIFY_PRE / HYBRID / POST; -1 when the range is empty
+  int32_t tiled;    // 1 when the tiled pre-filter scan answers this query
+};
+
 // Host-side tables of an index (the index file content), internal ids.
 struct HostIndex {
   int64_t n = 0;
@@ -63,7 +71,8 @@ void set_error(const std::string& msg);
 
 struct unify_index {
   int device = 0;
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // timing: before search, after search, after re-run
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // timing: before/after the tiled pre-filter,
+                                                            // after the search, after the re-run
   bool timed = false;
   uint32_t* tags = nullptr;    // visited epochs [nslots][n], allocated at the first search
   uint32_t* epochs = nullptr;  // [nslots]

@@ -33,6 +33,30 @@ __device__ __forceinline__ u64 shfl_xor64(u64 v, int m) {
   uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);
   return ((u64)hi << 32) | lo;
 }
+
+// Value of lane (lane ^ M), by DPP for M <= 8 (no LDS round trip):
+//   xor 1, 2: quad permutations; xor 4: quad [3,2,1,0] then half-row mirror
+//   (lane i reads i ^ 7, which holds the value of (i ^ 7) ^ 3 = i ^ 4);
+//   xor 8: row rotation by 8 (i +- 8 mod 16 = i ^ 8).
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t x) {
+  if constexpr (M == 1) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
+  } else if constexpr (M == 2) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);
+  } else if constexpr (M == 4) {
+    const int y = __builtin_amdgcn_update_dpp(0, (int)x, 0x1B, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x141, 0xF, 0xF, false);
+  } else if constexpr (M == 8) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);
+  } else {
+    return (uint32_t)__shfl_xor((int)x, M, WAVE);
+  }
+}
+template <int M>
+__device__ __forceinline__ u64 xor_lane64(u64 v) {
+  return ((u64)xor_lane32<M>((uint32_t)(v >> 32)) << 32) | xor_lane32<M>((uint32_t)v);
+}
 // Value of lane (i - n) mod 16 within each 16-lane row (DPP row rotate right).
 template <int N>
 __device__ __forceinline__ float row_ror(float x) {
@@ -69,19 +93,39 @@ __device__ __forceinline__ u64 wave_min64(u64 v) {
   return v;
 }
 
+// One compare-exchange step of a bitonic network: partner lane ^ J; the lower
+// lane keeps the minimum when `asc`, else the maximum.
+template <int J>
+__device__ __forceinline__ u64 cmpx(u64 x, bool asc, int lane) {
+  const u64 y = xor_lane64<J>(x);
+  const bool low = (lane & J) == 0;
+  return (low == asc) ? umin64(x, y) : umax64(x, y);
+}
+
 // Bitonic sort of one key per lane, ascending by lane index.
 __device__ __forceinline__ u64 sort64(u64 x) {
   const int lane = lane_id();
-#pragma unroll
-  for (int k = 2; k <= WAVE; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      u64 y = shfl_xor64(x, j);
-      bool asc = (lane & k) == 0;
-      bool low = (lane & j) == 0;
-      x = (low == asc) ? umin64(x, y) : umax64(x, y);
-    }
-  }
+  x = cmpx<1>(x, (lane & 2) == 0, lane);
+  x = cmpx<2>(x, (lane & 4) == 0, lane);
+  x = cmpx<1>(x, (lane & 4) == 0, lane);
+  x = cmpx<4>(x, (lane & 8) == 0, lane);
+  x = cmpx<2>(x, (lane & 8) == 0, lane);
+  x = cmpx<1>(x, (lane & 8) == 0, lane);
+  x = cmpx<8>(x, (lane & 16) == 0, lane);
+  x = cmpx<4>(x, (lane & 16) == 0, lane);
+  x = cmpx<2>(x, (lane & 16) == 0, lane);
+  x = cmpx<1>(x, (lane & 16) == 0, lane);
+  x = cmpx<16>(x, (lane & 32) == 0, lane);
+  x = cmpx<8>(x, (lane & 32) == 0, lane);
+  x = cmpx<4>(x, (lane & 32) == 0, lane);
+  x = cmpx<2>(x, (lane & 32) == 0, lane);
+  x = cmpx<1>(x, (lane & 32) == 0, lane);
+  x = cmpx<32>(x, true, lane);
+  x = cmpx<16>(x, true, lane);
+  x = cmpx<8>(x, true, lane);
+  x = cmpx<4>(x, true, lane);
+  x = cmpx<2>(x, true, lane);
+  x = cmpx<1>(x, true, lane);
   return x;
 }
 
@@ -91,14 +135,18 @@ __device__ __forceinline__ void merge64(u64& a, u64& b) {
   const int lane = lane_id();
   u64 br = shfl64(b, WAVE - 1 - lane);
   u64 lo = umin64(a, br), hi = umax64(a, br);
-#pragma unroll
-  for (int j = 32; j > 0; j >>= 1) {
-    u64 y = shfl_xor64(lo, j);
-    u64 z = shfl_xor64(hi, j);
-    bool low = (lane & j) == 0;
-    lo = low ? umin64(lo, y) : umax64(lo, y);
-    hi = low ? umin64(hi, z) : umax64(hi, z);
-  }
+  lo = cmpx<32>(lo, true, lane);
+  hi = cmpx<32>(hi, true, lane);
+  lo = cmpx<16>(lo, true, lane);
+  hi = cmpx<16>(hi, true, lane);
+  lo = cmpx<8>(lo, true, lane);
+  hi = cmpx<8>(hi, true, lane);
+  lo = cmpx<4>(lo, true, lane);
+  hi = cmpx<4>(hi, true, lane);
+  lo = cmpx<2>(lo, true, lane);
+  hi = cmpx<2>(hi, true, lane);
+  lo = cmpx<1>(lo, true, lane);
+  hi = cmpx<1>(hi, true, lane);
   a = lo;
   b = hi;
 }

@@ -90,6 +90,16 @@ def test_parity_neighbour_budget(c1, m):
     assert_parity(ref, got, f"m={m}")
 
 
+@pytest.mark.parametrize("strategy", [hsig.AUTO, hsig.PRE])
+def test_parity_tiled_prescan(c1, strategy):
+    W, ix, g = c1
+    print(f"[case] tiled pre-filter scan strategy={strategy}", flush=True)
+    for k in (10, 64):
+        ref = ix.search(W.queries, W.l, W.h, k, 64, strategy=strategy)
+        got = gpu_search(g, W, k, 64, strategy=None if strategy == hsig.AUTO else strategy, tiled_prescan=True)
+        assert_parity(ref, got, f"tiled strategy={strategy} k={k}")
+
+
 def test_pre_filter_matches_fp64_exact(c1):
     W, ix, g = c1
     print("[case] pre vs FP64 exact", flush=True)
