@@ -178,6 +178,30 @@ int unify_search_ex(unify_index_t index, const float* queries, int64_t nq, const
  */
 int unify_last_timing(unify_index_t index, float* prescan_ms, float* search_ms, float* rerun_ms);
 
+/*
+ * Selects the store later searches on this index rank by (UNIFY_FP32, UNIFY_BF16,
+ * UNIFY_FP8E4M3), building the copy on the device the first time a precision is
+ * selected; copies stay resident until unify_free_index.  Searches already
+ * enqueued keep the store they were issued with.  Not to be called concurrently
+ * with other calls on the same index.
+ */
+int unify_set_precision(unify_index_t index, int precision);
+
+/*
+ * Copies a resident low-precision store of an index (one loaded or built with
+ * precision UNIFY_BF16 / UNIFY_FP8E4M3, or selected by unify_set_precision), for
+ * inspection or export, in internal-id order
+ * (attribute order):
+ *   codes   device, [n][d] uint16 BF16 patterns or uint8 E4M3 codes, or NULL
+ *   scales  device, [n] float32 FP8 scales (value = code value * scale), or NULL;
+ *           ignored for BF16
+ *   eps     device, [n] float32 upper bounds on the Euclidean norm of
+ *           (stored values - FP32 vector), or NULL
+ * Enqueued on hip_stream.  UNIFY_EINVAL when the index holds no store of that precision.
+ */
+int unify_copy_store(unify_index_t index, int precision, void* codes, float* scales, float* eps,
+                     void* hip_stream);
+
 /* Frees the index and its device memory.  NULL is accepted. */
 int unify_free_index(unify_index_t index);
 

@@ -19,7 +19,8 @@ _LIB = os.path.join(_HERE, "liboracle_hsig.so")
 
 AUTO, PRE, HYBRID, POST = 0, 1, 2, 3
 # per-query counters written by search(): see the C_* enum in hsig_ref.cpp
-NDIST, NEXP, NVISIT0, MAXCAND, MAXLIVE, STRAT, LO, HI, NCOUNT = range(9)
+NDIST, NEXP, NVISIT0, MAXCAND, MAXLIVE, STRAT, LO, HI, NRERANK, NCOUNT = range(10)
+FP32, BF16, FP8E4M3 = 0, 1, 2
 
 
 def compile_oracle(force: bool = False) -> str:
@@ -72,6 +73,12 @@ def lib():
         L.orc_build_chunk.argtypes = [P, I64, I32, I32, P, I32]
         L.orc_build_level.restype = I32
         L.orc_build_level.argtypes = [P, I64]
+        L.orc_bf16.argtypes = [P, I64, P]
+        L.orc_e4m3_encode.argtypes = [P, I64, P]
+        L.orc_e4m3_decode.argtypes = [P, I64, P]
+        L.orc_fp8_rows.argtypes = [P, I64, I32, P, P, P]
+        L.orc_set_store.restype = I32
+        L.orc_set_store.argtypes = [P, I32, I32]
         _lib = L
     return _lib
 
@@ -96,6 +103,44 @@ def level_of(u: float, M: int) -> int:
     """Level drawn for uniform variate u with mL = 1/ln(M) (Alg. 6)."""
     import math
     return int(lib().orc_level_of(float(u), 1.0 / math.log(M)))
+
+
+def bf16_bits(x: np.ndarray) -> np.ndarray:
+    """Bit patterns of the nearest bfloat16 values (ties to even)."""
+    x = np.ascontiguousarray(x, np.float32)
+    out = np.zeros(x.shape, np.uint16)
+    lib().orc_bf16(_p(x), x.size, _p(out))
+    return out
+
+
+def bf16_values(x: np.ndarray) -> np.ndarray:
+    return (bf16_bits(x).astype(np.uint32) << 16).view(np.float32)
+
+
+def e4m3_encode(y: np.ndarray) -> np.ndarray:
+    """Nearest OCP E4M3 codes (ties to even, magnitudes above 448 clamp)."""
+    y = np.ascontiguousarray(y, np.float32)
+    out = np.zeros(y.shape, np.uint8)
+    lib().orc_e4m3_encode(_p(y), y.size, _p(out))
+    return out
+
+
+def e4m3_decode(c: np.ndarray) -> np.ndarray:
+    c = np.ascontiguousarray(c, np.uint8)
+    out = np.zeros(c.shape, np.float32)
+    lib().orc_e4m3_decode(_p(c), c.size, _p(out))
+    return out
+
+
+def fp8_rows(X: np.ndarray):
+    """FP8 copy of each row: (codes [n, d] u8, scales [n] f32, values read back [n, d] f32)."""
+    X = np.ascontiguousarray(X, np.float32)
+    n, d = X.shape
+    codes = np.zeros((n, d), np.uint8)
+    sc = np.zeros(n, np.float32)
+    back = np.zeros((n, d), np.float32)
+    lib().orc_fp8_rows(_p(X), n, d, _p(codes), _p(sc), _p(back))
+    return codes, sc, back
 
 
 def prune(owner: np.ndarray, cands: np.ndarray, M: int) -> list[int]:
@@ -190,6 +235,12 @@ class Index:
 
     def build_level(self, v: int) -> int:
         return lib().orc_build_level(self._h, v)
+
+    def set_store(self, precision: int, rerank_mult: int = 4) -> None:
+        """Graph searches rank by FP32 (0), a BF16 copy (1) or an FP8 E4M3 copy (2) of the
+        vectors; with a copy, the best rerank_mult * k results are re-scored in FP32."""
+        if lib().orc_set_store(self._h, precision, rerank_mult) != 0:
+            raise ValueError(lib().orc_last_error().decode())
 
     def search(self, Q, l, h, k, ef, m=0, p=1, strategy=AUTO, tau_a=0.01, tau_b=0.5,
                counters=False, batch_form=False):

@@ -53,6 +53,11 @@
 //       that pass the stopping test, expand them as one batch whose admission test
 //       uses the threshold from before the batch.  For p = 1 this gives the same
 //       result as the sequential loop of Alg. 7; the tests check that.
+//   R14 low-precision stores (not in the paper): the graph searches may rank by
+//       distances to a BF16 copy (nearest, ties to even) or an FP8 E4M3 copy
+//       (scale max|x|/448 per vector, nearest code, ties to even, clamp at 448);
+//       the first 4k in-range results (k = results wanted) are then re-scored with
+//       the FP32 distance.  The pre-filter scan stays exact.
 //
 // Pins (tests/test_oracle_*.py): Definition 1 and Eq. 1 by hand examples and a
 // library routine; dist32 by exact integer cases, a crafted rounding case and
@@ -61,7 +66,9 @@
 // single-segment inclusiveness = 1 and > 80% on 1..8 segments (Sec. 6.4);
 // layer search with ef >= n = brute force over the reachable set; pre-filter =
 // exact k-NN; the skip-list walk = the attribute slice; the beam form at p = 1
-// = the sequential loop.  Parity unpinned: the exact set of global-edge marks
+// = the sequential loop; the BF16 and E4M3 roundings against a library's
+// conversions, every E4M3 code's value, and a low-precision search on vectors
+// both formats hold exactly = the FP32 search.  Parity unpinned: the exact set of global-edge marks
 // that GlobalEdgeMasking leaves (only its invariants are checked: at most M
 // marks per node and layer, each mark an existing chunk edge), and the exact
 // graph the full build produces on realistic inputs (no printed graph exists).
@@ -115,6 +122,95 @@ float dist32(const float* q, const float* x, int d) {
     for (int i = 0; i < 16; ++i) P[i] = T[i];
   }
   return P[0];
+}
+
+// ---------------------------------------------------------------------------
+// Low-precision copies of the vectors (an extension for bandwidth-bound
+// hardware; the paper computes plain Euclidean distances, Sec. 6.1).  A graph
+// search may rank objects by distances to rounded copies and then re-score its
+// best results with the exact FP32 distance.  Each rounding below is written as
+// "pick the nearest representable value" over the format's value set, which is
+// slow but follows the formats' definitions directly.
+// ---------------------------------------------------------------------------
+
+// Value of a non-negative FP32 bit pattern, with the pattern just past the
+// largest finite one read as 2^128 (the next step of the significand grid).
+double f32_bits_value(uint32_t b) {
+  if (b >= 0x7F800000u) return std::ldexp(1.0, 128);
+  float f;
+  std::memcpy(&f, &b, 4);
+  return (double)f;
+}
+
+// bfloat16 = the upper 16 bits of an FP32 pattern.  Nearest bfloat16 to x,
+// ties to the even significand; returns its bit pattern.
+uint16_t bf16_nearest(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if (std::isnan(x)) return (uint16_t)((u >> 16) | 0x0040u);
+  const uint32_t sign = u & 0x80000000u, mag = u & 0x7FFFFFFFu;
+  if (mag == 0x7F800000u) return (uint16_t)(u >> 16);  // infinities stay
+  const uint32_t lo = mag & 0xFFFF0000u, hi = lo + 0x10000u;  // the two bfloat16 neighbours of |x|
+  const double a = (double)std::fabs(x), dlo = a - f32_bits_value(lo), dhi = f32_bits_value(hi) - a;
+  uint32_t pick;
+  if (dlo < dhi) pick = lo;
+  else if (dhi < dlo) pick = hi;
+  else pick = ((lo >> 16) & 1u) ? hi : lo;  // tie: even significand
+  return (uint16_t)((sign | pick) >> 16);
+}
+
+float bf16_value(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// OCP 8-bit E4M3 ("fn" variant): sign, 4 exponent bits (bias 7), 3 significand
+// bits; exponent field 0 holds subnormals m * 2^-9; no infinities; S.1111.111
+// is NaN; the largest finite magnitude is 1.75 * 2^8 = 448.
+double e4m3_value(uint8_t c) {
+  const int e = (c >> 3) & 15, m = c & 7;
+  double mag;
+  if (e == 15 && m == 7) mag = std::numeric_limits<double>::quiet_NaN();
+  else if (e == 0) mag = std::ldexp((double)m, -9);
+  else mag = std::ldexp(1.0 + m / 8.0, e - 7);
+  return (c & 0x80) ? -mag : mag;
+}
+
+// Nearest E4M3 code to y, ties to the even significand; magnitudes beyond 448
+// clamp to 448 (reading: a per-vector scale keeps |y| <= 448 up to the rounding
+// of the division).  Codes 0x00..0x7E have increasing values.
+uint8_t e4m3_nearest(float y) {
+  if (std::isnan(y)) return 0x7F;
+  const uint8_t sign = std::signbit(y) ? 0x80 : 0x00;
+  const double a = std::fabs((double)y);
+  if (a >= 448.0) return sign | 0x7E;
+  int lo = 0, hi = 0x7E;  // largest code with value <= a
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (e4m3_value((uint8_t)mid) <= a) lo = mid;
+    else hi = mid - 1;
+  }
+  const double dlo = a - e4m3_value((uint8_t)lo), dhi = e4m3_value((uint8_t)(lo + 1)) - a;
+  int pick;
+  if (dlo < dhi) pick = lo;
+  else if (dhi < dlo) pick = lo + 1;
+  else pick = (lo & 1) ? lo + 1 : lo;  // tie: even significand (the code's last bit)
+  return sign | (uint8_t)pick;
+}
+
+// FP8 copy of one vector: scale s = max_t |x_t| / 448 (1 for a zero vector),
+// codes of x_t / s, read back as e4m3_value(code) * s in FP32.
+float fp8_row(const float* x, int d, uint8_t* codes, float* back) {
+  float mx = 0.0f;
+  for (int t = 0; t < d; ++t) mx = std::max(mx, std::fabs(x[t]));
+  const float s = mx > 0.0f ? mx / 448.0f : 1.0f;
+  for (int t = 0; t < d; ++t) {
+    codes[t] = e4m3_nearest(x[t] / s);
+    back[t] = (float)e4m3_value(codes[t]) * s;
+  }
+  return s;
 }
 
 // Level of an inserted object (Alg. 6, second step; reading R2).
@@ -407,8 +503,13 @@ struct View {
   std::vector<float> X;
   std::vector<int32_t> adj0, adjU;
   std::vector<uint32_t> gbits0, gbitsU;
+  // Store the graph searches rank by: empty = X itself; else the values of a
+  // BF16 or FP8 copy of X, whose best rerank * k results are re-scored on X.
+  std::vector<float> XS;
+  int rerank = 0;
 
   const float* vec(int v) const { return &X[(size_t)v * d]; }
+  const float* svec(int v) const { return XS.empty() ? vec(v) : &XS[(size_t)v * d]; }
   int mcap(int l) const { return l == 0 ? M0 : MU; }
   // Pointer to chunk j of v on layer l (mcap(l) entries, -1 padded).
   const int32_t* chunk(int v, int l, int j) const {
@@ -684,7 +785,7 @@ int read_view(const char* path, View& V) {
 // ---------------------------------------------------------------------------
 
 enum { ST_AUTO = 0, ST_PRE = 1, ST_HYBRID = 2, ST_POST = 3 };
-enum { C_NDIST = 0, C_NEXP, C_NVISIT0, C_MAXCAND, C_MAXLIVE, C_STRAT, C_LO, C_HI, C_NCOUNT };
+enum { C_NDIST = 0, C_NEXP, C_NVISIT0, C_MAXCAND, C_MAXLIVE, C_STRAT, C_LO, C_HI, C_NRERANK, C_NCOUNT };
 
 struct Query {
   const View* V;
@@ -695,10 +796,13 @@ struct Query {
   int c = 0;               // entries per active chunk
   int64_t* cnt;
   bool in_range(int v) const { return V->attr[v] >= l && V->attr[v] <= h; }
+  // distance in the store the graph searches use
   FI key(int v) {
     ++cnt[C_NDIST];
-    return FI(dist32(q, V->vec(v), V->d), v);
+    return FI(dist32(q, V->svec(v), V->d), v);
   }
+  // exact FP32 distance
+  FI xkey(int v) const { return FI(dist32(q, V->vec(v), V->d), v); }
 };
 
 // Neighbours of o on layer l: the first c entries of each active chunk (hybrid),
@@ -860,7 +964,8 @@ struct Searcher {
   // first object >= l), exact top-k by (dist32, id).
   std::vector<FI> pre(Query& Q, int k) {
     std::vector<FI> all;
-    for (int64_t v = Q.lo; v < Q.hi; ++v) all.push_back(Q.key((int)v));
+    for (int64_t v = Q.lo; v < Q.hi; ++v) all.push_back(Q.xkey((int)v));
+    Q.cnt[C_NDIST] += Q.hi - Q.lo;
     std::sort(all.begin(), all.end());
     if ((int)all.size() > k) all.resize(k);
     return all;
@@ -884,8 +989,26 @@ struct Searcher {
     for (int l = top; l >= 1; --l) ep = layer_seq(Q, true, false, ep, l, 1, stamp, cur)[0].second;
     std::vector<FI> ann = (p == 1 && !batch_form) ? layer_seq(Q, true, true, ep, 0, ef, stamp, cur)
                                                   : layer_beam(Q, true, true, ep, ef, p, stamp, cur);
-    if ((int)ann.size() > k) ann.resize(k);
-    return ann;
+    return finish(Q, ann, k);
+  }
+
+  // The k results of a graph search from its ann list (ascending keys): the
+  // in-range entries in order.  With a low-precision store, the first
+  // rerank * k in-range entries are re-scored with the exact FP32 distance
+  // and re-sorted by (distance, id) before the first k are kept.
+  std::vector<FI> finish(Query& Q, const std::vector<FI>& ann, int k) const {
+    const bool low = !V->XS.empty();
+    const size_t R = low ? (size_t)V->rerank * k : (size_t)k;
+    std::vector<FI> out;
+    for (const FI& e : ann)
+      if (Q.in_range(e.second) && out.size() < R) out.push_back(e);
+    if (low) {
+      for (FI& e : out) e = Q.xkey(e.second);
+      Q.cnt[C_NRERANK] += (int64_t)out.size();
+      std::sort(out.begin(), out.end());
+    }
+    if (out.size() > (size_t)k) out.resize(k);
+    return out;
   }
 
   // Strategy B: Alg. 2 over the marked (global) edges, then the range filter.
@@ -895,10 +1018,7 @@ struct Searcher {
     for (int l = V->L; l >= 1; --l) ep = layer_seq(Q, false, false, ep, l, 1, stamp, cur)[0].second;
     std::vector<FI> ann = (p == 1 && !batch_form) ? layer_seq(Q, false, false, ep, 0, ef, stamp, cur)
                                                   : layer_beam(Q, false, false, ep, ef, p, stamp, cur);
-    std::vector<FI> out;
-    for (const FI& e : ann)
-      if (Q.in_range(e.second) && (int)out.size() < k) out.push_back(e);
-    return out;
+    return finish(Q, ann, k);
   }
 };
 
@@ -921,6 +1041,21 @@ extern "C" {
 const char* orc_last_error() { return g_err.c_str(); }
 
 float orc_dist32(const float* q, const float* x, int d) { return dist32(q, x, d); }
+
+void orc_bf16(const float* x, int64_t n, uint16_t* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = bf16_nearest(x[i]);
+}
+void orc_e4m3_encode(const float* y, int64_t n, uint8_t* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = e4m3_nearest(y[i]);
+}
+void orc_e4m3_decode(const uint8_t* c, int64_t n, float* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = (float)e4m3_value(c[i]);
+}
+// FP8 copies of n rows of X [n][d]: codes [n][d], scales [n], values read back [n][d].
+void orc_fp8_rows(const float* X, int64_t n, int d, uint8_t* codes, float* scales, float* back) {
+  for (int64_t v = 0; v < n; ++v)
+    scales[v] = fp8_row(X + v * d, d, codes + v * d, back + v * d);
+}
 int orc_level_of(double u, double mL) { return draw_level(u, mL); }
 double orc_dist64(const float* q, const float* x, int d) { return dist64(q, x, d); }
 
@@ -1123,6 +1258,31 @@ int orc_search(void* h, const float* Q, int64_t nq, const int64_t* L, const int6
         out_dist[i * k + t] = std::numeric_limits<float>::infinity();
       }
     }
+  }
+  return 0;
+}
+
+// Selects the store the graph searches rank by: 0 = the FP32 vectors, 1 = a
+// BF16 copy, 2 = an FP8 E4M3 copy with one scale per vector; rerank_mult >= 1
+// sets how many results (rerank_mult * k) are re-scored in FP32.
+int orc_set_store(void* h, int precision, int rerank_mult) {
+  OrcIndex* ix = (OrcIndex*)h;
+  View& V = ix->V;
+  if (precision < 0 || precision > 2 || (precision > 0 && rerank_mult < 1)) {
+    g_err = "orc_set_store: bad arguments";
+    return -22;
+  }
+  V.rerank = rerank_mult;
+  if (precision == 0) {
+    std::vector<float>().swap(V.XS);
+    return 0;
+  }
+  V.XS.resize(V.X.size());
+  if (precision == 1) {
+    for (size_t i = 0; i < V.X.size(); ++i) V.XS[i] = bf16_value(bf16_nearest(V.X[i]));
+  } else {
+    std::vector<uint8_t> codes(V.d);
+    for (int64_t v = 0; v < V.n; ++v) fp8_row(&V.X[(size_t)v * V.d], V.d, codes.data(), &V.XS[(size_t)v * V.d]);
   }
   return 0;
 }

@@ -54,6 +54,8 @@ SIGNATURES = {
     "unify_search": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P]),
     "unify_search_ex": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "unify_last_timing": (_I32, [_P, _P, _P, _P]),
+    "unify_copy_store": (_I32, [_P, _I32, _P, _P, _P, _P]),
+    "unify_set_precision": (_I32, [_P, _I32]),
     "unify_free_index": (_I32, [_P]),
     "unify_last_error": (_S, []),
 }
@@ -104,6 +106,7 @@ class Index:
         _check(load_library().unify_index_info(self._h, C.byref(n), C.byref(d), C.byref(S), C.byref(M),
                                                C.byref(L)))
         self.n, self.d, self.S, self.M, self.levels = n.value, d.value, S.value, M.value, L.value
+        self.precision = FP32
 
     @staticmethod
     def _prec(precision) -> int:
@@ -112,8 +115,11 @@ class Index:
     @classmethod
     def load(cls, path: str, device: int = 0, precision="fp32") -> "Index":
         h = C.c_void_p()
-        _check(load_library().unify_load_index(path.encode(), device, cls._prec(precision), C.byref(h)))
-        return cls(h.value, device)
+        prec = cls._prec(precision)
+        _check(load_library().unify_load_index(path.encode(), device, prec, C.byref(h)))
+        ix = cls(h.value, device)
+        ix.precision = prec
+        return ix
 
     @classmethod
     def build(cls, vectors: np.ndarray, attr: np.ndarray, level_u: np.ndarray, S: int, M: int,
@@ -125,7 +131,33 @@ class Index:
         _check(load_library().unify_build_index(X.ctypes.data, a.ctypes.data, u.ctypes.data, X.shape[0],
                                                 X.shape[1], S, M, ef_cons, device, cls._prec(precision),
                                                 C.byref(h)))
-        return cls(h.value, device)
+        ix = cls(h.value, device)
+        ix.precision = cls._prec(precision)
+        return ix
+
+    def set_precision(self, precision) -> None:
+        """Store later searches rank by ("fp32", "bf16", "fp8"); builds the copy on first use."""
+        prec = self._prec(precision)
+        _check(load_library().unify_set_precision(self._h, prec))
+        self.precision = prec
+
+    def copy_store(self, precision=None, stream=None):
+        """A resident BF16 / FP8 copy of the vectors in internal-id order, as device tensors:
+        (codes [n, d] int16 or uint8, scales [n] float32 or None, eps [n] float32)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        prec = self.precision if precision is None else self._prec(precision)
+        if prec == BF16:
+            codes, sc = torch.empty((self.n, self.d), dtype=torch.int16, device=dev), None
+        elif prec == FP8E4M3:
+            codes = torch.empty((self.n, self.d), dtype=torch.uint8, device=dev)
+            sc = torch.empty(self.n, dtype=torch.float32, device=dev)
+        else:
+            raise UnifyError(-22, "the index has no low-precision store")
+        eps = torch.empty(self.n, dtype=torch.float32, device=dev)
+        st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        _check(load_library().unify_copy_store(self._h, prec, _ptr(codes), _ptr(sc), _ptr(eps), st))
+        return codes, sc, eps
 
     def save(self, path: str) -> None:
         _check(load_library().unify_save_index(self._h, path.encode()))

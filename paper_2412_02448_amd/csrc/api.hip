@@ -21,43 +21,6 @@ thread_local std::string g_error;
 
 void set_error(const std::string& msg) { g_error = msg; }
 
-// Round-to-nearest-even FP32 -> BF16.
-uint16_t f32_to_bf16(float x) {
-  uint32_t u;
-  std::memcpy(&u, &x, 4);
-  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
-  uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(r >> 16);
-}
-
-// Round-to-nearest-even FP32 -> OCP FP8 E4M3 (saturating to +-448; no infinities).
-uint8_t f32_to_e4m3(float x) {
-  uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
-  float a = std::fabs(x);
-  if (std::isnan(x)) return 0x7F;
-  if (a >= 448.0f) return sign | 0x7E;
-  // candidates are k * 2^(e-3) for the binade of a; smallest normal 2^-6
-  int e;
-  std::frexp(a, &e);        // a = f * 2^e, f in [0.5, 1)
-  int ub = e - 1;           // unbiased exponent of a
-  if (ub < -6) ub = -6;     // subnormal spacing 2^-9
-  const float q = std::ldexp(1.0f, ub - 3);   // spacing of representable values
-  float m = a / q;          // exact: division by a power of two
-  float r = std::nearbyint(m);  // ties to even (default rounding mode)
-  float v = r * q;
-  if (v >= 448.0f) return sign | 0x7E;
-  if (v == 0.0f) return sign;
-  int ve;
-  float vf = std::frexp(v, &ve);
-  int vub = ve - 1;
-  if (vub < -6) {  // subnormal: value = mant * 2^-9
-    int mant = (int)std::lround(v / std::ldexp(1.0f, -9));
-    return sign | (uint8_t)mant;
-  }
-  int mant = (int)std::lround((vf * 2.0f - 1.0f) * 8.0f);
-  return sign | (uint8_t)(((vub + 7) << 3) | mant);
-}
-
 namespace {
 
 template <class T>
@@ -150,24 +113,7 @@ int make_resident(HostIndex&& H, int device, int precision, unify_index_t* out) 
   up(g0, &dv.glist0);
   up(H.adjU, &dv.adjU);
   up(gU, &dv.glistU);
-  if (rc == UNIFY_OK && precision == UNIFY_BF16) {
-    std::vector<uint16_t> b(H.vec.size());
-    for (size_t i = 0; i < b.size(); ++i) b[i] = f32_to_bf16(H.vec[i]);
-    up(b, &dv.vec_bf16);
-  }
-  if (rc == UNIFY_OK && precision == UNIFY_FP8E4M3) {
-    std::vector<uint8_t> c(H.vec.size());
-    std::vector<float> sc(H.n);
-    for (int64_t v = 0; v < H.n; ++v) {
-      float mx = 0.f;
-      for (int t = 0; t < H.d; ++t) mx = std::max(mx, std::fabs(H.vec[(size_t)v * H.d + t]));
-      const float s = mx > 0.f ? mx / 448.0f : 1.0f;
-      sc[v] = s;
-      for (int t = 0; t < H.d; ++t) c[(size_t)v * H.d + t] = f32_to_e4m3(H.vec[(size_t)v * H.d + t] / s);
-    }
-    up(c, &dv.vec_fp8);
-    up(sc, &dv.vec_scale);
-  }
+  if (rc == UNIFY_OK) rc = quantize_store(ix, precision);
   if (rc != UNIFY_OK) {
     for (void* p : ix->allocs) (void)hipFree(p);
     delete ix;
@@ -290,6 +236,42 @@ int unify_index_info(unify_index_t ix, int64_t* n, int32_t* d, int32_t* S, int32
   if (M) *M = ix->dv.M0;
   if (levels) *levels = ix->dv.L + 1;
   return UNIFY_OK;
+}
+
+int unify_copy_store(unify_index_t ix, int precision, void* codes, float* scales, float* eps, void* hip_stream) {
+  if (!ix || precision < UNIFY_BF16 || precision > UNIFY_FP8E4M3 || !ix->eps_of[precision]) {
+    set_error("unify_copy_store: the index holds no store of that precision");
+    return UNIFY_EINVAL;
+  }
+  const DevIndex& dv = ix->dv;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t cells = (size_t)dv.n * dv.d;
+  bool ok = hipSetDevice(ix->device) == hipSuccess;
+  if (ok && codes) {
+    const void* src = precision == UNIFY_BF16 ? (const void*)dv.vec_bf16 : (const void*)dv.vec_fp8;
+    ok = hipMemcpyAsync(codes, src, cells * (precision == UNIFY_BF16 ? 2 : 1), hipMemcpyDeviceToDevice, st) ==
+         hipSuccess;
+  }
+  if (ok && scales && precision == UNIFY_FP8E4M3)
+    ok = hipMemcpyAsync(scales, dv.vec_scale, sizeof(float) * dv.n, hipMemcpyDeviceToDevice, st) == hipSuccess;
+  if (ok && eps) ok = hipMemcpyAsync(eps, dv.vec_eps, sizeof(float) * dv.n, hipMemcpyDeviceToDevice, st) == hipSuccess;
+  if (!ok) {
+    set_error("unify_copy_store: copy failed");
+    return UNIFY_EDEVICE;
+  }
+  return UNIFY_OK;
+}
+
+int unify_set_precision(unify_index_t ix, int precision) {
+  if (!ix || precision < UNIFY_FP32 || precision > UNIFY_FP8E4M3) {
+    set_error("unify_set_precision: bad arguments");
+    return UNIFY_EINVAL;
+  }
+  if (hipSetDevice(ix->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return UNIFY_EDEVICE;
+  }
+  return quantize_store(ix, precision);
 }
 
 int unify_search(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,

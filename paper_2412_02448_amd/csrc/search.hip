@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "lowp.h"
 #include "unify_internal.h"
 #include "wave.h"
 
@@ -39,6 +40,7 @@ struct SearchArgs {
   int32_t k, ef, m, p, rerank;
   int32_t ccap, hcap, ef_blocks, nbr_cap;
   int32_t pass;  // 0: first pass, 1: larger-capacity re-run
+  float bA, bB, bC, bD;  // constants of root_bounds
   int64_t* out_ids;
   float* out_dist;
   int32_t* out_stats;
@@ -177,42 +179,98 @@ __global__ void k_worklist(const QPlan* __restrict__ plan, int64_t nq, int64_t n
 // ---------------------------------------------------------------------------
 // Vector loads: 4 consecutive elements of row v, group g, as FP32.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
-
-// OCP FP8 E4M3 (no infinities; 0x7F/0xFF are NaN): value = (-1)^s 2^(e-7) (1 + m/8),
-// subnormals 2^-6 m/8.
-__device__ __forceinline__ float e4m3_to_f32(uint32_t c) {
-  const uint32_t s = (c >> 7) & 1u, e = (c >> 3) & 15u, m = c & 7u;
-  float mag;
-  if (e == 0) mag = (float)m * 0.001953125f;  // m * 2^-9
-  else if (e == 15 && m == 7) mag = __builtin_nanf("");
-  else mag = __uint_as_float(((e + 120u) << 23) | (m << 20));
-  return s ? -mag : mag;
-}
-
+// Raw rows of each store: the words a lane loads for one 4-element group, kept
+// packed in registers until the distance is computed, so a wave can hold more
+// rows in flight the narrower the store is.
 template <int PREC>
-__device__ __forceinline__ float4 load4(const DevIndex& ix, int64_t v, int g) {
-  const int64_t off = v * ix.d + 4 * g;
-  if constexpr (PREC == UNIFY_FP32) {
-    return *reinterpret_cast<const float4*>(ix.vec + off);
-  } else if constexpr (PREC == UNIFY_BF16) {
-    uint2 w = *reinterpret_cast<const uint2*>(ix.vec_bf16 + off);
-    return make_float4(bf16_to_f32(w.x & 0xFFFFu), bf16_to_f32(w.x >> 16), bf16_to_f32(w.y & 0xFFFFu),
-                       bf16_to_f32(w.y >> 16));
-  } else {
-    uint32_t w = *reinterpret_cast<const uint32_t*>(ix.vec_fp8 + off);
-    const float sc = ix.vec_scale[v];
-    return make_float4(e4m3_to_f32(w & 0xFFu) * sc, e4m3_to_f32((w >> 8) & 0xFFu) * sc,
-                       e4m3_to_f32((w >> 16) & 0xFFu) * sc, e4m3_to_f32(w >> 24) * sc);
-  }
-}
+struct Store;
 
-// Keys of cnt vectors of the store selected by PREC (see eval_keys_generic).
-template <int NG, int PREC, class IdOf>
+template <>
+struct Store<UNIFY_FP32> {
+  typedef float4 Raw;
+  static constexpr int WORDS = 4;
+  __device__ static Raw load(const DevIndex& ix, int64_t v, int g) {
+    return *reinterpret_cast<const float4*>(ix.vec + v * ix.d + 4 * g);
+  }
+  __device__ static float scale(const DevIndex&, int64_t) { return 1.0f; }
+  __device__ static float4 decode(Raw r, float) { return r; }
+};
+
+template <>
+struct Store<UNIFY_BF16> {
+  typedef uint2 Raw;
+  static constexpr int WORDS = 2;
+  __device__ static Raw load(const DevIndex& ix, int64_t v, int g) {
+    return *reinterpret_cast<const uint2*>(ix.vec_bf16 + v * ix.d + 4 * g);
+  }
+  __device__ static float scale(const DevIndex&, int64_t) { return 1.0f; }
+  __device__ static float4 decode(Raw w, float) {
+    return make_float4(bf16_to_f32(w.x & 0xFFFFu), __uint_as_float(w.x & 0xFFFF0000u), bf16_to_f32(w.y & 0xFFFFu),
+                       __uint_as_float(w.y & 0xFFFF0000u));
+  }
+};
+
+template <>
+struct Store<UNIFY_FP8E4M3> {
+  typedef uint32_t Raw;
+  static constexpr int WORDS = 1;
+  __device__ static Raw load(const DevIndex& ix, int64_t v, int g) {
+    return *reinterpret_cast<const uint32_t*>(ix.vec_fp8 + v * ix.d + 4 * g);
+  }
+  __device__ static float scale(const DevIndex& ix, int64_t v) { return ix.vec_scale[v]; }
+  // gfx950's packed conversion decodes OCP E4M3 exactly (the same values as
+  // e4m3_to_f32); each value is then scaled as fp8_value does.
+  __device__ static float4 decode(Raw w, float sc) {
+    const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+    const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+    return make_float4(__builtin_fmaf(lo[0], sc, 0.0f), __builtin_fmaf(lo[1], sc, 0.0f),
+                       __builtin_fmaf(hi[0], sc, 0.0f), __builtin_fmaf(hi[1], sc, 0.0f));
+  }
+};
+
+// Keys (canonical FP32 distance, id) of cnt vectors of the store PREC: four
+// vectors per round (16 lanes each, lane s takes groups s, s + 16, ...), RB
+// rounds of raw loads in flight; the i-th vector is id_of(i) and its key lands
+// in keys[i] (LDS).  The hot evaluations use RB = 16 / NG rounds (at most 8:
+// 32 rows in flight at d <= 128); SHALLOW (2 rounds at most) serves the FP32
+// re-scores inside low-precision kernels, whose registers would otherwise
+// add to the hot path's and spill.
+template <int NG, int PREC, bool SHALLOW = false, class IdOf>
 __device__ __forceinline__ void eval_keys(const DevIndex& ix, const float4 (&qv)[NG], int cnt, IdOf id_of,
                                           u64* keys) {
-  eval_keys_generic<NG>(ix.d >> 2, qv, cnt, id_of, [&](int64_t v, int g) { return load4<PREC>(ix, v, g); },
-                        keys);
+  typedef Store<PREC> St;
+  constexpr int RB0 = (SHALLOW ? 2 : 16) / NG;
+  constexpr int RB = RB0 < 1 ? 1 : (RB0 > 8 ? 8 : RB0);
+  const int G = ix.d >> 2;
+  const int lane = lane_id();
+  const int s = lane & 15, g4 = lane >> 4;
+  for (int base = 0; base < cnt; base += 4 * RB) {
+    typename St::Raw x[RB][NG];
+    float sc[RB];
+    int32_t vid[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int idx = base + 4 * r + g4;
+      vid[r] = idx < cnt ? id_of(idx) : -1;
+      sc[r] = vid[r] >= 0 ? St::scale(ix, vid[r]) : 1.0f;
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+        const int g = s + 16 * i;
+        x[r][i] = (vid[r] >= 0 && g < G) ? St::load(ix, (int64_t)vid[r], g) : typename St::Raw{};
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+        if (s + 16 * i < G) acc = fma_sq4(St::decode(x[r][i], sc[r]), qv[i], acc);
+      }
+      acc = group_reduce16(acc);
+      const int idx = base + 4 * r + g4;
+      if (s == 0 && idx < cnt) keys[idx] = make_key(acc, vid[r]);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -274,7 +332,7 @@ __device__ __forceinline__ void wave_fence() {
 }
 
 struct Counters {
-  int32_t ndist = 0, nexp = 0, nvisit0 = 0, nadj = 0;
+  int32_t ndist = 0, nexp = 0, nrerank = 0, nadj = 0;
 };
 
 // One layer of the search (Alg. 1 / Alg. 7 with beam width p).  On return, the
@@ -299,7 +357,6 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
   bool tagged = false;
   bool overflow = false;
   if (lane == 0) L.hash[(cache_set(L.hash, setbits, ep) - L.hash)] = (uint32_t)ep;
-  int hcount = 1;
   // cand = {ep}; ann = {ep} unless filtered out
   if (lane == 0) L.cand[0] = ep_key;
   int cl = 1;
@@ -391,7 +448,6 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
         nn += __popcll(nm);
       }
     }
-    hcount += nn;
     if (nn == 0) continue;
     __syncthreads();
     cnt.ndist += nn;
@@ -434,12 +490,12 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
     }
     if (overflow) break;
   }
-  if (layer == 0) cnt.nvisit0 = hcount;
   return !__any(overflow);
 }
 
-// Strategy A: exact top-k over the id slice [lo, hi).
-template <int NG>
+// Strategy A: exact top-k over the id slice [lo, hi) (FP32 store; PREC names
+// the kernel's ranking store, for which this is the fallback when it is not FP32).
+template <int NG, int PREC>
 __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
                          int& al, Counters& cnt) {
   const int lane = lane_id();
@@ -449,7 +505,7 @@ __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[N
   __syncthreads();
   for (int base = P.lo; base < P.hi; base += WAVE) {
     const int cntv = min(WAVE, P.hi - base);
-    eval_keys<NG, UNIFY_FP32>(A.ix, qv, cntv, [&](int i) { return base + i; }, L.bkeys);
+    eval_keys<NG, UNIFY_FP32, (PREC != UNIFY_FP32)>(A.ix, qv, cntv, [&](int i) { return base + i; }, L.bkeys);
     __syncthreads();
     const u64 key = lane < cntv ? L.bkeys[lane] : KEY_MAX;
     const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
@@ -457,6 +513,142 @@ __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[N
     __syncthreads();
   }
   cnt.ndist += P.hi - P.lo;
+}
+
+// Bounds on sqrt(s), s = the canonical FP32 distance of an object, from st =
+// the same distance to its low-precision copy c, with ||c - x|| <= eps.  Both
+// distances carry a relative error of at most g (all terms are non-negative),
+// so with rho = ||x - q|| and rho~ = ||c - q||:
+//   sqrt(s) in rho [sqrt(1-g), sqrt(1+g)],  rho in [rho~ - eps, rho~ + eps],
+//   rho~ in sqrt(st) [1/sqrt(1+g), 1/sqrt(1-g)],
+// hence sqrt(s) >= sqrt(st) A - eps B and sqrt(s) <= sqrt(st) C + eps D with
+// A = sqrt((1-g)/(1+g)), B = sqrt(1-g), C = sqrt((1+g)/(1-g)), D = sqrt(1+g).
+// The host widens A, B, C, D by 2^-20 relative, far more than the few FP32
+// roundings below (each <= 2^-24; sqrtf within 2^-23), and 1e-18 covers
+// underflow; a negative lower bound is clamped to 0.
+__device__ __forceinline__ void root_bounds(float st, float eps, const SearchArgs& A, float& lb, float& ub) {
+  const float r = __builtin_sqrtf(st);
+  const float l = __builtin_fmaf(r, A.bA, -__builtin_fmaf(eps, A.bB, 1e-18f));
+  lb = l > 0.0f ? l : 0.0f;  // never -0: keys order non-negative floats by their bits
+  ub = __builtin_fmaf(r, A.bC, __builtin_fmaf(eps, A.bD, 1e-18f));
+}
+
+// Strategy A over a BF16 / FP8 copy, with the exact FP32 result.  Every object
+// of the slice gets bounds [lb, ub] on the root of its FP32 distance from the
+// copy's distance.  The k smallest ub are kept (ann); any object in the exact
+// top k has lb <= sqrt(s) <= sqrt(k-th smallest s) <= (k-th smallest ub), so
+// the objects whose lb is at most the current k-th smallest ub contain the
+// exact top k.  They are appended to cand (unsorted; when it fills, entries
+// above the current threshold are dropped), and the survivors of the final
+// threshold are re-scored in FP32.  Returns false when cand cannot hold the
+// qualifying objects (the caller then runs the FP32 scan).
+template <int NG, int PREC>
+__device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P, int& al,
+                              Counters& cnt) {
+  const DevIndex& ix = A.ix;
+  const int lane = lane_id();
+  const int k = A.k;
+  int ul = 0, cl = 0;
+  for (int blk = 0; blk * WAVE < k; ++blk) L.ann[blk * WAVE + lane] = KEY_MAX;
+  __syncthreads();
+  for (int base = P.lo; base < P.hi; base += WAVE) {
+    const int cntv = min(WAVE, P.hi - base);
+    eval_keys<NG, PREC>(ix, qv, cntv, [&](int i) { return base + i; }, L.bkeys);
+    __syncthreads();
+    float lb = 0.f, ub = 0.f;
+    const bool have = lane < cntv;
+    if (have) root_bounds(key_dist(L.bkeys[lane]), ix.vec_eps[base + lane], A, lb, ub);
+    const int32_t v = base + lane;
+    const u64 uk = have ? make_key(ub, v) : KEY_MAX;
+    const u64 TU0 = ul == k ? L.ann[k - 1] : KEY_MAX;
+    list_insert(L.ann, ul, k, uk < TU0 ? uk : KEY_MAX);
+    __syncthreads();
+    const float TU = ul == k ? key_dist(L.ann[k - 1]) : __builtin_inff();
+    const bool adm = have && lb <= TU;
+    const u64 am = ballot(adm);
+    const int add = __popcll(am);
+    if (cl + add > A.ccap) {
+      // drop the entries the threshold has passed since they were appended
+      int wpos = 0;
+      for (int b0 = 0; b0 < cl; b0 += WAVE) {
+        const int t = b0 + lane;
+        const u64 e = t < cl ? L.cand[t] : KEY_MAX;
+        const bool keep = t < cl && key_dist(e) <= TU;
+        const u64 km = ballot(keep);
+        __syncthreads();  // this block is read before any lane overwrites it
+        if (keep) L.cand[wpos + rank_in(km)] = e;
+        wpos += __popcll(km);
+      }
+      cl = wpos;
+      __syncthreads();
+      if (cl + add > A.ccap) return false;
+    }
+    if (adm) L.cand[cl + rank_in(am)] = make_key(lb, v);
+    cl += add;
+    __syncthreads();
+  }
+  cnt.ndist += P.hi - P.lo;
+  const float TU = ul == k ? key_dist(L.ann[k - 1]) : __builtin_inff();
+  // re-score the qualifying entries of cand in FP32
+  al = 0;
+  for (int blk = 0; blk * WAVE < k; ++blk) L.ann[blk * WAVE + lane] = KEY_MAX;
+  __syncthreads();
+  for (int base = 0; base < cl; base += WAVE) {
+    const int t = base + lane;
+    const bool use = t < cl && key_dist(L.cand[t]) <= TU;
+    const u64 um = ballot(use);
+    const int nb = __popcll(um);
+    if (nb == 0) continue;
+    const int32_t v = use ? key_id(L.cand[t]) : 0;
+    __syncthreads();
+    if (use) L.bkeys[rank_in(um)] = (uint32_t)v;
+    __syncthreads();
+    eval_keys<NG, UNIFY_FP32, true>(ix, qv, nb, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
+    __syncthreads();
+    const u64 key = lane < nb ? L.bkeys[lane] : KEY_MAX;
+    const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
+    list_insert(L.ann, al, k, key < T ? key : KEY_MAX);
+    __syncthreads();
+    cnt.nrerank += nb;
+  }
+  return true;
+}
+
+// Graph search results over a BF16 / FP8 copy: the first rerank * k in-range
+// entries of ann (ascending by the copy's distance) are re-scored with the FP32
+// distance into a sorted list of k in L.cand.  Returns that list's length.
+template <int NG>
+__device__ int rerank_graph(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P, int al,
+                            bool post, Counters& cnt) {
+  const int lane = lane_id();
+  const int k = A.k;
+  const int R = A.rerank * k;
+  int rl = 0, taken = 0;
+  for (int blk = 0; blk * WAVE < k; ++blk) L.cand[blk * WAVE + lane] = KEY_MAX;
+  __syncthreads();
+  for (int base = 0; base < al && taken < R; base += WAVE) {
+    const int t = base + lane;
+    const u64 key = t < al ? L.ann[t] : KEY_MAX;
+    const int32_t id = key_id(key);
+    bool keep = key != KEY_MAX && (!post || (id >= P.lo && id < P.hi));
+    const u64 km = ballot(keep);
+    keep = keep && taken + rank_in(km) < R;
+    const u64 um = ballot(keep);
+    const int nb = __popcll(um);
+    if (nb == 0) continue;
+    __syncthreads();
+    if (keep) L.bkeys[rank_in(um)] = (uint32_t)id;
+    __syncthreads();
+    eval_keys<NG, UNIFY_FP32, true>(A.ix, qv, nb, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
+    __syncthreads();
+    const u64 nk = lane < nb ? L.bkeys[lane] : KEY_MAX;
+    const u64 T = rl == k ? L.cand[k - 1] : KEY_MAX;
+    list_insert(L.cand, rl, k, nk < T ? nk : KEY_MAX);
+    __syncthreads();
+    taken += nb;
+    cnt.nrerank += nb;
+  }
+  return rl;
 }
 
 __device__ __forceinline__ bool ne_missing(int top) { return top < 0; }
@@ -482,7 +674,9 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, uint32_t
   const bool hybrid = P.strat == UNIFY_HYBRID;
   int kout = A.k;
   if (P.strat == UNIFY_PRE) {
-    pre_scan<NG>(A, L, qv, P, al, cnt);
+    // a low-precision scan that cannot prove its result re-runs in FP32 (pass 1)
+    if (PREC == UNIFY_FP32 || A.pass == 1) pre_scan<NG, PREC>(A, L, qv, P, al, cnt);
+    else ok = pre_scan_lowp<NG, PREC>(A, L, qv, P, al, cnt);
   } else {
     const int Sa = P.b - P.a + 1;
     const int c = (A.m + Sa - 1) / Sa;
@@ -547,13 +741,21 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, uint32_t
       return;
     }
   }
-  // outputs: hybrid / pre take the first k; post keeps in-range entries in order
+  // outputs: hybrid / pre take the first k; post keeps in-range entries in order.
+  // Graph results over a low-precision copy come re-scored and filtered.
+  const u64* res = L.ann;
+  bool post_filter = P.strat == UNIFY_POST;
+  if (PREC != UNIFY_FP32 && P.strat != UNIFY_PRE && ok && al > 0) {
+    al = rerank_graph<NG>(A, L, qv, P, al, post_filter, cnt);
+    res = L.cand;
+    post_filter = false;
+  }
   int written = 0;
   for (int base = 0; base < al && written < kout; base += WAVE) {
     const int t = base + lane;
-    const u64 key = t < al ? L.ann[t] : KEY_MAX;
+    const u64 key = t < al ? res[t] : KEY_MAX;
     const int32_t id = key_id(key);
-    const bool keep = key != KEY_MAX && (P.strat != UNIFY_POST || (id >= P.lo && id < P.hi));
+    const bool keep = key != KEY_MAX && (!post_filter || (id >= P.lo && id < P.hi));
     const u64 km = ballot(keep);
     const int pos = written + rank_in(km);
     if (keep && pos < kout) {
@@ -572,7 +774,7 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, uint32_t
     int32_t* st = A.out_stats + (int64_t)q * 8;
     st[0] = cnt.ndist;
     st[1] = cnt.nexp;
-    st[2] = cnt.nvisit0;
+    st[2] = cnt.nrerank;
     st[3] = ok ? A.pass : 2;
     st[4] = cnt.nadj;
     st[5] = P.strat;
@@ -700,14 +902,18 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
   const int p = P.beam_p > 0 ? P.beam_p : 1;
   const double ta = P.tau_a_frac > 0 ? P.tau_a_frac : 0.01;
   const double tb = P.tau_b_frac > 0 ? P.tau_b_frac : 0.5;
-  const int ccap = P.cand_cap > 0 ? P.cand_cap : 512;
+  int ccap = P.cand_cap > 0 ? P.cand_cap : 512;
   const int hcap = P.visit_cap > 0 ? P.visit_cap : 1024;
+  const int rerank = P.rerank_mult > 0 ? P.rerank_mult : 4;
   if (m > dv.S * dv.M0 || p > 8 || ta > 1.0 || tb > 1.0 || ccap < 64 || ccap > 4096 || (ccap & (ccap - 1)) ||
-      hcap < 256 || hcap > 16384 || (hcap & (hcap - 1))) {
+      hcap < 256 || hcap > 16384 || (hcap & (hcap - 1)) || rerank > 256) {
     set_error("params out of range (m <= S*M0, beam_p <= 8, tau fractions <= 1, cand_cap and visit_cap powers "
-              "of two in [64, 4096] and [256, 16384])");
+              "of two in [64, 4096] and [256, 16384], rerank_mult <= 256)");
     return UNIFY_EINVAL;
   }
+  // the FP32 rerank of a low-precision search builds its k results in the candidate array
+  if (dv.precision != UNIFY_FP32)
+    while (ccap < k) ccap *= 2;
   if (!queries || !l || !h || !out_ids || !out_dist) {
     if (nq == 0) return UNIFY_OK;
     set_error("null buffer");
@@ -797,7 +1003,20 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
     A.ef = ef;
     A.m = m;
     A.p = p;
-    A.rerank = P.rerank_mult > 0 ? P.rerank_mult : 4;
+    A.rerank = rerank;
+    {
+      // canonical FP32 distance: each term passes through at most e + 6 roundings
+      // (the subtraction, squared; e fused multiply-adds; 4 butterfly additions),
+      // e = elements per partial sum, so its relative error is at most
+      // g = n u / (1 - n u), n = e + 6, u = 2^-24
+      const int G = dv.d / 4;
+      const double nr = 4.0 * ((G + 15) / 16) + 6.0, u = std::ldexp(1.0, -24);
+      const double g = nr * u / (1.0 - nr * u), w = std::ldexp(1.0, -20);
+      A.bA = (float)(std::sqrt((1.0 - g) / (1.0 + g)) * (1.0 - w));
+      A.bB = (float)(std::sqrt(1.0 - g) * (1.0 + w));
+      A.bC = (float)(std::sqrt((1.0 + g) / (1.0 - g)) * (1.0 + w));
+      A.bD = (float)(std::sqrt(1.0 + g) * (1.0 + w));
+    }
     A.ef_blocks = (std::max(ef, k) + WAVE - 1) / WAVE;
     A.nbr_cap = std::max(p * nb1, WAVE);
     A.out_ids = out_ids;

@@ -18,7 +18,7 @@ struct DevIndex {
   int64_t n;
   int32_t d, S, M0, MU, GC, L, gentry;
   int64_t R;            // rows of the upper-layer tables
-  int32_t precision;    // UNIFY_FP32 / BF16 / FP8E4M3 store read by the graph searches
+  int32_t precision;    // UNIFY_FP32 / BF16 / FP8E4M3: the store the searches rank by
   int32_t pad;
   const int64_t* attr;       // [n] sorted attributes
   const int64_t* ext;        // [n] external id of each internal id
@@ -30,6 +30,7 @@ struct DevIndex {
   const uint16_t* vec_bf16;  // [n][d] BF16 store or null
   const uint8_t* vec_fp8;    // [n][d] FP8 E4M3 store or null
   const float* vec_scale;    // [n] FP8 scale or null
+  const float* vec_eps;      // [n] bound on ||copy - FP32 vector|| of the store in use, or null
   const int32_t* adj0;       // [n][S][M0] layer-0 chunks, -1 padded
   const int32_t* glist0;     // [n][GC] layer-0 global (marked) edges, -1 padded
   const int32_t* adjU;       // [R][S][MU]
@@ -67,6 +68,10 @@ int validate_index(const HostIndex& H, std::string& err);
 
 void set_error(const std::string& msg);
 
+// Selects the store the searches rank by, building the BF16 or FP8 copy of the
+// resident vectors and its error bounds when it is not resident yet.
+int quantize_store(unify_index_t ix, int precision);
+
 }  // namespace unify
 
 struct unify_index {
@@ -77,6 +82,7 @@ struct unify_index {
   uint32_t* tags = nullptr;    // visited epochs [nslots][n], allocated at the first search
   uint32_t* epochs = nullptr;  // [nslots]
   int64_t nslots = 0;
+  const float* eps_of[3] = {nullptr, nullptr, nullptr};  // error bounds of the resident BF16 / FP8 copies
   unify::DevIndex dv{};
   unify::HostIndex host;  // small tables kept on the host; large ones released after upload
   std::vector<void*> allocs;

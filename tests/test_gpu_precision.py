@@ -1,0 +1,196 @@
+"""GPU parity of the BF16 / FP8 stores and the FP32 rerank against the oracle.
+
+The library builds its low-precision copy on the device; the codes, scales and
+error bounds are compared with the oracle's own rounding of the same vectors.
+Searches over the copy must then return exactly what the oracle returns with
+the same store (ids and FP32 distances bit for bit), and the pre-filter scan,
+which ranks by the copy but proves its result, must equal the exact answer.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import exact, hsig
+from synth import workloads as w
+
+PRECS = [("bf16", hsig.BF16), ("fp8", hsig.FP8E4M3)]
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def c1(tmp_path_factory):
+    spec = w.SPECS["hybrid10k"]
+    W = w.make(spec, base_seed=0)
+    path = str(tmp_path_factory.mktemp("prec") / "hybrid10k.uix")
+    print(f"[fixture] oracle build {spec.name}", flush=True)
+    ix = hsig.Index.build(W.base, W.attr, W.level_u, spec.S, spec.M, spec.ef_cons, seed=0)
+    ix.write(path)
+    return W, ix, path
+
+
+def gpu_search(g, Q, l, h, k, ef, strategy=None, **kw):
+    torch = _torch()
+    dev = torch.device("cuda", 0)
+    out = g.search(torch.from_numpy(Q).to(dev), torch.from_numpy(l).to(dev), torch.from_numpy(h).to(dev), k, ef,
+                   strategy=strategy, stats=True, **kw)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in out]
+
+
+@pytest.mark.parametrize("name,prec", PRECS)
+def test_store_matches_oracle_rounding(c1, name, prec):
+    W, ix, path = c1
+    import paper_2412_02448_amd as u
+    print(f"[case] store {name}", flush=True)
+    g = u.Index.load(path, device=0, precision=name)
+    codes, sc, eps = g.copy_store()
+    _torch().cuda.synchronize()
+    X = W.base[ix.ext_ids()]  # internal-id order
+    if prec == hsig.BF16:
+        ref = hsig.bf16_bits(X)
+        assert np.array_equal(codes.cpu().numpy().view(np.uint16), ref)
+        back = hsig.bf16_values(X)
+    else:
+        rc, rs, back = hsig.fp8_rows(X)
+        assert np.array_equal(codes.cpu().numpy(), rc)
+        assert np.array_equal(sc.cpu().numpy().view(np.uint32), rs.view(np.uint32))
+    err = np.sqrt(((back.astype(np.float64) - X) ** 2).sum(1))
+    e = eps.cpu().numpy().astype(np.float64)
+    assert np.all(e >= err) and np.all(e <= err * (1 + 1e-6) + 1e-30)
+    g.close()
+
+
+@pytest.mark.parametrize("name,prec", PRECS)
+@pytest.mark.parametrize("strategy", [hsig.AUTO, hsig.PRE, hsig.HYBRID, hsig.POST])
+def test_parity_low_precision(c1, name, prec, strategy):
+    W, ix, path = c1
+    import paper_2412_02448_amd as u
+    print(f"[case] {name} strategy={strategy}", flush=True)
+    g = u.Index.load(path, device=0, precision=name)
+    ix.set_store(prec, 4)
+    try:
+        for k, ef, p in ((10, 64, 1), (10, 48, 2), (16, 100, 4)):
+            ref = ix.search(W.queries, W.l, W.h, k, ef, p=p, strategy=strategy)
+            gid, gd, _, gst = gpu_search(g, W.queries, W.l, W.h, k, ef, None if strategy == hsig.AUTO else strategy,
+                                         beam_p=p)
+            assert (gst[:, 3] != 2).all()
+            bad = np.nonzero((ref[0] != gid).any(1) | (ref[1].view(np.uint32) != gd.view(np.uint32)).any(1))[0]
+            assert bad.size == 0, f"{name} k={k} ef={ef} p={p}: {bad.size} rows differ, first {bad[:5]}"
+    finally:
+        ix.set_store(hsig.FP32)
+        g.close()
+
+
+@pytest.mark.parametrize("name", ["bf16", "fp8"])
+def test_low_precision_pre_scan_is_exact(c1, name):
+    W, ix, path = c1
+    import paper_2412_02448_amd as u
+    print(f"[case] exact pre-filter over {name}", flush=True)
+    g = u.Index.load(path, device=0, precision=name)
+    for k in (1, 10, 100):
+        gid, gd, _, gst = gpu_search(g, W.queries, W.l, W.h, k, max(k, 10), hsig.PRE)
+        ref = ix.search(W.queries, W.l, W.h, k, max(k, 10), strategy=hsig.PRE)
+        assert np.array_equal(ref[0], gid) and np.array_equal(ref[1].view(np.uint32), gd.view(np.uint32))
+        # the copy decided most rows by itself (status 0), re-scoring few objects
+        assert (gst[:, 3] == 0).mean() > 0.9
+        if k == 10:
+            for i in range(0, len(W.queries), 37):
+                tid, td = exact.rfknn(W.base, W.attr, W.queries[i], W.l[i], W.h[i], 10)
+                assert gid[i, : len(tid)].tolist() == tid.tolist()
+            print(f"[info] {name}: mean FP32 re-scores per pre query {gst[:, 2].mean():.1f}", flush=True)
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["bf16", "fp8"])
+def test_low_precision_edge_cases(c1, name):
+    W, ix, path = c1
+    import paper_2412_02448_amd as u
+    g = u.Index.load(path, device=0, precision=name)
+    prec = dict(PRECS)[name]
+    a = ix.attr_sorted()
+    n = len(a)
+    Q = W.queries[:6]
+    l = np.array([10, a[-1] + 1, a[7], a[0], a[100], a[0]], np.int64)
+    h = np.array([5, a[-1] + 50, a[7], a[-1], a[130], a[n // 3]], np.int64)
+    print(f"[case] {name} edge cases", flush=True)
+    try:
+        for mult in (1, 4, 64):
+            ix.set_store(prec, mult)
+            for strategy in (hsig.AUTO, hsig.PRE, hsig.HYBRID, hsig.POST):
+                for k, ef in ((1, 1), (10, 10), (256, 256), (37, 100)):
+                    ref = ix.search(Q, l, h, k, ef, strategy=strategy)
+                    gid, gd, _, gst = gpu_search(g, Q, l, h, k, ef, None if strategy == hsig.AUTO else strategy,
+                                                 rerank_mult=mult)
+                    assert np.array_equal(ref[0], gid), (mult, strategy, k, ef)
+                    assert np.array_equal(ref[1].view(np.uint32), gd.view(np.uint32))
+    finally:
+        ix.set_store(hsig.FP32)
+        g.close()
+
+
+def test_set_precision_switches_stores(c1):
+    W, ix, path = c1
+    import paper_2412_02448_amd as u
+    print("[case] set_precision", flush=True)
+    g = u.Index.load(path, device=0)
+    base = gpu_search(g, W.queries, W.l, W.h, 10, 48)
+    for name, prec in PRECS:
+        g.set_precision(name)
+        ix.set_store(prec, 4)
+        ref = ix.search(W.queries, W.l, W.h, 10, 48)
+        got = gpu_search(g, W.queries, W.l, W.h, 10, 48)
+        assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1].view(np.uint32), got[1].view(np.uint32))
+    ix.set_store(hsig.FP32)
+    # both copies stay resident and readable; FP32 again gives the first results
+    assert g.copy_store("bf16")[0].shape == (ix.n, ix.d)
+    g.set_precision("fp32")
+    again = gpu_search(g, W.queries, W.l, W.h, 10, 48)
+    for x, y in zip(base, again):
+        assert np.array_equal(x, y)
+    g.close()
+
+
+def test_fp8_every_code(tmp_path):
+    """Vectors made of every finite E4M3 magnitude (both signs), scaled by powers
+    of two so that the per-vector scale is exact: the device store must hold the
+    codes themselves with a zero error bound, and searches over it (which decode
+    every code, subnormals included) must equal the FP32 searches."""
+    import paper_2412_02448_amd as u
+    rng = np.random.default_rng(11)
+    n, d = 400, 128
+    vals = hsig.e4m3_decode(np.arange(0x7F, dtype=np.uint8))  # 0 .. 448
+    X = np.empty((n, d), np.float32)
+    for i in range(n):
+        row = rng.permutation(vals) * rng.choice([-1.0, 1.0], size=0x7F)
+        X[i, 0] = 448.0
+        X[i, 1:] = row
+        X[i] *= np.float32(2.0 ** rng.integers(-4, 5))
+        X[i] = X[i][rng.permutation(d)]
+    attr = rng.permutation(n).astype(np.int64)
+    lu = 1.0 - rng.random(n)
+    ix = hsig.Index.build(X, attr, lu, 2, 8, 32)
+    path = str(tmp_path / "codes.uix")
+    ix.write(path)
+    print("[case] fp8 every code", flush=True)
+    g = u.Index.load(path, device=0, precision="fp8")
+    codes, sc, eps = g.copy_store()
+    Xi = X[ix.ext_ids()]
+    rc, rs, back = hsig.fp8_rows(Xi)
+    assert np.array_equal(back, Xi)
+    assert np.array_equal(codes.cpu().numpy(), rc) and np.array_equal(sc.cpu().numpy(), rs)
+    assert (eps.cpu().numpy() == 0).all()
+    assert len(np.unique(rc & 0x7F)) == 0x7F
+    Q = (rng.standard_normal((50, d)) * 100).astype(np.float32)
+    l = rng.integers(0, n // 2, 50).astype(np.int64)
+    h = l + rng.integers(0, n // 2, 50)
+    for strategy in (hsig.PRE, hsig.HYBRID, hsig.POST):
+        ref = ix.search(Q, l, h, 10, 32, strategy=strategy)
+        gid, gd, _, _ = gpu_search(g, Q, l, h, 10, 32, strategy)
+        assert np.array_equal(ref[0], gid) and np.array_equal(ref[1].view(np.uint32), gd.view(np.uint32))
+    g.close()
