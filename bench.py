@@ -176,7 +176,7 @@ def main():
         by_prec[prec] = {
             "qps": round(nq / sec, 1), "ms_per_step": round(sec * 1e3, 4), "recall@10": round(rec, 4),
             "m": m, "ef": ef, "beam_p": bp, "search_launch_ms": round(search_ms, 4),
-            "worklist_ms": round(pre_ms, 4), "rerun_launch_ms": round(rerun_ms, 4),
+            "plan_ms": round(pre_ms, 4), "rerun_launch_ms": round(rerun_ms, 4),
             "rerun_queries": int((st[:, 3] == 1).sum()), "failed_queries": int((st[:, 3] == 2).sum()),
             "bytes_per_launch": bts, "achieved_GBps": round(bts / (search_ms * 1e-3) / 1e9, 1),
             "fp32_rescores_per_query": round(float(st[:, 2].mean()), 2),
@@ -209,9 +209,6 @@ def main():
         s, o = timed(m, ef, bp, sv, steps=max(1, args.steps // 2 + 1), warmup=1)
         per_strategy[name] = {"qps": round(nq / s, 1), "recall@10": round(recall_of(o[0]), 4)}
         log(f"{name}: {nq / s:,.0f} QPS recall {per_strategy[name]['recall@10']}")
-    s, o = timed(m, ef, bp, steps=max(1, args.steps // 2 + 1), warmup=1, tiled_prescan=True)
-    tiled_alt = {"qps": round(nq / s, 1), "same_ids_as_default": bool((o[0] == out[0]).all().item())}
-    log(f"auto with the tile-shared pre-filter scan: {nq / s:,.0f} QPS")
 
     # ---- roofline of the search kernel: counters of one more (identical) call ----
     ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, stats=True, timing=True)
@@ -258,7 +255,6 @@ def main():
         "by_precision": by_prec,
         "per_strategy": per_strategy,
         "roofline": roofline,
-        "alt_tiled_prescan": tiled_alt,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

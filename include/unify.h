@@ -69,10 +69,7 @@ enum {
 
 /* Bits of unify_params.flags. */
 enum {
-  UNIFY_FLAG_TIMING = 1,         /* record HIP events around the search kernels; see unify_last_timing */
-  UNIFY_FLAG_TILED_PRESCAN = 2   /* answer narrow pre-filter queries with the tile-shared scan
-                                    (reads each tile once per group of 16 queries) instead of
-                                    one wavefront per query; same results */
+  UNIFY_FLAG_TIMING = 1  /* record HIP events around the search kernels; see unify_last_timing */
 };
 
 /* Search parameters.  Zero in a field selects its default. */
@@ -91,6 +88,9 @@ typedef struct {
   int32_t visit_cap;    /* on-chip visited-cache entries per query, a power of two in
                            [256, 16384]; default 1024 (larger visited sets spill to HBM,
                            same results) */
+  int32_t pre_chunk;    /* pre-filter scans with k <= 32 split their slice into chunks of
+                           about this many objects (at most 8 chunks), scanned by different
+                           wavefronts and merged exactly; default 2048, minimum 64 */
 } unify_params;
 
 /*
@@ -156,11 +156,13 @@ int unify_search(unify_index_t index, const float* queries, int64_t nq, const in
 /*
  * unify_search plus per-query counters:
  *   out_stats  device, [nq][8] int32: [0] distance evaluations, [1] expansions,
- *              [2] objects visited on layer 0, [3] status (0 = ran in the first
- *              search pass, 1 = re-run with larger on-chip lists, 2 = capacity exceeded
- *              even then: the row is padded, 3 = answered by the tiled pre-filter scan), [4] adjacency entries read, [5] strategy run
- *              (-1 for an empty range), [6] Y = objects in range, [7] active segments
- *              (hybrid only, else 0).
+ *              [2] FP32 re-scores of a BF16 / FP8 search, [3] status (0 = answered
+ *              in the first search pass, 1 = re-run: with larger on-chip lists for a
+ *              graph search, by the FP32 scan for a low-precision pre-filter scan whose
+ *              bounds could not settle the result, 2 = capacity exceeded even then: the
+ *              row is padded), [4] adjacency entries read, [5] strategy run (-1 for an
+ *              empty range), [6] Y = objects in range, [7] active segments (hybrid only,
+ *              else 0).
  */
 int unify_search_ex(unify_index_t index, const float* queries, int64_t nq, const int64_t* l,
                     const int64_t* h, int32_t k, int32_t ef, const int8_t* strategy,
@@ -170,13 +172,13 @@ int unify_search_ex(unify_index_t index, const float* queries, int64_t nq, const
 /*
  * Durations of the kernels of the last unify_search* call on this index that set
  * UNIFY_FLAG_TIMING, from HIP events recorded on that call's stream:
- *   prescan_ms  the tiled pre-filter scan (pre-filter queries of narrow ranges);
- *   search_ms   the main search launch (graph searches and the remaining scans);
+ *   plan_ms     the plan and work-list kernels;
+ *   search_ms   the main search launch (graph searches and pre-filter scans);
  *   rerun_ms    the launch that re-runs queries whose on-chip lists overflowed.
  * Waits for the events to complete.  Outputs are host pointers, any may be NULL.
  * Returns UNIFY_EINVAL when no timed search has been issued.
  */
-int unify_last_timing(unify_index_t index, float* prescan_ms, float* search_ms, float* rerun_ms);
+int unify_last_timing(unify_index_t index, float* plan_ms, float* search_ms, float* rerun_ms);
 
 /*
  * Selects the store later searches on this index rank by (UNIFY_FP32, UNIFY_BF16,

@@ -18,7 +18,6 @@ __all__ = ["Index", "UnifyError", "AUTO", "PRE", "HYBRID", "POST", "FP32", "BF16
 
 AUTO, PRE, HYBRID, POST = 0, 1, 2, 3
 FLAG_TIMING = 1
-FLAG_TILED_PRESCAN = 2
 FP32, BF16, FP8E4M3 = 0, 1, 2
 _PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8E4M3, "fp8e4m3": FP8E4M3}
 
@@ -38,7 +37,7 @@ class UnifyError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("m", C.c_int32), ("beam_p", C.c_int32), ("rerank_mult", C.c_int32), ("cand_cap", C.c_int32),
                 ("tau_a_frac", C.c_double), ("tau_b_frac", C.c_double), ("flags", C.c_uint32),
-                ("visit_cap", C.c_int32)]
+                ("visit_cap", C.c_int32), ("pre_chunk", C.c_int32)]
 
 
 _lib = None
@@ -174,15 +173,14 @@ class Index:
             pass
 
     def last_timing(self):
-        """(prescan_ms, search_ms, rerun_ms) of the last search issued with timing=True (waits for it)."""
+        """(plan_ms, search_ms, rerun_ms) of the last search issued with timing=True (waits for it)."""
         a, b, c = C.c_float(), C.c_float(), C.c_float()
         _check(load_library().unify_last_timing(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
 
     def search(self, queries, l, h, k: int, ef: int, strategy=None, m: int = 0, beam_p: int = 1,
                rerank_mult: int = 0, tau_a: float = 0.0, tau_b: float = 0.0, stats: bool = False,
-               out=None, stream=None, timing: bool = False, cand_cap: int = 0, visit_cap: int = 0,
-               tiled_prescan: bool = False):
+               out=None, stream=None, timing: bool = False, cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0):
         """Enqueues a search on the current stream (or `stream`) and returns torch tensors.
 
         queries: cuda float32 [nq, d]; l, h: cuda int64 [nq] (inclusive); strategy: None (auto),
@@ -211,8 +209,8 @@ class Index:
             sts = torch.empty((nq, 8), dtype=torch.int32, device=dev) if stats else None
         else:
             ids, dist, ost, sts = out
-        flags = (FLAG_TIMING if timing else 0) | (FLAG_TILED_PRESCAN if tiled_prescan else 0)
-        prm = _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, flags, visit_cap)
+        flags = FLAG_TIMING if timing else 0
+        prm = _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, flags, visit_cap, pre_chunk)
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         lib = load_library()
         if stats:

@@ -288,7 +288,7 @@ int unify_search_ex(unify_index_t ix, const float* queries, int64_t nq, const in
                      hip_stream);
 }
 
-int unify_last_timing(unify_index_t ix, float* prescan_ms, float* search_ms, float* rerun_ms) {
+int unify_last_timing(unify_index_t ix, float* plan_ms, float* search_ms, float* rerun_ms) {
   if (!ix || !ix->timed) {
     set_error("no timed search on this index");
     return UNIFY_EINVAL;
@@ -304,7 +304,7 @@ int unify_last_timing(unify_index_t ix, float* prescan_ms, float* search_ms, flo
     set_error("hipEventElapsedTime failed");
     return UNIFY_EDEVICE;
   }
-  if (prescan_ms) *prescan_ms = a;
+  if (plan_ms) *plan_ms = a;
   if (search_ms) *search_ms = b;
   if (rerun_ms) *rerun_ms = c;
   return UNIFY_OK;

@@ -46,7 +46,11 @@ struct SearchArgs {
   int32_t* out_stats;
   const QPlan* plan;
   const int32_t* work;    // query indices to run
+  const int32_t* wchunk;  // chunk of each work entry (pre-filter scans), or null for 0
   const int32_t* nwork;   // number of entries in work
+  u64* part;              // partial top-k lists of split pre-filter scans, k keys per chunk
+  int32_t* qacc;          // [nq][4] per query: chunks finished, FP32 re-scores, objects scanned,
+                          // chunks that fell back to the FP32 scan
   int32_t* next;          // work counter
   int32_t* fb_list;       // queries abandoned by the first pass
   int32_t* fb_count;
@@ -56,6 +60,8 @@ struct SearchArgs {
 };
 
 constexpr uint32_t HASH_EMPTY = 0xFFFFFFFFu;
+constexpr int PRE_NCH_MAX = 8;      // chunks per pre-filter scan at most
+constexpr int PRE_SPLIT_KMAX = 32;  // larger k scans its slice in one wavefront
 
 // ---------------------------------------------------------------------------
 // Plan: the range becomes an id interval [lo, hi) (the skip-list walk of
@@ -84,7 +90,7 @@ __device__ int64_t upper_bound_i64(const int64_t* a, int64_t n, int64_t x) {
 
 __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t* __restrict__ h,
                        const int8_t* __restrict__ strat_in, int64_t nq, int64_t tauA, int64_t tauB,
-                       int32_t k, QPlan* __restrict__ plan, int8_t* __restrict__ out_strat,
+                       int32_t k, int32_t chunk, QPlan* __restrict__ plan, int8_t* __restrict__ out_strat,
                        int64_t* __restrict__ out_ids, float* __restrict__ out_dist,
                        int32_t* __restrict__ out_stats) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,11 +110,17 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
   P.lo = (int32_t)lo;
   P.hi = (int32_t)hi;
   P.a = P.b = 0;
-  P.tiled = 0;
+  P.nch = 1;
+  P.clen = (int32_t)Y;
+  P.pbase = 0;
   if (Y > 0) {
     P.a = (int32_t)(upper_bound_i64(ix.seg_start, ix.S + 1, lo) - 1);
     P.b = (int32_t)(upper_bound_i64(ix.seg_start, ix.S + 1, hi - 1) - 1);
     P.strat = s;
+    if (s == UNIFY_PRE && k <= PRE_SPLIT_KMAX) {
+      P.nch = (int32_t)std::min<int64_t>(PRE_NCH_MAX, (Y + chunk - 1) / chunk);
+      P.clen = (int32_t)((Y + P.nch - 1) / P.nch);
+    }
   } else {
     P.strat = -1;
     for (int t = 0; t < k; ++t) {
@@ -124,56 +136,83 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
 }
 
 // Work list: the graph-search queries (hybrid, post) in query order, then the
-// pre-filter queries bucketed by the start of their slice, so that waves that
-// scan at the same time read overlapping slices.  Resets the counters.
-__global__ void k_worklist(const QPlan* __restrict__ plan, int64_t nq, int64_t n, int32_t* __restrict__ work,
+// chunks of the pre-filter scans bucketed by where they start, so that waves
+// that scan at the same time read nearby rows.  Also numbers the partial-list
+// slots of split scans (QPlan.pbase) and resets the counters.  One block.
+__global__ void k_worklist(QPlan* __restrict__ plan, int64_t nq, int64_t n, int32_t* __restrict__ work,
+                           int32_t* __restrict__ wchunk,
                            int32_t* __restrict__ counters /* nwork, next, fb_count, fb_next */) {
   constexpr int NB = 1024;
   __shared__ int32_t part[1024];
+  __shared__ int32_t spart[1024];
   __shared__ int32_t bucket[NB];
   const int t = threadIdx.x, T = blockDim.x;
   const int64_t per = (nq + T - 1) / T;
   const int64_t s0 = std::min<int64_t>(nq, t * per), s1 = std::min<int64_t>(nq, s0 + per);
   for (int b = t; b < NB; b += T) bucket[b] = 0;
   __syncthreads();
-  int32_t c = 0;
+  int32_t c = 0, sc = 0;
   for (int64_t q = s0; q < s1; ++q) {
     const QPlan P = plan[q];
-    if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) ++c;
-    else if (P.strat == UNIFY_PRE && !P.tiled) atomicAdd(&bucket[(int)((int64_t)P.lo * NB / n)], 1);
+    if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) {
+      ++c;
+    } else if (P.strat == UNIFY_PRE) {
+      for (int j = 0; j < P.nch; ++j)
+        atomicAdd(&bucket[(int)((int64_t)(P.lo + j * P.clen) * NB / n)], 1);
+      if (P.nch > 1) sc += P.nch;
+    }
   }
   part[t] = c;
+  spart[t] = sc;
   __syncthreads();
   for (int off = 1; off < T; off <<= 1) {
-    int32_t v = t >= off ? part[t - off] : 0;
-    int32_t bv = (t >= off && t < NB) ? bucket[t - off] : 0;
+    const int32_t v = t >= off ? part[t - off] : 0;
+    const int32_t sv = t >= off ? spart[t - off] : 0;
+    const int32_t bv = (t >= off && t < NB) ? bucket[t - off] : 0;
     __syncthreads();
     part[t] += v;
+    spart[t] += sv;
     if (t < NB) bucket[t] += bv;
     __syncthreads();
   }
   const int32_t nbeam = part[T - 1];
-  const int32_t npre = bucket[NB - 1];
-  const int32_t my_end = t < NB ? bucket[t] : 0;  // inclusive prefix count of pre queries
+  const int32_t nchunks = bucket[NB - 1];
+  const int32_t my_end = t < NB ? bucket[t] : 0;  // inclusive prefix count of chunks
   __syncthreads();
   if (t < NB) bucket[t] = nbeam + my_end;  // one past the last slot of bucket t
   __syncthreads();
   int32_t pos = part[t] - c;
+  int32_t spos = spart[t] - sc;
   for (int64_t q = s0; q < s1; ++q) {
-    const QPlan P = plan[q];
+    QPlan P = plan[q];
     if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) {
-      work[pos++] = (int32_t)q;
-    } else if (P.strat == UNIFY_PRE && !P.tiled) {
-      const int b = (int)((int64_t)P.lo * NB / n);
-      work[atomicSub(&bucket[b], 1) - 1] = (int32_t)q;
+      work[pos] = (int32_t)q;
+      wchunk[pos] = 0;
+      ++pos;
+    } else if (P.strat == UNIFY_PRE) {
+      for (int j = 0; j < P.nch; ++j) {
+        const int b = (int)((int64_t)(P.lo + j * P.clen) * NB / n);
+        const int32_t w = atomicSub(&bucket[b], 1) - 1;
+        work[w] = (int32_t)q;
+        wchunk[w] = j;
+      }
+      if (P.nch > 1) {
+        plan[q].pbase = spos;
+        spos += P.nch;
+      }
     }
   }
   if (t == 0) {
-    counters[0] = nbeam + npre;
+    counters[0] = nbeam + nchunks;
     counters[1] = 0;
     counters[2] = 0;
     counters[3] = 0;
   }
+}
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -555,6 +594,7 @@ __device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&
     const int cntv = min(WAVE, P.hi - base);
     eval_keys<NG, PREC>(ix, qv, cntv, [&](int i) { return base + i; }, L.bkeys);
     __syncthreads();
+    cnt.ndist += cntv;
     float lb = 0.f, ub = 0.f;
     const bool have = lane < cntv;
     if (have) root_bounds(key_dist(L.bkeys[lane]), ix.vec_eps[base + lane], A, lb, ub);
@@ -587,7 +627,6 @@ __device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&
     cl += add;
     __syncthreads();
   }
-  cnt.ndist += P.hi - P.lo;
   const float TU = ul == k ? key_dist(L.ann[k - 1]) : __builtin_inff();
   // re-score the qualifying entries of cand in FP32
   al = 0;
@@ -651,10 +690,29 @@ __device__ int rerank_graph(const SearchArgs& A, const Lds& L, const float4 (&qv
   return rl;
 }
 
+// A pre-filter scan split into chunks: each chunk's wavefront stores its exact
+// top-k list (ascending, KEY_MAX padded) and adds its counters; k_pre_merge,
+// launched after the search kernel, merges the lists (the union of the chunks'
+// top-k lists holds the slice's top k).
+__device__ void pre_store_chunk(const SearchArgs& A, const Lds& L, int32_t q, const QPlan& P, int chunk, int al,
+                                const Counters& cnt, bool fell) {
+  const int lane = lane_id();
+  const int k = A.k;
+  u64* mine = A.part + ((int64_t)P.pbase + chunk) * k;
+  for (int t = lane; t < k; t += WAVE) mine[t] = t < al ? L.ann[t] : KEY_MAX;
+  if (lane == 0) {
+    int32_t* acc = A.qacc + (int64_t)q * 4;
+    atomicAdd(acc + 1, cnt.nrerank);
+    atomicAdd(acc + 2, cnt.ndist);
+    if (fell) atomicAdd(acc + 3, 1);
+  }
+}
+
 __device__ __forceinline__ bool ne_missing(int top) { return top < 0; }
 
 template <int NG, int PREC>
-__device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, uint32_t* tags, uint32_t& epoch) {
+__device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chunk, uint32_t* tags,
+                          uint32_t& epoch) {
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
   const QPlan P = A.plan[q];
@@ -673,10 +731,22 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, uint32_t
   bool ok = true;
   const bool hybrid = P.strat == UNIFY_HYBRID;
   int kout = A.k;
+  int status = A.pass;
   if (P.strat == UNIFY_PRE) {
-    // a low-precision scan that cannot prove its result re-runs in FP32 (pass 1)
-    if (PREC == UNIFY_FP32 || A.pass == 1) pre_scan<NG, PREC>(A, L, qv, P, al, cnt);
-    else ok = pre_scan_lowp<NG, PREC>(A, L, qv, P, al, cnt);
+    QPlan Pc = P;  // this chunk of the slice
+    Pc.lo = P.lo + chunk * P.clen;
+    Pc.hi = min(P.hi, Pc.lo + P.clen);
+    // a low-precision scan whose bounds cannot settle its top k is redone in FP32
+    bool fell = false;
+    if (PREC == UNIFY_FP32 || !pre_scan_lowp<NG, PREC>(A, L, qv, Pc, al, cnt)) {
+      fell = PREC != UNIFY_FP32;
+      pre_scan<NG, PREC>(A, L, qv, Pc, al, cnt);
+    }
+    if (P.nch > 1) {
+      pre_store_chunk(A, L, q, P, chunk, al, cnt, fell);
+      return;
+    }
+    if (fell) status = 1;
   } else {
     const int Sa = P.b - P.a + 1;
     const int c = (A.m + Sa - 1) / Sa;
@@ -775,7 +845,7 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, uint32_t
     st[0] = cnt.ndist;
     st[1] = cnt.nexp;
     st[2] = cnt.nrerank;
-    st[3] = ok ? A.pass : 2;
+    st[3] = ok ? status : 2;
     st[4] = cnt.nadj;
     st[5] = P.strat;
     st[6] = P.hi - P.lo;
@@ -805,19 +875,56 @@ __global__ void __launch_bounds__(64) k_search(SearchArgs A) {
     if (lane_id() == 0) w = atomicAdd(A.next, 1);
     w = __shfl(w, 0, WAVE);
     if (w >= nwork) break;
-    run_query<NG, PREC>(A, L, A.work[w], tags, epoch);
+    run_query<NG, PREC>(A, L, A.work[w], A.wchunk ? A.wchunk[w] : 0, tags, epoch);
     __syncthreads();
   }
   if (lane_id() == 0) __hip_atomic_store(&A.epochs[slot], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Outputs of the split pre-filter scans: one wavefront per query merges its
+// chunks' top-k lists (k <= 32) and writes the k results and the counters.
+__global__ void __launch_bounds__(256) k_pre_merge(DevIndex ix, const QPlan* __restrict__ plan, int64_t nq, int k,
+                                                   const u64* __restrict__ part, const int32_t* __restrict__ qacc,
+                                                   int64_t* __restrict__ out_ids, float* __restrict__ out_dist,
+                                                   int32_t* __restrict__ out_stats) {
+  __shared__ u64 lists[4][WAVE];
+  const int lane = lane_id();
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= nq) return;  // uniform per wavefront
+  const QPlan P = plan[q];
+  if (P.strat != UNIFY_PRE || P.nch <= 1) return;
+  u64* lst = lists[threadIdx.x >> 6];
+  lst[lane] = KEY_MAX;
+  int al = 0;
+  const u64* all = part + (int64_t)P.pbase * k;
+  const int tot = P.nch * k;
+  for (int base = 0; base < tot; base += WAVE) {
+    const int t = base + lane;
+    const u64 key = t < tot ? all[t] : KEY_MAX;
+    const u64 T = al == k ? lst[k - 1] : KEY_MAX;
+    list_insert(lst, al, k, key < T ? key : KEY_MAX);
+  }
+  if (lane < k) {
+    const u64 key = lane < al ? lst[lane] : KEY_MAX;
+    out_ids[q * k + lane] = key != KEY_MAX ? ix.ext[key_id(key)] : -1;
+    out_dist[q * k + lane] = key != KEY_MAX ? key_dist(key) : __builtin_inff();
+  }
+  if (out_stats && lane == 0) {
+    int32_t* st = out_stats + q * 8;
+    st[0] = qacc[q * 4 + 2];
+    st[1] = 0;
+    st[2] = qacc[q * 4 + 1];
+    st[3] = qacc[q * 4 + 3] > 0 ? 1 : 0;
+    st[4] = 0;
+    st[5] = UNIFY_PRE;
+    st[6] = P.hi - P.lo;
+    st[7] = 0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-size_t prescan_scratch_bytes(const DevIndex& dv, int64_t nq, int k, int span_cap);
-int span_cap_for(const DevIndex& dv, int64_t tauA);
-int launch_prescan(const DevIndex& dv, const float* Q, int64_t nq, int k, int span_cap, QPlan* plan, void* scratch,
-                   int64_t* out_ids, float* out_dist, int32_t* out_stats, int device, hipStream_t st);
 
 namespace {
 
@@ -905,10 +1012,11 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
   int ccap = P.cand_cap > 0 ? P.cand_cap : 512;
   const int hcap = P.visit_cap > 0 ? P.visit_cap : 1024;
   const int rerank = P.rerank_mult > 0 ? P.rerank_mult : 4;
+  const int pre_chunk = P.pre_chunk > 0 ? P.pre_chunk : 2048;
   if (m > dv.S * dv.M0 || p > 8 || ta > 1.0 || tb > 1.0 || ccap < 64 || ccap > 4096 || (ccap & (ccap - 1)) ||
-      hcap < 256 || hcap > 16384 || (hcap & (hcap - 1)) || rerank > 256) {
+      hcap < 256 || hcap > 16384 || (hcap & (hcap - 1)) || rerank > 256 || pre_chunk < 64) {
     set_error("params out of range (m <= S*M0, beam_p <= 8, tau fractions <= 1, cand_cap and visit_cap powers "
-              "of two in [64, 4096] and [256, 16384], rerank_mult <= 256)");
+              "of two in [64, 4096] and [256, 16384], rerank_mult <= 256, pre_chunk >= 64)");
     return UNIFY_EINVAL;
   }
   // the FP32 rerank of a low-precision search builds its k results in the candidate array
@@ -956,17 +1064,23 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
     ix->allocs.push_back(e);
   }
 
-  // scratch: plans, work list, fallback list, counters, tiled pre-filter scan
-  const int span_cap = span_cap_for(dv, tauA);
-  const size_t plan_b = (sizeof(QPlan) * nq + 255) / 256 * 256, list_b = (sizeof(int32_t) * nq + 255) / 256 * 256;
-  const size_t pre_b = (P.flags & UNIFY_FLAG_TILED_PRESCAN) ? prescan_scratch_bytes(dv, nq, k, span_cap) : 0;
+  // scratch: plans, work list (graph queries and pre-filter chunks), chunk of each
+  // entry, fallback list, counters, per-query merge counters, partial top-k lists
+  auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  const int64_t wcap = nq * PRE_NCH_MAX;
+  const size_t plan_b = up256(sizeof(QPlan) * nq), work_b = up256(sizeof(int32_t) * wcap),
+               fb_b = up256(sizeof(int32_t) * nq), acc_b = up256(sizeof(int32_t) * 4 * nq),
+               part_b = k <= PRE_SPLIT_KMAX ? up256(sizeof(u64) * (size_t)wcap * k) : 0;
   void* scratch = nullptr;
-  HIP_OK(hipMallocAsync(&scratch, plan_b + 2 * list_b + 256 + pre_b, st));
-  QPlan* plan = reinterpret_cast<QPlan*>(scratch);
-  int32_t* work = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(scratch) + plan_b);
-  int32_t* fb = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(work) + list_b);
-  int32_t* counters = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(fb) + list_b);  // nwork, next, fb_count, fb_next
-  void* pre_scratch = reinterpret_cast<char*>(counters) + 256;
+  HIP_OK(hipMallocAsync(&scratch, plan_b + 2 * work_b + fb_b + 256 + acc_b + part_b, st));
+  char* sp = reinterpret_cast<char*>(scratch);
+  QPlan* plan = reinterpret_cast<QPlan*>(sp);
+  int32_t* work = reinterpret_cast<int32_t*>(sp += plan_b);
+  int32_t* wchunk = reinterpret_cast<int32_t*>(sp += work_b);
+  int32_t* fb = reinterpret_cast<int32_t*>(sp += work_b);
+  int32_t* counters = reinterpret_cast<int32_t*>(sp += fb_b);  // nwork, next, fb_count, fb_next
+  int32_t* qacc = reinterpret_cast<int32_t*>(sp += 256);
+  u64* part = part_b ? reinterpret_cast<u64*>(sp += acc_b) : nullptr;
 
   const bool timing = (P.flags & UNIFY_FLAG_TIMING) != 0;
   int rc = UNIFY_OK;
@@ -975,14 +1089,12 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
       if (!ix->ev[e] && hipEventCreate(&ix->ev[e]) != hipSuccess) rc = UNIFY_EDEVICE;
     ix->timed = rc == UNIFY_OK;
   }
+  if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[0], st) != hipSuccess) rc = UNIFY_EDEVICE;
   const unsigned pb = 256;
   hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, dv, l, h, strategy, nq,
-                     tauA, tauB, k, plan, out_strategy, out_ids, out_dist, out_stats);
-  if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[0], st) != hipSuccess) rc = UNIFY_EDEVICE;
-  if (rc == UNIFY_OK && (P.flags & UNIFY_FLAG_TILED_PRESCAN))
-    rc = launch_prescan(dv, queries, nq, k, span_cap, plan, pre_scratch, out_ids, out_dist, out_stats, ix->device,
-                        st);
-  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, plan, nq, dv.n, work, counters);
+                     tauA, tauB, k, pre_chunk, plan, out_strategy, out_ids, out_dist, out_stats);
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((4 * nq + pb - 1) / pb)), dim3(pb), 0, st, qacc, 4 * nq, 0);
+  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, plan, nq, dv.n, work, wchunk, counters);
   if (hipGetLastError() != hipSuccess) rc = UNIFY_EDEVICE;
 
   KernelFn fn = kernel_for<0>(dv.d, dv.precision);
@@ -1031,12 +1143,20 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
     A.hcap = hcap;
     A.pass = 0;
     A.work = work;
+    A.wchunk = wchunk;
+    A.part = part;
+    A.qacc = qacc;
     A.nwork = counters + 0;
     A.next = counters + 1;
     A.fb_list = fb;
     A.fb_count = counters + 2;
     if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[1], st) != hipSuccess) rc = UNIFY_EDEVICE;
     if (rc == UNIFY_OK) rc = launch_pass(fn, A, ix->device, st, lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap));
+    if (rc == UNIFY_OK && part) {
+      hipLaunchKernelGGL(k_pre_merge, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, dv, plan, nq, k, part, qacc,
+                         out_ids, out_dist, out_stats);
+      if (hipGetLastError() != hipSuccess) rc = UNIFY_EDEVICE;
+    }
     if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[2], st) != hipSuccess) rc = UNIFY_EDEVICE;
     if (rc == UNIFY_OK) {
       // second pass over the abandoned queries with the largest LDS that fits
@@ -1050,6 +1170,7 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
       B.hcap = hc;
       B.pass = 1;
       B.work = fb;
+      B.wchunk = nullptr;  // only graph searches are re-run
       B.nwork = counters + 2;
       B.next = counters + 3;
       rc = launch_pass(fn_rerun, B, ix->device, st, lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap));

@@ -42,7 +42,9 @@ struct QPlan {
   int32_t lo, hi;   // in-range internal ids [lo, hi)
   int32_t a, b;     // active segments a..b (segments holding an in-range object)
   int32_t strat;    // UNIFY_PRE / HYBRID / POST; -1 when the range is empty
-  int32_t tiled;    // 1 when the tiled pre-filter scan answers this query
+  int32_t nch;      // pre-filter: chunks the slice is split into (1 = one wavefront)
+  int32_t clen;     // pre-filter: objects per chunk (the last one may be shorter)
+  int32_t pbase;    // pre-filter, nch > 1: first slot of the query's partial top-k lists
 };
 
 // Host-side tables of an index (the index file content), internal ids.
@@ -76,8 +78,8 @@ int quantize_store(unify_index_t ix, int precision);
 
 struct unify_index {
   int device = 0;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // timing: before/after the tiled pre-filter,
-                                                            // after the search, after the re-run
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // timing: before the plan, after the work
+                                                            // list, after the search, after the re-run
   bool timed = false;
   uint32_t* tags = nullptr;    // visited epochs [nslots][n], allocated at the first search
   uint32_t* epochs = nullptr;  // [nslots]

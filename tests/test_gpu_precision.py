@@ -87,14 +87,15 @@ def test_parity_low_precision(c1, name, prec, strategy):
         g.close()
 
 
+@pytest.mark.parametrize("chunk", [0, 64])
 @pytest.mark.parametrize("name", ["bf16", "fp8"])
-def test_low_precision_pre_scan_is_exact(c1, name):
+def test_low_precision_pre_scan_is_exact(c1, name, chunk):
     W, ix, path = c1
     import paper_2412_02448_amd as u
-    print(f"[case] exact pre-filter over {name}", flush=True)
+    print(f"[case] exact pre-filter over {name}, chunk={chunk}", flush=True)
     g = u.Index.load(path, device=0, precision=name)
     for k in (1, 10, 100):
-        gid, gd, _, gst = gpu_search(g, W.queries, W.l, W.h, k, max(k, 10), hsig.PRE)
+        gid, gd, _, gst = gpu_search(g, W.queries, W.l, W.h, k, max(k, 10), hsig.PRE, pre_chunk=chunk)
         ref = ix.search(W.queries, W.l, W.h, k, max(k, 10), strategy=hsig.PRE)
         assert np.array_equal(ref[0], gid) and np.array_equal(ref[1].view(np.uint32), gd.view(np.uint32))
         # the copy decided most rows by itself (status 0), re-scoring few objects

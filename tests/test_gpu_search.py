@@ -90,14 +90,20 @@ def test_parity_neighbour_budget(c1, m):
     assert_parity(ref, got, f"m={m}")
 
 
-@pytest.mark.parametrize("strategy", [hsig.AUTO, hsig.PRE])
-def test_parity_tiled_prescan(c1, strategy):
+@pytest.mark.parametrize("chunk", [64, 100, 1000])
+def test_parity_split_pre_filter(c1, chunk):
+    """Pre-filter scans split into chunks on several wavefronts and merged."""
     W, ix, g = c1
-    print(f"[case] tiled pre-filter scan strategy={strategy}", flush=True)
-    for k in (10, 64):
-        ref = ix.search(W.queries, W.l, W.h, k, 64, strategy=strategy)
-        got = gpu_search(g, W, k, 64, strategy=None if strategy == hsig.AUTO else strategy, tiled_prescan=True)
-        assert_parity(ref, got, f"tiled strategy={strategy} k={k}")
+    print(f"[case] split pre-filter chunk={chunk}", flush=True)
+    for k in (1, 10, 32, 33):
+        for strategy in (hsig.PRE, hsig.AUTO):
+            ref = ix.search(W.queries, W.l, W.h, k, max(k, 40), strategy=strategy)
+            got = gpu_search(g, W, k, max(k, 40), strategy=None if strategy == hsig.AUTO else strategy,
+                             pre_chunk=chunk)
+            assert_parity(ref, got, f"chunk={chunk} k={k} strategy={strategy}")
+            pre = got[3][:, 5] == hsig.PRE
+            # every object of the slice scanned once, whatever the split
+            assert (got[3][pre, 0] == got[3][pre, 6]).all()
 
 
 def test_pre_filter_matches_fp64_exact(c1):
