@@ -204,6 +204,25 @@ int unify_set_precision(unify_index_t index, int precision);
 int unify_copy_store(unify_index_t index, int precision, void* codes, float* scales, float* eps,
                      void* hip_stream);
 
+/*
+ * Batched form for fixed-size batches (serving loops, benchmark replays): the
+ * whole search of unify_search_ex over the given buffers (plan, work list,
+ * search, merge, re-run) is captured once into a HIP graph, with its scratch
+ * allocated once; each unify_batch_run replays it on the caller's stream and
+ * reads whatever the buffers hold at that time.  Arguments are those of
+ * unify_search_ex (nq >= 1; out_stats may be NULL); the buffers stay owned by
+ * the caller and must stay allocated, at the same addresses, until
+ * unify_batch_free.  The search parameters and the index's store at creation
+ * are kept.  Replays of one batch must not overlap; the index must outlive it.
+ */
+typedef struct unify_batch* unify_batch_t;
+int unify_batch_create(unify_index_t index, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                       int32_t k, int32_t ef, const int8_t* strategy, const unify_params* params,
+                       int64_t* out_ids, float* out_dist, int8_t* out_strategy, int32_t* out_stats,
+                       unify_batch_t* out);
+int unify_batch_run(unify_batch_t batch, void* hip_stream);
+int unify_batch_free(unify_batch_t batch);  /* NULL is accepted */
+
 /* Frees the index and its device memory.  NULL is accepted. */
 int unify_free_index(unify_index_t index);
 

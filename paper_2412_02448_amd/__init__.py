@@ -55,6 +55,9 @@ SIGNATURES = {
     "unify_last_timing": (_I32, [_P, _P, _P, _P]),
     "unify_copy_store": (_I32, [_P, _I32, _P, _P, _P, _P]),
     "unify_set_precision": (_I32, [_P, _I32]),
+    "unify_batch_create": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "unify_batch_run": (_I32, [_P, _P]),
+    "unify_batch_free": (_I32, [_P]),
     "unify_free_index": (_I32, [_P]),
     "unify_last_error": (_S, []),
 }
@@ -221,3 +224,54 @@ class Index:
                                   _ptr(ids), _ptr(dist), _ptr(ost), s.cuda_stream)
         _check(rc)
         return (ids, dist, ost, sts) if stats else (ids, dist, ost)
+
+
+class Batch:
+    """A fixed-size batch whose whole search is captured once as a HIP graph and
+    replayed by run().  The query tensors passed in are read at every replay
+    (write new queries into them in place); results land in .ids, .dist,
+    .strategy_run and .stats (when stats=True).  Keyword arguments are those of
+    Index.search."""
+
+    def __init__(self, index: Index, queries, l, h, k: int, ef: int, strategy=None, stats: bool = False,
+                 m: int = 0, beam_p: int = 1, rerank_mult: int = 0, tau_a: float = 0.0, tau_b: float = 0.0,
+                 cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0):
+        import torch
+        dev = torch.device("cuda", index.device)
+        nq = queries.shape[0]
+        if queries.dtype != torch.float32 or queries.device != dev or not queries.is_contiguous() \
+                or queries.shape != (nq, index.d):
+            raise ValueError("queries must be a contiguous float32 [nq, d] tensor on the index's device")
+        for t in (l, h):
+            if t.dtype != torch.int64 or t.device != dev or not t.is_contiguous() or t.shape != (nq,):
+                raise ValueError("l and h must be contiguous int64 [nq] tensors on the index's device")
+        if strategy is not None and not isinstance(strategy, torch.Tensor):
+            strategy = torch.full((nq,), int(strategy), dtype=torch.int8, device=dev)
+        self.index, self.queries, self.l, self.h, self.strategy = index, queries, l, h, strategy
+        self.ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
+        self.dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        self.strategy_run = torch.empty((nq,), dtype=torch.int8, device=dev)
+        self.stats = torch.empty((nq, 8), dtype=torch.int32, device=dev) if stats else None
+        prm = _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, 0, visit_cap, pre_chunk)
+        torch.cuda.synchronize(dev)  # the tensors above exist before the capture reads their addresses
+        self._b = C.c_void_p()
+        _check(load_library().unify_batch_create(index._h, _ptr(queries), nq, _ptr(l), _ptr(h), k, ef,
+                                                 _ptr(strategy), C.byref(prm), _ptr(self.ids), _ptr(self.dist),
+                                                 _ptr(self.strategy_run), _ptr(self.stats), C.byref(self._b)))
+
+    def run(self, stream=None) -> None:
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(torch.device("cuda", self.index.device))
+        _check(load_library().unify_batch_run(self._b, s.cuda_stream))
+
+    def close(self) -> None:
+        if getattr(self, "_b", None) and self._b.value:
+            load_library().unify_batch_free(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

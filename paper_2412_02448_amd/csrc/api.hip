@@ -310,6 +310,25 @@ int unify_last_timing(unify_index_t ix, float* plan_ms, float* search_ms, float*
   return UNIFY_OK;
 }
 
+int unify_batch_create(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                       int32_t k, int32_t ef, const int8_t* strategy, const unify_params* params, int64_t* out_ids,
+                       float* out_dist, int8_t* out_strategy, int32_t* out_stats, unify_batch_t* out) {
+  return batch_create(ix, queries, nq, l, h, k, ef, strategy, params, out_ids, out_dist, out_strategy, out_stats,
+                      out);
+}
+
+int unify_batch_run(unify_batch_t b, void* hip_stream) { return batch_run(b, hip_stream); }
+
+int unify_batch_free(unify_batch_t b) {
+  if (!b) return UNIFY_OK;
+  (void)hipSetDevice(b->ix->device);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->scratch) (void)hipFree(b->scratch);
+  delete b;
+  return UNIFY_OK;
+}
+
 int unify_free_index(unify_index_t ix) {
   if (!ix) return UNIFY_OK;
   (void)hipSetDevice(ix->device);

@@ -961,36 +961,19 @@ KernelFn kernel_for(int d, int prec) {
     }                                                                        \
   } while (0)
 
-int launch_pass(KernelFn fn, SearchArgs A, int device, hipStream_t st, size_t lds) {
-  HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  int per_cu = 0;
-  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), 64, lds));
-  int cus = 0;
-  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-  if (per_cu < 1) {
-    set_error("search kernel does not fit on a compute unit");
-    return UNIFY_EDEVICE;
-  }
-  int64_t grid = (int64_t)per_cu * cus;
-  if (grid > A.nslots) grid = A.nslots;
-  if (grid > A.nq) grid = A.nq;
-  if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), lds, st, A);
-  HIP_OK(hipGetLastError());
-  return UNIFY_OK;
-}
+// Validated parameters of one search configuration.
+struct Resolved {
+  int32_t k, ef, m, p, ccap, hcap, rerank, pre_chunk;
+  int64_t tauA, tauB;
+  uint32_t flags;
+};
 
-}  // namespace
-
-int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
-                int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
-                float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream) {
+int resolve(unify_index_t ix, int64_t nq, int32_t k, int32_t ef, const unify_params* prm, Resolved& R) {
   if (!ix) {
     set_error("null index");
     return UNIFY_EINVAL;
   }
-  if (nq < 0 || nq >= (int64_t(1) << 31)) {
+  if (nq < 0 || nq >= (int64_t(1) << 28)) {
     set_error("nq out of range");
     return UNIFY_EINVAL;
   }
@@ -1005,23 +988,270 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
   unify_params P{};
   if (prm) P = *prm;
   const DevIndex& dv = ix->dv;
-  const int m = P.m > 0 ? P.m : dv.M0;
-  const int p = P.beam_p > 0 ? P.beam_p : 1;
+  R.k = k;
+  R.ef = ef;
+  R.m = P.m > 0 ? P.m : dv.M0;
+  R.p = P.beam_p > 0 ? P.beam_p : 1;
   const double ta = P.tau_a_frac > 0 ? P.tau_a_frac : 0.01;
   const double tb = P.tau_b_frac > 0 ? P.tau_b_frac : 0.5;
-  int ccap = P.cand_cap > 0 ? P.cand_cap : 512;
-  const int hcap = P.visit_cap > 0 ? P.visit_cap : 1024;
-  const int rerank = P.rerank_mult > 0 ? P.rerank_mult : 4;
-  const int pre_chunk = P.pre_chunk > 0 ? P.pre_chunk : 2048;
-  if (m > dv.S * dv.M0 || p > 8 || ta > 1.0 || tb > 1.0 || ccap < 64 || ccap > 4096 || (ccap & (ccap - 1)) ||
-      hcap < 256 || hcap > 16384 || (hcap & (hcap - 1)) || rerank > 256 || pre_chunk < 64) {
+  R.ccap = P.cand_cap > 0 ? P.cand_cap : 512;
+  R.hcap = P.visit_cap > 0 ? P.visit_cap : 1024;
+  R.rerank = P.rerank_mult > 0 ? P.rerank_mult : 4;
+  R.pre_chunk = P.pre_chunk > 0 ? P.pre_chunk : 2048;
+  R.flags = P.flags;
+  if (R.m > dv.S * dv.M0 || R.p > 8 || ta > 1.0 || tb > 1.0 || R.ccap < 64 || R.ccap > 4096 ||
+      (R.ccap & (R.ccap - 1)) || R.hcap < 256 || R.hcap > 16384 || (R.hcap & (R.hcap - 1)) || R.rerank > 256 ||
+      R.pre_chunk < 64) {
     set_error("params out of range (m <= S*M0, beam_p <= 8, tau fractions <= 1, cand_cap and visit_cap powers "
               "of two in [64, 4096] and [256, 16384], rerank_mult <= 256, pre_chunk >= 64)");
     return UNIFY_EINVAL;
   }
   // the FP32 rerank of a low-precision search builds its k results in the candidate array
   if (dv.precision != UNIFY_FP32)
-    while (ccap < k) ccap *= 2;
+    while (R.ccap < k) R.ccap *= 2;
+  R.tauA = (int64_t)std::floor(ta * (double)dv.n);
+  R.tauB = (int64_t)std::ceil(tb * (double)dv.n);
+  if (!kernel_for<0>(dv.d, dv.precision)) {
+    set_error("unsupported dimension");
+    return UNIFY_EINVAL;
+  }
+  return UNIFY_OK;
+}
+
+// Visited tags: one row of n epochs per persistent wave, kept with the index.
+int ensure_tags(unify_index_t ix) {
+  if (ix->tags) return UNIFY_OK;
+  const DevIndex& dv = ix->dv;
+  HIP_OK(hipDeviceGetAttribute(&ix->cus, hipDeviceAttributeMultiprocessorCount, ix->device));
+  size_t free_b = 0, total_b = 0;
+  HIP_OK(hipMemGetInfo(&free_b, &total_b));
+  int64_t slots = (int64_t)ix->cus * 16;
+  const int64_t fit = (int64_t)(free_b / 4 / (sizeof(uint32_t) * (size_t)dv.n));
+  if (slots > fit) slots = fit;
+  if (slots < 1) {
+    set_error("no device memory for the visited tags");
+    return UNIFY_ENOMEM;
+  }
+  void* t = nullptr;
+  void* e = nullptr;
+  if (hipMalloc(&t, sizeof(uint32_t) * (size_t)dv.n * slots) != hipSuccess ||
+      hipMalloc(&e, sizeof(uint32_t) * slots) != hipSuccess) {
+    if (t) (void)hipFree(t);
+    set_error("no device memory for the visited tags");
+    return UNIFY_ENOMEM;
+  }
+  HIP_OK(hipMemset(t, 0, sizeof(uint32_t) * (size_t)dv.n * slots));
+  HIP_OK(hipMemset(e, 0, sizeof(uint32_t) * slots));
+  HIP_OK(hipDeviceSynchronize());
+  ix->tags = static_cast<uint32_t*>(t);
+  ix->epochs = static_cast<uint32_t*>(e);
+  ix->nslots = slots;
+  ix->allocs.push_back(t);
+  ix->allocs.push_back(e);
+  return UNIFY_OK;
+}
+
+// Per-call device scratch: plans, work list (graph queries and pre-filter
+// chunks), chunk of each entry, fallback list, counters, per-query merge
+// counters, partial top-k lists of split pre-filter scans.
+struct Scratch {
+  QPlan* plan;
+  int32_t *work, *wchunk, *fb, *counters, *qacc;
+  u64* part;
+};
+
+size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t scratch_layout(int64_t nq, int k, void* base, Scratch* S) {
+  const int64_t wcap = nq * PRE_NCH_MAX;
+  const size_t plan_b = up256(sizeof(QPlan) * nq), work_b = up256(sizeof(int32_t) * wcap),
+               fb_b = up256(sizeof(int32_t) * nq), acc_b = up256(sizeof(int32_t) * 4 * nq),
+               part_b = k <= PRE_SPLIT_KMAX ? up256(sizeof(u64) * (size_t)wcap * k) : 0;
+  if (S) {
+    char* sp = static_cast<char*>(base);
+    S->plan = reinterpret_cast<QPlan*>(sp);
+    S->work = reinterpret_cast<int32_t*>(sp += plan_b);
+    S->wchunk = reinterpret_cast<int32_t*>(sp += work_b);
+    S->fb = reinterpret_cast<int32_t*>(sp += work_b);
+    S->counters = reinterpret_cast<int32_t*>(sp += fb_b);  // nwork, next, fb_count, fb_next
+    S->qacc = reinterpret_cast<int32_t*>(sp += 256);
+    S->part = part_b ? reinterpret_cast<u64*>(sp += acc_b) : nullptr;
+  }
+  return plan_b + 2 * work_b + fb_b + 256 + acc_b + part_b;
+}
+
+// A launch configuration of the persistent search kernel, prepared outside any
+// stream capture: dynamic LDS size set on the function, grid from occupancy.
+struct Pass {
+  KernelFn fn;
+  size_t lds;
+  unsigned grid;
+};
+
+int prepare_pass(unify_index_t ix, KernelFn fn, size_t lds, int64_t nq, Pass& out) {
+  const auto key = std::make_pair(reinterpret_cast<const void*>(fn), lds);
+  auto it = ix->occupancy.find(key);
+  int per_cu = 0;
+  if (it != ix->occupancy.end()) {
+    per_cu = it->second;
+  } else {
+    HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), 64, lds));
+    ix->occupancy[key] = per_cu;
+  }
+  if (per_cu < 1) {
+    set_error("search kernel does not fit on a compute unit");
+    return UNIFY_EDEVICE;
+  }
+  int64_t grid = (int64_t)per_cu * ix->cus;
+  grid = std::min<int64_t>(grid, ix->nslots);
+  grid = std::min<int64_t>(grid, nq);
+  out.fn = fn;
+  out.lds = lds;
+  out.grid = (unsigned)std::max<int64_t>(grid, 1);
+  return UNIFY_OK;
+}
+
+// Everything one search launches, with its arguments fixed.
+struct Launch {
+  DevIndex dv;
+  const float* queries;
+  int64_t nq;
+  const int64_t *l, *h;
+  const int8_t* strategy;
+  int64_t* out_ids;
+  float* out_dist;
+  int8_t* out_strategy;
+  int32_t* out_stats;
+  Resolved R;
+  Scratch S;
+  SearchArgs A, B;  // first pass, re-run pass
+  Pass p0, p1;
+};
+
+int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, int64_t nq, const int64_t* l,
+                   const int64_t* h, const int8_t* strategy, int64_t* out_ids, float* out_dist,
+                   int8_t* out_strategy, int32_t* out_stats, void* scratch, Launch& X) {
+  const DevIndex& dv = ix->dv;
+  X.dv = dv;
+  X.queries = queries;
+  X.nq = nq;
+  X.l = l;
+  X.h = h;
+  X.strategy = strategy;
+  X.out_ids = out_ids;
+  X.out_dist = out_dist;
+  X.out_strategy = out_strategy;
+  X.out_stats = out_stats;
+  X.R = R;
+  scratch_layout(nq, R.k, scratch, &X.S);
+  const int S = dv.S;
+  const int per_node = std::max(std::min(R.m + S - 1, S * std::max(dv.M0, dv.MU)), dv.GC);
+  const int nb1 = (per_node + WAVE - 1) / WAVE * WAVE;
+  SearchArgs A{};
+  A.ix = dv;
+  A.Q = queries;
+  A.nq = nq;
+  A.k = R.k;
+  A.ef = R.ef;
+  A.m = R.m;
+  A.p = R.p;
+  A.rerank = R.rerank;
+  {
+    // canonical FP32 distance: each term passes through at most e + 6 roundings
+    // (the subtraction, squared; e fused multiply-adds; 4 butterfly additions),
+    // e = elements per partial sum, so its relative error is at most
+    // g = n u / (1 - n u), n = e + 6, u = 2^-24
+    const int G = dv.d / 4;
+    const double nr = 4.0 * ((G + 15) / 16) + 6.0, u = std::ldexp(1.0, -24);
+    const double g = nr * u / (1.0 - nr * u), w = std::ldexp(1.0, -20);
+    A.bA = (float)(std::sqrt((1.0 - g) / (1.0 + g)) * (1.0 - w));
+    A.bB = (float)(std::sqrt(1.0 - g) * (1.0 + w));
+    A.bC = (float)(std::sqrt((1.0 + g) / (1.0 - g)) * (1.0 + w));
+    A.bD = (float)(std::sqrt(1.0 + g) * (1.0 + w));
+  }
+  A.ef_blocks = (std::max(R.ef, R.k) + WAVE - 1) / WAVE;
+  A.nbr_cap = std::max(R.p * nb1, WAVE);
+  A.out_ids = out_ids;
+  A.out_dist = out_dist;
+  A.out_stats = out_stats;
+  A.plan = X.S.plan;
+  A.tags = ix->tags;
+  A.epochs = ix->epochs;
+  A.nslots = ix->nslots;
+  // first pass: modest LDS per wave for occupancy
+  A.ccap = R.ccap;
+  A.hcap = R.hcap;
+  A.pass = 0;
+  A.work = X.S.work;
+  A.wchunk = X.S.wchunk;
+  A.part = X.S.part;
+  A.qacc = X.S.qacc;
+  A.nwork = X.S.counters + 0;
+  A.next = X.S.counters + 1;
+  A.fb_list = X.S.fb;
+  A.fb_count = X.S.counters + 2;
+  // second pass over the abandoned queries with the largest LDS that fits
+  int maxlds = 0;
+  if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) != hipSuccess)
+    maxlds = 65536;
+  int cc = 16384, hc = std::max(R.hcap, 2048);
+  while (lds_bytes(A.ef_blocks, cc, hc, A.nbr_cap) > (size_t)maxlds && cc > 2 * R.ccap) cc /= 2;
+  SearchArgs B = A;
+  B.ccap = cc;
+  B.hcap = hc;
+  B.pass = 1;
+  B.work = X.S.fb;
+  B.wchunk = nullptr;  // only graph searches are re-run
+  B.nwork = X.S.counters + 2;
+  B.next = X.S.counters + 3;
+  X.A = A;
+  X.B = B;
+  int rc = prepare_pass(ix, kernel_for<0>(dv.d, dv.precision), lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap),
+                        nq, X.p0);
+  if (rc == UNIFY_OK)
+    rc = prepare_pass(ix, kernel_for<1>(dv.d, dv.precision), lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap), nq,
+                      X.p1);
+  return rc;
+}
+
+// Kernel launches only (no allocation, no memset, no synchronisation), so the
+// sequence can be captured into a HIP graph.  ev: 4 events to record, or null.
+int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev) {
+  const unsigned pb = 256;
+  const int64_t nq = X.nq;
+  if (ev) HIP_OK(hipEventRecord(ev[0], st));
+  hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, X.dv, X.l, X.h, X.strategy, nq,
+                     X.R.tauA, X.R.tauB, X.R.k, X.R.pre_chunk, X.S.plan, X.out_strategy, X.out_ids, X.out_dist,
+                     X.out_stats);
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((4 * nq + pb - 1) / pb)), dim3(pb), 0, st, X.S.qacc, 4 * nq, 0);
+  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, X.S.plan, nq, X.dv.n, X.S.work, X.S.wchunk,
+                     X.S.counters);
+  HIP_OK(hipGetLastError());
+  if (ev) HIP_OK(hipEventRecord(ev[1], st));
+  hipLaunchKernelGGL(X.p0.fn, dim3(X.p0.grid), dim3(64), X.p0.lds, st, X.A);
+  HIP_OK(hipGetLastError());
+  if (X.S.part) {
+    hipLaunchKernelGGL(k_pre_merge, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, X.dv, X.S.plan, nq, X.R.k,
+                       X.S.part, X.S.qacc, X.out_ids, X.out_dist, X.out_stats);
+    HIP_OK(hipGetLastError());
+  }
+  if (ev) HIP_OK(hipEventRecord(ev[2], st));
+  hipLaunchKernelGGL(X.p1.fn, dim3(X.p1.grid), dim3(64), X.p1.lds, st, X.B);
+  HIP_OK(hipGetLastError());
+  if (ev) HIP_OK(hipEventRecord(ev[3], st));
+  return UNIFY_OK;
+}
+
+}  // namespace
+
+int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
+                float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream) {
+  Resolved R;
+  int rc = resolve(ix, nq, k, ef, prm, R);
+  if (rc != UNIFY_OK) return rc;
   if (!queries || !l || !h || !out_ids || !out_dist) {
     if (nq == 0) return UNIFY_OK;
     set_error("null buffer");
@@ -1030,155 +1260,86 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
   if (nq == 0) return UNIFY_OK;
   HIP_OK(hipSetDevice(ix->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int64_t tauA = (int64_t)std::floor(ta * (double)dv.n);
-  const int64_t tauB = (int64_t)std::ceil(tb * (double)dv.n);
-
-  // visited tags: one row of n epochs per persistent wave, kept with the index
-  if (!ix->tags) {
-    int cus = 0;
-    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ix->device));
-    size_t free_b = 0, total_b = 0;
-    HIP_OK(hipMemGetInfo(&free_b, &total_b));
-    int64_t slots = (int64_t)cus * 16;
-    const int64_t fit = (int64_t)(free_b / 4 / (sizeof(uint32_t) * (size_t)dv.n));
-    if (slots > fit) slots = fit;
-    if (slots < 1) {
-      set_error("no device memory for the visited tags");
-      return UNIFY_ENOMEM;
-    }
-    void* t = nullptr;
-    void* e = nullptr;
-    if (hipMalloc(&t, sizeof(uint32_t) * (size_t)dv.n * slots) != hipSuccess ||
-        hipMalloc(&e, sizeof(uint32_t) * slots) != hipSuccess) {
-      if (t) (void)hipFree(t);
-      set_error("no device memory for the visited tags");
-      return UNIFY_ENOMEM;
-    }
-    HIP_OK(hipMemset(t, 0, sizeof(uint32_t) * (size_t)dv.n * slots));
-    HIP_OK(hipMemset(e, 0, sizeof(uint32_t) * slots));
-    HIP_OK(hipDeviceSynchronize());
-    ix->tags = static_cast<uint32_t*>(t);
-    ix->epochs = static_cast<uint32_t*>(e);
-    ix->nslots = slots;
-    ix->allocs.push_back(t);
-    ix->allocs.push_back(e);
-  }
-
-  // scratch: plans, work list (graph queries and pre-filter chunks), chunk of each
-  // entry, fallback list, counters, per-query merge counters, partial top-k lists
-  auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
-  const int64_t wcap = nq * PRE_NCH_MAX;
-  const size_t plan_b = up256(sizeof(QPlan) * nq), work_b = up256(sizeof(int32_t) * wcap),
-               fb_b = up256(sizeof(int32_t) * nq), acc_b = up256(sizeof(int32_t) * 4 * nq),
-               part_b = k <= PRE_SPLIT_KMAX ? up256(sizeof(u64) * (size_t)wcap * k) : 0;
-  void* scratch = nullptr;
-  HIP_OK(hipMallocAsync(&scratch, plan_b + 2 * work_b + fb_b + 256 + acc_b + part_b, st));
-  char* sp = reinterpret_cast<char*>(scratch);
-  QPlan* plan = reinterpret_cast<QPlan*>(sp);
-  int32_t* work = reinterpret_cast<int32_t*>(sp += plan_b);
-  int32_t* wchunk = reinterpret_cast<int32_t*>(sp += work_b);
-  int32_t* fb = reinterpret_cast<int32_t*>(sp += work_b);
-  int32_t* counters = reinterpret_cast<int32_t*>(sp += fb_b);  // nwork, next, fb_count, fb_next
-  int32_t* qacc = reinterpret_cast<int32_t*>(sp += 256);
-  u64* part = part_b ? reinterpret_cast<u64*>(sp += acc_b) : nullptr;
-
-  const bool timing = (P.flags & UNIFY_FLAG_TIMING) != 0;
-  int rc = UNIFY_OK;
+  rc = ensure_tags(ix);
+  if (rc != UNIFY_OK) return rc;
+  const bool timing = (R.flags & UNIFY_FLAG_TIMING) != 0;
   if (timing) {
-    for (int e = 0; e < 4 && rc == UNIFY_OK; ++e)
-      if (!ix->ev[e] && hipEventCreate(&ix->ev[e]) != hipSuccess) rc = UNIFY_EDEVICE;
-    ix->timed = rc == UNIFY_OK;
+    for (int e = 0; e < 4; ++e)
+      if (!ix->ev[e]) HIP_OK(hipEventCreate(&ix->ev[e]));
+    ix->timed = true;
   }
-  if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[0], st) != hipSuccess) rc = UNIFY_EDEVICE;
-  const unsigned pb = 256;
-  hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, dv, l, h, strategy, nq,
-                     tauA, tauB, k, pre_chunk, plan, out_strategy, out_ids, out_dist, out_stats);
-  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((4 * nq + pb - 1) / pb)), dim3(pb), 0, st, qacc, 4 * nq, 0);
-  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, plan, nq, dv.n, work, wchunk, counters);
-  if (hipGetLastError() != hipSuccess) rc = UNIFY_EDEVICE;
-
-  KernelFn fn = kernel_for<0>(dv.d, dv.precision);
-  KernelFn fn_rerun = kernel_for<1>(dv.d, dv.precision);
-  if (rc == UNIFY_OK && (!fn || !fn_rerun)) {
-    set_error("unsupported dimension");
-    rc = UNIFY_EINVAL;
-  }
-  if (rc == UNIFY_OK) {
-    const int S = dv.S;
-    const int per_node = std::max(std::min(m + S - 1, S * std::max(dv.M0, dv.MU)), dv.GC);
-    const int nb1 = (per_node + WAVE - 1) / WAVE * WAVE;
-    SearchArgs A{};
-    A.ix = dv;
-    A.Q = queries;
-    A.nq = nq;
-    A.k = k;
-    A.ef = ef;
-    A.m = m;
-    A.p = p;
-    A.rerank = rerank;
-    {
-      // canonical FP32 distance: each term passes through at most e + 6 roundings
-      // (the subtraction, squared; e fused multiply-adds; 4 butterfly additions),
-      // e = elements per partial sum, so its relative error is at most
-      // g = n u / (1 - n u), n = e + 6, u = 2^-24
-      const int G = dv.d / 4;
-      const double nr = 4.0 * ((G + 15) / 16) + 6.0, u = std::ldexp(1.0, -24);
-      const double g = nr * u / (1.0 - nr * u), w = std::ldexp(1.0, -20);
-      A.bA = (float)(std::sqrt((1.0 - g) / (1.0 + g)) * (1.0 - w));
-      A.bB = (float)(std::sqrt(1.0 - g) * (1.0 + w));
-      A.bC = (float)(std::sqrt((1.0 + g) / (1.0 - g)) * (1.0 + w));
-      A.bD = (float)(std::sqrt(1.0 + g) * (1.0 + w));
-    }
-    A.ef_blocks = (std::max(ef, k) + WAVE - 1) / WAVE;
-    A.nbr_cap = std::max(p * nb1, WAVE);
-    A.out_ids = out_ids;
-    A.out_dist = out_dist;
-    A.out_stats = out_stats;
-    A.plan = plan;
-    A.tags = ix->tags;
-    A.epochs = ix->epochs;
-    A.nslots = ix->nslots;
-    // first pass: modest LDS per wave for occupancy
-    A.ccap = ccap;
-    A.hcap = hcap;
-    A.pass = 0;
-    A.work = work;
-    A.wchunk = wchunk;
-    A.part = part;
-    A.qacc = qacc;
-    A.nwork = counters + 0;
-    A.next = counters + 1;
-    A.fb_list = fb;
-    A.fb_count = counters + 2;
-    if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[1], st) != hipSuccess) rc = UNIFY_EDEVICE;
-    if (rc == UNIFY_OK) rc = launch_pass(fn, A, ix->device, st, lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap));
-    if (rc == UNIFY_OK && part) {
-      hipLaunchKernelGGL(k_pre_merge, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, dv, plan, nq, k, part, qacc,
-                         out_ids, out_dist, out_stats);
-      if (hipGetLastError() != hipSuccess) rc = UNIFY_EDEVICE;
-    }
-    if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[2], st) != hipSuccess) rc = UNIFY_EDEVICE;
-    if (rc == UNIFY_OK) {
-      // second pass over the abandoned queries with the largest LDS that fits
-      int maxlds = 0;
-      if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) != hipSuccess)
-        maxlds = 65536;
-      int cc = 16384, hc = std::max(hcap, 2048);
-      while (lds_bytes(A.ef_blocks, cc, hc, A.nbr_cap) > (size_t)maxlds && cc > 2 * ccap) cc /= 2;
-      SearchArgs B = A;
-      B.ccap = cc;
-      B.hcap = hc;
-      B.pass = 1;
-      B.work = fb;
-      B.wchunk = nullptr;  // only graph searches are re-run
-      B.nwork = counters + 2;
-      B.next = counters + 3;
-      rc = launch_pass(fn_rerun, B, ix->device, st, lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap));
-      if (rc == UNIFY_OK && timing && hipEventRecord(ix->ev[3], st) != hipSuccess) rc = UNIFY_EDEVICE;
-    }
-  }
+  void* scratch = nullptr;
+  HIP_OK(hipMallocAsync(&scratch, scratch_layout(nq, k, nullptr, nullptr), st));
+  Launch X;
+  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, X);
+  if (rc == UNIFY_OK) rc = enqueue_launch(X, st, timing ? ix->ev : nullptr);
   if (hipFreeAsync(scratch, st) != hipSuccess && rc == UNIFY_OK) rc = UNIFY_EDEVICE;
   return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: every buffer allocated once, the launch sequence captured into
+// a HIP graph and replayed.
+// ---------------------------------------------------------------------------
+
+int batch_create(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h, int32_t k,
+                 int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids, float* out_dist,
+                 int8_t* out_strategy, int32_t* out_stats, unify_batch_t* out) {
+  if (!out) {
+    set_error("null output");
+    return UNIFY_EINVAL;
+  }
+  Resolved R;
+  int rc = resolve(ix, nq, k, ef, prm, R);
+  if (rc != UNIFY_OK) return rc;
+  if (nq < 1 || !queries || !l || !h || !out_ids || !out_dist) {
+    set_error("a batch needs nq >= 1 and its query and output buffers");
+    return UNIFY_EINVAL;
+  }
+  R.flags &= ~(uint32_t)UNIFY_FLAG_TIMING;
+  HIP_OK(hipSetDevice(ix->device));
+  rc = ensure_tags(ix);
+  if (rc != UNIFY_OK) return rc;
+  unify_batch_t b = new unify_batch();
+  b->ix = ix;
+  auto fail = [&](int code, const char* msg) {
+    set_error(msg);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->scratch) (void)hipFree(b->scratch);
+    delete b;
+    return code;
+  };
+  if (hipMalloc(&b->scratch, scratch_layout(nq, k, nullptr, nullptr)) != hipSuccess)
+    return fail(UNIFY_ENOMEM, "device allocation failed (batch scratch)");
+  Launch X;
+  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, b->scratch, X);
+  if (rc != UNIFY_OK) return fail(rc, "batch preparation failed");
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    return fail(UNIFY_EDEVICE, "hipStreamCreate failed");
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = enqueue_launch(X, cs, nullptr);
+    const hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
+    if (e2 != hipSuccess) e = e2;
+  }
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess || rc != UNIFY_OK) return fail(UNIFY_EDEVICE, "capturing the search into a graph failed");
+  if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+    return fail(UNIFY_EDEVICE, "hipGraphInstantiate failed");
+  *out = b;
+  return UNIFY_OK;
+}
+
+int batch_run(unify_batch_t b, void* stream) {
+  if (!b) {
+    set_error("null batch");
+    return UNIFY_EINVAL;
+  }
+  HIP_OK(hipSetDevice(b->ix->device));
+  HIP_OK(hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream)));
+  return UNIFY_OK;
 }
 
 }  // namespace unify

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/unify.h"
@@ -85,7 +87,24 @@ struct unify_index {
   uint32_t* epochs = nullptr;  // [nslots]
   int64_t nslots = 0;
   const float* eps_of[3] = {nullptr, nullptr, nullptr};  // error bounds of the resident BF16 / FP8 copies
+  int cus = 0;                                            // compute units of the device
+  std::map<std::pair<const void*, size_t>, int> occupancy;  // (kernel, LDS bytes) -> waves per CU
   unify::DevIndex dv{};
   unify::HostIndex host;  // small tables kept on the host; large ones released after upload
   std::vector<void*> allocs;
 };
+
+// A batch: the search over fixed caller buffers captured as a HIP graph.
+struct unify_batch {
+  unify_index_t ix = nullptr;
+  void* scratch = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace unify {
+int batch_create(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h, int32_t k,
+                 int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids, float* out_dist,
+                 int8_t* out_strategy, int32_t* out_stats, unify_batch_t* out);
+int batch_run(unify_batch_t b, void* stream);
+}  // namespace unify
