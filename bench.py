@@ -60,6 +60,7 @@ def parse():
                          "and one counted call (every search-kernel launch has the same configuration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch100k", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=0, help="queries in the CPU sample (0: all)")
     return ap.parse_args()
 
@@ -242,6 +243,15 @@ def main():
             log(f"batch100k failed: {e!r}")
             b100 = {"failed": repr(e)}
 
+    # ---- serving: open-loop Poisson arrivals through the continuous-batching server ----
+    serving = None
+    if not args.no_serving:
+        try:
+            serving = serve_bench(args, index, spec, W, m, ef, bp, head)
+        except Exception as e:  # the headline line is still reported
+            log(f"serving failed: {e!r}")
+            serving = {"failed": repr(e)}
+
     # ---- CPU baseline: the oracle's HSIG search on the same index ----
     cpu = None
     if not args.no_cpu_baseline:
@@ -266,9 +276,54 @@ def main():
         "per_strategy": per_strategy,
         "roofline": roofline,
         "batch100k": b100,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def serve_bench(args, index, spec, W, m, ef, bp, prec):
+    """Poisson arrivals at several rates into the server over the mixed1m index, with
+    the serving range mix (30% of fractions log-uniform in [1e-5, 1e-3), 40% in
+    [1e-3, 0.1), 30% in [0.1, 1]); latency = completion - arrival per request."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import paper_2412_02448_amd as u
+    from synth import workloads as w
+    sspec = dataclasses.replace(spec, ranges="serving")
+    k = spec.k
+    n = 40000
+    q, l, h, _ = w.more_queries(sspec, W.attr, n, base_seed=0, stream=5)
+    # the same requests searched as one batch: each served result must equal its row
+    dev = torch.device("cuda", 0)
+    ref = index.search(torch.from_numpy(q).to(dev), torch.from_numpy(l).to(dev), torch.from_numpy(h).to(dev), k,
+                       ef, m=m, beam_p=bp)[0].cpu().numpy()
+    rng = np.random.default_rng(12)
+    rows = []
+    for rate in (10_000, 100_000, 1_000_000, None):
+        cnt = n if rate is None or rate >= 100_000 else 20_000
+        arrive = np.zeros(cnt) if rate is None else np.cumsum(rng.exponential(1.0 / rate, cnt))
+        srv = u.Server(index, k, ef, max_batch=4096, inflight=2, m=m, beam_p=bp)
+        t0 = time.perf_counter()
+        tickets = srv.submit(q[:cnt], l[:cnt], h[:cnt], arrive_s=arrive)
+        ids, _, lat = srv.wait(tickets, timeout_s=120)
+        wall = time.perf_counter() - t0
+        done, batches, busy = srv.stats()
+        srv.close()
+        span = max(wall, 1e-9)
+        row = {"offered_qps": rate if rate else "all at t=0", "requests": cnt, "achieved_qps": round(cnt / span, 1),
+               "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "batches": batches,
+               "mean_batch": round(cnt / max(batches, 1), 1),
+               "equal_to_batch_search": bool(np.array_equal(ids, ref[:cnt]))}
+        rows.append(row)
+        log(f"serving {row['offered_qps']}: {row['achieved_qps']:,.0f} QPS, p50 {row['p50_ms']} ms, "
+            f"p99 {row['p99_ms']} ms, {batches} batches, identical {row['equal_to_batch_search']}")
+    return {"workload": f"mixed1m index ({prec} store, m={m} ef={ef} p={bp}), k={k}, serving range mix",
+            "max_batch": 4096, "inflight": 2, "rates": rows}
 
 
 def batch100k(args, prec):

@@ -147,6 +147,9 @@ int unify_index_info(unify_index_t index, int64_t* n, int32_t* d, int32_t* S, in
  *   out_strategy  device, [nq] int8 strategy actually run, or NULL
  *   hip_stream    hipStream_t to enqueue on, or NULL
  * nq = 0 is a no-op.  Scratch space is allocated by the library per call.
+ * Calls may come from several threads and streams: the search kernels of
+ * successive calls on one index run one after another (they share the index's
+ * visited-set memory), ordered by an event the library records.
  */
 int unify_search(unify_index_t index, const float* queries, int64_t nq, const int64_t* l,
                  const int64_t* h, int32_t k, int32_t ef, const int8_t* strategy,
@@ -222,6 +225,43 @@ int unify_batch_create(unify_index_t index, const float* queries, int64_t nq, co
                        unify_batch_t* out);
 int unify_batch_run(unify_batch_t batch, void* hip_stream);
 int unify_batch_free(unify_batch_t batch);  /* NULL is accepted */
+
+/*
+ * Serving: continuous batching over a resident index (one worker thread per
+ * server).  Requests are submitted from host memory with an arrival time; the
+ * worker admits the requests that have arrived into a batch whenever one of
+ * its `inflight` slots is free (each slot holds pinned staging, device buffers
+ * and scratch for max_batch queries, allocated at creation, so admission is
+ * bounded by slot memory and no allocation happens while serving), searches it
+ * on the slot's stream and completes the requests when the slot's event fires.
+ * Every request's result is the one unify_search returns for it alone.
+ */
+typedef struct unify_server* unify_server_t;
+typedef struct {
+  int32_t k, ef;          /* results per request and beam, as for unify_search */
+  int32_t max_batch;      /* requests per launch at most; default 4096 */
+  int32_t inflight;       /* batches in flight, 1..8; default 2 */
+  double max_wait_s;      /* a partial batch waits until its oldest request has waited this
+                             long (0: it launches as soon as a slot is free) */
+  unify_params params;    /* search parameters (flags ignored) */
+} unify_server_config;
+
+int unify_server_create(unify_index_t index, const unify_server_config* config, unify_server_t* out);
+/* Submits n requests (host arrays: queries [n][d] f32, l, h [n] i64, strategy [n]
+ * i8 or NULL for UNIFY_AUTO).  arrive_s [n] (or NULL for now): seconds from the
+ * call at which each request arrives; the worker ignores a request until then
+ * (an open-loop arrival process).  tickets [n] receives one id per request. */
+int unify_server_submit(unify_server_t server, int64_t n, const float* queries, const int64_t* l,
+                        const int64_t* h, const int8_t* strategy, const double* arrive_s, int64_t* tickets);
+/* Waits for n tickets (timeout_s <= 0: no limit) and copies their results to host
+ * arrays ids [n][k], dist [n][k] and latency_s [n] (completion - arrival), any may
+ * be NULL.  UNIFY_EIO on time-out.  Results stay retrievable until the server is freed. */
+int unify_server_wait(unify_server_t server, int64_t n, const int64_t* tickets, int64_t* ids, float* dist,
+                      double* latency_s, double timeout_s);
+/* Requests completed, batches launched, and seconds with at least one batch in flight. */
+int unify_server_stats(unify_server_t server, int64_t* completed, int64_t* batches, double* busy_s);
+/* Serves every submitted request, stops the worker and frees the server (NULL accepted). */
+int unify_server_free(unify_server_t server);
 
 /* Frees the index and its device memory.  NULL is accepted. */
 int unify_free_index(unify_index_t index);

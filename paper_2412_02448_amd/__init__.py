@@ -56,6 +56,11 @@ SIGNATURES = {
     "unify_copy_store": (_I32, [_P, _I32, _P, _P, _P, _P]),
     "unify_set_precision": (_I32, [_P, _I32]),
     "unify_batch_create": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "unify_server_create": (_I32, [_P, _P, _P]),
+    "unify_server_submit": (_I32, [_P, _I64, _P, _P, _P, _P, _P, _P]),
+    "unify_server_wait": (_I32, [_P, _I64, _P, _P, _P, _P, C.c_double]),
+    "unify_server_stats": (_I32, [_P, _P, _P, _P]),
+    "unify_server_free": (_I32, [_P]),
     "unify_batch_run": (_I32, [_P, _P]),
     "unify_batch_free": (_I32, [_P]),
     "unify_free_index": (_I32, [_P]),
@@ -268,6 +273,70 @@ class Batch:
         if getattr(self, "_b", None) and self._b.value:
             load_library().unify_batch_free(self._b)
             self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _ServerConfig(C.Structure):
+    _fields_ = [("k", C.c_int32), ("ef", C.c_int32), ("max_batch", C.c_int32), ("inflight", C.c_int32),
+                ("max_wait_s", C.c_double), ("params", _Params)]
+
+
+class Server:
+    """Continuous-batching server over a resident index (the library's worker
+    thread admits arrived requests into batches of at most max_batch whenever
+    one of `inflight` slots is free).  Requests come from host arrays."""
+
+    def __init__(self, index: Index, k: int, ef: int, max_batch: int = 4096, inflight: int = 2,
+                 max_wait_s: float = 0.0, m: int = 0, beam_p: int = 1, rerank_mult: int = 0, tau_a: float = 0.0,
+                 tau_b: float = 0.0, cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0):
+        self.index, self.k = index, k
+        cfg = _ServerConfig(k, ef, max_batch, inflight, max_wait_s,
+                            _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, 0, visit_cap, pre_chunk))
+        self._s = C.c_void_p()
+        _check(load_library().unify_server_create(index._h, C.byref(cfg), C.byref(self._s)))
+
+    def submit(self, queries, l, h, strategy=None, arrive_s=None) -> np.ndarray:
+        """Submits len(l) requests; arrive_s: seconds from now at which each arrives (None: now).
+        Returns their tickets."""
+        q = np.ascontiguousarray(queries, np.float32)
+        lo = np.ascontiguousarray(l, np.int64)
+        hi = np.ascontiguousarray(h, np.int64)
+        n = lo.shape[0]
+        if q.shape != (n, self.index.d) or hi.shape != (n,):
+            raise ValueError("queries must be [n, d] and l, h [n]")
+        st = None if strategy is None else np.ascontiguousarray(strategy, np.int8)
+        ar = None if arrive_s is None else np.ascontiguousarray(arrive_s, np.float64)
+        t = np.zeros(n, np.int64)
+        p = lambda a: None if a is None else a.ctypes.data  # noqa: E731
+        _check(load_library().unify_server_submit(self._s, n, p(q), p(lo), p(hi), p(st), p(ar), p(t)))
+        return t
+
+    def wait(self, tickets, timeout_s: float = 0.0):
+        """(ids [n, k], dist [n, k], latency_s [n]) of the given tickets, waiting for them."""
+        t = np.ascontiguousarray(tickets, np.int64)
+        n = t.shape[0]
+        ids = np.zeros((n, self.k), np.int64)
+        dist = np.zeros((n, self.k), np.float32)
+        lat = np.zeros(n, np.float64)
+        _check(load_library().unify_server_wait(self._s, n, t.ctypes.data, ids.ctypes.data, dist.ctypes.data,
+                                                lat.ctypes.data, float(timeout_s)))
+        return ids, dist, lat
+
+    def stats(self):
+        """(requests completed, batches launched, seconds with a batch in flight)."""
+        c, b, s = C.c_int64(), C.c_int64(), C.c_double()
+        _check(load_library().unify_server_stats(self._s, C.byref(c), C.byref(b), C.byref(s)))
+        return c.value, b.value, s.value
+
+    def close(self) -> None:
+        if getattr(self, "_s", None) and self._s.value:
+            load_library().unify_server_free(self._s)
+            self._s = C.c_void_p()
 
     def __del__(self):
         try:

@@ -334,6 +334,7 @@ int unify_free_index(unify_index_t ix) {
   (void)hipSetDevice(ix->device);
   for (hipEvent_t e : ix->ev)
     if (e) (void)hipEventDestroy(e);
+  if (ix->last_search) (void)hipEventDestroy(ix->last_search);
   for (void* p : ix->allocs) (void)hipFree(p);
   delete ix;
   return UNIFY_OK;

@@ -1218,7 +1218,9 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
 
 // Kernel launches only (no allocation, no memset, no synchronisation), so the
 // sequence can be captured into a HIP graph.  ev: 4 events to record, or null.
-int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev) {
+// order: the index whose previous search kernels the search kernels must follow
+// (null inside a graph capture, where the caller orders the replay instead).
+int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, unify_index_t order = nullptr) {
   const unsigned pb = 256;
   const int64_t nq = X.nq;
   if (ev) HIP_OK(hipEventRecord(ev[0], st));
@@ -1230,6 +1232,12 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev) {
                      X.S.counters);
   HIP_OK(hipGetLastError());
   if (ev) HIP_OK(hipEventRecord(ev[1], st));
+  std::unique_lock<std::mutex> g;
+  if (order) {
+    g = std::unique_lock<std::mutex>(order->order_mu);
+    if (!order->last_search) HIP_OK(hipEventCreateWithFlags(&order->last_search, hipEventDisableTiming));
+    else HIP_OK(hipStreamWaitEvent(st, order->last_search, 0));
+  }
   hipLaunchKernelGGL(X.p0.fn, dim3(X.p0.grid), dim3(64), X.p0.lds, st, X.A);
   HIP_OK(hipGetLastError());
   if (X.S.part) {
@@ -1240,6 +1248,7 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev) {
   if (ev) HIP_OK(hipEventRecord(ev[2], st));
   hipLaunchKernelGGL(X.p1.fn, dim3(X.p1.grid), dim3(64), X.p1.lds, st, X.B);
   HIP_OK(hipGetLastError());
+  if (order) HIP_OK(hipEventRecord(order->last_search, st));
   if (ev) HIP_OK(hipEventRecord(ev[3], st));
   return UNIFY_OK;
 }
@@ -1272,8 +1281,33 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
   HIP_OK(hipMallocAsync(&scratch, scratch_layout(nq, k, nullptr, nullptr), st));
   Launch X;
   rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, X);
-  if (rc == UNIFY_OK) rc = enqueue_launch(X, st, timing ? ix->ev : nullptr);
+  if (rc == UNIFY_OK) rc = enqueue_launch(X, st, timing ? ix->ev : nullptr, ix);
   if (hipFreeAsync(scratch, st) != hipSuccess && rc == UNIFY_OK) rc = UNIFY_EDEVICE;
+  return rc;
+}
+
+size_t search_scratch_bytes(int64_t nq, int32_t k) { return scratch_layout(nq, k, nullptr, nullptr); }
+
+// unify_search with caller-provided scratch (at least search_scratch_bytes(nq, k)
+// bytes of device memory), for loops that must not allocate per call.
+int search_impl_scratch(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                        int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
+                        float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* scratch,
+                        size_t scratch_bytes, void* stream) {
+  Resolved R;
+  int rc = resolve(ix, nq, k, ef, prm, R);
+  if (rc != UNIFY_OK) return rc;
+  if (nq == 0) return UNIFY_OK;
+  if (!queries || !l || !h || !out_ids || !out_dist || !scratch || scratch_bytes < search_scratch_bytes(nq, k)) {
+    set_error("null buffer or scratch too small");
+    return UNIFY_EINVAL;
+  }
+  HIP_OK(hipSetDevice(ix->device));
+  rc = ensure_tags(ix);
+  if (rc != UNIFY_OK) return rc;
+  Launch X;
+  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, X);
+  if (rc == UNIFY_OK) rc = enqueue_launch(X, reinterpret_cast<hipStream_t>(stream), nullptr, ix);
   return rc;
 }
 
@@ -1338,7 +1372,13 @@ int batch_run(unify_batch_t b, void* stream) {
     return UNIFY_EINVAL;
   }
   HIP_OK(hipSetDevice(b->ix->device));
-  HIP_OK(hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream)));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  unify_index_t ix = b->ix;
+  std::lock_guard<std::mutex> g(ix->order_mu);
+  if (!ix->last_search) HIP_OK(hipEventCreateWithFlags(&ix->last_search, hipEventDisableTiming));
+  else HIP_OK(hipStreamWaitEvent(st, ix->last_search, 0));
+  HIP_OK(hipGraphLaunch(b->exec, st));
+  HIP_OK(hipEventRecord(ix->last_search, st));
   return UNIFY_OK;
 }
 

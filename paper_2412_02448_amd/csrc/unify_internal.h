@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -88,6 +89,10 @@ struct unify_index {
   int64_t nslots = 0;
   const float* eps_of[3] = {nullptr, nullptr, nullptr};  // error bounds of the resident BF16 / FP8 copies
   int cus = 0;                                            // compute units of the device
+  // The visited tags are shared by every search on the index: the search
+  // kernels of successive calls are ordered across streams by this event.
+  std::mutex order_mu;
+  hipEvent_t last_search = nullptr;
   std::map<std::pair<const void*, size_t>, int> occupancy;  // (kernel, LDS bytes) -> waves per CU
   unify::DevIndex dv{};
   unify::HostIndex host;  // small tables kept on the host; large ones released after upload
