@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch100k", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-wide", action="store_true")
+    ap.add_argument("--wide-n", type=int, default=250_000, help="objects of the 960-wide workload")
     ap.add_argument("--cpu-queries", type=int, default=0, help="queries in the CPU sample (0: all)")
     return ap.parse_args()
 
@@ -243,6 +245,15 @@ def main():
             log(f"batch100k failed: {e!r}")
             b100 = {"failed": repr(e)}
 
+    # ---- the 960-wide workload: every store on the GIST-like shape ----
+    wide = None
+    if not args.no_wide:
+        try:
+            wide = wide_bench(args)
+        except Exception as e:  # the headline line is still reported
+            log(f"wide workload failed: {e!r}")
+            wide = {"failed": repr(e)}
+
     # ---- serving: open-loop Poisson arrivals through the continuous-batching server ----
     serving = None
     if not args.no_serving:
@@ -276,10 +287,69 @@ def main():
         "per_strategy": per_strategy,
         "roofline": roofline,
         "batch100k": b100,
+        "wide960": wide,
         "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def wide_bench(args):
+    """GIST-like shape (d = 960, 512-centre mixture, S = 8, M = 16) at n = --wide-n:
+    FP32 vs BF16 vs FP8 stores, each tuned for recall@10 >= 0.95 on held-out queries."""
+    import numpy as np
+    import torch
+
+    import paper_2412_02448_amd as u
+    from paper_2412_02448_amd import autotune
+    from synth import workloads as w
+    spec = w.scaled(w.SPECS["gist1m"], n=args.wide_n)
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    W = w.make(spec, base_seed=0)
+    index = u.Index.build(W.base, W.attr, W.level_u, spec.S, spec.M, spec.ef_cons, device=0)
+    build_s = time.time() - t0
+    Q = torch.from_numpy(W.queries).to(dev)
+    L = torch.from_numpy(W.l).to(dev)
+    H = torch.from_numpy(W.h).to(dev)
+    nq, k, d = Q.shape[0], spec.k, spec.d
+    truth = index.search(Q, L, H, k, k, strategy=u.PRE)[0].cpu().numpy()
+    cq, cl, ch, _ = w.more_queries(spec, W.attr, 1000, base_seed=0, stream=1)
+    Qc, Lc, Hc = (torch.from_numpy(a).to(dev) for a in (cq, cl, ch))
+    out = {"workload": f"gist-like: n={spec.n} d={d} (512-centre mixture, sigma 0.2), attribute uniform in "
+                       f"[0, 2^31), HSIG S={spec.S} M={spec.M} built on GPU ({build_s:.0f}s); {nq} queries, "
+                       f"range fraction log-uniform [1e-3, 1], k={k}"}
+    for prec in ("fp32", "bf16", "fp8"):
+        index.set_precision(prec)
+        best, table = autotune.tune(index, Qc, Lc, Hc, k, args.recall_target, efs=(32, 64, 128))
+        if best is None:
+            best = max(table, key=lambda s: s.recall)
+        m, ef, bp = best.m, best.ef, best.beam_p
+        for _ in range(2):
+            index.search(Q, L, H, k, ef, m=m, beam_p=bp)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            o = index.search(Q, L, H, k, ef, m=m, beam_p=bp)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / 5
+        ids, _, _, st = index.search(Q, L, H, k, ef, m=m, beam_p=bp, stats=True, timing=True)
+        torch.cuda.synchronize()
+        search_ms = index.last_timing()[1]
+        st = st.cpu().numpy().astype(np.int64)
+        b = int(bytes_per_query(st, d, k, prec)[st[:, 3] == 0].sum())
+        ids = o[0].cpu().numpy()
+        rec = float(np.mean([len(set(ids[i][ids[i] >= 0]) & set(truth[i][truth[i] >= 0]))
+                             / max(1, (truth[i] >= 0).sum()) if (truth[i] >= 0).any() else 1.0
+                             for i in range(nq)]))
+        out[prec] = {"qps": round(nq / sec, 1), "recall@10": round(rec, 4), "m": m, "ef": ef, "beam_p": bp,
+                     "search_launch_ms": round(search_ms, 4), "bytes_per_launch": b,
+                     "achieved_GBps": round(b / (search_ms * 1e-3) / 1e9, 1),
+                     "fp32_rescores_per_query": round(float(st[:, 2].mean()), 2)}
+        log(f"wide960 {prec}: {nq / sec:,.0f} QPS, recall {rec:.4f} (m={m} ef={ef} p={bp}), "
+            f"{out[prec]['achieved_GBps']} GB/s algorithmic")
+    index.close()
+    return out
 
 
 def serve_bench(args, index, spec, W, m, ef, bp, prec):

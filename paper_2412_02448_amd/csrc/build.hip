@@ -248,11 +248,15 @@ __device__ __forceinline__ float group_dist(const float4 (&a)[NG], const float4 
   return group_reduce16(acc);
 }
 
+// SG > 0: kept vectors stay in registers (4 per group of 16 lanes, SG groups);
+// SG == 0 (wide vectors): kept ids stay in LDS and their distances to each
+// candidate are evaluated from memory.
 template <int NG, int SG>
 __global__ void __launch_bounds__(64) b_prune(PruneArgs A) {
   __shared__ u64 lst[CAPR];
   __shared__ u64 bk[WAVE];
   __shared__ int32_t ids[WAVE];
+  __shared__ int32_t selid[WAVE];
   const int lane = lane_id(), g4 = lane >> 4;
   for (int64_t t = blockIdx.x; t < A.ntask; t += gridDim.x) {
     const int64_t owner = A.owner0 + t / A.owner_div;
@@ -311,8 +315,37 @@ __global__ void __launch_bounds__(64) b_prune(PruneArgs A) {
       __syncthreads();
       continue;
     }
+    if constexpr (SG == 0) {
+      int nsel = 0;
+      for (int pos = 0; pos < len && nsel < A.Mcap; ++pos) {
+        const u64 key = lst[pos];
+        const int32_t r = key_id(key);
+        const float dvr = key_dist(key);
+        bool bad = false;
+        if (nsel > 0) {
+          float4 xr[NG];
+          load_row<NG>(A.X, A.d, r, xr);
+          eval_keys_generic<NG>(
+              A.d >> 2, xr, nsel, [&](int i) { return selid[i]; },
+              [&](int64_t v, int g) { return *reinterpret_cast<const float4*>(A.X + v * A.d + 4 * g); }, bk);
+          __syncthreads();
+          bad = lane < nsel && key_dist(bk[lane]) < dvr;
+          __syncthreads();
+        }
+        if (__any(bad)) continue;
+        if (lane == 0) {
+          selid[nsel] = r;
+          out[nsel] = key;
+        }
+        ++nsel;
+        __syncthreads();
+      }
+      for (int i = nsel + lane; i < A.Mcap; i += WAVE) out[i] = KEY_MAX;
+      __syncthreads();
+      continue;
+    }
     // greedy selection; kept vectors stay in registers (group g keeps numbers 4s+g)
-    float4 sel[SG][NG];
+    float4 sel[SG > 0 ? SG : 1][NG];
 #pragma unroll
     for (int s = 0; s < SG; ++s)
 #pragma unroll
@@ -503,19 +536,24 @@ int scan(DevBuf& buf, const int32_t* cnt, int64_t n, int64_t* off) {
 typedef void (*PruneFn)(PruneArgs);
 PruneFn prune_kernel(int d, int Mcap) {
   const int ng = (d + 63) / 64;
+  if (Mcap > 64) return nullptr;
   if (Mcap <= 32) {
     if (ng <= 2) return b_prune<2, 8>;
     if (ng <= 4) return b_prune<4, 8>;
-  } else if (Mcap <= 64) {
+  } else {
     if (ng <= 2) return b_prune<2, 16>;
   }
+  if (ng <= 4) return b_prune<4, 0>;
+  if (ng <= 8) return b_prune<8, 0>;
+  if (ng <= 15) return b_prune<15, 0>;
+  if (ng <= 32) return b_prune<32, 0>;
   return nullptr;
 }
 
 int run_prune(PruneArgs A) {
   PruneFn fn = prune_kernel(A.d, A.Mcap);
   if (!fn) {
-    set_error("build: unsupported (d, M) for the GPU builder (d <= 256 with M <= 32, or d <= 128 with M <= 64)");
+    set_error("build: unsupported (d, M) for the GPU builder (d <= 2048, M <= 64)");
     return UNIFY_EINVAL;
   }
   const int64_t grid = std::min<int64_t>(A.ntask, 1 << 20);
@@ -727,9 +765,9 @@ int build_impl(const float* vectors, const int64_t* attr, const double* level_u,
     set_error("build: null argument");
     return UNIFY_EINVAL;
   }
-  if (n < 2 || n >= (int64_t(1) << 31) || d < 4 || d % 4 || d > 256 || S < 1 || S > 64 || M < 2 || M > 64 ||
+  if (n < 2 || n >= (int64_t(1) << 31) || d < 4 || d % 4 || d > 2048 || S < 1 || S > 64 || M < 2 || M > 64 ||
       ef_cons < 1) {
-    set_error("build: arguments out of range (2 <= n < 2^31, d % 4 == 0, d <= 256, 1 <= S <= 64, 2 <= M <= 64)");
+    set_error("build: arguments out of range (2 <= n < 2^31, d % 4 == 0, d <= 2048, 1 <= S <= 64, 2 <= M <= 64)");
     return UNIFY_EINVAL;
   }
   for (int64_t i = 0; i < n; ++i)

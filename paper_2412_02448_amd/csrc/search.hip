@@ -271,9 +271,10 @@ struct Store<UNIFY_FP8E4M3> {
 // vectors per round (16 lanes each, lane s takes groups s, s + 16, ...), RB
 // rounds of raw loads in flight; the i-th vector is id_of(i) and its key lands
 // in keys[i] (LDS).  The hot evaluations use RB = 16 / NG rounds (at most 8:
-// 32 rows in flight at d <= 128); SHALLOW (2 rounds at most) serves the FP32
-// re-scores inside low-precision kernels, whose registers would otherwise
-// add to the hot path's and spill.
+// 32 rows in flight at d <= 128; wider rows keep fewer, since the query itself
+// then holds NG * 4 registers); SHALLOW (2 rounds at most) serves the FP32
+// re-scores inside low-precision kernels, whose registers would otherwise add
+// to the hot path's and spill.
 template <int NG, int PREC, bool SHALLOW = false, class IdOf>
 __device__ __forceinline__ void eval_keys(const DevIndex& ix, const float4 (&qv)[NG], int cnt, IdOf id_of,
                                           u64* keys) {
@@ -342,25 +343,29 @@ __device__ __forceinline__ bool cache_hit(const uint32_t* base, int32_t v) {
   return a.x == u || a.y == u || a.z == u || a.w == u || b.x == u || b.y == u || b.z == u || b.w == u;
 }
 
-// Local mode: true when v is new; `full` when it could not be recorded.
+// Local mode: true when v is new; `full` when it could not be recorded.  Lanes
+// holding the same id in one batch race through the same ways: one inserts it,
+// the others find it in the way they tried and report it visited.
 __device__ __forceinline__ bool visit_local(uint32_t* cache, int setbits, int32_t v, bool& full) {
   uint32_t* base = cache_set(cache, setbits, v);
   if (cache_hit(base, v)) return false;
 #pragma unroll
   for (int w = 0; w < VWAYS; ++w) {
-    if (atomicCAS(base + w, HASH_EMPTY, (uint32_t)v) == HASH_EMPTY) return true;
+    const uint32_t old = atomicCAS(base + w, HASH_EMPTY, (uint32_t)v);
+    if (old == HASH_EMPTY) return true;
+    if (old == (uint32_t)v) return false;
   }
   full = true;
   return true;
 }
 
-// Tagged mode: the tag row is authoritative, the cache only saves reads.
+// Tagged mode: the tag row is authoritative, the cache only saves reads.  The
+// exchange lets exactly one lane of a batch claim an id the batch holds twice.
 __device__ __forceinline__ bool visit_tagged(uint32_t* cache, int setbits, uint32_t* tags, uint32_t epoch,
                                              int32_t v) {
   uint32_t* base = cache_set(cache, setbits, v);
   if (cache_hit(base, v)) return false;
-  if (tags[v] == epoch) return false;
-  tags[v] = epoch;
+  if (__hip_atomic_exchange(tags + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == epoch) return false;
   base[(uint32_t)v & (VWAYS - 1)] = (uint32_t)v;
   return true;
 }
@@ -443,30 +448,44 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
     if (npop == 0) break;
     cnt.nexp += npop;
     cnt.nadj += npop * per_node;
-    // unvisited neighbours of the popped candidates
+    // unvisited neighbours of the popped candidates.  The adjacency entries of
+    // all popped objects are loaded first (GB loads of 64 entries in flight per
+    // wave) into the neighbour buffer, densely, so a step waits for one round
+    // trip; the visited checks then compact the buffer in place.
     int nn = 0;
-    for (int t = 0; t < npop; ++t) {
-      const int32_t o = popped[t];
-      const int32_t* row;
-      if (hybrid) {
-        row = layer == 0 ? ix.adj0 + (int64_t)o * ix.S * mc
-                         : ix.adjU + ((int64_t)ix.uprow[o] + layer - 1) * ix.S * mc;
-      } else {
-        row = layer == 0 ? ix.glist0 + (int64_t)o * ix.GC
-                         : ix.glistU + ((int64_t)ix.uprow[o] + layer - 1) * ix.GC;
+    int64_t rowbase = 0;  // lane t < npop: first entry of popped[t]'s row
+    if (lane < npop) {
+      int32_t o = popped[0];
+      for (int t = 1; t < npop; ++t)
+        if (lane == t) o = popped[t];
+      const int64_t r = layer == 0 ? (int64_t)o : (int64_t)ix.uprow[o] + layer - 1;
+      rowbase = r * (hybrid ? (int64_t)ix.S * mc : (int64_t)ix.GC);
+    }
+    const int32_t* table = hybrid ? (layer == 0 ? ix.adj0 : ix.adjU) : (layer == 0 ? ix.glist0 : ix.glistU);
+    const int cc = min(c, mc);
+    const int ntot = npop * per_node;
+    constexpr int GB = 8;
+    for (int e0 = 0; e0 < ntot; e0 += GB * WAVE) {
+      int32_t vv[GB];
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
+        const int e = e0 + u * WAVE + lane;
+        const int t = e / per_node, tt = e - t * per_node;
+        const int64_t rb = (int64_t)shfl64((u64)rowbase, min(t, WAVE - 1));
+        vv[u] = e < ntot ? (hybrid ? table[rb + (int64_t)(P.a + tt / cc) * mc + tt % cc] : table[rb + tt]) : -1;
       }
-      for (int base = 0; base < per_node; base += WAVE) {
-        const int tt = base + lane;
-        int32_t v = -1;
-        if (tt < per_node) {
-          if (hybrid) {
-            const int cc = min(c, mc);
-            const int j = P.a + tt / cc, r = tt % cc;
-            v = row[j * mc + r];
-          } else {
-            v = row[tt];
-          }
-        }
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
+        const int e = e0 + u * WAVE + lane;
+        if (e < ntot) L.bkeys[e] = (u64)(uint32_t)vv[u];
+      }
+    }
+    __syncthreads();
+    for (int base = 0; base < ntot; base += WAVE) {
+      {
+        const int e = base + lane;
+        const int32_t v = e < ntot ? (int32_t)(uint32_t)L.bkeys[e] : -1;
+        __syncthreads();  // this block is read before new ids are written over it
         bool isnew = false, full = false;
         if (v >= 0) {
           isnew = tagged ? visit_tagged(L.hash, setbits, tags, epoch, v)
@@ -478,7 +497,8 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
             const uint32_t id = L.hash[i];
             if (id != HASH_EMPTY) tags[id] = epoch;
           }
-          if (full) tags[v] = epoch;
+          // an id that found its set full may appear twice in the batch: one lane claims it
+          if (full) isnew = __hip_atomic_exchange(tags + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != epoch;
           tagged = true;
         }
         if (tagged) wave_fence();
@@ -1148,7 +1168,6 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   scratch_layout(nq, R.k, scratch, &X.S);
   const int S = dv.S;
   const int per_node = std::max(std::min(R.m + S - 1, S * std::max(dv.M0, dv.MU)), dv.GC);
-  const int nb1 = (per_node + WAVE - 1) / WAVE * WAVE;
   SearchArgs A{};
   A.ix = dv;
   A.Q = queries;
@@ -1172,7 +1191,7 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
     A.bD = (float)(std::sqrt(1.0 + g) * (1.0 + w));
   }
   A.ef_blocks = (std::max(R.ef, R.k) + WAVE - 1) / WAVE;
-  A.nbr_cap = std::max(R.p * nb1, WAVE);
+  A.nbr_cap = std::max((R.p * per_node + WAVE - 1) / WAVE * WAVE, WAVE);
   A.out_ids = out_ids;
   A.out_dist = out_dist;
   A.out_stats = out_stats;

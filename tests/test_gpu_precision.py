@@ -195,3 +195,25 @@ def test_fp8_every_code(tmp_path):
         gid, gd, _, _ = gpu_search(g, Q, l, h, 10, 32, strategy)
         assert np.array_equal(ref[0], gid) and np.array_equal(ref[1].view(np.uint32), gd.view(np.uint32))
     g.close()
+
+
+@pytest.mark.parametrize("name,prec", PRECS)
+def test_parity_low_precision_d960(tmp_path, name, prec):
+    """The GIST-like width (960 = 15 groups of 64): one 16-lane group per vector
+    with 15 rounds of groups, for both copies."""
+    import paper_2412_02448_amd as u
+    spec = w.scaled(w.SPECS["gist1m"], n=2500, nq=60, S=4, M=8, ef_cons=40)
+    W = w.make(spec, base_seed=9)
+    print(f"[case] d=960 {name}", flush=True)
+    ix = hsig.Index.build(W.base, W.attr, W.level_u, spec.S, spec.M, spec.ef_cons, seed=9)
+    path = str(tmp_path / "g.uix")
+    ix.write(path)
+    g = u.Index.load(path, device=0, precision=name)
+    ix.set_store(prec, 4)
+    for strategy in (hsig.AUTO, hsig.PRE, hsig.HYBRID, hsig.POST):
+        ref = ix.search(W.queries, W.l, W.h, 10, 32, strategy=strategy)
+        gid, gd, _, gst = gpu_search(g, W.queries, W.l, W.h, 10, 32, None if strategy == hsig.AUTO else strategy,
+                                     pre_chunk=128)
+        assert np.array_equal(ref[0], gid) and np.array_equal(ref[1].view(np.uint32), gd.view(np.uint32)), strategy
+    g.close()
+
