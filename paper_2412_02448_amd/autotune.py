@@ -5,9 +5,11 @@ recall for speed; Sec. 4.2: tau_A and tau_B come from sample queries).  This
 tuner does the same on the GPU: for sample queries with known exact answers
 (the pre-filter scan forced on every sample query gives them), it measures
 recall@k and throughput of the range-aware search over a grid of
-(m, ef, beam width p) and returns the fastest setting whose recall reaches the
-target.  Every measurement runs the library's kernels; this module only
-orchestrates calls and computes recall.
+(tau_A, tau_B, m, ef, beam width p) and returns the fastest setting whose
+recall reaches the target (the GPU's cost crossovers between the strategies
+differ from the CPU's that the paper's 1% / 50% reflect).  Every measurement
+runs the library's kernels; this module only orchestrates calls and computes
+recall.
 """
 from __future__ import annotations
 
@@ -24,6 +26,12 @@ class Setting:
     beam_p: int
     recall: float
     qps: float
+    tau_a: float = 0.01
+    tau_b: float = 0.5
+
+    def kwargs(self) -> dict:
+        """Search keyword arguments of this setting."""
+        return dict(m=self.m, beam_p=self.beam_p, tau_a=self.tau_a, tau_b=self.tau_b)
 
 
 def recall_at_k(ids: np.ndarray, truth: np.ndarray) -> float:
@@ -49,8 +57,9 @@ def exact_answers(index, Q, L, H, k):
 
 
 def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256), ps=(1, 2, 4),
-         reps: int = 3, log=None):
-    """Fastest (m, ef, p) reaching recall@k >= target on the given sample queries.
+         taus=((0.01, 0.5), (0.01, 0.3), (0.005, 0.3), (0.01, 0.2)), reps: int = 5, log=None):
+    """Fastest (tau_A, tau_B, m, ef, p) reaching recall@k >= target on the given sample
+    queries; taus lists the (tau_A, tau_B) fractions of the strategy rule to try.
 
     Returns (best Setting or None, list of every Setting measured)."""
     import torch
@@ -59,30 +68,32 @@ def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256),
         ms = (M, (3 * M) // 2, 2 * M, 3 * M)
     truth = exact_answers(index, Q, L, H, k)
     table = []
-    for m in ms:
-        if m > index.S * index.M:
-            continue
-        for ef in efs:
-            if ef < k:
+    for ta, tb in taus:
+        for m in ms:
+            if m > index.S * index.M:
                 continue
-            ids, _, _ = index.search(Q, L, H, k, ef, m=m)
-            torch.cuda.synchronize()
-            rec = recall_at_k(ids.cpu().numpy(), truth)
-            if rec < target:
-                table.append(Setting(m, ef, 1, rec, 0.0))
-                continue
-            for p in ps:
-                index.search(Q, L, H, k, ef, m=m, beam_p=p)
+            for ef in efs:
+                if ef < k:
+                    continue
+                ids, _, _ = index.search(Q, L, H, k, ef, m=m, tau_a=ta, tau_b=tb)
                 torch.cuda.synchronize()
-                t = time.perf_counter()
-                for _ in range(reps):
-                    index.search(Q, L, H, k, ef, m=m, beam_p=p)
-                torch.cuda.synchronize()
-                qps = Q.shape[0] * reps / (time.perf_counter() - t)
-                table.append(Setting(m, ef, p, rec, qps))
-                if log:
-                    log(f"tune m={m} ef={ef} p={p}: recall {rec:.4f}, {qps:,.0f} QPS")
-            break  # larger ef only costs more once the target is met
+                rec = recall_at_k(ids.cpu().numpy(), truth)
+                if rec < target:
+                    table.append(Setting(m, ef, 1, rec, 0.0, ta, tb))
+                    continue
+                for p in ps:
+                    kw = dict(m=m, beam_p=p, tau_a=ta, tau_b=tb)
+                    index.search(Q, L, H, k, ef, **kw)
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    for _ in range(reps):
+                        index.search(Q, L, H, k, ef, **kw)
+                    torch.cuda.synchronize()
+                    qps = Q.shape[0] * reps / (time.perf_counter() - t)
+                    table.append(Setting(m, ef, p, rec, qps, ta, tb))
+                    if log:
+                        log(f"tune tau=({ta}, {tb}) m={m} ef={ef} p={p}: recall {rec:.4f}, {qps:,.0f} QPS")
+                break  # larger ef only costs more once the target is met
     ok = [s for s in table if s.recall >= target and s.qps > 0]
     best = max(ok, key=lambda s: s.qps) if ok else None
     return best, table

@@ -135,60 +135,67 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
   if (out_strat) out_strat[q] = (int8_t)s;
 }
 
-// Work list: the graph-search queries (hybrid, post) in query order, then the
-// chunks of the pre-filter scans bucketed by where they start, so that waves
-// that scan at the same time read nearby rows.  Also numbers the partial-list
-// slots of split scans (QPlan.pbase) and resets the counters.  One block.
+// Work list, longest work first so that the persistent waves finish together:
+// the hybrid searches from the smallest range up (a narrow range leaves more
+// out-of-range objects to walk through), then the post-filter searches, then
+// the chunks of the pre-filter scans (short and uniform) bucketed by where they
+// start, so that waves scanning at the same time read nearby rows.  Also
+// numbers the partial-list slots of split scans (QPlan.pbase) and resets the
+// counters.  One block.
+__device__ __forceinline__ int graph_bucket(const QPlan& P) {
+  const int lg = 31 - __clz(max(P.hi - P.lo, 1));  // floor(log2 Y)
+  return P.strat == UNIFY_HYBRID ? lg : 32 + lg;
+}
+
 __global__ void k_worklist(QPlan* __restrict__ plan, int64_t nq, int64_t n, int32_t* __restrict__ work,
                            int32_t* __restrict__ wchunk,
                            int32_t* __restrict__ counters /* nwork, next, fb_count, fb_next */) {
-  constexpr int NB = 1024;
-  __shared__ int32_t part[1024];
+  constexpr int NB = 1024, NG = 64;
   __shared__ int32_t spart[1024];
   __shared__ int32_t bucket[NB];
+  __shared__ int32_t gbucket[NG];
   const int t = threadIdx.x, T = blockDim.x;
   const int64_t per = (nq + T - 1) / T;
   const int64_t s0 = std::min<int64_t>(nq, t * per), s1 = std::min<int64_t>(nq, s0 + per);
   for (int b = t; b < NB; b += T) bucket[b] = 0;
+  if (t < NG) gbucket[t] = 0;
   __syncthreads();
-  int32_t c = 0, sc = 0;
+  int32_t sc = 0;
   for (int64_t q = s0; q < s1; ++q) {
     const QPlan P = plan[q];
     if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) {
-      ++c;
+      atomicAdd(&gbucket[graph_bucket(P)], 1);
     } else if (P.strat == UNIFY_PRE) {
       for (int j = 0; j < P.nch; ++j)
         atomicAdd(&bucket[(int)((int64_t)(P.lo + j * P.clen) * NB / n)], 1);
       if (P.nch > 1) sc += P.nch;
     }
   }
-  part[t] = c;
   spart[t] = sc;
   __syncthreads();
   for (int off = 1; off < T; off <<= 1) {
-    const int32_t v = t >= off ? part[t - off] : 0;
     const int32_t sv = t >= off ? spart[t - off] : 0;
     const int32_t bv = (t >= off && t < NB) ? bucket[t - off] : 0;
+    const int32_t gv = (t >= off && t < NG) ? gbucket[t - off] : 0;
     __syncthreads();
-    part[t] += v;
     spart[t] += sv;
     if (t < NB) bucket[t] += bv;
+    if (t < NG) gbucket[t] += gv;
     __syncthreads();
   }
-  const int32_t nbeam = part[T - 1];
+  const int32_t nbeam = gbucket[NG - 1];
   const int32_t nchunks = bucket[NB - 1];
   const int32_t my_end = t < NB ? bucket[t] : 0;  // inclusive prefix count of chunks
   __syncthreads();
   if (t < NB) bucket[t] = nbeam + my_end;  // one past the last slot of bucket t
   __syncthreads();
-  int32_t pos = part[t] - c;
   int32_t spos = spart[t] - sc;
   for (int64_t q = s0; q < s1; ++q) {
     QPlan P = plan[q];
     if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) {
-      work[pos] = (int32_t)q;
-      wchunk[pos] = 0;
-      ++pos;
+      const int32_t w = atomicSub(&gbucket[graph_bucket(P)], 1) - 1;
+      work[w] = (int32_t)q;
+      wchunk[w] = 0;
     } else if (P.strat == UNIFY_PRE) {
       for (int j = 0; j < P.nch; ++j) {
         const int b = (int)((int64_t)(P.lo + j * P.clen) * NB / n);
