@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--p", type=int, default=0, help="fixed beam width (0: tuned)")
     ap.add_argument("--tau-a", type=float, default=0.0, help="fixed tau_A fraction (0: tuned, with --tau-b)")
     ap.add_argument("--tau-b", type=float, default=0.5, help="tau_B fraction used with --tau-a")
+    ap.add_argument("--visit-cap", type=int, default=0, help="visited-cache entries for --profile-run (0: default)")
     ap.add_argument("--precisions", default=",".join(PRECISIONS),
                     help="comma-separated vector stores to measure (fp32, bf16, fp8)")
     ap.add_argument("--recall-target", type=float, default=0.95)
@@ -146,14 +147,14 @@ def main():
     Lc = torch.from_numpy(cl).to(dev)
     Hc = torch.from_numpy(ch).to(dev)
 
-    def timed(m, ef, bp, strategy=None, steps=args.steps, warmup=args.warmup, ta=0.01, tb=0.5, **kw):
+    def timed(m, ef, bp, strategy=None, steps=args.steps, warmup=args.warmup, ta=0.01, tb=0.5, vc=0, **kw):
         out = None
         for _ in range(warmup):
-            out = index.search(Q, L, H, k, ef, strategy=strategy, m=m, beam_p=bp, tau_a=ta, tau_b=tb, **kw)
+            out = index.search(Q, L, H, k, ef, strategy=strategy, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, **kw)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
-            out = index.search(Q, L, H, k, ef, strategy=strategy, m=m, beam_p=bp, tau_a=ta, tau_b=tb, **kw)
+            out = index.search(Q, L, H, k, ef, strategy=strategy, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, **kw)
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / steps, out
 
@@ -170,12 +171,12 @@ def main():
                                     ps=ps_grid, log=lambda s, p=prec: log(f"[{p}] {s}"), **kw_t)
         if best is None:
             best = max(table, key=lambda s: s.recall)
-        m, ef, bp, ta, tb = best.m, best.ef, best.beam_p, best.tau_a, best.tau_b
+        m, ef, bp, ta, tb, vc = best.m, best.ef, best.beam_p, best.tau_a, best.tau_b, best.visit_cap
         log(f"[{prec}] tuned on 2000 held-out queries ({time.time() - t0:.1f}s): m={m} ef={ef} p={bp} "
             f"tau=({ta}, {tb})")
-        sec, out = timed(m, ef, bp, ta=ta, tb=tb)
+        sec, out = timed(m, ef, bp, ta=ta, tb=tb, vc=vc)
         rec = recall_of(out[0])
-        ids, _, _, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, stats=True, timing=True)
+        ids, _, _, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True, timing=True)
         torch.cuda.synchronize()
         pre_ms, search_ms, rerun_ms = index.last_timing()
         st = stats.cpu().numpy().astype(np.int64)
@@ -183,7 +184,7 @@ def main():
         bts = int(bytes_per_query(st, d, k, prec)[first].sum())
         by_prec[prec] = {
             "qps": round(nq / sec, 1), "ms_per_step": round(sec * 1e3, 4), "recall@10": round(rec, 4),
-            "m": m, "ef": ef, "beam_p": bp, "tau_a": ta, "tau_b": tb, "search_launch_ms": round(search_ms, 4),
+            "m": m, "ef": ef, "beam_p": bp, "tau_a": ta, "tau_b": tb, "visit_cap": vc, "search_launch_ms": round(search_ms, 4),
             "plan_ms": round(pre_ms, 4), "rerun_launch_ms": round(rerun_ms, 4),
             "rerun_queries": int((st[:, 3] == 1).sum()), "failed_queries": int((st[:, 3] == 2).sum()),
             "bytes_per_launch": bts, "achieved_GBps": round(bts / (search_ms * 1e-3) / 1e9, 1),
@@ -197,29 +198,29 @@ def main():
     ok = [p for p in precs if by_prec[p]["recall@10"] >= args.recall_target]
     head = max(ok or precs, key=lambda p: by_prec[p]["qps"] if ok else by_prec[p]["recall@10"])
     H0 = by_prec[head]
-    m, ef, bp, ta, tb = H0["m"], H0["ef"], H0["beam_p"], H0["tau_a"], H0["tau_b"]
+    m, ef, bp, ta, tb, vc = H0["m"], H0["ef"], H0["beam_p"], H0["tau_a"], H0["tau_b"], H0["visit_cap"]
     index.set_precision(head)
     log(f"headline store: {head} (m={m} ef={ef} p={bp} tau=({ta}, {tb}))")
 
     recalls = {}
     for e in (32, 64, 128, 256):
-        ids, _, _ = index.search(Q, L, H, k, e, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+        ids, _, _ = index.search(Q, L, H, k, e, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
         torch.cuda.synchronize()
         recalls[e] = recall_of(ids)
     log("recall@10 by ef: " + ", ".join(f"ef={e}: {r:.4f}" for e, r in recalls.items()))
 
     # ---- timed region of the headline: K steps of the whole path ----
-    sec, out = timed(m, ef, bp, ta=ta, tb=tb)
+    sec, out = timed(m, ef, bp, ta=ta, tb=tb, vc=vc)
     qps = nq / sec
     log(f"auto ({head}): {qps:,.0f} QPS ({sec * 1e3:.3f} ms/step)")
     per_strategy = {}
     for name, sv in (("pre", u.PRE), ("hybrid", u.HYBRID), ("post", u.POST)):
-        s, o = timed(m, ef, bp, sv, steps=max(1, args.steps // 2 + 1), warmup=1, ta=ta, tb=tb)
+        s, o = timed(m, ef, bp, sv, steps=max(1, args.steps // 2 + 1), warmup=1, ta=ta, tb=tb, vc=vc)
         per_strategy[name] = {"qps": round(nq / s, 1), "recall@10": round(recall_of(o[0]), 4)}
         log(f"{name}: {nq / s:,.0f} QPS recall {per_strategy[name]['recall@10']}")
 
     # ---- roofline of the search kernel: counters of one more (identical) call ----
-    ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, stats=True, timing=True)
+    ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True, timing=True)
     torch.cuda.synchronize()
     pre_ms, search_ms, rerun_ms = index.last_timing()
     st = stats.cpu().numpy().astype(np.int64)
@@ -230,7 +231,7 @@ def main():
     kern = f"k_search<*, {KCODE[head]}, 0>"
     roofline = {"bound": "hbm", "kernel": f"{kern} (first pass)", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": profiled_traffic(head, m, ef, bp, ta, tb), "bytes_per_launch": bytes_first,
+                "traffic": profiled_traffic(head, m, ef, bp, ta, tb, vc), "bytes_per_launch": bytes_first,
                 "launch_ms": round(search_ms, 4), "rerun_launch_ms": round(rerun_ms, 4),
                 "rerun_queries": int((st[:, 3] == 1).sum()), "failed_queries": int((st[:, 3] == 2).sum())}
     ids_np = ids.cpu().numpy()
@@ -262,7 +263,7 @@ def main():
     serving = None
     if not args.no_serving:
         try:
-            serving = serve_bench(args, index, spec, W, m, ef, bp, ta, tb, head)
+            serving = serve_bench(args, index, spec, W, m, ef, bp, ta, tb, vc, head)
         except Exception as e:  # the headline line is still reported
             log(f"serving failed: {e!r}")
             serving = {"failed": repr(e)}
@@ -283,7 +284,7 @@ def main():
                                f"uniform in [0, 2^31), HSIG S={spec.S} M={spec.M} efCons={spec.ef_cons} built on GPU; "
                                f"{nq} queries, range fraction log-uniform [1e-3, 1], k={k}, auto strategy",
                    "n": spec.n, "d": d, "nq": nq, "k": k, "store": head, "ef": ef, "m": m, "beam_p": bp,
-                   "tau_a": ta, "tau_b": tb,
+                   "tau_a": ta, "tau_b": tb, "visit_cap": vc,
                    "recall@10": round(recall_of(out[0]), 4),
                    "recall_by_ef": {str(e): round(r, 4) for e, r in recalls.items()},
                    "strategy_mix": {"pre": int(mix[1]), "hybrid": int(mix[2]), "post": int(mix[3])},
@@ -329,16 +330,16 @@ def wide_bench(args):
         best, table = autotune.tune(index, Qc, Lc, Hc, k, args.recall_target, efs=(32, 64, 128))
         if best is None:
             best = max(table, key=lambda s: s.recall)
-        m, ef, bp, ta, tb = best.m, best.ef, best.beam_p, best.tau_a, best.tau_b
+        m, ef, bp, ta, tb, vc = best.m, best.ef, best.beam_p, best.tau_a, best.tau_b, best.visit_cap
         for _ in range(2):
-            index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+            index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(5):
-            o = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+            o = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t) / 5
-        ids, _, _, st = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, stats=True, timing=True)
+        ids, _, _, st = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True, timing=True)
         torch.cuda.synchronize()
         search_ms = index.last_timing()[1]
         st = st.cpu().numpy().astype(np.int64)
@@ -348,7 +349,7 @@ def wide_bench(args):
                              / max(1, (truth[i] >= 0).sum()) if (truth[i] >= 0).any() else 1.0
                              for i in range(nq)]))
         out[prec] = {"qps": round(nq / sec, 1), "recall@10": round(rec, 4), "m": m, "ef": ef, "beam_p": bp,
-                     "tau_a": ta, "tau_b": tb,
+                     "tau_a": ta, "tau_b": tb, "visit_cap": vc, "visit_cap": vc,
                      "search_launch_ms": round(search_ms, 4), "bytes_per_launch": b,
                      "achieved_GBps": round(b / (search_ms * 1e-3) / 1e9, 1),
                      "fp32_rescores_per_query": round(float(st[:, 2].mean()), 2)}
@@ -358,7 +359,7 @@ def wide_bench(args):
     return out
 
 
-def serve_bench(args, index, spec, W, m, ef, bp, ta, tb, prec):
+def serve_bench(args, index, spec, W, m, ef, bp, ta, tb, vc, prec):
     """Poisson arrivals at several rates into the server over the mixed1m index, with
     the serving range mix (30% of fractions log-uniform in [1e-5, 1e-3), 40% in
     [1e-3, 0.1), 30% in [0.1, 1]); latency = completion - arrival per request."""
@@ -376,13 +377,13 @@ def serve_bench(args, index, spec, W, m, ef, bp, ta, tb, prec):
     # the same requests searched as one batch: each served result must equal its row
     dev = torch.device("cuda", 0)
     ref = index.search(torch.from_numpy(q).to(dev), torch.from_numpy(l).to(dev), torch.from_numpy(h).to(dev), k,
-                       ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb)[0].cpu().numpy()
+                       ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)[0].cpu().numpy()
     rng = np.random.default_rng(12)
     rows = []
     for rate in (10_000, 100_000, 1_000_000, None):
         cnt = n if rate is None or rate >= 100_000 else 20_000
         arrive = np.zeros(cnt) if rate is None else np.cumsum(rng.exponential(1.0 / rate, cnt))
-        srv = u.Server(index, k, ef, max_batch=4096, inflight=2, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+        srv = u.Server(index, k, ef, max_batch=4096, inflight=2, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
         t0 = time.perf_counter()
         tickets = srv.submit(q[:cnt], l[:cnt], h[:cnt], arrive_s=arrive)
         ids, _, lat = srv.wait(tickets, timeout_s=120)
@@ -426,9 +427,9 @@ def batch100k(args, prec):
                                 torch.from_numpy(ch).to(dev), k, args.recall_target, efs=(16, 32, 64, 128))
     if best is None:
         best = max(table, key=lambda s: s.recall)
-    m, ef, bp, ta, tb = best.m, best.ef, best.beam_p, best.tau_a, best.tau_b
+    m, ef, bp, ta, tb, vc = best.m, best.ef, best.beam_p, best.tau_a, best.tau_b, best.visit_cap
     truth = index.search(Q, L, H, k, k, strategy=u.PRE)[0].cpu().numpy()
-    b = u.Batch(index, Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+    b = u.Batch(index, Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
     steps = max(args.steps, 5)
     for _ in range(2):
         b.run()
@@ -441,32 +442,32 @@ def batch100k(args, prec):
     ids = b.ids.cpu().numpy()
     rec = float(np.mean([len(set(ids[i][ids[i] >= 0]) & set(truth[i][truth[i] >= 0])) / max(1, (truth[i] >= 0).sum())
                          if (truth[i] >= 0).any() else 1.0 for i in range(nq)]))
-    eager = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+    eager = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
     same = bool((eager[0] == b.ids).all().item())
     for _ in range(2):
-        index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+        index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(steps):
-        index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+        index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
     torch.cuda.synchronize()
     e_s = (time.perf_counter() - t) / steps
     # one launch sequence per query (the first 2,000 queries)
     npq = 2000
     views = [(Q[i:i + 1], L[i:i + 1], H[i:i + 1]) for i in range(npq)]
     for i in range(50):
-        index.search(*views[i], k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+        index.search(*views[i], k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for v in views:
-        index.search(*v, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+        index.search(*v, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
     torch.cuda.synchronize()
     pq_s = time.perf_counter() - t
     b.close()
     out = {"workload": f"batch100k: n={spec.n} d={spec.d} (16-centre mixture, sigma 0.3), permutation attribute, "
                        f"HSIG S={spec.S} M={spec.M} built on GPU; {nq} queries, range fraction log-uniform "
                        f"[1e-4, 1], k={k}, auto strategy, {prec} store",
-           "m": m, "ef": ef, "beam_p": bp, "tau_a": ta, "tau_b": tb, "recall@10": round(rec, 4),
+           "m": m, "ef": ef, "beam_p": bp, "tau_a": ta, "tau_b": tb, "visit_cap": vc, "recall@10": round(rec, 4),
            "graph_qps": round(nq / g_s, 1), "graph_ms_per_step": round(g_s * 1e3, 4),
            "eager_qps": round(nq / e_s, 1), "per_query_launch_qps": round(npq / pq_s, 1),
            "graph_equals_eager": same, "per_query_sample": npq}
@@ -526,7 +527,7 @@ def source_hash():
     return hashlib.sha256(src).hexdigest()
 
 
-def profiled_traffic(prec, m, ef, bp, ta, tb):
+def profiled_traffic(prec, m, ef, bp, ta, tb, vc):
     """HBM bytes per launch of the search kernel from the committed rocprofv3 counter summary,
     or None when the kernel sources or the setting differ from what was profiled."""
     path = os.path.join(ROOT, "profiles", f"k_search_mixed1m_{prec}.json")
@@ -535,7 +536,7 @@ def profiled_traffic(prec, m, ef, bp, ta, tb):
     prof = json.load(open(path))
     if source_hash() != prof["source_sha256"]:
         return None
-    if f"--m {m} --ef {ef} --p {bp} --tau-a {ta} --tau-b {tb} " not in prof["args"] + " ":
+    if f"--m {m} --ef {ef} --p {bp} --tau-a {ta} --tau-b {tb} --visit-cap {vc} " not in prof["args"] + " ":
         return None
     return int(prof["traffic_bytes"])
 
@@ -548,21 +549,22 @@ def profile_run(args, index, Q, L, H, k, spec, nq, build_s, prec):
     index.set_precision(prec)
     m, ef, bp = args.m, args.ef, args.p
     ta, tb = (args.tau_a, args.tau_b) if args.tau_a else (0.01, 0.5)
+    vc = args.visit_cap
     for _ in range(args.warmup):
-        index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+        index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(args.steps):
-        index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb)
+        index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t) / args.steps
-    ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, stats=True, timing=True)
+    ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True, timing=True)
     torch.cuda.synchronize()
     pre_ms, search_ms, rerun_ms = index.last_timing()
     st = stats.cpu().numpy().astype(np.int64)
     b = int(bytes_per_query(st, spec.d, k, prec)[st[:, 3] == 0].sum())
     print(json.dumps({"profile_run": True, "store": prec, "m": m, "ef": ef, "beam_p": bp, "tau_a": ta, "tau_b": tb,
-                      "qps": round(nq / sec, 1),
+                      "visit_cap": vc, "qps": round(nq / sec, 1),
                       "ms_per_step": round(sec * 1e3, 4), "search_launch_ms": round(search_ms, 4),
                       "rerun_launch_ms": round(rerun_ms, 4), "bytes_per_launch": b,
                       "achieved_GBps": round(b / (search_ms * 1e-3) / 1e9, 1), "build_s": round(build_s, 1),

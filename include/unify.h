@@ -86,7 +86,8 @@ typedef struct {
   double tau_b_frac;    /* tau_B = ceil(tau_b_frac * n); default 0.5 (Sec. 6.2) */
   uint32_t flags;       /* UNIFY_FLAG_* bits, 0 for none */
   int32_t visit_cap;    /* on-chip visited-cache entries per query, a power of two in
-                           [256, 16384]; default 1024 (larger visited sets spill to HBM,
+                           [256, 16384]; default 1024 for the FP32 store, 512 for BF16 /
+                           FP8 (more wavefronts fit; larger visited sets spill to HBM,
                            same results) */
   int32_t pre_chunk;    /* pre-filter scans with k <= 32 split their slice into chunks of
                            about this many objects (at most 8 chunks), scanned by different

@@ -28,10 +28,11 @@ class Setting:
     qps: float
     tau_a: float = 0.01
     tau_b: float = 0.5
+    visit_cap: int = 0  # 0: the library's default
 
     def kwargs(self) -> dict:
         """Search keyword arguments of this setting."""
-        return dict(m=self.m, beam_p=self.beam_p, tau_a=self.tau_a, tau_b=self.tau_b)
+        return dict(m=self.m, beam_p=self.beam_p, tau_a=self.tau_a, tau_b=self.tau_b, visit_cap=self.visit_cap)
 
 
 def recall_at_k(ids: np.ndarray, truth: np.ndarray) -> float:
@@ -57,9 +58,11 @@ def exact_answers(index, Q, L, H, k):
 
 
 def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256), ps=(1, 2, 4),
-         taus=((0.01, 0.5), (0.01, 0.3), (0.005, 0.3), (0.01, 0.2)), reps: int = 5, log=None):
+         taus=((0.01, 0.5), (0.01, 0.3), (0.005, 0.3), (0.01, 0.2)), visit_caps=(512, 1024), reps: int = 5,
+         log=None):
     """Fastest (tau_A, tau_B, m, ef, p) reaching recall@k >= target on the given sample
-    queries; taus lists the (tau_A, tau_B) fractions of the strategy rule to try.
+    queries; taus lists the (tau_A, tau_B) fractions of the strategy rule to try.  The
+    visited-cache sizes in visit_caps are then timed on the best setting.
 
     Returns (best Setting or None, list of every Setting measured)."""
     import torch
@@ -96,4 +99,22 @@ def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256),
                 break  # larger ef only costs more once the target is met
     ok = [s for s in table if s.recall >= target and s.qps > 0]
     best = max(ok, key=lambda s: s.qps) if ok else None
+    if best is not None:
+        # the on-chip visited cache trades LDS (waves per CU) against HBM tag reads;
+        # results do not depend on it
+        for vc in visit_caps:
+            kw = dict(best.kwargs(), visit_cap=vc)
+            index.search(Q, L, H, k, best.ef, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                index.search(Q, L, H, k, best.ef, **kw)
+            torch.cuda.synchronize()
+            qps = Q.shape[0] * reps / (time.perf_counter() - t)
+            cand = dataclasses.replace(best, qps=qps, visit_cap=vc)
+            table.append(cand)
+            if log:
+                log(f"tune visit_cap={vc}: {qps:,.0f} QPS")
+            if qps > 1.03 * best.qps:  # the default stays unless another size is clearly faster
+                best = cand
     return best, table

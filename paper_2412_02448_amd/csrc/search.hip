@@ -1,8 +1,10 @@
 // Range-filtered k-NN search over a resident HSIG on gfx950.
 //
-// One 64-lane wavefront runs one query (persistent waves pull queries from a
-// work list).  The strategies follow Sec. 4.2 of the paper:
-//   pre    (strategy A): exact scan of the contiguous id slice [lo, hi);
+// One 64-lane wavefront runs one work item (persistent waves pull items from a
+// work list): a graph search, or one chunk of a pre-filter scan.  The
+// strategies follow Sec. 4.2 of the paper:
+//   pre    (strategy A): exact scan of the contiguous id slice [lo, hi), split
+//          into chunks on several wavefronts and merged by k_pre_merge;
 //   hybrid (strategy C): the scheme of Alg. 2 with Alg. 7 on each layer, over the
 //          first ceil(m / S') entries of each active chunk;
 //   post   (strategy B): Alg. 2 with Alg. 1 over the global (marked) edges, then
@@ -10,17 +12,20 @@
 // The choice between them is the range-aware rule of Sec. 4.2.
 //
 // A layer search keeps three structures in LDS:
-//   visited  per-wave epoch tags in HBM (one u32 per object; exact and
-//            unbounded), fronted by a direct-mapped LDS cache of recent ids;
+//   visited  an 8-way set-associative cache of ids, exact until a set
+//            overflows; then per-wave epoch tags in HBM (one u32 per object)
+//            take over, with the cache saving reads;
 //   cand     an unsorted array of keys with tombstones; pop = wave argmin;
 //   ann      a sorted key list kept by bitonic block merges.
 // One step pops up to p candidates (p = 1 is the sequential loop), gathers
 // their unvisited neighbours, evaluates all distances at once, and admits each
 // neighbour against the threshold taken before the step.  With a strict total
 // order on keys this gives the same ann and the same stopping point as
-// evaluating the neighbours one at a time; see DESIGN notes on batch admission.
-// If a query's candidate array outgrows its LDS capacity, the query is
-// abandoned and re-run by a second launch with a larger array.
+// evaluating the neighbours one at a time (the batch-admission argument of
+// the design notes).  If a query's candidate array outgrows its LDS capacity,
+// the query is abandoned and re-run by a second launch with a larger array.
+// With a BF16 / FP8 store, graph results are re-scored in FP32 and the
+// pre-filter scan proves its result with error bounds.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,6 +65,13 @@ struct SearchArgs {
 };
 
 constexpr uint32_t HASH_EMPTY = 0xFFFFFFFFu;
+// Register budgets of the search kernels (measured on the 1M workload): the
+// BF16 and FP8 kernels are held to 128 VGPRs for 4 wavefronts per SIMD (BF16
+// with 4 rounds of raw loads in flight instead of 8, which would spill), the
+// FP32 kernel to 168 for 3; a wavefront's LDS then decides (about 8.5 KB with
+// a 512-entry visited cache for 4 per SIMD).  Rows wider than 256 elements
+// hold the query in NG * 4 registers and keep the compiler's own budget.
+constexpr int WAVES_PER_SIMD_FP32 = 3, WAVES_PER_SIMD_LOW = 4, BF16_ROUNDS = 4;
 constexpr int PRE_NCH_MAX = 8;      // chunks per pre-filter scan at most
 constexpr int PRE_SPLIT_KMAX = 32;  // larger k scans its slice in one wavefront
 
@@ -287,7 +299,8 @@ __device__ __forceinline__ void eval_keys(const DevIndex& ix, const float4 (&qv)
                                           u64* keys) {
   typedef Store<PREC> St;
   constexpr int RB0 = (SHALLOW ? 2 : 16) / NG;
-  constexpr int RB = RB0 < 1 ? 1 : (RB0 > 8 ? 8 : RB0);
+  constexpr int RBMAX = PREC == UNIFY_BF16 ? BF16_ROUNDS : 8;
+  constexpr int RB = RB0 < 1 ? 1 : (RB0 > RBMAX ? RBMAX : RB0);
   const int G = ix.d >> 2;
   const int lane = lane_id();
   const int s = lane & 15, g4 = lane >> 4;
@@ -881,7 +894,7 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
 }
 
 template <int NG, int PREC, int PASS>
-__global__ void __launch_bounds__(64) k_search(SearchArgs A) {
+__global__ void __launch_bounds__(64, NG > 4 ? 1 : (PREC == UNIFY_FP32 ? WAVES_PER_SIMD_FP32 : WAVES_PER_SIMD_LOW)) k_search(SearchArgs A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   Lds L;
   unsigned char* p = lds_raw;
@@ -1022,7 +1035,7 @@ int resolve(unify_index_t ix, int64_t nq, int32_t k, int32_t ef, const unify_par
   const double ta = P.tau_a_frac > 0 ? P.tau_a_frac : 0.01;
   const double tb = P.tau_b_frac > 0 ? P.tau_b_frac : 0.5;
   R.ccap = P.cand_cap > 0 ? P.cand_cap : 512;
-  R.hcap = P.visit_cap > 0 ? P.visit_cap : 1024;
+  R.hcap = P.visit_cap > 0 ? P.visit_cap : (dv.precision == UNIFY_FP32 ? 1024 : 512);
   R.rerank = P.rerank_mult > 0 ? P.rerank_mult : 4;
   R.pre_chunk = P.pre_chunk > 0 ? P.pre_chunk : 2048;
   R.flags = P.flags;
