@@ -58,7 +58,7 @@ def exact_answers(index, Q, L, H, k):
 
 
 def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256), ps=(1, 2, 4),
-         taus=((0.01, 0.5), (0.01, 0.3), (0.005, 0.3), (0.01, 0.2)), visit_caps=(512, 1024), reps: int = 5,
+         taus=((0.01, 0.5), (0.01, 0.3), (0.005, 0.3), (0.01, 0.2)), visit_caps=(512, 1024), reps: int = 10,
          log=None):
     """Fastest (tau_A, tau_B, m, ef, p) reaching recall@k >= target on the given sample
     queries; taus lists the (tau_A, tau_B) fractions of the strategy rule to try.  The
@@ -98,7 +98,11 @@ def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256),
                         log(f"tune tau=({ta}, {tb}) m={m} ef={ef} p={p}: recall {rec:.4f}, {qps:,.0f} QPS")
                 break  # larger ef only costs more once the target is met
     ok = [s for s in table if s.recall >= target and s.qps > 0]
-    best = max(ok, key=lambda s: s.qps) if ok else None
+    best = None
+    if ok:
+        # settings within 2% of the fastest are within the timing noise: take the most accurate
+        top = max(s.qps for s in ok)
+        best = max((s for s in ok if s.qps >= 0.98 * top), key=lambda s: (s.recall, s.qps))
     if best is not None:
         # the on-chip visited cache trades LDS (waves per CU) against HBM tag reads;
         # results do not depend on it
