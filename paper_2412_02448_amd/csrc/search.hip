@@ -289,17 +289,21 @@ struct Store<UNIFY_FP8E4M3> {
 // Keys (canonical FP32 distance, id) of cnt vectors of the store PREC: four
 // vectors per round (16 lanes each, lane s takes groups s, s + 16, ...), RB
 // rounds of raw loads in flight; the i-th vector is id_of(i) and its key lands
-// in keys[i] (LDS).  The hot evaluations use RB = 16 / NG rounds (at most 8:
-// 32 rows in flight at d <= 128; wider rows keep fewer, since the query itself
-// then holds NG * 4 registers); SHALLOW (2 rounds at most) serves the FP32
+// in keys[i] (LDS).  Depth: GRAPH evaluations use RB = 16 / NG rounds (at most
+// 8: 32 rows in flight at d <= 128; wider rows keep fewer, since the query
+// itself then holds NG * 4 registers; BF16 at most BF16_ROUNDS, for its
+// register budget); STREAM (the pre-filter scans, whose loop holds little else)
+// keeps 16 / NG for every store; SHALLOW (2 rounds at most) serves the FP32
 // re-scores inside low-precision kernels, whose registers would otherwise add
 // to the hot path's and spill.
-template <int NG, int PREC, bool SHALLOW = false, class IdOf>
+enum EvalDepth { GRAPH = 0, SHALLOW = 1, STREAM = 2 };
+
+template <int NG, int PREC, int DEPTH = GRAPH, class IdOf>
 __device__ __forceinline__ void eval_keys(const DevIndex& ix, const float4 (&qv)[NG], int cnt, IdOf id_of,
                                           u64* keys) {
   typedef Store<PREC> St;
-  constexpr int RB0 = (SHALLOW ? 2 : 16) / NG;
-  constexpr int RBMAX = PREC == UNIFY_BF16 ? BF16_ROUNDS : 8;
+  constexpr int RB0 = (DEPTH == SHALLOW ? 2 : 16) / NG;
+  constexpr int RBMAX = (PREC == UNIFY_BF16 && DEPTH == GRAPH) ? BF16_ROUNDS : 8;
   constexpr int RB = RB0 < 1 ? 1 : (RB0 > RBMAX ? RBMAX : RB0);
   const int G = ix.d >> 2;
   const int lane = lane_id();
@@ -584,7 +588,8 @@ __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[N
   __syncthreads();
   for (int base = P.lo; base < P.hi; base += WAVE) {
     const int cntv = min(WAVE, P.hi - base);
-    eval_keys<NG, UNIFY_FP32, (PREC != UNIFY_FP32)>(A.ix, qv, cntv, [&](int i) { return base + i; }, L.bkeys);
+    eval_keys<NG, UNIFY_FP32, (PREC != UNIFY_FP32 ? SHALLOW : STREAM)>(A.ix, qv, cntv,
+                                                                      [&](int i) { return base + i; }, L.bkeys);
     __syncthreads();
     const u64 key = lane < cntv ? L.bkeys[lane] : KEY_MAX;
     const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
@@ -632,7 +637,7 @@ __device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&
   __syncthreads();
   for (int base = P.lo; base < P.hi; base += WAVE) {
     const int cntv = min(WAVE, P.hi - base);
-    eval_keys<NG, PREC>(ix, qv, cntv, [&](int i) { return base + i; }, L.bkeys);
+    eval_keys<NG, PREC, STREAM>(ix, qv, cntv, [&](int i) { return base + i; }, L.bkeys);
     __syncthreads();
     cnt.ndist += cntv;
     float lb = 0.f, ub = 0.f;
@@ -682,7 +687,7 @@ __device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&
     __syncthreads();
     if (use) L.bkeys[rank_in(um)] = (uint32_t)v;
     __syncthreads();
-    eval_keys<NG, UNIFY_FP32, true>(ix, qv, nb, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
+    eval_keys<NG, UNIFY_FP32, SHALLOW>(ix, qv, nb, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
     __syncthreads();
     const u64 key = lane < nb ? L.bkeys[lane] : KEY_MAX;
     const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
@@ -718,7 +723,7 @@ __device__ int rerank_graph(const SearchArgs& A, const Lds& L, const float4 (&qv
     __syncthreads();
     if (keep) L.bkeys[rank_in(um)] = (uint32_t)id;
     __syncthreads();
-    eval_keys<NG, UNIFY_FP32, true>(A.ix, qv, nb, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
+    eval_keys<NG, UNIFY_FP32, SHALLOW>(A.ix, qv, nb, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
     __syncthreads();
     const u64 nk = lane < nb ? L.bkeys[lane] : KEY_MAX;
     const u64 T = rl == k ? L.cand[k - 1] : KEY_MAX;
