@@ -73,6 +73,7 @@ constexpr uint32_t HASH_EMPTY = 0xFFFFFFFFu;
 // hold the query in NG * 4 registers and keep the compiler's own budget.
 constexpr int WAVES_PER_SIMD_FP32 = 3, WAVES_PER_SIMD_LOW = 4, BF16_ROUNDS = 4;
 constexpr int PRE_NCH_MAX = 8;      // chunks per pre-filter scan at most
+constexpr int PLAN_SAMPLES = 2048;  // sorted attributes staged in LDS by the plan kernel
 constexpr int PRE_SPLIT_KMAX = 32;  // larger k scans its slice in one wavefront
 
 // ---------------------------------------------------------------------------
@@ -105,13 +106,25 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
                        int32_t k, int32_t chunk, QPlan* __restrict__ plan, int8_t* __restrict__ out_strat,
                        int64_t* __restrict__ out_ids, float* __restrict__ out_dist,
                        int32_t* __restrict__ out_stats) {
+  // every stride-th sorted attribute in LDS: the binary searches then touch HBM
+  // only inside one stride-long window
+  __shared__ int64_t samp[PLAN_SAMPLES];
+  const int64_t stride = (ix.n + PLAN_SAMPLES - 1) / PLAN_SAMPLES;
+  const int64_t ns = (ix.n + stride - 1) / stride;
+  for (int64_t j = threadIdx.x; j < ns; j += blockDim.x) samp[j] = ix.attr[j * stride];
+  __syncthreads();
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
   const int64_t lq = l[q], hq = h[q];
   int64_t lo = 0, hi = 0;
   if (lq <= hq) {
-    lo = lower_bound_i64(ix.attr, ix.n, lq);
-    hi = upper_bound_i64(ix.attr, ix.n, hq);
+    // samp[a - 1] < lq <= samp[a] bounds the first attr >= lq to ((a-1) stride, a stride];
+    // likewise the first attr > hq
+    const int64_t a = lower_bound_i64(samp, ns, lq), b = upper_bound_i64(samp, ns, hq);
+    const int64_t a0 = a > 0 ? (a - 1) * stride + 1 : 0, a1 = a < ns ? a * stride : ix.n;
+    const int64_t b0 = b > 0 ? (b - 1) * stride + 1 : 0, b1 = b < ns ? b * stride : ix.n;
+    lo = a0 + lower_bound_i64(ix.attr + a0, a1 - a0, lq);
+    hi = b0 + upper_bound_i64(ix.attr + b0, b1 - b0, hq);
     if (hi < lo) hi = lo;
   }
   const int64_t Y = hi - lo;
@@ -167,13 +180,11 @@ __global__ void k_worklist(QPlan* __restrict__ plan, int64_t nq, int64_t n, int3
   __shared__ int32_t bucket[NB];
   __shared__ int32_t gbucket[NG];
   const int t = threadIdx.x, T = blockDim.x;
-  const int64_t per = (nq + T - 1) / T;
-  const int64_t s0 = std::min<int64_t>(nq, t * per), s1 = std::min<int64_t>(nq, s0 + per);
   for (int b = t; b < NB; b += T) bucket[b] = 0;
   if (t < NG) gbucket[t] = 0;
   __syncthreads();
   int32_t sc = 0;
-  for (int64_t q = s0; q < s1; ++q) {
+  for (int64_t q = t; q < nq; q += T) {  // interleaved, so that plan reads coalesce
     const QPlan P = plan[q];
     if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) {
       atomicAdd(&gbucket[graph_bucket(P)], 1);
@@ -202,7 +213,7 @@ __global__ void k_worklist(QPlan* __restrict__ plan, int64_t nq, int64_t n, int3
   if (t < NB) bucket[t] = nbeam + my_end;  // one past the last slot of bucket t
   __syncthreads();
   int32_t spos = spart[t] - sc;
-  for (int64_t q = s0; q < s1; ++q) {
+  for (int64_t q = t; q < nq; q += T) {
     QPlan P = plan[q];
     if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) {
       const int32_t w = atomicSub(&gbucket[graph_bucket(P)], 1) - 1;
@@ -1254,9 +1265,10 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   X.B = B;
   int rc = prepare_pass(ix, kernel_for<0>(dv.d, dv.precision), lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap),
                         nq, X.p0);
+  // the re-run pass holds the few queries that overflowed: a small grid launches faster
   if (rc == UNIFY_OK)
-    rc = prepare_pass(ix, kernel_for<1>(dv.d, dv.precision), lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap), nq,
-                      X.p1);
+    rc = prepare_pass(ix, kernel_for<1>(dv.d, dv.precision), lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap),
+                      std::min<int64_t>(nq, 512), X.p1);
   return rc;
 }
 
