@@ -225,6 +225,17 @@ def main():
         per_strategy[name] = {"qps": round(nq / s, 1), "recall@10": round(recall_of(o[0]), 4)}
         log(f"{name}: {nq / s:,.0f} QPS recall {per_strategy[name]['recall@10']}")
 
+    # ---- hybrid neighbour selections S1 and S2 (Sec. 4.2) on the forced hybrid search ----
+    selection = {}
+    for sel_name, s1 in (("S2", False), ("S1", True)):
+        for e in (16, 32, 64, 128):
+            s, o = timed(m, e, bp, u.HYBRID, steps=max(1, args.steps // 2 + 1), warmup=1, ta=ta, tb=tb, vc=vc,
+                         select_s1=s1)
+            selection[f"{sel_name}_ef{e}"] = {"qps": round(nq / s, 1), "recall@10": round(recall_of(o[0]), 4)}
+        log(f"hybrid selection {sel_name}: " + ", ".join(
+            f"ef={e}: {selection[f'{sel_name}_ef{e}']['qps']:,.0f} QPS r={selection[f'{sel_name}_ef{e}']['recall@10']}"
+            for e in (16, 32, 64, 128)))
+
     # ---- roofline of the search kernel: counters of one more (identical) call ----
     ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True, timing=True)
     torch.cuda.synchronize()
@@ -297,6 +308,7 @@ def main():
                    "build_s": round(build_s, 1)},
         "by_precision": by_prec,
         "per_strategy": per_strategy,
+        "hybrid_selection": selection,
         "roofline": roofline,
         "batch100k": b100,
         "wide960": wide,

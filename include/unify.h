@@ -69,7 +69,10 @@ enum {
 
 /* Bits of unify_params.flags. */
 enum {
-  UNIFY_FLAG_TIMING = 1  /* record HIP events around the search kernels; see unify_last_timing */
+  UNIFY_FLAG_TIMING = 1,    /* record HIP events around the search kernels; see unify_last_timing */
+  UNIFY_FLAG_SELECT_S1 = 2  /* hybrid neighbour selection S1 (Sec. 4.2): rank every entry of the
+                               active chunks by its distance to the expanded object and take the
+                               m nearest, instead of the first ceil(m / S') of each chunk (S2) */
 };
 
 /* Search parameters.  Zero in a field selects its default. */

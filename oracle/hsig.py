@@ -57,7 +57,7 @@ def lib():
         L.orc_dist64.restype = D
         L.orc_dist64.argtypes = [P, P, I32]
         L.orc_search.restype = I32
-        L.orc_search.argtypes = [P, P, I64, P, P, I32, I32, I32, I32, I32, D, D, P, P, P, I32]
+        L.orc_search.argtypes = [P, P, I64, P, P, I32, I32, I32, I32, I32, D, D, P, P, P, I32, I32]
         L.orc_layer_search.restype = I32
         L.orc_layer_search.argtypes = [P, P, I32, I32, I32, I32, I32, I32, I32, I32, I64, I64, P, P]
         L.orc_prune.restype = I32
@@ -77,6 +77,8 @@ def lib():
         L.orc_e4m3_encode.argtypes = [P, I64, P]
         L.orc_e4m3_decode.argtypes = [P, I64, P]
         L.orc_fp8_rows.argtypes = [P, I64, I32, P, P, P]
+        L.orc_neighbours.restype = I32
+        L.orc_neighbours.argtypes = [P, I32, I32, I32, I32, I32, I32, P, I32]
         L.orc_set_store.restype = I32
         L.orc_set_store.argtypes = [P, I32, I32]
         _lib = L
@@ -219,6 +221,15 @@ class Index:
         lib().orc_get_layer(self._h, l, _p(adj), _p(gl))
         return adj, gl
 
+    def neighbours(self, o: int, l: int, a: int, b: int, m: int, select_s1: bool = False) -> np.ndarray:
+        """Internal ids a hybrid expansion of o on layer l takes (active segments a..b, budget m;
+        selection S1 or S2 of Sec. 4.2, distances in the current store)."""
+        out = np.zeros(self.S * max(self.M0, self.MU), np.int32)
+        c = lib().orc_neighbours(self._h, o, l, a, b, m, int(select_s1), _p(out), out.size)
+        if c < 0:
+            raise IndexError((o, l, a, b, m))
+        return out[:c]
+
     def skiplist_range(self, l: int, h: int):
         out = np.zeros(self.n, np.int64)
         c = lib().orc_skiplist_range(self._h, l, h, _p(out), self.n)
@@ -243,7 +254,7 @@ class Index:
             raise ValueError(lib().orc_last_error().decode())
 
     def search(self, Q, l, h, k, ef, m=0, p=1, strategy=AUTO, tau_a=0.01, tau_b=0.5,
-               counters=False, batch_form=False):
+               counters=False, batch_form=False, select_s1=False):
         Q = np.ascontiguousarray(Q, np.float32)
         l = np.ascontiguousarray(l, np.int64)
         h = np.ascontiguousarray(h, np.int64)
@@ -252,7 +263,7 @@ class Index:
         dist = np.zeros((nq, k), np.float32)
         cnt = np.zeros((nq, NCOUNT), np.int64)
         rc = lib().orc_search(self._h, _p(Q), nq, _p(l), _p(h), k, ef, m, p, strategy, tau_a, tau_b,
-                              _p(ids), _p(dist), _p(cnt), int(batch_form))
+                              _p(ids), _p(dist), _p(cnt), int(batch_form), int(select_s1))
         if rc != 0:
             raise ValueError(lib().orc_last_error().decode())
         return (ids, dist, cnt) if counters else (ids, dist)

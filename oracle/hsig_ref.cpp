@@ -793,7 +793,9 @@ struct Query {
   int64_t lo = 0, hi = 0;  // in-range internal ids are [lo, hi)
   int64_t l = 0, h = 0;    // inclusive attribute range
   int a = 0, b = -1;       // active segments
-  int c = 0;               // entries per active chunk
+  int c = 0;               // entries per active chunk (selection S2)
+  int m = 0;               // neighbours per expansion (selection S1)
+  bool s1 = false;         // hybrid neighbour selection S1 instead of S2
   int64_t* cnt;
   bool in_range(int v) const { return V->attr[v] >= l && V->attr[v] <= h; }
   // distance in the store the graph searches use
@@ -807,9 +809,23 @@ struct Query {
 
 // Neighbours of o on layer l: the first c entries of each active chunk (hybrid),
 // or the marked global edges (post).
+// Hybrid selections (Sec. 4.2): S2 (default) takes the first ceil(m / S') entries of
+// each active chunk; S1 ranks every entry of the active chunks by its distance
+// to o and takes the m nearest (key (distance, id); distances in the search's
+// store, o's copy standing in for the query).
 void neighbours(const Query& Q, bool hybrid, int o, int l, std::vector<int>& out) {
   out.clear();
-  if (hybrid) {
+  if (hybrid && Q.s1) {
+    const int mc = Q.V->mcap(l);
+    std::vector<FI> all;
+    for (int j = Q.a; j <= Q.b; ++j) {
+      const int32_t* ch = Q.V->chunk(o, l, j);
+      for (int r = 0; r < mc; ++r)
+        if (ch[r] >= 0) all.push_back(FI(dist32(Q.V->svec(o), Q.V->svec(ch[r]), Q.V->d), ch[r]));
+    }
+    std::sort(all.begin(), all.end());
+    for (size_t i = 0; i < all.size() && (int)i < Q.m; ++i) out.push_back(all[i].second);
+  } else if (hybrid) {
     const int mc = Q.V->mcap(l);
     for (int j = Q.a; j <= Q.b; ++j) {
       const int32_t* ch = Q.V->chunk(o, l, j);
@@ -975,6 +991,7 @@ struct Searcher {
   std::vector<FI> hybrid(Query& Q, int k, int ef, int m, int p, bool batch_form) {
     const int Sa = Q.b - Q.a + 1;
     Q.c = (m + Sa - 1) / Sa;
+    Q.m = m;
     int top = -1;
     for (int j = Q.a; j <= Q.b; ++j)
       if (V->seg_entry[j] >= 0) top = std::max(top, V->seg_maxlevel[j]);
@@ -1217,7 +1234,7 @@ int orc_prune(const float* owner, const float* cands, int nc, int d, int Mcap, i
 // runs layer 0 in the beam form even for p = 1 (and records live-candidate counts).
 int orc_search(void* h, const float* Q, int64_t nq, const int64_t* L, const int64_t* H, int k,
                int ef, int m, int p, int strategy, double tau_a, double tau_b, int64_t* out_ids,
-               float* out_dist, int64_t* counters, int batch_form) {
+               float* out_dist, int64_t* counters, int batch_form, int select_s1) {
   OrcIndex* ix = (OrcIndex*)h;
   const View& V = ix->V;
   if (k < 1 || ef < 1 || p < 1 || strategy < 0 || strategy > 3) {
@@ -1236,6 +1253,7 @@ int orc_search(void* h, const float* Q, int64_t nq, const int64_t* L, const int6
     qq.V = &V;
     qq.q = Q + (size_t)i * V.d;
     qq.cnt = cnt;
+    qq.s1 = select_s1 != 0;
     srch.plan(qq, L[i], H[i]);
     const int64_t Y = qq.hi - qq.lo;
     int st = strategy;
@@ -1311,6 +1329,27 @@ int orc_layer_search(void* h, const float* q, int ep, int layer, int ef, int hyb
     out_dist[t] = r[t].first;
   }
   return (int)r.size();
+}
+
+// The neighbours a hybrid expansion of o on layer l takes with the active
+// segments a..b and budget m: selection S1 (s1 != 0) or S2 (Sec. 4.2), in the
+// current store.  Writes at most cap ids; returns how many there are.
+int orc_neighbours(void* h, int o, int l, int a, int b, int m, int s1, int32_t* out, int cap) {
+  const View& V = ((OrcIndex*)h)->V;
+  if (o < 0 || o >= V.n || V.level[o] < l || a < 0 || b < a || b >= V.S || m < 1) return -1;
+  std::vector<int64_t> cnt(C_NCOUNT, 0);
+  Query qq;
+  qq.V = &V;
+  qq.cnt = cnt.data();
+  qq.a = a;
+  qq.b = b;
+  qq.m = m;
+  qq.c = (m + (b - a + 1) - 1) / (b - a + 1);
+  qq.s1 = s1 != 0;
+  std::vector<int> nb;
+  neighbours(qq, true, o, l, nb);
+  for (size_t t = 0; t < nb.size() && (int)t < cap; ++t) out[t] = nb[t];
+  return (int)nb.size();
 }
 
 }  // extern "C"

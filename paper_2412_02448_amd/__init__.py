@@ -18,6 +18,7 @@ __all__ = ["Index", "UnifyError", "AUTO", "PRE", "HYBRID", "POST", "FP32", "BF16
 
 AUTO, PRE, HYBRID, POST = 0, 1, 2, 3
 FLAG_TIMING = 1
+FLAG_SELECT_S1 = 2
 FP32, BF16, FP8E4M3 = 0, 1, 2
 _PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8E4M3, "fp8e4m3": FP8E4M3}
 
@@ -188,11 +189,14 @@ class Index:
 
     def search(self, queries, l, h, k: int, ef: int, strategy=None, m: int = 0, beam_p: int = 1,
                rerank_mult: int = 0, tau_a: float = 0.0, tau_b: float = 0.0, stats: bool = False,
-               out=None, stream=None, timing: bool = False, cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0):
+               out=None, stream=None, timing: bool = False, cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0,
+               select_s1: bool = False):
         """Enqueues a search on the current stream (or `stream`) and returns torch tensors.
 
         queries: cuda float32 [nq, d]; l, h: cuda int64 [nq] (inclusive); strategy: None (auto),
-        an int for every query, or a cuda int8 [nq] tensor.  Returns (ids, dist, strategy[, stats]).
+        an int for every query, or a cuda int8 [nq] tensor.  select_s1: hybrid neighbour selection S1
+        (the m entries of the active chunks nearest the expanded object) instead of S2 (the first
+        ceil(m / S') of each chunk).  Returns (ids, dist, strategy[, stats]).
         """
         import torch
         dev = torch.device("cuda", self.device)
@@ -217,7 +221,7 @@ class Index:
             sts = torch.empty((nq, 8), dtype=torch.int32, device=dev) if stats else None
         else:
             ids, dist, ost, sts = out
-        flags = FLAG_TIMING if timing else 0
+        flags = (FLAG_TIMING if timing else 0) | (FLAG_SELECT_S1 if select_s1 else 0)
         prm = _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, flags, visit_cap, pre_chunk)
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         lib = load_library()
@@ -240,7 +244,7 @@ class Batch:
 
     def __init__(self, index: Index, queries, l, h, k: int, ef: int, strategy=None, stats: bool = False,
                  m: int = 0, beam_p: int = 1, rerank_mult: int = 0, tau_a: float = 0.0, tau_b: float = 0.0,
-                 cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0):
+                 cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0, select_s1: bool = False):
         import torch
         dev = torch.device("cuda", index.device)
         nq = queries.shape[0]
@@ -257,7 +261,8 @@ class Batch:
         self.dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
         self.strategy_run = torch.empty((nq,), dtype=torch.int8, device=dev)
         self.stats = torch.empty((nq, 8), dtype=torch.int32, device=dev) if stats else None
-        prm = _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, 0, visit_cap, pre_chunk)
+        prm = _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, FLAG_SELECT_S1 if select_s1 else 0, visit_cap,
+                      pre_chunk)
         torch.cuda.synchronize(dev)  # the tensors above exist before the capture reads their addresses
         self._b = C.c_void_p()
         _check(load_library().unify_batch_create(index._h, _ptr(queries), nq, _ptr(l), _ptr(h), k, ef,
@@ -293,10 +298,12 @@ class Server:
 
     def __init__(self, index: Index, k: int, ef: int, max_batch: int = 4096, inflight: int = 2,
                  max_wait_s: float = 0.0, m: int = 0, beam_p: int = 1, rerank_mult: int = 0, tau_a: float = 0.0,
-                 tau_b: float = 0.0, cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0):
+                 tau_b: float = 0.0, cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0,
+                 select_s1: bool = False):
         self.index, self.k = index, k
+        flags = FLAG_SELECT_S1 if select_s1 else 0
         cfg = _ServerConfig(k, ef, max_batch, inflight, max_wait_s,
-                            _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, 0, visit_cap, pre_chunk))
+                            _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, flags, visit_cap, pre_chunk))
         self._s = C.c_void_p()
         _check(load_library().unify_server_create(index._h, C.byref(cfg), C.byref(self._s)))
 

@@ -43,7 +43,7 @@ struct SearchArgs {
   const float* Q;
   int64_t nq;
   int32_t k, ef, m, p, rerank;
-  int32_t ccap, hcap, ef_blocks, nbr_cap;
+  int32_t ccap, hcap, ef_blocks, nbr_cap, sel_cap;
   int32_t pass;  // 0: first pass, 1: larger-capacity re-run
   float bA, bB, bC, bD;  // constants of root_bounds
   int64_t* out_ids;
@@ -356,6 +356,7 @@ struct Lds {
   u64* cand;
   uint32_t* hash;
   u64* bkeys;  // neighbour ids (low 32 bits) before evaluation, their keys after
+  u64* sel;    // selection S1: the ranked list (sel_cap - 64 entries), then 64 scratch keys
 };
 
 // Visited set of one layer search.  An 8-way set-associative cache of ids in
@@ -416,7 +417,7 @@ struct Counters {
 
 // One layer of the search (Alg. 1 / Alg. 7 with beam width p).  On return, the
 // ann list holds `al` keys ascending.  Returns false on capacity overflow.
-template <int NG, int PREC>
+template <int NG, int PREC, bool S1 = false>
 __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
                              bool hybrid, bool filter, int c, int32_t ep, u64 ep_key, int layer, int efl,
                              int p, int& al, Counters& cnt, uint32_t* tags, uint32_t& epoch) {
@@ -482,7 +483,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
     }
     if (npop == 0) break;
     cnt.nexp += npop;
-    cnt.nadj += npop * per_node;
+    cnt.nadj += npop * ((S1 && hybrid) ? Sa * mc : per_node);
     // unvisited neighbours of the popped candidates.  The adjacency entries of
     // all popped objects are loaded first (GB loads of 64 entries in flight per
     // wave) into the neighbour buffer, densely, so a step waits for one round
@@ -498,9 +499,54 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
     }
     const int32_t* table = hybrid ? (layer == 0 ? ix.adj0 : ix.adjU) : (layer == 0 ? ix.glist0 : ix.glistU);
     const int cc = min(c, mc);
-    const int ntot = npop * per_node;
+    int ntot = npop * per_node;
     constexpr int GB = 8;
-    for (int e0 = 0; e0 < ntot; e0 += GB * WAVE) {
+    if constexpr (S1) {
+      if (hybrid) {
+        // selection S1: each popped object's entries in the active chunks, ranked by
+        // the distance to that object (its row stands in for the query); the m nearest
+        ntot = 0;
+        const int etot = Sa * mc, mk = A.m;
+        u64* slist = L.sel;
+        u64* stmp = L.sel + A.sel_cap - WAVE;
+        for (int t = 0; t < npop; ++t) {
+          const int32_t o = popped[t];
+          const int64_t rb = (int64_t)shfl64((u64)rowbase, t);
+          float4 qo[NG];
+          {
+            const int s = lane & 15, G = ix.d >> 2;
+            const float sc = Store<PREC>::scale(ix, o);
+#pragma unroll
+            for (int i = 0; i < NG; ++i) {
+              const int g = s + 16 * i;
+              qo[i] = g < G ? Store<PREC>::decode(Store<PREC>::load(ix, o, g), sc) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+          }
+          int sl = 0;
+          for (int i = lane; i < A.sel_cap - WAVE; i += WAVE) slist[i] = KEY_MAX;
+          __syncthreads();
+          for (int e0 = 0; e0 < etot; e0 += WAVE) {
+            const int e = e0 + lane;
+            const int32_t u = e < etot ? table[rb + (int64_t)(P.a + e / mc) * mc + e % mc] : -1;
+            const u64 um = ballot(u >= 0);
+            const int cu = __popcll(um);
+            if (cu == 0) continue;
+            if (u >= 0) stmp[rank_in(um)] = (uint32_t)u;
+            __syncthreads();
+            eval_keys<NG, PREC>(ix, qo, cu, [&](int i) { return key_id(stmp[i]); }, stmp);
+            __syncthreads();
+            const u64 key = lane < cu ? stmp[lane] : KEY_MAX;
+            const u64 Tm = sl == mk ? slist[mk - 1] : KEY_MAX;
+            list_insert(slist, sl, mk, key < Tm ? key : KEY_MAX);
+            __syncthreads();
+          }
+          for (int i = lane; i < sl; i += WAVE) L.bkeys[ntot + i] = (u64)(uint32_t)key_id(slist[i]);
+          ntot += sl;
+          __syncthreads();
+        }
+      }
+    }
+    for (int e0 = 0; e0 < ntot && !(S1 && hybrid); e0 += GB * WAVE) {
       int32_t vv[GB];
 #pragma unroll
       for (int u = 0; u < GB; ++u) {
@@ -766,7 +812,7 @@ __device__ void pre_store_chunk(const SearchArgs& A, const Lds& L, int32_t q, co
 
 __device__ __forceinline__ bool ne_missing(int top) { return top < 0; }
 
-template <int NG, int PREC>
+template <int NG, int PREC, bool S1 = false>
 __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chunk, uint32_t* tags,
                           uint32_t& epoch) {
   const DevIndex& ix = A.ix;
@@ -846,13 +892,13 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
       __syncthreads();
     }
     for (int layer = top; layer >= 1 && ok; --layer) {
-      ok = layer_search<NG, PREC>(A, L, qv, P, hybrid, false, c, ep, ep_key, layer, 1, 1, al, cnt, tags, epoch);
+      ok = layer_search<NG, PREC, S1>(A, L, qv, P, hybrid, false, c, ep, ep_key, layer, 1, 1, al, cnt, tags, epoch);
       ep_key = L.ann[0];
       ep = key_id(ep_key);
       __syncthreads();
     }
     if (ok)
-      ok = layer_search<NG, PREC>(A, L, qv, P, hybrid, hybrid, c, ep, ep_key, 0, A.ef, A.p, al, cnt, tags, epoch);
+      ok = layer_search<NG, PREC, S1>(A, L, qv, P, hybrid, hybrid, c, ep, ep_key, 0, A.ef, A.p, al, cnt, tags, epoch);
     if (ne_missing(top)) {
       al = 0;
       ok = true;
@@ -909,7 +955,7 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
   }
 }
 
-template <int NG, int PREC, int PASS>
+template <int NG, int PREC, int PASS, bool S1 = false>
 __global__ void __launch_bounds__(64, NG > 4 ? 1 : (PREC == UNIFY_FP32 ? WAVES_PER_SIMD_FP32 : WAVES_PER_SIMD_LOW)) k_search(SearchArgs A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   Lds L;
@@ -920,6 +966,8 @@ __global__ void __launch_bounds__(64, NG > 4 ? 1 : (PREC == UNIFY_FP32 ? WAVES_P
   p += sizeof(u64) * A.ccap;
   L.bkeys = reinterpret_cast<u64*>(p);
   p += sizeof(u64) * A.nbr_cap;
+  L.sel = reinterpret_cast<u64*>(p);  // S1 only (sel_cap = 0 otherwise)
+  p += sizeof(u64) * A.sel_cap;
   L.hash = reinterpret_cast<uint32_t*>(p);
   const int32_t nwork = *A.nwork;
   // this wave's visited tags; the epoch persists across launches in A.epochs
@@ -931,7 +979,7 @@ __global__ void __launch_bounds__(64, NG > 4 ? 1 : (PREC == UNIFY_FP32 ? WAVES_P
     if (lane_id() == 0) w = atomicAdd(A.next, 1);
     w = __shfl(w, 0, WAVE);
     if (w >= nwork) break;
-    run_query<NG, PREC>(A, L, A.work[w], A.wchunk ? A.wchunk[w] : 0, tags, epoch);
+    run_query<NG, PREC, S1>(A, L, A.work[w], A.wchunk ? A.wchunk[w] : 0, tags, epoch);
     __syncthreads();
   }
   if (lane_id() == 0) __hip_atomic_store(&A.epochs[slot], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -984,28 +1032,33 @@ __global__ void __launch_bounds__(256) k_pre_merge(DevIndex ix, const QPlan* __r
 
 namespace {
 
-size_t lds_bytes(int ef_blocks, int ccap, int hcap, int nbr_cap) {
-  return sizeof(u64) * ((size_t)ef_blocks * WAVE + ccap + nbr_cap) + sizeof(uint32_t) * hcap;
+size_t lds_bytes(int ef_blocks, int ccap, int hcap, int nbr_cap, int sel_cap = 0) {
+  return sizeof(u64) * ((size_t)ef_blocks * WAVE + ccap + nbr_cap + sel_cap) + sizeof(uint32_t) * hcap;
 }
 
 typedef void (*KernelFn)(SearchArgs);
 
-template <int PREC, int PASS>
+template <int PREC, int PASS, bool S1>
 KernelFn pick_kernel(int d) {
   const int ng = (d + 63) / 64;
-  if (ng <= 2) return k_search<2, PREC, PASS>;
-  if (ng <= 4) return k_search<4, PREC, PASS>;
-  if (ng <= 8) return k_search<8, PREC, PASS>;
-  if (ng <= 15) return k_search<15, PREC, PASS>;
-  if (ng <= 32) return k_search<32, PREC, PASS>;
+  if (ng <= 2) return k_search<2, PREC, PASS, S1>;
+  if (ng <= 4) return k_search<4, PREC, PASS, S1>;
+  if (ng <= 8) return k_search<8, PREC, PASS, S1>;
+  if (ng <= 15) return k_search<15, PREC, PASS, S1>;
+  if (ng <= 32) return k_search<32, PREC, PASS, S1>;
   return nullptr;
 }
 
+template <int PASS, bool S1>
+KernelFn kernel_for_sel(int d, int prec) {
+  if (prec == UNIFY_BF16) return pick_kernel<UNIFY_BF16, PASS, S1>(d);
+  if (prec == UNIFY_FP8E4M3) return pick_kernel<UNIFY_FP8E4M3, PASS, S1>(d);
+  return pick_kernel<UNIFY_FP32, PASS, S1>(d);
+}
+
 template <int PASS>
-KernelFn kernel_for(int d, int prec) {
-  if (prec == UNIFY_BF16) return pick_kernel<UNIFY_BF16, PASS>(d);
-  if (prec == UNIFY_FP8E4M3) return pick_kernel<UNIFY_FP8E4M3, PASS>(d);
-  return pick_kernel<UNIFY_FP32, PASS>(d);
+KernelFn kernel_for(int d, int prec, bool s1 = false) {
+  return s1 ? kernel_for_sel<PASS, true>(d, prec) : kernel_for_sel<PASS, false>(d, prec);
 }
 
 #define HIP_OK(x)                                                            \
@@ -1228,6 +1281,8 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   }
   A.ef_blocks = (std::max(R.ef, R.k) + WAVE - 1) / WAVE;
   A.nbr_cap = std::max((R.p * per_node + WAVE - 1) / WAVE * WAVE, WAVE);
+  // selection S1 ranks a popped object's entries: a list of m plus 64 scratch keys
+  A.sel_cap = (R.flags & UNIFY_FLAG_SELECT_S1) ? (R.m + WAVE - 1) / WAVE * WAVE + WAVE : 0;
   A.out_ids = out_ids;
   A.out_dist = out_dist;
   A.out_stats = out_stats;
@@ -1252,7 +1307,7 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) != hipSuccess)
     maxlds = 65536;
   int cc = 16384, hc = std::max(R.hcap, 2048);
-  while (lds_bytes(A.ef_blocks, cc, hc, A.nbr_cap) > (size_t)maxlds && cc > 2 * R.ccap) cc /= 2;
+  while (lds_bytes(A.ef_blocks, cc, hc, A.nbr_cap, A.sel_cap) > (size_t)maxlds && cc > 2 * R.ccap) cc /= 2;
   SearchArgs B = A;
   B.ccap = cc;
   B.hcap = hc;
@@ -1263,12 +1318,13 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   B.next = X.S.counters + 3;
   X.A = A;
   X.B = B;
-  int rc = prepare_pass(ix, kernel_for<0>(dv.d, dv.precision), lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap),
-                        nq, X.p0);
+  const bool s1 = (R.flags & UNIFY_FLAG_SELECT_S1) != 0;
+  int rc = prepare_pass(ix, kernel_for<0>(dv.d, dv.precision, s1),
+                        lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap, A.sel_cap), nq, X.p0);
   // the re-run pass holds the few queries that overflowed: a small grid launches faster
   if (rc == UNIFY_OK)
-    rc = prepare_pass(ix, kernel_for<1>(dv.d, dv.precision), lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap),
-                      std::min<int64_t>(nq, 512), X.p1);
+    rc = prepare_pass(ix, kernel_for<1>(dv.d, dv.precision, s1),
+                      lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap, B.sel_cap), std::min<int64_t>(nq, 512), X.p1);
   return rc;
 }
 

@@ -82,6 +82,13 @@ def test_parity_low_precision(c1, name, prec, strategy):
             assert (gst[:, 3] != 2).all()
             bad = np.nonzero((ref[0] != gid).any(1) | (ref[1].view(np.uint32) != gd.view(np.uint32)).any(1))[0]
             assert bad.size == 0, f"{name} k={k} ef={ef} p={p}: {bad.size} rows differ, first {bad[:5]}"
+        if strategy in (hsig.AUTO, hsig.HYBRID):
+            # selection S1 ranks chunk entries by distances in the same store
+            ref = ix.search(W.queries, W.l, W.h, 10, 48, m=16, p=2, strategy=strategy, select_s1=True)
+            gid, gd, _, gst = gpu_search(g, W.queries, W.l, W.h, 10, 48, None if strategy == hsig.AUTO else strategy,
+                                         beam_p=2, m=16, select_s1=True)
+            bad = np.nonzero((ref[0] != gid).any(1) | (ref[1].view(np.uint32) != gd.view(np.uint32)).any(1))[0]
+            assert bad.size == 0, f"{name} S1: {bad.size} rows differ, first {bad[:5]}"
     finally:
         ix.set_store(hsig.FP32)
         g.close()

@@ -90,6 +90,22 @@ def test_parity_neighbour_budget(c1, m):
     assert_parity(ref, got, f"m={m}")
 
 
+@pytest.mark.parametrize("m,p", [(4, 1), (16, 2), (64, 1)])
+@pytest.mark.parametrize("strategy", [hsig.HYBRID, hsig.AUTO])
+def test_parity_selection_s1(c1, strategy, m, p):
+    """Selection S1: each expanded object's active-chunk entries ranked by distance."""
+    W, ix, g = c1
+    print(f"[case] hybrid10k S1 m={m} p={p} strategy={strategy}", flush=True)
+    ref = ix.search(W.queries, W.l, W.h, 10, 32, m=m, p=p, strategy=strategy, select_s1=True)
+    got = gpu_search(g, W, 10, 32, strategy=None if strategy == hsig.AUTO else strategy, m=m, beam_p=p,
+                     select_s1=True)
+    assert_parity(ref, got, f"S1 m={m} p={p}")
+    if strategy == hsig.HYBRID and m == 16:
+        # S1 and S2 are different selections: the searches are not all the same
+        s2 = ix.search(W.queries, W.l, W.h, 10, 32, m=m, p=p, strategy=strategy)
+        assert (s2[0] != ref[0]).any()
+
+
 @pytest.mark.parametrize("chunk", [64, 100, 1000])
 def test_parity_split_pre_filter(c1, chunk):
     """Pre-filter scans split into chunks on several wavefronts and merged."""

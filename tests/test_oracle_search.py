@@ -169,3 +169,72 @@ def test_recall_grows_with_ef(small_index, small_workload):
             r.append(exact.recall(ids[i], tid, 10, Y))
         rec.append(np.mean(r))
     assert rec == sorted(rec) and rec[-1] > 0.97, rec
+
+
+def test_neighbour_selection_brute_force(small_index, small_workload):
+    """One expansion's neighbours (Sec. 4.2) against the chunks themselves: S2 = the
+    first ceil(m / S') entries of each active chunk in chunk order; S1 = the m entries
+    of the active chunks nearest the expanded object, checked with FP64 distances
+    (any FP32 rounding can only swap entries whose FP64 distances nearly tie)."""
+    ix, W = small_index, small_workload
+    ext = ix.ext_ids()
+    X = W.base[ext].astype(np.float64)  # rows in internal-id order
+    rng = np.random.default_rng(5)
+    checked = 0
+    for l in (0, 1):
+        adj, _ = ix.layer(l)
+        lev = ix.levels()
+        objs = np.nonzero(lev >= l)[0]
+        for o in rng.choice(objs, size=min(40, objs.size), replace=False):
+            a = int(rng.integers(0, ix.S))
+            b = int(rng.integers(a, ix.S))
+            for m in (1, 3, 8, 40):
+                sa = b - a + 1
+                c = -(-m // sa)
+                s2 = ix.neighbours(int(o), l, a, b, m)
+                want2 = [int(u) for j in range(a, b + 1) for u in adj[o, j, :c] if u >= 0]
+                assert s2.tolist() == want2
+                s1 = ix.neighbours(int(o), l, a, b, m, select_s1=True)
+                ent = np.array([u for j in range(a, b + 1) for u in adj[o, j] if u >= 0], np.int64)
+                assert len(s1) == min(m, ent.size)
+                if ent.size == 0:
+                    continue
+                d64 = ((X[ent] - X[o]) ** 2).sum(1)
+                order = np.lexsort((ent, d64))
+                t = d64[order[len(s1) - 1]]  # the m-th smallest FP64 distance
+                ds1 = ((X[s1] - X[o]) ** 2).sum(1)
+                # S1's picks are the nearest: none beyond the m-th FP64 distance,
+                # and every entry strictly nearer than it is picked
+                assert np.all(ds1 <= t * (1 + 1e-5) + 1e-30)
+                nearer = ent[d64 < t * (1 - 1e-5)]
+                assert np.isin(nearer, s1).all()
+                # in (distance, id) order, duplicates (an object in two chunks) kept
+                assert np.all(np.diff(ds1) >= -1e-5 * t - 1e-30)
+                checked += 1
+    assert checked > 100
+
+
+def test_selection_s1_special_cases(small_index, small_workload):
+    """Hybrid selection S1 (Sec. 4.2: the m entries of the active chunks nearest to
+    the expanded object): with m covering every entry it picks the same neighbours as
+    S2 (so results are identical); with a smaller m it never examines more than m
+    neighbours per expansion; its results are in range, sorted, with exact distances."""
+    ix, W = small_index, small_workload
+    mall = ix.S * ix.M0
+    a = ix.search(W.queries, W.l, W.h, 10, 40, m=mall, strategy=hsig.HYBRID)
+    b = ix.search(W.queries, W.l, W.h, 10, 40, m=mall, strategy=hsig.HYBRID, select_s1=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for m in (4, 12):
+        ids, dist, cnt = ix.search(W.queries, W.l, W.h, 10, 40, m=m, strategy=hsig.HYBRID, select_s1=True,
+                                   counters=True)
+        # entry distances of each active segment (<= S per query) plus m per expansion
+        assert np.all(cnt[:, hsig.NDIST] <= ix.S + m * cnt[:, hsig.NEXP])
+        for i in range(len(ids)):
+            row = ids[i][ids[i] >= 0]
+            assert np.all((W.attr[row] >= W.l[i]) & (W.attr[row] <= W.h[i]))
+            d32 = np.array([hsig.dist32(W.queries[i], W.base[e]) for e in row], np.float32)
+            assert np.array_equal(d32, dist[i][: len(row)])
+    # S1 and S2 differ once m is smaller than the active entries (the test above is not vacuous)
+    s2 = ix.search(W.queries, W.l, W.h, 10, 40, m=4, strategy=hsig.HYBRID, counters=True)
+    s1 = ix.search(W.queries, W.l, W.h, 10, 40, m=4, strategy=hsig.HYBRID, select_s1=True, counters=True)
+    assert not np.array_equal(s1[2][:, hsig.NDIST], s2[2][:, hsig.NDIST])
