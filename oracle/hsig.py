@@ -42,7 +42,9 @@ def lib():
         L = C.CDLL(compile_oracle())
         P, I64, I32, D, F = C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_float
         L.orc_build.restype = P
-        L.orc_build.argtypes = [P, P, P, I64, I32, I32, I32, I32, I32, D, C.c_uint64, I32]
+        L.orc_build.argtypes = [P, P, P, I64, I32, I32, I32, I32, I32, D, C.c_uint64, I32, I64]
+        L.orc_insert.restype = I32
+        L.orc_insert.argtypes = [P, P, P, P, I64]
         L.orc_read.restype = P
         L.orc_read.argtypes = [C.c_char_p]
         L.orc_write.restype = I32
@@ -165,13 +167,27 @@ class Index:
         (self.n, self.d, self.S, self.M0, self.MU, self.L, self.gentry, self.R, self.ef_cons) = map(int, info)
 
     @classmethod
-    def build(cls, X, attr, level_u, S, M, ef_cons, M0=0, mL=0.0, seed=0, hnsw=False):
+    def build(cls, X, attr, level_u, S, M, ef_cons, M0=0, mL=0.0, seed=0, hnsw=False, bnd_n=0):
+        """HSIG over X (Alg. 6, objects inserted in row order); segment boundaries from
+        the attributes of the first bnd_n rows (0: all)."""
         X = np.ascontiguousarray(X, np.float32)
         attr = np.ascontiguousarray(attr, np.int64)
         level_u = np.ascontiguousarray(level_u, np.float64)
         n, d = X.shape
-        h = lib().orc_build(_p(X), _p(attr), _p(level_u), n, d, S, M, M0, ef_cons, mL, seed, int(hnsw))
+        h = lib().orc_build(_p(X), _p(attr), _p(level_u), n, d, S, M, M0, ef_cons, mL, seed, int(hnsw), int(bnd_n))
         return cls(h)
+
+    def insert(self, X, attr, level_u) -> None:
+        """Inserts more objects (Alg. 6) into an index built here; they take the next
+        external ids.  Segment boundaries do not move."""
+        X = np.ascontiguousarray(X, np.float32)
+        attr = np.ascontiguousarray(attr, np.int64)
+        level_u = np.ascontiguousarray(level_u, np.float64)
+        if lib().orc_insert(self._h, _p(X), _p(attr), _p(level_u), X.shape[0]) != 0:
+            raise ValueError(lib().orc_last_error().decode())
+        info = np.zeros(9, np.int64)
+        lib().orc_info(self._h, _p(info))
+        (self.n, self.d, self.S, self.M0, self.MU, self.L, self.gentry, self.R, self.ef_cons) = map(int, info)
 
     @classmethod
     def read(cls, path: str):

@@ -455,8 +455,10 @@ struct Builder {
     ++n_inserted;
   }
 
+  // Segment boundaries come from the attributes of the first bnd_n objects (all
+  // of them when bnd_n <= 0): the objects present when the index is created.
   void init(const float* X_, const int64_t* attr_, int64_t n_, int d_, int S_, int M_, int M0_,
-            int efCons_, double mL_) {
+            int efCons_, double mL_, int64_t bnd_n = 0) {
     n = n_;
     d = d_;
     S = S_;
@@ -466,10 +468,11 @@ struct Builder {
     mL = mL_ > 0 ? mL_ : 1.0 / std::log((double)M_);
     X.assign(X_, X_ + (size_t)n * d);
     attr.assign(attr_, attr_ + n);
-    std::vector<int64_t> srt(attr);
+    const int64_t nb = bnd_n > 0 && bnd_n < n ? bnd_n : n;
+    std::vector<int64_t> srt(attr.begin(), attr.begin() + nb);
     std::sort(srt.begin(), srt.end());
     bnd.clear();
-    for (int j = 1; j < S; ++j) bnd.push_back(srt[(size_t)((int64_t)j * n / S)]);
+    for (int j = 1; j < S; ++j) bnd.push_back(srt[(size_t)((int64_t)j * nb / S)]);
     seg.resize(n);
     for (int64_t v = 0; v < n; ++v) seg[v] = seg_of(attr[v]);
     level.assign(n, 0);
@@ -481,6 +484,21 @@ struct Builder {
     head_next.clear();
     stamp.assign(n, 0u);
     cur = 0;
+  }
+
+  // Room for m more objects (external ids n .. n + m - 1); the segment
+  // boundaries stay as they are.  HSIGInsert then inserts them (Alg. 6).
+  void append(const float* X_, const int64_t* attr_, int64_t m) {
+    X.insert(X.end(), X_, X_ + (size_t)m * d);
+    attr.insert(attr.end(), attr_, attr_ + m);
+    n += m;
+    seg.resize(n);
+    for (int64_t v = n - m; v < n; ++v) seg[v] = hnsw_mode ? 0 : seg_of(attr[v]);
+    level.resize(n, 0);
+    adj.resize(n);
+    marks.resize(n);
+    next.resize(n);
+    stamp.resize(n, 0u);
   }
 };
 
@@ -1080,14 +1098,14 @@ double orc_dist64(const float* q, const float* x, int d) { return dist64(q, x, d
 // the uniform variate of object v's level draw.  M0 <= 0 means M0 = M;
 // mL <= 0 means 1/ln(M).  hnsw != 0 builds a plain HNSW (Alg. 3) instead.
 void* orc_build(const float* X, const int64_t* attr, const double* level_u, int64_t n, int d,
-                int S, int M, int M0, int efCons, double mL, uint64_t seed, int hnsw) {
+                int S, int M, int M0, int efCons, double mL, uint64_t seed, int hnsw, int64_t bnd_n) {
   if (n < 1 || d < 4 || d % 4 || S < 1 || M < 1 || efCons < 1) {
     g_err = "orc_build: bad arguments";
     return nullptr;
   }
   OrcIndex* ix = new OrcIndex();
   ix->B.hnsw_mode = hnsw != 0;
-  ix->B.init(X, attr, n, d, hnsw ? 1 : S, M, M0, efCons, mL);
+  ix->B.init(X, attr, n, d, hnsw ? 1 : S, M, M0, efCons, mL, bnd_n);
   if (hnsw) {
     ix->B.bnd.clear();
     std::fill(ix->B.seg.begin(), ix->B.seg.end(), 0);
@@ -1096,6 +1114,28 @@ void* orc_build(const float* X, const int64_t* attr, const double* level_u, int6
   ix->has_builder = true;
   freeze(ix->B, ix->V, seed);
   return ix;
+}
+
+// Incremental insertion (Alg. 6) of m more objects into an index this library
+// built; they take external ids n .. n + m - 1.  Returns 0, or -1.
+int orc_insert(void* h, const float* X, const int64_t* attr, const double* level_u, int64_t m) {
+  OrcIndex* ix = (OrcIndex*)h;
+  if (!ix->has_builder || m < 0) {
+    g_err = "orc_insert: the index was not built here (no builder state)";
+    return -1;
+  }
+  for (int64_t t = 0; t < m; ++t)
+    if (!(level_u[t] > 0.0 && level_u[t] <= 1.0)) {
+      g_err = "orc_insert: level variates must lie in (0, 1]";
+      return -1;
+    }
+  const int64_t n0 = ix->B.n;
+  ix->B.append(X, attr, m);
+  for (int64_t t = 0; t < m; ++t) ix->B.insert((int)(n0 + t), level_u[t]);
+  const uint64_t seed = ix->V.seed;
+  ix->V = View();
+  freeze(ix->B, ix->V, seed);
+  return 0;
 }
 
 void* orc_read(const char* path) {
