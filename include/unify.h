@@ -123,6 +123,30 @@ int unify_build_index(const float* vectors, const int64_t* attr, const double* l
                       unify_index_t* out);
 
 /*
+ * Incremental insertion (Alg. 6, HSIGInsert; the paper's incremental-construction
+ * objective) of m more objects into a resident index.
+ *   vectors   host, [m][d] float32 row-major; row t takes external id X + t, where X
+ *             is one more than the largest external id already in the index
+ *   attr      host, [m] int64 attribute values
+ *   level_u   host, [m] float64 in (0, 1]: the level variates, as for unify_build_index
+ * Segment boundaries stay those of the index (each new object joins the segment its
+ * attribute falls in).  The library builds a new version of the resident tables in
+ * merged attribute order, connects the new objects on every layer they reach (chunks
+ * from exact per-segment candidates and Prune, reverse edges into the chunks of
+ * their neighbours, which are re-pruned when they overflow, Alg. 4), recomputes the
+ * global-edge marks of those layers from their final chunks (Alg. 5), and swaps the
+ * new version in: searches already enqueued finish on the old version, later ones
+ * see every object.  Concurrent searches on other threads are allowed; batches
+ * created before the call must be created again (unify_batch_run then fails with
+ * UNIFY_EINVAL).  The low-precision store in use is rebuilt; other copies are
+ * dropped.  Synchronous; m = 0 does nothing.  Errors: UNIFY_EINVAL (null arrays,
+ * m < 0, a level variate outside (0, 1], more than 2^31 - 1 objects in total),
+ * UNIFY_ENOMEM, UNIFY_EDEVICE; on error the index is unchanged.
+ */
+int unify_insert(unify_index_t index, const float* vectors, const int64_t* attr, const double* level_u,
+                 int64_t m);
+
+/*
  * Reads and checks an index file on the host only (no GPU needed): header,
  * checksum, section sizes and the range of every adjacency entry.  Outputs are
  * host pointers, any may be NULL.  Returns UNIFY_EIO or UNIFY_EFORMAT on failure.

@@ -56,6 +56,7 @@ SIGNATURES = {
     "unify_last_timing": (_I32, [_P, _P, _P, _P]),
     "unify_copy_store": (_I32, [_P, _I32, _P, _P, _P, _P]),
     "unify_set_precision": (_I32, [_P, _I32]),
+    "unify_insert": (_I32, [_P, _P, _P, _P, _I64]),
     "unify_batch_create": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "unify_server_create": (_I32, [_P, _P, _P]),
     "unify_server_submit": (_I32, [_P, _I64, _P, _P, _P, _P, _P, _P]),
@@ -142,6 +143,19 @@ class Index:
         ix = cls(h.value, device)
         ix.precision = cls._prec(precision)
         return ix
+
+    def insert(self, vectors: np.ndarray, attr: np.ndarray, level_u: np.ndarray) -> None:
+        """Inserts more objects (Alg. 6) into the resident index; they take the next external
+        ids.  Searches enqueued afterwards see them; Batch objects must be created again."""
+        X = np.ascontiguousarray(vectors, np.float32)
+        a = np.ascontiguousarray(attr, np.int64)
+        u = np.ascontiguousarray(level_u, np.float64)
+        if X.ndim != 2 or X.shape[1] != self.d or a.shape != (X.shape[0],) or u.shape != (X.shape[0],):
+            raise ValueError(f"vectors must be [m, {self.d}] with attr and level_u of length m")
+        _check(load_library().unify_insert(self._h, X.ctypes.data, a.ctypes.data, u.ctypes.data, X.shape[0]))
+        n, L = C.c_int64(), C.c_int32()
+        _check(load_library().unify_index_info(self._h, C.byref(n), None, None, None, C.byref(L)))
+        self.n, self.levels = n.value, L.value
 
     def set_precision(self, precision) -> None:
         """Store later searches rank by ("fp32", "bf16", "fp8"); builds the copy on first use."""

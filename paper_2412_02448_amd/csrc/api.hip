@@ -181,6 +181,7 @@ int unify_save_index(unify_index_t ix, const char* path) {
     set_error("hipSetDevice failed");
     return UNIFY_EDEVICE;
   }
+  std::shared_lock<std::shared_mutex> version(ix->version_mu);
   HostIndex H = ix->host;
   const DevIndex& dv = ix->dv;
   H.vec.resize((size_t)dv.n * dv.d);
@@ -230,6 +231,7 @@ int unify_index_info(unify_index_t ix, int64_t* n, int32_t* d, int32_t* S, int32
     set_error("null index");
     return UNIFY_EINVAL;
   }
+  std::shared_lock<std::shared_mutex> version(ix->version_mu);
   if (n) *n = ix->dv.n;
   if (d) *d = ix->dv.d;
   if (S) *S = ix->dv.S;
@@ -243,6 +245,7 @@ int unify_copy_store(unify_index_t ix, int precision, void* codes, float* scales
     set_error("unify_copy_store: the index holds no store of that precision");
     return UNIFY_EINVAL;
   }
+  std::shared_lock<std::shared_mutex> version(ix->version_mu);
   const DevIndex& dv = ix->dv;
   hipStream_t st = (hipStream_t)hip_stream;
   const size_t cells = (size_t)dv.n * dv.d;
@@ -271,6 +274,7 @@ int unify_set_precision(unify_index_t ix, int precision) {
     set_error("hipSetDevice failed");
     return UNIFY_EDEVICE;
   }
+  std::unique_lock<std::shared_mutex> version(ix->version_mu);
   return quantize_store(ix, precision);
 }
 
@@ -338,6 +342,10 @@ int unify_free_index(unify_index_t ix) {
   for (void* p : ix->allocs) (void)hipFree(p);
   delete ix;
   return UNIFY_OK;
+}
+
+int unify_insert(unify_index_t ix, const float* vectors, const int64_t* attr, const double* level_u, int64_t m) {
+  return insert_impl(ix, vectors, attr, level_u, m);
 }
 
 int unify_build_index(const float* vectors, const int64_t* attr, const double* level_u, int64_t n, int32_t d,

@@ -27,6 +27,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <shared_mutex>
 
 #include "unify_internal.h"
 #include "wave.h"
@@ -88,7 +89,8 @@ __device__ u64 glist_insert(u64* lst, int& len, int cap, u64 key) {
   return total == cap ? worst : KEY_MAX;
 }
 
-// Exact K nearest candidates of segment j for rows [row0, row0 + nrows) of a layer.
+// Exact K nearest candidates of segment j for rows [row0, row0 + nrows) of a layer
+// (or for rows[row0 .. row0 + nrows) when a row list is given).
 struct KnnArgs {
   const float* X;
   const float* xn;
@@ -98,6 +100,7 @@ struct KnnArgs {
   u64* lists;             // [nrows][S][KC]
   int32_t* lens;          // [nrows][S]
   u64* pend;              // [nrows][S][KT_C]
+  const int32_t* rows;    // optional: the layer rows to process
 };
 
 __global__ void __launch_bounds__(256) b_knn(KnnArgs A) {
@@ -131,8 +134,10 @@ __global__ void __launch_bounds__(256) b_knn(KnnArgs A) {
         const int r = idx % KT_R, g = idx / KT_R;
         const int64_t lr = lr0 + r;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (lr < A.nrows && k0 + 4 * g < d)
-          v = *reinterpret_cast<const float4*>(A.X + (A.row0 + lr) * d + k0 + 4 * g);
+        if (lr < A.nrows && k0 + 4 * g < d) {
+          const int64_t row = A.rows ? (int64_t)A.rows[A.row0 + lr] : A.row0 + lr;
+          v = *reinterpret_cast<const float4*>(A.X + row * d + k0 + 4 * g);
+        }
         qT[4 * g + 0][r] = v.x;
         qT[4 * g + 1][r] = v.y;
         qT[4 * g + 2][r] = v.z;
@@ -169,7 +174,7 @@ __global__ void __launch_bounds__(256) b_knn(KnnArgs A) {
       const int r = rg * 8 + i;
       const int64_t lr = lr0 + r;
       if (lr >= A.nrows) continue;
-      const int64_t row = A.row0 + lr;
+      const int64_t row = A.rows ? (int64_t)A.rows[A.row0 + lr] : A.row0 + lr;
       const float qn = A.xn[row];
       const u64 tr = tau[r];
 #pragma unroll
@@ -227,7 +232,9 @@ struct PruneArgs {
   const int32_t* b_cnt;
   int32_t Mcap;
   int32_t only_if_over;
-  u64* out;  // [ntask][Mcap]
+  u64* out;                // [ntask][Mcap]
+  const int32_t* owners;   // optional: owner = owners[owner0 + task / owner_div]
+  const int64_t* task_of;  // optional: the tasks to run (all ntask of them otherwise)
 };
 
 template <int NG>
@@ -258,8 +265,10 @@ __global__ void __launch_bounds__(64) b_prune(PruneArgs A) {
   __shared__ int32_t ids[WAVE];
   __shared__ int32_t selid[WAVE];
   const int lane = lane_id(), g4 = lane >> 4;
-  for (int64_t t = blockIdx.x; t < A.ntask; t += gridDim.x) {
-    const int64_t owner = A.owner0 + t / A.owner_div;
+  for (int64_t it = blockIdx.x; it < A.ntask; it += gridDim.x) {
+    const int64_t t = A.task_of ? A.task_of[it] : it;
+    const int64_t oi = A.owner0 + t / A.owner_div;
+    const int64_t owner = A.owners ? (int64_t)A.owners[oi] : oi;
     float4 qv[NG];
     load_row<NG>(A.X, A.d, owner, qv);
     int len = 0;
@@ -381,13 +390,16 @@ __global__ void __launch_bounds__(64) b_prune(PruneArgs A) {
 }
 
 // Reverse edges: every forward edge row -> o (row in segment si) is offered to chunk si of o.
+// Row r of fwd belongs to layer row rows[r] when a row list is given.
 __global__ void b_rev(const u64* __restrict__ fwd, int64_t nrows, int S, int M, const int32_t* __restrict__ segc,
-                      int32_t* __restrict__ cnt, const int64_t* __restrict__ off, u64* __restrict__ rev) {
+                      int32_t* __restrict__ cnt, const int64_t* __restrict__ off, u64* __restrict__ rev,
+                      const int32_t* __restrict__ rows) {
   const int64_t total = nrows * S * M;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const u64 kk = fwd[e];
     if (kk == KEY_MAX) continue;
-    const int64_t row = e / ((int64_t)S * M);
+    const int64_t r = e / ((int64_t)S * M);
+    const int64_t row = rows ? (int64_t)rows[r] : r;
     const int32_t o = key_id(kk);
     const int64_t slot = (int64_t)o * S + segc[row];
     const int32_t p = atomicAdd(&cnt[slot], 1);
@@ -665,7 +677,7 @@ int build_layer(const float* dX, int d, int S, int M, int K, const std::vector<i
     return UNIFY_ENOMEM;
   }
   BHIP(hipMemset(rcnt, 0, 4 * (size_t)nl * S));
-  hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nl, S, M, dsegc, rcnt, nullptr, nullptr);
+  hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nl, S, M, dsegc, rcnt, nullptr, nullptr, nullptr);
   int rc = scan(buf, rcnt, nl * S, roff);
   if (rc) return rc;
   int64_t total = 0;
@@ -676,7 +688,7 @@ int build_layer(const float* dX, int d, int S, int M, int K, const std::vector<i
     return UNIFY_ENOMEM;
   }
   BHIP(hipMemset(rcnt, 0, 4 * (size_t)nl * S));
-  hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nl, S, M, dsegc, rcnt, roff, rev);
+  hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nl, S, M, dsegc, rcnt, roff, rev, nullptr);
   {
     PruneArgs pa{};
     pa.X = X;
@@ -897,6 +909,551 @@ int build_impl(const float* vectors, const int64_t* attr, const double* level_u,
     return rc;
   }
   return make_resident(std::move(H), device, precision, out);
+}
+
+// ---------------------------------------------------------------------------
+// Incremental insertion (Alg. 6, HSIGInsert, applied to a batch of new objects).
+//
+// The new objects take the next external ids.  Internal ids stay attribute
+// ranks, so the resident tables are rebuilt in the merged order (a remap pass
+// over every row, bandwidth-bound) into a new version of the index; segment
+// boundaries do not move.  Then, on every layer that gains objects, the new
+// objects get their chunks from exact candidates among the layer's objects of
+// each segment (old and new) and Prune, each kept neighbour is offered the
+// reverse edge (chunks that overflow are re-pruned; untouched chunks keep their
+// order), and the layer's global-edge marks are recomputed from its final chunks
+// by the builder's rule.  The new version replaces the old one between searches.
+// ---------------------------------------------------------------------------
+namespace {
+
+// dst[rowmap[r]][c] = idmap[src[r][c]] (-1 stays -1) for c < ws; dst rows are wd wide.
+__global__ void i_remap(const int32_t* __restrict__ src, int64_t rows, int ws, int32_t* __restrict__ dst, int wd,
+                        const int32_t* __restrict__ rowmap, const int32_t* __restrict__ idmap) {
+  const int64_t total = rows * ws;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / ws;
+    const int c = (int)(e - r * ws);
+    const int32_t v = src[e];
+    dst[(int64_t)rowmap[r] * wd + c] = v >= 0 ? idmap[v] : -1;
+  }
+}
+
+// Row r of src (d floats) to row rowmap[r] of dst.
+__global__ void i_scatter_vec(const float* __restrict__ src, int64_t rows, int d, float* __restrict__ dst,
+                              const int32_t* __restrict__ rowmap) {
+  const int64_t G = d / 4, total = rows * G;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / G, g = e - r * G;
+    reinterpret_cast<float4*>(dst + (int64_t)rowmap[r] * d)[g] = reinterpret_cast<const float4*>(src + r * d)[g];
+  }
+}
+
+// The layer's chunks as keys over layer positions; position p reads adjacency row rowsrc[p].
+__global__ void i_load_chunks(const int32_t* __restrict__ adj, const int64_t* __restrict__ rowsrc, int64_t nl,
+                              int width, const int32_t* __restrict__ pos_of, u64* __restrict__ out) {
+  const int64_t total = nl * width;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / width;
+    const int c = (int)(e - p * width);
+    const int32_t v = adj[rowsrc[p] * width + c];
+    const int32_t q = v >= 0 ? pos_of[v] : -1;
+    out[e] = q >= 0 ? make_key(0.f, q) : KEY_MAX;
+  }
+}
+
+// Row r of fwd (the r-th new object) into the chunk table at position newpos[r].
+__global__ void i_scatter_keys(const u64* __restrict__ fwd, int64_t nnew, int width, const int32_t* __restrict__ newpos,
+                               u64* __restrict__ chunks) {
+  const int64_t total = nnew * width;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / width;
+    const int c = (int)(e - r * width);
+    chunks[(int64_t)newpos[r] * width + c] = fwd[e];
+  }
+}
+
+// The (position, segment) chunks that receive reverse edges, in any order.
+__global__ void i_tasks(const int32_t* __restrict__ cnt, int64_t n, int64_t* __restrict__ tasks,
+                        unsigned long long* __restrict__ ntask) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (cnt[i] > 0) tasks[atomicAdd(ntask, 1ull)] = i;
+}
+
+// Chunks back into the adjacency rows, as internal ids.
+__global__ void i_store_chunks(const u64* __restrict__ chunks, int64_t nl, int width,
+                               const int64_t* __restrict__ rowsrc, const int32_t* __restrict__ nodes,
+                               int32_t* __restrict__ adj) {
+  const int64_t total = nl * width;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / width;
+    const int c = (int)(e - p * width);
+    const u64 kk = chunks[e];
+    adj[rowsrc[p] * width + c] = kk == KEY_MAX ? -1 : nodes[key_id(kk)];
+  }
+}
+
+// Marks (layer positions, M per row) into the global-edge lists (GC per row).
+__global__ void i_store_glist(const int32_t* __restrict__ marks, int64_t nl, int M,
+                              const int64_t* __restrict__ rowsrc, const int32_t* __restrict__ nodes,
+                              int32_t* __restrict__ glist, int GC) {
+  const int64_t total = nl * GC;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / GC;
+    const int c = (int)(e - p * GC);
+    const int32_t v = c < M ? marks[p * M + c] : -1;
+    glist[rowsrc[p] * GC + c] = v >= 0 ? nodes[v] : -1;
+  }
+}
+
+unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); }
+
+// One layer of an insertion.  nodes: the layer's objects (new internal ids,
+// ascending); rowsrc[p]: adjacency/global-list row of nodes[p]; newpos: the
+// positions of the new objects.  Reads and rewrites adj (width S * mc) and glist.
+int insert_layer(const float* dX, int d, int S, int mc, int K, const std::vector<int32_t>& nodes,
+                 const std::vector<int64_t>& rowsrc, const std::vector<int32_t>& newpos,
+                 const std::vector<int64_t>& seg_start, const std::vector<int64_t>& ext, int64_t nall, int32_t* adj,
+                 int32_t* glist, int GC, bool verbose) {
+  const int64_t nl = (int64_t)nodes.size(), nnew = (int64_t)newpos.size();
+  const int W = S * mc;
+  DevBuf buf;
+  std::vector<int64_t> sst(S + 1, 0);
+  std::vector<int32_t> segc(nl);
+  {
+    int j = 0;
+    for (int64_t c = 0; c < nl; ++c) {
+      while (j + 1 <= S && nodes[c] >= seg_start[j + 1]) ++j;
+      segc[c] = j;
+    }
+    for (int jj = 0; jj <= S; ++jj)
+      sst[jj] = std::lower_bound(nodes.begin(), nodes.end(), (int32_t)std::min<int64_t>(seg_start[jj], INT32_MAX)) -
+                nodes.begin();
+    sst[S] = nl;
+  }
+  std::vector<int32_t> pos_of((size_t)nall, -1);
+  std::vector<int64_t> ext_c(nl);
+  for (int64_t p = 0; p < nl; ++p) {
+    pos_of[nodes[p]] = (int32_t)p;
+    ext_c[p] = ext[nodes[p]];
+  }
+  int32_t* dnodes = buf.alloc<int32_t>(nl);
+  float* X = buf.alloc<float>((size_t)nl * d);
+  float* xn = buf.alloc<float>(nl);
+  int64_t* dsst = buf.alloc<int64_t>(S + 1);
+  int32_t* dsegc = buf.alloc<int32_t>(nl);
+  int64_t* dext = buf.alloc<int64_t>(nl);
+  int64_t* drow = buf.alloc<int64_t>(nl);
+  int32_t* dnew = buf.alloc<int32_t>(nnew);
+  int32_t* dpos = buf.alloc<int32_t>(nall);
+  u64* chunks = buf.alloc<u64>((size_t)nl * W);
+  u64* fwd = buf.alloc<u64>((size_t)nnew * W);
+  if (!dnodes || !X || !xn || !dsst || !dsegc || !dext || !drow || !dnew || !dpos || !chunks || !fwd) {
+    set_error("insert: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  BHIP(hipMemcpy(dnodes, nodes.data(), 4 * nl, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(dsst, sst.data(), 8 * (S + 1), hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(dsegc, segc.data(), 4 * nl, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(dext, ext_c.data(), 8 * nl, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(drow, rowsrc.data(), 8 * nl, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(dnew, newpos.data(), 4 * nnew, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(dpos, pos_of.data(), 4 * nall, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(b_gather, dim3(1024), dim3(256), 0, 0, dX, d, dnodes, nl, X);
+  hipLaunchKernelGGL(b_norms, dim3(1024), dim3(256), 0, 0, X, d, nl, xn);
+  hipLaunchKernelGGL(i_load_chunks, dim3(grid_for(nl * W)), dim3(256), 0, 0, adj, drow, nl, W, dpos, chunks);
+  BHIP(hipGetLastError());
+
+  // 1-2: candidates of the new objects in every segment of the layer, forward chunks
+  double t0 = now_s();
+  const int64_t rows_per = std::min<int64_t>(nnew, 131072);
+  u64* lists = buf.alloc<u64>((size_t)rows_per * S * KC);
+  int32_t* lens = buf.alloc<int32_t>((size_t)rows_per * S);
+  u64* pend = buf.alloc<u64>((size_t)rows_per * S * KT_C);
+  if (!lists || !lens || !pend) {
+    set_error("insert: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  for (int64_t r0 = 0; r0 < nnew; r0 += rows_per) {
+    const int64_t nr = std::min(rows_per, nnew - r0);
+    KnnArgs ka{X, xn, d, S, K, r0, nr, dsst, lists, lens, pend, dnew};
+    hipLaunchKernelGGL(b_knn, dim3((unsigned)((nr + KT_R - 1) / KT_R), (unsigned)S), dim3(256), 0, 0, ka);
+    BHIP(hipGetLastError());
+    PruneArgs pa{};
+    pa.X = X;
+    pa.d = d;
+    pa.ntask = nr * S;
+    pa.owner0 = r0;
+    pa.owner_div = S;
+    pa.owners = dnew;
+    pa.a = lists;
+    pa.a_stride = KC;
+    pa.a_cnt = lens;
+    pa.Mcap = mc;
+    pa.only_if_over = 0;
+    pa.out = fwd + (size_t)r0 * W;
+    int rc = run_prune(pa);
+    if (rc) return rc;
+  }
+  BHIP(hipDeviceSynchronize());
+  buf.release(lists);
+  buf.release(lens);
+  buf.release(pend);
+  hipLaunchKernelGGL(i_scatter_keys, dim3(grid_for(nnew * W)), dim3(256), 0, 0, fwd, nnew, W, dnew, chunks);
+  BHIP(hipGetLastError());
+  if (verbose)
+    std::fprintf(stderr, "[insert] layer n=%lld new=%lld: candidates+prune (%.2fs)\n", (long long)nl, (long long)nnew,
+                 now_s() - t0);
+
+  // 3: reverse edges of the new objects; chunks that receive some are merged and re-pruned
+  int32_t* rcnt = buf.alloc<int32_t>((size_t)nl * S);
+  int64_t* roff = buf.alloc<int64_t>((size_t)nl * S + 1);
+  unsigned long long* dnt = buf.alloc<unsigned long long>(1);
+  if (!rcnt || !roff || !dnt) {
+    set_error("insert: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  BHIP(hipMemset(rcnt, 0, 4 * (size_t)nl * S));
+  hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nnew, S, mc, dsegc, rcnt, nullptr, nullptr, dnew);
+  int rc = scan(buf, rcnt, nl * S, roff);
+  if (rc) return rc;
+  int64_t total = 0;
+  BHIP(hipMemcpy(&total, roff + (size_t)nl * S, 8, hipMemcpyDeviceToHost));
+  u64* rev = buf.alloc<u64>((size_t)std::max<int64_t>(total, 1));
+  int64_t* tasks = buf.alloc<int64_t>((size_t)std::max<int64_t>(std::min<int64_t>(total, nl * S), 1));
+  if (!rev || !tasks) {
+    set_error("insert: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  BHIP(hipMemset(rcnt, 0, 4 * (size_t)nl * S));
+  hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nnew, S, mc, dsegc, rcnt, roff, rev, dnew);
+  BHIP(hipMemset(dnt, 0, sizeof(unsigned long long)));
+  hipLaunchKernelGGL(i_tasks, dim3(grid_for(nl * S)), dim3(256), 0, 0, rcnt, nl * S, tasks, dnt);
+  BHIP(hipGetLastError());
+  unsigned long long ntask = 0;
+  BHIP(hipMemcpy(&ntask, dnt, sizeof(ntask), hipMemcpyDeviceToHost));
+  if ((int64_t)ntask > std::min<int64_t>(total, nl * S)) {
+    set_error("insert: reverse-edge task count out of range");
+    return UNIFY_EDEVICE;
+  }
+  if (ntask > 0) {
+    PruneArgs pa{};
+    pa.X = X;
+    pa.d = d;
+    pa.ntask = (int64_t)ntask;
+    pa.owner0 = 0;
+    pa.owner_div = S;
+    pa.a = chunks;
+    pa.a_stride = mc;
+    pa.b = rev;
+    pa.b_off = roff;
+    pa.b_cnt = rcnt;
+    pa.Mcap = mc;
+    pa.only_if_over = 1;
+    pa.out = chunks;  // each task reads its own row before writing it
+    pa.task_of = tasks;
+    rc = run_prune(pa);
+    if (rc) return rc;
+  }
+  BHIP(hipDeviceSynchronize());
+  buf.release(rev);
+  buf.release(tasks);
+  if (verbose)
+    std::fprintf(stderr, "[insert] layer n=%lld: reverse edges %lld into %llu chunks (%.2fs)\n", (long long)nl,
+                 (long long)total, ntask, now_s() - t0);
+
+  // 4: global-edge marks of the layer from its final chunks
+  u64* P = buf.alloc<u64>((size_t)nl * mc);
+  int32_t* mcnt = buf.alloc<int32_t>(nl);
+  int64_t* moff = buf.alloc<int64_t>(nl + 1);
+  int32_t* marks = buf.alloc<int32_t>((size_t)nl * mc);
+  if (!P || !mcnt || !moff || !marks) {
+    set_error("insert: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  {
+    PruneArgs pa{};
+    pa.X = X;
+    pa.d = d;
+    pa.ntask = nl;
+    pa.owner0 = 0;
+    pa.owner_div = 1;
+    pa.a = chunks;
+    pa.a_stride = W;
+    pa.Mcap = mc;
+    pa.only_if_over = 1;
+    pa.out = P;
+    rc = run_prune(pa);
+    if (rc) return rc;
+  }
+  BHIP(hipMemset(mcnt, 0, 4 * nl));
+  hipLaunchKernelGGL(b_mask_rev, dim3(4096), dim3(256), 0, 0, P, chunks, nl, S, mc, dsegc, mcnt, nullptr, nullptr);
+  rc = scan(buf, mcnt, nl, moff);
+  if (rc) return rc;
+  int64_t mtotal = 0;
+  BHIP(hipMemcpy(&mtotal, moff + nl, 8, hipMemcpyDeviceToHost));
+  int32_t* mrev = buf.alloc<int32_t>((size_t)std::max<int64_t>(mtotal, 1));
+  if (!mrev) {
+    set_error("insert: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  BHIP(hipMemset(mcnt, 0, 4 * nl));
+  hipLaunchKernelGGL(b_mask_rev, dim3(4096), dim3(256), 0, 0, P, chunks, nl, S, mc, dsegc, mcnt, moff, mrev);
+  hipLaunchKernelGGL(b_mask_final, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, 0, P, nl, mc, moff, mrev, dext,
+                     marks);
+  // 5: back into the index
+  hipLaunchKernelGGL(i_store_chunks, dim3(grid_for(nl * W)), dim3(256), 0, 0, chunks, nl, W, drow, dnodes, adj);
+  hipLaunchKernelGGL(i_store_glist, dim3(grid_for(nl * GC)), dim3(256), 0, 0, marks, nl, mc, drow, dnodes, glist, GC);
+  BHIP(hipGetLastError());
+  BHIP(hipDeviceSynchronize());
+  if (verbose) std::fprintf(stderr, "[insert] layer n=%lld: global marks (%.2fs)\n", (long long)nl, now_s() - t0);
+  return UNIFY_OK;
+}
+
+// Device allocations of a new index version; freed unless kept.
+struct Version {
+  std::vector<void*> ptrs;
+  bool keep = false;
+  ~Version() {
+    if (!keep)
+      for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+};
+
+}  // namespace
+
+int insert_impl(unify_index_t ix, const float* vectors, const int64_t* attr, const double* level_u, int64_t m) {
+  if (!ix || m < 0 || (m > 0 && (!vectors || !attr || !level_u))) {
+    set_error("insert: null argument or negative count");
+    return UNIFY_EINVAL;
+  }
+  if (m == 0) return UNIFY_OK;
+  std::lock_guard<std::mutex> serial(ix->insert_mu);
+  if (hipSetDevice(ix->device) != hipSuccess) {
+    set_error("insert: hipSetDevice failed");
+    return UNIFY_EDEVICE;
+  }
+  const bool verbose = std::getenv("UNIFY_BUILD_VERBOSE") != nullptr;
+  std::shared_lock<std::shared_mutex> rl(ix->version_mu);
+  const DevIndex dv = ix->dv;
+  const HostIndex& O = ix->host;
+  const int64_t n = dv.n, n2 = n + m;
+  const int S = dv.S, d = dv.d;
+  if (n2 >= (int64_t(1) << 31)) {
+    set_error("insert: the index would exceed 2^31 - 1 objects");
+    return UNIFY_EINVAL;
+  }
+  if (!prune_kernel(d, dv.M0) || !prune_kernel(d, dv.MU) || O.ef_cons < 1) {
+    set_error("insert: unsupported index shape (d <= 2048, M <= 64, efCons >= 1)");
+    return UNIFY_EINVAL;
+  }
+  for (int64_t t = 0; t < m; ++t)
+    if (!(level_u[t] > 0.0 && level_u[t] <= 1.0)) {
+      set_error("insert: level variates must lie in (0, 1]");
+      return UNIFY_EINVAL;
+    }
+  const double mL = O.mL > 0 ? O.mL : 1.0 / std::log((double)dv.M0);
+  const int K = std::min(O.ef_cons, KC);
+  int64_t xb = 0;
+  for (int64_t i = 0; i < n; ++i) xb = std::max(xb, O.ext[i] + 1);
+  std::vector<int> lev_new(m);
+  for (int64_t t = 0; t < m; ++t) lev_new[t] = (int)std::min(std::floor(-std::log(level_u[t]) * mL), 30.0);
+  // merged attribute order; an old object precedes a new one with the same attribute (smaller external id)
+  std::vector<int64_t> ordn(m);
+  std::iota(ordn.begin(), ordn.end(), 0);
+  std::stable_sort(ordn.begin(), ordn.end(), [&](int64_t a, int64_t b) { return attr[a] < attr[b]; });
+  std::vector<int32_t> nid_old(n), nid_new(m);
+  HostIndex H;
+  H.n = n2;
+  H.d = d;
+  H.S = S;
+  H.M0 = O.M0;
+  H.MU = O.MU;
+  H.ef_cons = O.ef_cons;
+  H.mL = O.mL;
+  H.seed = O.seed;
+  H.W0 = O.W0;
+  H.WU = O.WU;
+  H.attr.resize(n2);
+  H.ext.resize(n2);
+  H.level.resize(n2);
+  std::vector<uint8_t> isnew(n2, 0);
+  {
+    int64_t i = 0, t = 0;
+    for (int64_t r = 0; r < n2; ++r) {
+      if (t >= m || (i < n && O.attr[i] <= attr[ordn[t]])) {
+        nid_old[i] = (int32_t)r;
+        H.attr[r] = O.attr[i];
+        H.ext[r] = O.ext[i];
+        H.level[r] = O.level[i];
+        ++i;
+      } else {
+        const int64_t u = ordn[t++];
+        nid_new[u] = (int32_t)r;
+        H.attr[r] = attr[u];
+        H.ext[r] = xb + u;
+        H.level[r] = (uint8_t)lev_new[u];
+        isnew[r] = 1;
+      }
+    }
+  }
+  H.uprow.resize(n2);
+  int64_t R2 = 0;
+  for (int64_t r = 0; r < n2; ++r) {
+    H.uprow[r] = H.level[r] > 0 ? (int32_t)R2 : -1;
+    R2 += H.level[r];
+  }
+  H.R = R2;
+  std::vector<int32_t> rowmap_up((size_t)std::max<int64_t>(dv.R, 1));
+  for (int64_t i = 0; i < n; ++i)
+    for (int l = 1; l <= O.level[i]; ++l) rowmap_up[O.uprow[i] + l - 1] = H.uprow[nid_old[i]] + l - 1;
+  // fixed boundaries: segment j starts at the first attribute >= b_j
+  std::vector<int64_t> bval(S > 1 ? S - 1 : 0);
+  for (int j = 1; j < S; ++j) bval[j - 1] = O.seg_start[j] < n ? O.attr[O.seg_start[j]] : INT64_MAX;
+  H.seg_start.assign(S + 1, 0);
+  for (int j = 1; j < S; ++j)
+    H.seg_start[j] = std::lower_bound(H.attr.begin(), H.attr.end(), bval[j - 1]) - H.attr.begin();
+  H.seg_start[S] = n2;
+  // entries (Alg. 6): a segment's entry changes only when an object of that
+  // segment exceeds its top level; the first such object wins
+  H.seg_entry.resize(S);
+  H.seg_maxlevel = O.seg_maxlevel;
+  for (int j = 0; j < S; ++j) H.seg_entry[j] = O.seg_entry[j] >= 0 ? nid_old[O.seg_entry[j]] : -1;
+  H.L = O.L;
+  H.gentry = O.gentry >= 0 ? nid_old[O.gentry] : -1;
+  for (int64_t t = 0; t < m; ++t) {
+    const int j = (int)(std::upper_bound(bval.begin(), bval.end(), attr[t]) - bval.begin());
+    if (lev_new[t] > H.seg_maxlevel[j]) {
+      H.seg_maxlevel[j] = lev_new[t];
+      H.seg_entry[j] = nid_new[t];
+    }
+    if (lev_new[t] > H.L) {
+      H.L = lev_new[t];
+      H.gentry = nid_new[t];
+    }
+  }
+
+  // the new version: remapped copies of the resident tables
+  Version V;
+  const int GC2 = std::max(dv.GC, std::max(dv.M0, dv.MU));
+  const int W0 = S * dv.M0, WU = S * dv.MU;
+  int64_t* d_attr = V.alloc<int64_t>(n2);
+  int64_t* d_ext = V.alloc<int64_t>(n2);
+  int64_t* d_ss = V.alloc<int64_t>(S + 1);
+  int32_t* d_se = V.alloc<int32_t>(S);
+  int32_t* d_sm = V.alloc<int32_t>(S);
+  int32_t* d_up = V.alloc<int32_t>(n2);
+  float* d_vec = V.alloc<float>((size_t)n2 * d);
+  int32_t* d_adj0 = V.alloc<int32_t>((size_t)n2 * W0);
+  int32_t* d_gl0 = V.alloc<int32_t>((size_t)n2 * GC2);
+  int32_t* d_adjU = V.alloc<int32_t>((size_t)R2 * WU);
+  int32_t* d_glU = V.alloc<int32_t>((size_t)R2 * GC2);
+  DevBuf tmp;
+  float* d_new = tmp.alloc<float>((size_t)m * d);
+  int32_t* d_nold = tmp.alloc<int32_t>(n);
+  int32_t* d_nnew = tmp.alloc<int32_t>(m);
+  int32_t* d_rmap = tmp.alloc<int32_t>(rowmap_up.size());
+  if (!d_attr || !d_ext || !d_ss || !d_se || !d_sm || !d_up || !d_vec || !d_adj0 || !d_gl0 || !d_adjU || !d_glU ||
+      !d_new || !d_nold || !d_nnew || !d_rmap) {
+    set_error("insert: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  BHIP(hipMemcpy(d_attr, H.attr.data(), 8 * n2, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(d_ext, H.ext.data(), 8 * n2, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(d_ss, H.seg_start.data(), 8 * (S + 1), hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(d_se, H.seg_entry.data(), 4 * S, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(d_sm, H.seg_maxlevel.data(), 4 * S, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(d_up, H.uprow.data(), 4 * n2, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(d_new, vectors, 4 * (size_t)m * d, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(d_nold, nid_old.data(), 4 * n, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(d_nnew, nid_new.data(), 4 * m, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(d_rmap, rowmap_up.data(), 4 * rowmap_up.size(), hipMemcpyHostToDevice));
+  BHIP(hipMemset(d_adj0, 0xFF, 4 * (size_t)n2 * W0));
+  BHIP(hipMemset(d_gl0, 0xFF, 4 * (size_t)n2 * GC2));
+  if (R2 > 0) {
+    BHIP(hipMemset(d_adjU, 0xFF, 4 * (size_t)R2 * WU));
+    BHIP(hipMemset(d_glU, 0xFF, 4 * (size_t)R2 * GC2));
+  }
+  const double t0 = now_s();
+  hipLaunchKernelGGL(i_scatter_vec, dim3(grid_for(n * d / 4)), dim3(256), 0, 0, dv.vec, n, d, d_vec, d_nold);
+  hipLaunchKernelGGL(i_scatter_vec, dim3(grid_for(m * d / 4)), dim3(256), 0, 0, d_new, m, d, d_vec, d_nnew);
+  hipLaunchKernelGGL(i_remap, dim3(grid_for(n * W0)), dim3(256), 0, 0, dv.adj0, n, W0, d_adj0, W0, d_nold, d_nold);
+  hipLaunchKernelGGL(i_remap, dim3(grid_for(n * dv.GC)), dim3(256), 0, 0, dv.glist0, n, dv.GC, d_gl0, GC2, d_nold,
+                     d_nold);
+  if (dv.R > 0) {
+    hipLaunchKernelGGL(i_remap, dim3(grid_for(dv.R * WU)), dim3(256), 0, 0, dv.adjU, dv.R, WU, d_adjU, WU, d_rmap,
+                       d_nold);
+    hipLaunchKernelGGL(i_remap, dim3(grid_for(dv.R * dv.GC)), dim3(256), 0, 0, dv.glistU, dv.R, dv.GC, d_glU, GC2,
+                       d_rmap, d_nold);
+  }
+  BHIP(hipGetLastError());
+  BHIP(hipDeviceSynchronize());
+  if (verbose) std::fprintf(stderr, "[insert] remapped %lld + %lld objects (%.2fs)\n", (long long)n, (long long)m,
+                            now_s() - t0);
+
+  // every layer that gains objects, top down
+  for (int l = H.L; l >= 0; --l) {
+    std::vector<int32_t> nodes, newpos;
+    std::vector<int64_t> rowsrc;
+    for (int64_t r = 0; r < n2; ++r) {
+      if (H.level[r] < l) continue;
+      if (isnew[r]) newpos.push_back((int32_t)nodes.size());
+      nodes.push_back((int32_t)r);
+      rowsrc.push_back(l == 0 ? r : (int64_t)H.uprow[r] + l - 1);
+    }
+    if (newpos.empty() || nodes.size() < 2) continue;
+    int rc = insert_layer(d_vec, d, S, l == 0 ? dv.M0 : dv.MU, K, nodes, rowsrc, newpos, H.seg_start, H.ext, n2,
+                          l == 0 ? d_adj0 : d_adjU, l == 0 ? d_gl0 : d_glU, GC2, verbose);
+    if (rc) return rc;
+  }
+  if (verbose) std::fprintf(stderr, "[insert] done (%.2fs)\n", now_s() - t0);
+
+  DevIndex nv = dv;
+  nv.n = n2;
+  nv.L = H.L;
+  nv.gentry = H.gentry;
+  nv.R = R2;
+  nv.GC = GC2;
+  nv.attr = d_attr;
+  nv.ext = d_ext;
+  nv.seg_start = d_ss;
+  nv.seg_entry = d_se;
+  nv.seg_maxlevel = d_sm;
+  nv.uprow = d_up;
+  nv.vec = d_vec;
+  nv.adj0 = d_adj0;
+  nv.glist0 = d_gl0;
+  nv.adjU = R2 > 0 ? d_adjU : nullptr;
+  nv.glistU = R2 > 0 ? d_glU : nullptr;
+  nv.vec_bf16 = nullptr;
+  nv.vec_fp8 = nullptr;
+  nv.vec_scale = nullptr;
+  nv.vec_eps = nullptr;
+  nv.precision = UNIFY_FP32;
+  const int precision = dv.precision;
+  rl.unlock();
+
+  // swap between searches: wait for every search enqueued on the old version
+  std::unique_lock<std::shared_mutex> wl(ix->version_mu);
+  if (ix->last_search) BHIP(hipEventSynchronize(ix->last_search));
+  BHIP(hipDeviceSynchronize());
+  for (void* p : ix->allocs) (void)hipFree(p);
+  ix->allocs = V.ptrs;
+  V.keep = true;
+  ix->tags = nullptr;
+  ix->epochs = nullptr;
+  ix->nslots = 0;
+  for (auto& e : ix->eps_of) e = nullptr;
+  ix->dv = nv;
+  ix->host = std::move(H);
+  ++ix->version;
+  return quantize_store(ix, precision);
 }
 
 }  // namespace unify

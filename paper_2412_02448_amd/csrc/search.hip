@@ -1370,6 +1370,11 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, unify_index_
 int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
                 int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
                 float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream) {
+  if (!ix) {
+    set_error("null index");
+    return UNIFY_EINVAL;
+  }
+  std::shared_lock<std::shared_mutex> version(ix->version_mu);
   Resolved R;
   int rc = resolve(ix, nq, k, ef, prm, R);
   if (rc != UNIFY_OK) return rc;
@@ -1406,6 +1411,11 @@ int search_impl_scratch(unify_index_t ix, const float* queries, int64_t nq, cons
                         int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
                         float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* scratch,
                         size_t scratch_bytes, void* stream) {
+  if (!ix) {
+    set_error("null index");
+    return UNIFY_EINVAL;
+  }
+  std::shared_lock<std::shared_mutex> version(ix->version_mu);
   Resolved R;
   int rc = resolve(ix, nq, k, ef, prm, R);
   if (rc != UNIFY_OK) return rc;
@@ -1431,10 +1441,11 @@ int search_impl_scratch(unify_index_t ix, const float* queries, int64_t nq, cons
 int batch_create(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h, int32_t k,
                  int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids, float* out_dist,
                  int8_t* out_strategy, int32_t* out_stats, unify_batch_t* out) {
-  if (!out) {
-    set_error("null output");
+  if (!out || !ix) {
+    set_error("null index or output");
     return UNIFY_EINVAL;
   }
+  std::shared_lock<std::shared_mutex> version(ix->version_mu);
   Resolved R;
   int rc = resolve(ix, nq, k, ef, prm, R);
   if (rc != UNIFY_OK) return rc;
@@ -1448,6 +1459,7 @@ int batch_create(unify_index_t ix, const float* queries, int64_t nq, const int64
   if (rc != UNIFY_OK) return rc;
   unify_batch_t b = new unify_batch();
   b->ix = ix;
+  b->version = ix->version;
   auto fail = [&](int code, const char* msg) {
     set_error(msg);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1486,6 +1498,11 @@ int batch_run(unify_batch_t b, void* stream) {
   HIP_OK(hipSetDevice(b->ix->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   unify_index_t ix = b->ix;
+  std::shared_lock<std::shared_mutex> version(ix->version_mu);
+  if (b->version != ix->version) {
+    set_error("the index changed (objects were inserted) after this batch was created: create it again");
+    return UNIFY_EINVAL;
+  }
   std::lock_guard<std::mutex> g(ix->order_mu);
   if (!ix->last_search) HIP_OK(hipEventCreateWithFlags(&ix->last_search, hipEventDisableTiming));
   else HIP_OK(hipStreamWaitEvent(st, ix->last_search, 0));

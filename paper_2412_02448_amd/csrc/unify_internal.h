@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <map>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -93,6 +94,13 @@ struct unify_index {
   // kernels of successive calls are ordered across streams by this event.
   std::mutex order_mu;
   hipEvent_t last_search = nullptr;
+  // An insertion builds a new version of the tables and swaps it in while no
+  // search is being enqueued: entry points that read dv hold version_mu shared,
+  // the swap holds it exclusively.  version counts the swaps; insert_mu keeps
+  // insertions one at a time.
+  std::shared_mutex version_mu;
+  std::mutex insert_mu;
+  uint64_t version = 0;
   std::map<std::pair<const void*, size_t>, int> occupancy;  // (kernel, LDS bytes) -> waves per CU
   unify::DevIndex dv{};
   unify::HostIndex host;  // small tables kept on the host; large ones released after upload
@@ -102,6 +110,7 @@ struct unify_index {
 // A batch: the search over fixed caller buffers captured as a HIP graph.
 struct unify_batch {
   unify_index_t ix = nullptr;
+  uint64_t version = 0;  // the index version the graph was captured on
   void* scratch = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -112,4 +121,5 @@ int batch_create(unify_index_t ix, const float* queries, int64_t nq, const int64
                  int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids, float* out_dist,
                  int8_t* out_strategy, int32_t* out_stats, unify_batch_t* out);
 int batch_run(unify_batch_t b, void* stream);
+int insert_impl(unify_index_t ix, const float* vectors, const int64_t* attr, const double* level_u, int64_t m);
 }  // namespace unify
