@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--no-batch100k", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-wide", action="store_true")
+    ap.add_argument("--no-insert", action="store_true")
     ap.add_argument("--wide-n", type=int, default=250_000, help="objects of the 960-wide workload")
     ap.add_argument("--cpu-queries", type=int, default=0, help="queries in the CPU sample (0: all)")
     return ap.parse_args()
@@ -276,6 +277,16 @@ def main():
             log(f"wide workload failed: {e!r}")
             wide = {"failed": repr(e)}
 
+    # ---- incremental insertion: 200k objects, then four insertions of 200k (1M in the end) ----
+    ins = None
+    if not args.no_insert:
+        try:
+            ins = insert_bench(args, spec, W, Q, L, H, k, m, ef, bp, ta, tb, vc, head, build_s,
+                               recall_of(out[0]), nq / sec)
+        except Exception as e:  # the headline line is still reported
+            log(f"insertion failed: {e!r}")
+            ins = {"failed": repr(e)}
+
     # ---- serving: open-loop Poisson arrivals through the continuous-batching server ----
     serving = None
     if not args.no_serving:
@@ -312,6 +323,7 @@ def main():
         "roofline": roofline,
         "batch100k": b100,
         "wide960": wide,
+        "insertion": ins,
         "serving": serving,
         "cpu_baseline": cpu,
     }
@@ -375,6 +387,59 @@ def wide_bench(args):
             f"{out[prec]['achieved_GBps']} GB/s algorithmic")
     index.close()
     return out
+
+
+def insert_bench(args, spec, W, Q, L, H, k, m, ef, bp, ta, tb, vc, prec, build_s, rec_single, qps_single):
+    """The insertion experiment's shape on the mixed1m objects: an index of the first
+    200k, then four insertions of 200k each.  Per round: insertion time, then QPS and
+    recall@10 (against the exact answer over the objects present) at the headline
+    setting.  The last round holds the same 1M objects as the single build."""
+    import numpy as np
+    import torch
+
+    import paper_2412_02448_amd as u
+    n = spec.n
+    step = n // 5
+    nq = Q.shape[0]
+    t0 = time.perf_counter()
+    g = u.Index.build(W.base[:step], W.attr[:step], W.level_u[:step], spec.S, spec.M, spec.ef_cons, device=0)
+    first_s = time.perf_counter() - t0
+    rounds = []
+    try:
+        for r in range(5):
+            if r > 0:
+                a, b = r * step, (r + 1) * step if r < 4 else n
+                t0 = time.perf_counter()
+                g.insert(W.base[a:b], W.attr[a:b], W.level_u[a:b])
+                ins_s = time.perf_counter() - t0
+            else:
+                ins_s = None
+            g.set_precision(prec)
+            truth = g.search(Q, L, H, k, k, strategy=u.PRE)[0].cpu().numpy()
+            for _ in range(2):
+                o = g.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(5):
+                o = g.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t) / 5
+            ids = o[0].cpu().numpy()
+            rec = float(np.mean([len(set(ids[i][ids[i] >= 0]) & set(truth[i][truth[i] >= 0]))
+                                 / max(1, (truth[i] >= 0).sum()) if (truth[i] >= 0).any() else 1.0
+                                 for i in range(nq)]))
+            row = {"n": int(g.n), "insert_s": None if ins_s is None else round(ins_s, 2),
+                   "qps": round(nq / sec, 1), "recall@10": round(rec, 4)}
+            rounds.append(row)
+            log(f"insertion round {r}: n={g.n}, insert {row['insert_s']} s, {nq / sec:,.0f} QPS, recall {rec:.4f}")
+    finally:
+        g.close()
+    return {"workload": f"mixed1m objects in ext-id order: GPU build of the first {step} ({first_s:.1f} s), then "
+                        f"four insertions of {step}; {prec} store at the headline setting (m={m} ef={ef} p={bp} "
+                        f"tau=({ta}, {tb})), {nq} queries",
+            "rounds": rounds,
+            "single_build": {"n": n, "build_s": round(build_s, 1), "qps": round(qps_single, 1),
+                             "recall@10": round(rec_single, 4)}}
 
 
 def serve_bench(args, index, spec, W, m, ef, bp, ta, tb, vc, prec):
