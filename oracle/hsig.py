@@ -59,7 +59,9 @@ def lib():
         L.orc_dist64.restype = D
         L.orc_dist64.argtypes = [P, P, I32]
         L.orc_search.restype = I32
-        L.orc_search.argtypes = [P, P, I64, P, P, I32, I32, I32, I32, I32, D, D, P, P, P, I32, I32]
+        L.orc_search.argtypes = [P, P, I64, P, P, I32, I32, I32, I32, I32, D, D, P, P, P, I32, I32, P, P]
+        L.orc_set_attr2.restype = I32
+        L.orc_set_attr2.argtypes = [P, P, I64]
         L.orc_layer_search.restype = I32
         L.orc_layer_search.argtypes = [P, P, I32, I32, I32, I32, I32, I32, I32, I32, I64, I64, P, P]
         L.orc_prune.restype = I32
@@ -269,17 +271,31 @@ class Index:
         if lib().orc_set_store(self._h, precision, rerank_mult) != 0:
             raise ValueError(lib().orc_last_error().decode())
 
+    def set_attr2(self, attr2) -> None:
+        """Second attribute of every object, indexed by external id (conjunctive queries)."""
+        a = np.ascontiguousarray(attr2, np.int64)
+        if lib().orc_set_attr2(self._h, _p(a), a.size) != 0:
+            raise ValueError(lib().orc_last_error().decode())
+
     def search(self, Q, l, h, k, ef, m=0, p=1, strategy=AUTO, tau_a=0.01, tau_b=0.5,
-               counters=False, batch_form=False, select_s1=False):
+               counters=False, batch_form=False, select_s1=False, l2=None, h2=None):
+        """l2, h2: optional inclusive ranges on the second attribute (both or neither)."""
         Q = np.ascontiguousarray(Q, np.float32)
         l = np.ascontiguousarray(l, np.int64)
         h = np.ascontiguousarray(h, np.int64)
+        if (l2 is None) != (h2 is None):
+            raise ValueError("l2 and h2 go together")
+        l2p = h2p = None
+        if l2 is not None:
+            l2 = np.ascontiguousarray(l2, np.int64)
+            h2 = np.ascontiguousarray(h2, np.int64)
+            l2p, h2p = _p(l2), _p(h2)
         nq = Q.shape[0]
         ids = np.zeros((nq, k), np.int64)
         dist = np.zeros((nq, k), np.float32)
         cnt = np.zeros((nq, NCOUNT), np.int64)
         rc = lib().orc_search(self._h, _p(Q), nq, _p(l), _p(h), k, ef, m, p, strategy, tau_a, tau_b,
-                              _p(ids), _p(dist), _p(cnt), int(batch_form), int(select_s1))
+                              _p(ids), _p(dist), _p(cnt), int(batch_form), int(select_s1), l2p, h2p)
         if rc != 0:
             raise ValueError(lib().orc_last_error().decode())
         return (ids, dist, cnt) if counters else (ids, dist)

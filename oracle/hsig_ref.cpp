@@ -525,6 +525,9 @@ struct View {
   // BF16 or FP8 copy of X, whose best rerank * k results are re-scored on X.
   std::vector<float> XS;
   int rerank = 0;
+  // A second attribute per object (internal order; empty when not set) for
+  // conjunctive two-attribute queries (Sec. 6.5's extension, approach 1).
+  std::vector<int64_t> attr2;
 
   const float* vec(int v) const { return &X[(size_t)v * d]; }
   const float* svec(int v) const { return XS.empty() ? vec(v) : &XS[(size_t)v * d]; }
@@ -814,8 +817,12 @@ struct Query {
   int c = 0;               // entries per active chunk (selection S2)
   int m = 0;               // neighbours per expansion (selection S1)
   bool s1 = false;         // hybrid neighbour selection S1 instead of S2
+  bool multi = false;      // also require l2 <= attr2 <= h2 (conjunctive query)
+  int64_t l2 = 0, h2 = 0;
   int64_t* cnt;
-  bool in_range(int v) const { return V->attr[v] >= l && V->attr[v] <= h; }
+  bool second_ok(int v) const { return !multi || (V->attr2[v] >= l2 && V->attr2[v] <= h2); }
+  // the filter of Alg. 7 (its ann admission) and of the post-filter: every range of the query
+  bool in_range(int v) const { return V->attr[v] >= l && V->attr[v] <= h && second_ok(v); }
   // distance in the store the graph searches use
   FI key(int v) {
     ++cnt[C_NDIST];
@@ -998,7 +1005,8 @@ struct Searcher {
   // first object >= l), exact top-k by (dist32, id).
   std::vector<FI> pre(Query& Q, int k) {
     std::vector<FI> all;
-    for (int64_t v = Q.lo; v < Q.hi; ++v) all.push_back(Q.xkey((int)v));
+    for (int64_t v = Q.lo; v < Q.hi; ++v)
+      if (Q.second_ok((int)v)) all.push_back(Q.xkey((int)v));
     Q.cnt[C_NDIST] += Q.hi - Q.lo;
     std::sort(all.begin(), all.end());
     if ((int)all.size() > k) all.resize(k);
@@ -1272,13 +1280,18 @@ int orc_prune(const float* owner, const float* cands, int nc, int d, int Mcap, i
 // Outputs external ids and FP32 distances, ascending by (distance, internal id),
 // padded with (-1, +inf).  counters: [nq][C_NCOUNT] or NULL.  batch_form != 0
 // runs layer 0 in the beam form even for p = 1 (and records live-candidate counts).
+// L2, H2 (both or neither): the second attribute's inclusive range per query; an
+// object qualifies when both of its attributes are in range.  The strategy rule
+// looks at the first (indexed) attribute's range only.
 int orc_search(void* h, const float* Q, int64_t nq, const int64_t* L, const int64_t* H, int k,
                int ef, int m, int p, int strategy, double tau_a, double tau_b, int64_t* out_ids,
-               float* out_dist, int64_t* counters, int batch_form, int select_s1) {
+               float* out_dist, int64_t* counters, int batch_form, int select_s1, const int64_t* L2,
+               const int64_t* H2) {
   OrcIndex* ix = (OrcIndex*)h;
   const View& V = ix->V;
-  if (k < 1 || ef < 1 || p < 1 || strategy < 0 || strategy > 3) {
-    g_err = "orc_search: bad arguments";
+  if (k < 1 || ef < 1 || p < 1 || strategy < 0 || strategy > 3 || (!L2) != (!H2) ||
+      (L2 && V.attr2.empty())) {
+    g_err = "orc_search: bad arguments (or a second range without a second attribute)";
     return -22;
   }
   if (m <= 0) m = V.M0;
@@ -1294,6 +1307,11 @@ int orc_search(void* h, const float* Q, int64_t nq, const int64_t* L, const int6
     qq.q = Q + (size_t)i * V.d;
     qq.cnt = cnt;
     qq.s1 = select_s1 != 0;
+    if (L2) {
+      qq.multi = true;
+      qq.l2 = L2[i];
+      qq.h2 = H2[i];
+    }
     srch.plan(qq, L[i], H[i]);
     const int64_t Y = qq.hi - qq.lo;
     int st = strategy;
@@ -1317,6 +1335,26 @@ int orc_search(void* h, const float* Q, int64_t nq, const int64_t* L, const int6
       }
     }
   }
+  return 0;
+}
+
+// Sets the second attribute: attr2[e] belongs to the object with external id e
+// (external ids must be 0 .. n-1).  Returns 0, or -22.
+int orc_set_attr2(void* h, const int64_t* attr2, int64_t n) {
+  View& V = ((OrcIndex*)h)->V;
+  if (n != V.n) {
+    g_err = "orc_set_attr2: one value per object";
+    return -22;
+  }
+  std::vector<int64_t> a(n);
+  for (int64_t i = 0; i < n; ++i) {
+    if (V.ext[i] < 0 || V.ext[i] >= n) {
+      g_err = "orc_set_attr2: external ids are not 0 .. n-1";
+      return -22;
+    }
+    a[i] = attr2[V.ext[i]];
+  }
+  V.attr2.swap(a);
   return 0;
 }
 

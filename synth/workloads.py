@@ -181,3 +181,15 @@ def make(spec: WorkloadSpec, base_seed: int = 0) -> Workload:
         q = np.repeat(q, len(spec.fractions), axis=0)
     l, h = ranges_for(attr, fr, base_seed)
     return Workload(spec, base, attr, np.ascontiguousarray(q), l, h, fr, level_uniforms(spec.n, base_seed))
+
+
+def second_attribute(n: int, nsearch: int, base_seed: int = 0, f_lo: float = 0.05, f_hi: float = 1.0):
+    """A second attribute per object (uniform in [0, 2^31), independent of the first)
+    and, per search, an inclusive range on it covering a fraction log-uniform in
+    [f_lo, f_hi] of the objects.  Returns (attr2 [n], l2 [nsearch], h2 [nsearch])."""
+    rng = _rng(base_seed, SEED_ATTR + 500)
+    attr2 = rng.integers(0, 1 << 31, size=n, dtype=np.int64)
+    u = _rng(base_seed, SEED_RANGE + 500).random(nsearch)
+    fr = np.exp(math.log(f_lo) + u * (math.log(f_hi) - math.log(f_lo)))
+    l2, h2 = ranges_for(attr2, fr, base_seed, stream_offset=31337)
+    return attr2, l2, h2
