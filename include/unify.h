@@ -201,6 +201,33 @@ int unify_search_ex(unify_index_t index, const float* queries, int64_t nq, const
                     int8_t* out_strategy, int32_t* out_stats, void* hip_stream);
 
 /*
+ * Second attribute for conjunctive two-attribute queries (the paper's
+ * multi-attribute extension, approach 1: the HSIG stays built on the first
+ * attribute; the filter also tests the second).
+ *   attr2   host, [n] int64: the second attribute of the object with external id e is
+ *           attr2[e] (the index's external ids must be 0 .. n-1)
+ * Replaces a previous second attribute once the searches already enqueued have
+ * finished.  unify_insert drops it (set it again for the grown index).
+ * Errors: UNIFY_EINVAL (n is not the index's object count, external ids not dense),
+ * UNIFY_ENOMEM, UNIFY_EDEVICE.
+ */
+int unify_set_attr2(unify_index_t index, const int64_t* attr2, int64_t n);
+
+/*
+ * Conjunctive range-filtered k-NN: the k nearest objects with l <= attribute <= h AND
+ * l2 <= second attribute <= h2 (Alg. 7's ann admission, the post-filter test and the
+ * pre-filter scan test both ranges).  Arguments as unify_search_ex, plus
+ *   l2, h2  device, [nq] int64, inclusive ranges on the second attribute
+ * The strategy rule and the entry segments follow the first range only (the index
+ * knows the first attribute's distribution); fewer than k results pad the row.
+ * Errors: as unify_search, and UNIFY_EINVAL when no second attribute is set.
+ */
+int unify_search_multi(unify_index_t index, const float* queries, int64_t nq, const int64_t* l,
+                       const int64_t* h, const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef,
+                       const int8_t* strategy, const unify_params* params, int64_t* out_ids,
+                       float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* hip_stream);
+
+/*
  * Durations of the kernels of the last unify_search* call on this index that set
  * UNIFY_FLAG_TIMING, from HIP events recorded on that call's stream:
  *   plan_ms     the plan and work-list kernels;

@@ -57,6 +57,8 @@ SIGNATURES = {
     "unify_copy_store": (_I32, [_P, _I32, _P, _P, _P, _P]),
     "unify_set_precision": (_I32, [_P, _I32]),
     "unify_insert": (_I32, [_P, _P, _P, _P, _I64]),
+    "unify_set_attr2": (_I32, [_P, _P, _I64]),
+    "unify_search_multi": (_I32, [_P, _P, _I64, _P, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "unify_batch_create": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "unify_server_create": (_I32, [_P, _P, _P]),
     "unify_server_submit": (_I32, [_P, _I64, _P, _P, _P, _P, _P, _P]),
@@ -157,6 +159,12 @@ class Index:
         _check(load_library().unify_index_info(self._h, C.byref(n), None, None, None, C.byref(L)))
         self.n, self.levels = n.value, L.value
 
+    def set_attr2(self, attr2: np.ndarray) -> None:
+        """Second attribute of every object, indexed by external id, for conjunctive queries
+        (search with l2, h2).  Dropped by insert()."""
+        a = np.ascontiguousarray(attr2, np.int64)
+        _check(load_library().unify_set_attr2(self._h, a.ctypes.data, a.size))
+
     def set_precision(self, precision) -> None:
         """Store later searches rank by ("fp32", "bf16", "fp8"); builds the copy on first use."""
         prec = self._prec(precision)
@@ -204,13 +212,14 @@ class Index:
     def search(self, queries, l, h, k: int, ef: int, strategy=None, m: int = 0, beam_p: int = 1,
                rerank_mult: int = 0, tau_a: float = 0.0, tau_b: float = 0.0, stats: bool = False,
                out=None, stream=None, timing: bool = False, cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0,
-               select_s1: bool = False):
+               select_s1: bool = False, l2=None, h2=None):
         """Enqueues a search on the current stream (or `stream`) and returns torch tensors.
 
         queries: cuda float32 [nq, d]; l, h: cuda int64 [nq] (inclusive); strategy: None (auto),
         an int for every query, or a cuda int8 [nq] tensor.  select_s1: hybrid neighbour selection S1
         (the m entries of the active chunks nearest the expanded object) instead of S2 (the first
-        ceil(m / S') of each chunk).  Returns (ids, dist, strategy[, stats]).
+        ceil(m / S') of each chunk).  l2, h2: cuda int64 [nq] inclusive ranges on the second
+        attribute (conjunctive query; set_attr2 first).  Returns (ids, dist, strategy[, stats]).
         """
         import torch
         dev = torch.device("cuda", self.device)
@@ -239,7 +248,16 @@ class Index:
         prm = _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, flags, visit_cap, pre_chunk)
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         lib = load_library()
-        if stats:
+        if (l2 is None) != (h2 is None):
+            raise ValueError("l2 and h2 go together")
+        if l2 is not None:
+            for t in (l2, h2):
+                if t.dtype != torch.int64 or t.device != dev or not t.is_contiguous() or t.shape != (nq,):
+                    raise ValueError("l2 and h2 must be contiguous int64 [nq] tensors on the index's device")
+            rc = lib.unify_search_multi(self._h, _ptr(queries), nq, _ptr(l), _ptr(h), _ptr(l2), _ptr(h2), k, ef,
+                                        _ptr(st), C.byref(prm), _ptr(ids), _ptr(dist), _ptr(ost), _ptr(sts),
+                                        s.cuda_stream)
+        elif stats:
             rc = lib.unify_search_ex(self._h, _ptr(queries), nq, _ptr(l), _ptr(h), k, ef, _ptr(st), C.byref(prm),
                                      _ptr(ids), _ptr(dist), _ptr(ost), _ptr(sts), s.cuda_stream)
         else:

@@ -14,6 +14,10 @@ int build_impl(const float* vectors, const int64_t* attr, const double* level_u,
 int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
                 int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
                 float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream);
+int search_multi_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                      const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef, const int8_t* strategy,
+                      const unify_params* prm, int64_t* out_ids, float* out_dist, int8_t* out_strategy,
+                      int32_t* out_stats, void* stream);
 
 namespace {
 thread_local std::string g_error;
@@ -292,6 +296,65 @@ int unify_search_ex(unify_index_t ix, const float* queries, int64_t nq, const in
                      hip_stream);
 }
 
+int unify_search_multi(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                       const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef, const int8_t* strategy,
+                       const unify_params* params, int64_t* out_ids, float* out_dist, int8_t* out_strategy,
+                       int32_t* out_stats, void* hip_stream) {
+  return search_multi_impl(ix, queries, nq, l, h, l2, h2, k, ef, strategy, params, out_ids, out_dist, out_strategy,
+                           out_stats, hip_stream);
+}
+
+int unify_set_attr2(unify_index_t ix, const int64_t* attr2, int64_t n) {
+  if (!ix || (!attr2 && n > 0)) {
+    set_error("unify_set_attr2: null argument");
+    return UNIFY_EINVAL;
+  }
+  if (hipSetDevice(ix->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return UNIFY_EDEVICE;
+  }
+  std::unique_lock<std::shared_mutex> version(ix->version_mu);
+  const int64_t N = ix->dv.n;
+  if (n != N) {
+    set_error("unify_set_attr2: one value per object of the index");
+    return UNIFY_EINVAL;
+  }
+  const std::vector<int64_t>& ext = ix->host.ext;
+  std::vector<int64_t> a((size_t)N);
+  for (int64_t i = 0; i < N; ++i) {
+    if (ext[i] < 0 || ext[i] >= N) {
+      set_error("unify_set_attr2: the index's external ids are not 0 .. n-1");
+      return UNIFY_EINVAL;
+    }
+    a[i] = attr2[ext[i]];
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(int64_t) * (size_t)std::max<int64_t>(N, 1)) != hipSuccess) {
+    set_error("device allocation failed (second attribute)");
+    return UNIFY_ENOMEM;
+  }
+  if (hipMemcpy(p, a.data(), sizeof(int64_t) * (size_t)N, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p);
+    set_error("host-to-device copy failed");
+    return UNIFY_EDEVICE;
+  }
+  // searches enqueued before may still read the previous array
+  if (ix->last_search && hipEventSynchronize(ix->last_search) != hipSuccess) {
+    (void)hipFree(p);
+    set_error("hipEventSynchronize failed");
+    return UNIFY_EDEVICE;
+  }
+  void* old = const_cast<int64_t*>(ix->dv.attr2);
+  if (old) {
+    for (auto& q : ix->allocs)
+      if (q == old) q = nullptr;
+    (void)hipFree(old);
+  }
+  ix->allocs.push_back(p);
+  ix->dv.attr2 = static_cast<const int64_t*>(p);
+  return UNIFY_OK;
+}
+
 int unify_last_timing(unify_index_t ix, float* plan_ms, float* search_ms, float* rerun_ms) {
   if (!ix || !ix->timed) {
     set_error("no timed search on this index");
@@ -339,7 +402,8 @@ int unify_free_index(unify_index_t ix) {
   for (hipEvent_t e : ix->ev)
     if (e) (void)hipEventDestroy(e);
   if (ix->last_search) (void)hipEventDestroy(ix->last_search);
-  for (void* p : ix->allocs) (void)hipFree(p);
+  for (void* p : ix->allocs)
+    if (p) (void)hipFree(p);
   delete ix;
   return UNIFY_OK;
 }

@@ -1435,6 +1435,7 @@ int insert_impl(unify_index_t ix, const float* vectors, const int64_t* attr, con
   nv.vec_fp8 = nullptr;
   nv.vec_scale = nullptr;
   nv.vec_eps = nullptr;
+  nv.attr2 = nullptr;  // a second attribute is set again for the grown index
   nv.precision = UNIFY_FP32;
   const int precision = dv.precision;
   rl.unlock();
@@ -1443,7 +1444,8 @@ int insert_impl(unify_index_t ix, const float* vectors, const int64_t* attr, con
   std::unique_lock<std::shared_mutex> wl(ix->version_mu);
   if (ix->last_search) BHIP(hipEventSynchronize(ix->last_search));
   BHIP(hipDeviceSynchronize());
-  for (void* p : ix->allocs) (void)hipFree(p);
+  for (void* p : ix->allocs)
+    if (p) (void)hipFree(p);
   ix->allocs = V.ptrs;
   V.keep = true;
   ix->tags = nullptr;

@@ -62,6 +62,15 @@ struct SearchArgs {
   uint32_t* tags;         // [nslots][n] visited epochs, one row per persistent wave
   uint32_t* epochs;       // [nslots] last epoch used by each row
   int64_t nslots;
+  const int64_t* l2;      // conjunctive queries: inclusive range on the second attribute
+  const int64_t* h2;      // per query, or null
+};
+
+// The second-attribute test of a conjunctive query (always true for others).
+struct Sec {
+  const int64_t* attr2;  // null: no second range
+  int64_t lo, hi;
+  __device__ __forceinline__ bool ok(int32_t v) const { return !attr2 || (attr2[v] >= lo && attr2[v] <= hi); }
 };
 
 constexpr uint32_t HASH_EMPTY = 0xFFFFFFFFu;
@@ -419,7 +428,7 @@ struct Counters {
 // ann list holds `al` keys ascending.  Returns false on capacity overflow.
 template <int NG, int PREC, bool S1 = false>
 __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
-                             bool hybrid, bool filter, int c, int32_t ep, u64 ep_key, int layer, int efl,
+                             const Sec& sec, bool hybrid, bool filter, int c, int32_t ep, u64 ep_key, int layer, int efl,
                              int p, int& al, Counters& cnt, uint32_t* tags, uint32_t& epoch) {
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
@@ -440,7 +449,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
   // cand = {ep}; ann = {ep} unless filtered out
   if (lane == 0) L.cand[0] = ep_key;
   int cl = 1;
-  const bool ep_in = !filter || (ep >= P.lo && ep < P.hi);
+  const bool ep_in = !filter || (ep >= P.lo && ep < P.hi && sec.ok(ep));
   L.ann[lane] = (ep_in && lane == 0) ? ep_key : KEY_MAX;
   al = ep_in ? 1 : 0;
   __syncthreads();
@@ -624,7 +633,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
       if (adm) L.cand[cl + rank_in(am)] = key;
       cl += na;
       const int32_t id = key_id(key);
-      const bool in_r = adm && (!filter || (id >= P.lo && id < P.hi));
+      const bool in_r = adm && (!filter || (id >= P.lo && id < P.hi && sec.ok(id)));
       list_insert(L.ann, al, efl, in_r ? key : KEY_MAX);
       __syncthreads();
     }
@@ -637,7 +646,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
 // the kernel's ranking store, for which this is the fallback when it is not FP32).
 template <int NG, int PREC>
 __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
-                         int& al, Counters& cnt) {
+                         const Sec& sec, int& al, Counters& cnt) {
   const int lane = lane_id();
   const int k = A.k;
   al = 0;
@@ -648,7 +657,7 @@ __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[N
     eval_keys<NG, UNIFY_FP32, (PREC != UNIFY_FP32 ? SHALLOW : STREAM)>(A.ix, qv, cntv,
                                                                       [&](int i) { return base + i; }, L.bkeys);
     __syncthreads();
-    const u64 key = lane < cntv ? L.bkeys[lane] : KEY_MAX;
+    const u64 key = lane < cntv && sec.ok(base + lane) ? L.bkeys[lane] : KEY_MAX;
     const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
     list_insert(L.ann, al, k, key < T ? key : KEY_MAX);
     __syncthreads();
@@ -684,8 +693,8 @@ __device__ __forceinline__ void root_bounds(float st, float eps, const SearchArg
 // threshold are re-scored in FP32.  Returns false when cand cannot hold the
 // qualifying objects (the caller then runs the FP32 scan).
 template <int NG, int PREC>
-__device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P, int& al,
-                              Counters& cnt) {
+__device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
+                              const Sec& sec, int& al, Counters& cnt) {
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
   const int k = A.k;
@@ -698,7 +707,7 @@ __device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&
     __syncthreads();
     cnt.ndist += cntv;
     float lb = 0.f, ub = 0.f;
-    const bool have = lane < cntv;
+    const bool have = lane < cntv && sec.ok(base + lane);
     if (have) root_bounds(key_dist(L.bkeys[lane]), ix.vec_eps[base + lane], A, lb, ub);
     const int32_t v = base + lane;
     const u64 uk = have ? make_key(ub, v) : KEY_MAX;
@@ -759,8 +768,8 @@ __device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&
 // entries of ann (ascending by the copy's distance) are re-scored with the FP32
 // distance into a sorted list of k in L.cand.  Returns that list's length.
 template <int NG>
-__device__ int rerank_graph(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P, int al,
-                            bool post, Counters& cnt) {
+__device__ int rerank_graph(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
+                            const Sec& sec, int al, bool post, Counters& cnt) {
   const int lane = lane_id();
   const int k = A.k;
   const int R = A.rerank * k;
@@ -771,7 +780,7 @@ __device__ int rerank_graph(const SearchArgs& A, const Lds& L, const float4 (&qv
     const int t = base + lane;
     const u64 key = t < al ? L.ann[t] : KEY_MAX;
     const int32_t id = key_id(key);
-    bool keep = key != KEY_MAX && (!post || (id >= P.lo && id < P.hi));
+    bool keep = key != KEY_MAX && (!post || (id >= P.lo && id < P.hi && sec.ok(id)));
     const u64 km = ballot(keep);
     keep = keep && taken + rank_in(km) < R;
     const u64 um = ballot(keep);
@@ -818,6 +827,7 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
   const QPlan P = A.plan[q];
+  const Sec sec{A.l2 ? ix.attr2 : nullptr, A.l2 ? A.l2[q] : 0, A.h2 ? A.h2[q] : 0};
   float4 qv[NG];
   {
     const int s = lane & 15, G = ix.d >> 2;
@@ -840,9 +850,9 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
     Pc.hi = min(P.hi, Pc.lo + P.clen);
     // a low-precision scan whose bounds cannot settle its top k is redone in FP32
     bool fell = false;
-    if (PREC == UNIFY_FP32 || !pre_scan_lowp<NG, PREC>(A, L, qv, Pc, al, cnt)) {
+    if (PREC == UNIFY_FP32 || !pre_scan_lowp<NG, PREC>(A, L, qv, Pc, sec, al, cnt)) {
       fell = PREC != UNIFY_FP32;
-      pre_scan<NG, PREC>(A, L, qv, Pc, al, cnt);
+      pre_scan<NG, PREC>(A, L, qv, Pc, sec, al, cnt);
     }
     if (P.nch > 1) {
       pre_store_chunk(A, L, q, P, chunk, al, cnt, fell);
@@ -892,13 +902,15 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
       __syncthreads();
     }
     for (int layer = top; layer >= 1 && ok; --layer) {
-      ok = layer_search<NG, PREC, S1>(A, L, qv, P, hybrid, false, c, ep, ep_key, layer, 1, 1, al, cnt, tags, epoch);
+      ok = layer_search<NG, PREC, S1>(A, L, qv, P, sec, hybrid, false, c, ep, ep_key, layer, 1, 1, al, cnt, tags,
+                                      epoch);
       ep_key = L.ann[0];
       ep = key_id(ep_key);
       __syncthreads();
     }
     if (ok)
-      ok = layer_search<NG, PREC, S1>(A, L, qv, P, hybrid, hybrid, c, ep, ep_key, 0, A.ef, A.p, al, cnt, tags, epoch);
+      ok = layer_search<NG, PREC, S1>(A, L, qv, P, sec, hybrid, hybrid, c, ep, ep_key, 0, A.ef, A.p, al, cnt, tags,
+                                      epoch);
     if (ne_missing(top)) {
       al = 0;
       ok = true;
@@ -918,7 +930,7 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
   const u64* res = L.ann;
   bool post_filter = P.strat == UNIFY_POST;
   if (PREC != UNIFY_FP32 && P.strat != UNIFY_PRE && ok && al > 0) {
-    al = rerank_graph<NG>(A, L, qv, P, al, post_filter, cnt);
+    al = rerank_graph<NG>(A, L, qv, P, sec, al, post_filter, cnt);
     res = L.cand;
     post_filter = false;
   }
@@ -927,7 +939,7 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
     const int t = base + lane;
     const u64 key = t < al ? res[t] : KEY_MAX;
     const int32_t id = key_id(key);
-    const bool keep = key != KEY_MAX && (!post_filter || (id >= P.lo && id < P.hi));
+    const bool keep = key != KEY_MAX && (!post_filter || (id >= P.lo && id < P.hi && sec.ok(id)));
     const u64 km = ballot(keep);
     const int pos = written + rank_in(km);
     if (keep && pos < kout) {
@@ -1241,7 +1253,8 @@ struct Launch {
 
 int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, int64_t nq, const int64_t* l,
                    const int64_t* h, const int8_t* strategy, int64_t* out_ids, float* out_dist,
-                   int8_t* out_strategy, int32_t* out_stats, void* scratch, Launch& X) {
+                   int8_t* out_strategy, int32_t* out_stats, void* scratch, Launch& X,
+                   const int64_t* l2 = nullptr, const int64_t* h2 = nullptr) {
   const DevIndex& dv = ix->dv;
   X.dv = dv;
   X.queries = queries;
@@ -1286,6 +1299,8 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   A.out_ids = out_ids;
   A.out_dist = out_dist;
   A.out_stats = out_stats;
+  A.l2 = l2;
+  A.h2 = h2;
   A.plan = X.S.plan;
   A.tags = ix->tags;
   A.epochs = ix->epochs;
@@ -1367,14 +1382,21 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, unify_index_
 
 }  // namespace
 
-int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
-                int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
-                float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream) {
+namespace {
+int search_common(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                  const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef, const int8_t* strategy,
+                  const unify_params* prm, int64_t* out_ids, float* out_dist, int8_t* out_strategy,
+                  int32_t* out_stats, void* stream) {
   if (!ix) {
     set_error("null index");
     return UNIFY_EINVAL;
   }
   std::shared_lock<std::shared_mutex> version(ix->version_mu);
+  if ((!l2) != (!h2) || (l2 && !ix->dv.attr2)) {
+    set_error(l2 && h2 ? "the index has no second attribute (unify_set_attr2)"
+                       : "l2 and h2 are given together");
+    return UNIFY_EINVAL;
+  }
   Resolved R;
   int rc = resolve(ix, nq, k, ef, prm, R);
   if (rc != UNIFY_OK) return rc;
@@ -1397,11 +1419,33 @@ int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_
   void* scratch = nullptr;
   HIP_OK(hipMallocAsync(&scratch, scratch_layout(nq, k, nullptr, nullptr), st));
   Launch X;
-  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, X);
+  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, X,
+                      l2, h2);
   if (rc == UNIFY_OK) rc = enqueue_launch(X, st, timing ? ix->ev : nullptr, ix);
   if (hipFreeAsync(scratch, st) != hipSuccess && rc == UNIFY_OK) rc = UNIFY_EDEVICE;
   return rc;
 }
+}  // namespace
+
+int search_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
+                float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream) {
+  return search_common(ix, queries, nq, l, h, nullptr, nullptr, k, ef, strategy, prm, out_ids, out_dist,
+                       out_strategy, out_stats, stream);
+}
+
+int search_multi_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                      const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef, const int8_t* strategy,
+                      const unify_params* prm, int64_t* out_ids, float* out_dist, int8_t* out_strategy,
+                      int32_t* out_stats, void* stream) {
+  if (nq > 0 && (!l2 || !h2)) {
+    set_error("null second range");
+    return UNIFY_EINVAL;
+  }
+  return search_common(ix, queries, nq, l, h, l2, h2, k, ef, strategy, prm, out_ids, out_dist, out_strategy,
+                       out_stats, stream);
+}
+
 
 size_t search_scratch_bytes(int64_t nq, int32_t k) { return scratch_layout(nq, k, nullptr, nullptr); }
 

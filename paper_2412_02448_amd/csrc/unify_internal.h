@@ -39,6 +39,7 @@ struct DevIndex {
   const int32_t* glist0;     // [n][GC] layer-0 global (marked) edges, -1 padded
   const int32_t* adjU;       // [R][S][MU]
   const int32_t* glistU;     // [R][GC]
+  const int64_t* attr2;      // [n] second attribute (conjunctive queries), or null
 };
 
 // Per-query plan written by the plan kernel.
