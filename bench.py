@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--no-insert", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--wide-n", type=int, default=250_000, help="objects of the 960-wide workload")
     ap.add_argument("--cpu-queries", type=int, default=0, help="queries in the CPU sample (0: all)")
     return ap.parse_args()
@@ -277,6 +278,15 @@ def main():
             log(f"wide workload failed: {e!r}")
             wide = {"failed": repr(e)}
 
+    # ---- conjunctive queries: a second attribute, range fraction log-uniform in [0.05, 1] ----
+    multi = None
+    if not args.no_multi:
+        try:
+            multi = multi_bench(args, index, spec, Q, L, H, k, m, ef, bp, ta, tb, vc, head)
+        except Exception as e:  # the headline line is still reported
+            log(f"conjunctive queries failed: {e!r}")
+            multi = {"failed": repr(e)}
+
     # ---- incremental insertion: 200k objects, then four insertions of 200k (1M in the end) ----
     ins = None
     if not args.no_insert:
@@ -324,6 +334,7 @@ def main():
         "batch100k": b100,
         "wide960": wide,
         "insertion": ins,
+        "conjunctive": multi,
         "serving": serving,
         "cpu_baseline": cpu,
     }
@@ -386,6 +397,45 @@ def wide_bench(args):
         log(f"wide960 {prec}: {nq / sec:,.0f} QPS, recall {rec:.4f} (m={m} ef={ef} p={bp}), "
             f"{out[prec]['achieved_GBps']} GB/s algorithmic")
     index.close()
+    return out
+
+
+def multi_bench(args, index, spec, Q, L, H, k, m, ef, bp, ta, tb, vc, prec):
+    """Conjunctive two-attribute queries on the mixed1m index: the benchmark queries
+    with a second range (fraction log-uniform in [0.05, 1]) on an independent uniform
+    second attribute.  Recall against the exact conjunctive answer (the pre-filter
+    scan with both ranges)."""
+    import numpy as np
+    import torch
+
+    import paper_2412_02448_amd as u
+    from synth import workloads as w
+    dev = torch.device("cuda", 0)
+    nq = Q.shape[0]
+    a2, l2, h2 = w.second_attribute(spec.n, nq, base_seed=0)
+    index.set_attr2(a2)
+    L2 = torch.from_numpy(l2).to(dev)
+    H2 = torch.from_numpy(h2).to(dev)
+    truth = index.search(Q, L, H, k, k, strategy=u.PRE, l2=L2, h2=H2)[0].cpu().numpy()
+    out = {"workload": f"mixed1m index ({prec} store), the {nq} benchmark queries plus a second range "
+                       f"(fraction log-uniform in [0.05, 1]) on an independent uniform attribute; k={k}"}
+    for name, sv, e in (("auto", None, ef), ("auto_ef64", None, 64), ("hybrid", u.HYBRID, ef)):
+        for _ in range(2):
+            o = index.search(Q, L, H, k, e, strategy=sv, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc,
+                             l2=L2, h2=H2)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            o = index.search(Q, L, H, k, e, strategy=sv, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc,
+                             l2=L2, h2=H2)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / 5
+        ids = o[0].cpu().numpy()
+        rec = float(np.mean([len(set(ids[i][ids[i] >= 0]) & set(truth[i][truth[i] >= 0]))
+                             / max(1, (truth[i] >= 0).sum()) if (truth[i] >= 0).any() else 1.0
+                             for i in range(nq)]))
+        out[name] = {"ef": e, "qps": round(nq / sec, 1), "recall@10": round(rec, 4)}
+        log(f"conjunctive {name} (ef={e}): {nq / sec:,.0f} QPS, recall {rec:.4f}")
     return out
 
 
