@@ -247,7 +247,7 @@ def main():
     bytes_first = int(bytes_per_query(st, d, k, head)[first].sum())
     achieved = bytes_first / (search_ms * 1e-3) / 1e9
     mix = np.bincount(np.maximum(st[:, 5], 0), minlength=4)
-    kern = f"k_search<*, {KCODE[head]}, 0>"
+    kern = f"k_search<*, {KCODE[head]}, 0, false>"
     roofline = {"bound": "hbm", "kernel": f"{kern} (first pass)", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(head, m, ef, bp, ta, tb, vc), "bytes_per_launch": bytes_first,
@@ -656,7 +656,7 @@ def cpu_baseline(args, W, index, ids, k, ef, m, bp, ta, tb, nq, prec):
 
 def source_hash():
     src = b"".join(open(os.path.join(ROOT, "paper_2412_02448_amd", "csrc", x), "rb").read()
-                   for x in ("search.hip", "wave.h", "lowp.h"))
+                   for x in ("search.hip", "wave.h", "lowp.h", "unify_internal.h"))
     return hashlib.sha256(src).hexdigest()
 
 

@@ -67,11 +67,14 @@ struct SearchArgs {
 };
 
 // The second-attribute test of a conjunctive query (always true for others).
+// Only the query index is kept: its range is read where the test is made, so
+// single-attribute searches hold no extra registers.
 struct Sec {
-  const int64_t* attr2;  // null: no second range
-  int64_t lo, hi;
-  __device__ __forceinline__ bool ok(int32_t v) const { return !attr2 || (attr2[v] >= lo && attr2[v] <= hi); }
+  int32_t q;
 };
+__device__ __forceinline__ bool sec_ok(const SearchArgs& A, Sec s, int32_t v) {
+  return !A.l2 || (A.ix.attr2[v] >= A.l2[s.q] && A.ix.attr2[v] <= A.h2[s.q]);
+}
 
 constexpr uint32_t HASH_EMPTY = 0xFFFFFFFFu;
 // Register budgets of the search kernels (measured on the 1M workload): the
@@ -428,7 +431,7 @@ struct Counters {
 // ann list holds `al` keys ascending.  Returns false on capacity overflow.
 template <int NG, int PREC, bool S1 = false>
 __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
-                             const Sec& sec, bool hybrid, bool filter, int c, int32_t ep, u64 ep_key, int layer, int efl,
+                             Sec sec, bool hybrid, bool filter, int c, int32_t ep, u64 ep_key, int layer, int efl,
                              int p, int& al, Counters& cnt, uint32_t* tags, uint32_t& epoch) {
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
@@ -449,7 +452,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
   // cand = {ep}; ann = {ep} unless filtered out
   if (lane == 0) L.cand[0] = ep_key;
   int cl = 1;
-  const bool ep_in = !filter || (ep >= P.lo && ep < P.hi && sec.ok(ep));
+  const bool ep_in = !filter || (ep >= P.lo && ep < P.hi && sec_ok(A, sec, ep));
   L.ann[lane] = (ep_in && lane == 0) ? ep_key : KEY_MAX;
   al = ep_in ? 1 : 0;
   __syncthreads();
@@ -633,7 +636,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
       if (adm) L.cand[cl + rank_in(am)] = key;
       cl += na;
       const int32_t id = key_id(key);
-      const bool in_r = adm && (!filter || (id >= P.lo && id < P.hi && sec.ok(id)));
+      const bool in_r = adm && (!filter || (id >= P.lo && id < P.hi && sec_ok(A, sec, id)));
       list_insert(L.ann, al, efl, in_r ? key : KEY_MAX);
       __syncthreads();
     }
@@ -646,7 +649,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
 // the kernel's ranking store, for which this is the fallback when it is not FP32).
 template <int NG, int PREC>
 __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
-                         const Sec& sec, int& al, Counters& cnt) {
+                         Sec sec, int& al, Counters& cnt) {
   const int lane = lane_id();
   const int k = A.k;
   al = 0;
@@ -657,7 +660,7 @@ __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[N
     eval_keys<NG, UNIFY_FP32, (PREC != UNIFY_FP32 ? SHALLOW : STREAM)>(A.ix, qv, cntv,
                                                                       [&](int i) { return base + i; }, L.bkeys);
     __syncthreads();
-    const u64 key = lane < cntv && sec.ok(base + lane) ? L.bkeys[lane] : KEY_MAX;
+    const u64 key = lane < cntv && sec_ok(A, sec, base + lane) ? L.bkeys[lane] : KEY_MAX;
     const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
     list_insert(L.ann, al, k, key < T ? key : KEY_MAX);
     __syncthreads();
@@ -694,7 +697,7 @@ __device__ __forceinline__ void root_bounds(float st, float eps, const SearchArg
 // qualifying objects (the caller then runs the FP32 scan).
 template <int NG, int PREC>
 __device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
-                              const Sec& sec, int& al, Counters& cnt) {
+                              Sec sec, int& al, Counters& cnt) {
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
   const int k = A.k;
@@ -707,7 +710,7 @@ __device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&
     __syncthreads();
     cnt.ndist += cntv;
     float lb = 0.f, ub = 0.f;
-    const bool have = lane < cntv && sec.ok(base + lane);
+    const bool have = lane < cntv && sec_ok(A, sec, base + lane);
     if (have) root_bounds(key_dist(L.bkeys[lane]), ix.vec_eps[base + lane], A, lb, ub);
     const int32_t v = base + lane;
     const u64 uk = have ? make_key(ub, v) : KEY_MAX;
@@ -769,7 +772,7 @@ __device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&
 // distance into a sorted list of k in L.cand.  Returns that list's length.
 template <int NG>
 __device__ int rerank_graph(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
-                            const Sec& sec, int al, bool post, Counters& cnt) {
+                            Sec sec, int al, bool post, Counters& cnt) {
   const int lane = lane_id();
   const int k = A.k;
   const int R = A.rerank * k;
@@ -780,7 +783,7 @@ __device__ int rerank_graph(const SearchArgs& A, const Lds& L, const float4 (&qv
     const int t = base + lane;
     const u64 key = t < al ? L.ann[t] : KEY_MAX;
     const int32_t id = key_id(key);
-    bool keep = key != KEY_MAX && (!post || (id >= P.lo && id < P.hi && sec.ok(id)));
+    bool keep = key != KEY_MAX && (!post || (id >= P.lo && id < P.hi && sec_ok(A, sec, id)));
     const u64 km = ballot(keep);
     keep = keep && taken + rank_in(km) < R;
     const u64 um = ballot(keep);
@@ -827,7 +830,7 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
   const QPlan P = A.plan[q];
-  const Sec sec{A.l2 ? ix.attr2 : nullptr, A.l2 ? A.l2[q] : 0, A.h2 ? A.h2[q] : 0};
+  const Sec sec{q};
   float4 qv[NG];
   {
     const int s = lane & 15, G = ix.d >> 2;
@@ -939,7 +942,7 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
     const int t = base + lane;
     const u64 key = t < al ? res[t] : KEY_MAX;
     const int32_t id = key_id(key);
-    const bool keep = key != KEY_MAX && (!post_filter || (id >= P.lo && id < P.hi && sec.ok(id)));
+    const bool keep = key != KEY_MAX && (!post_filter || (id >= P.lo && id < P.hi && sec_ok(A, sec, id)));
     const u64 km = ballot(keep);
     const int pos = written + rank_in(km);
     if (keep && pos < kout) {
