@@ -528,6 +528,9 @@ struct View {
   // A second attribute per object (internal order; empty when not set) for
   // conjunctive two-attribute queries (Sec. 6.5's extension, approach 1).
   std::vector<int64_t> attr2;
+  // sorted sample of attr2 for the strategy rule: the value at rank floor(j n / ns)
+  // of the sorted attr2, j < ns = min(n, 2048)
+  std::vector<int64_t> attr2_sample;
 
   const float* vec(int v) const { return &X[(size_t)v * d]; }
   const float* svec(int v) const { return XS.empty() ? vec(v) : &XS[(size_t)v * d]; }
@@ -1315,7 +1318,18 @@ int orc_search(void* h, const float* Q, int64_t nq, const int64_t* L, const int6
     srch.plan(qq, L[i], H[i]);
     const int64_t Y = qq.hi - qq.lo;
     int st = strategy;
-    if (st == ST_AUTO) st = Y <= tA ? ST_PRE : (Y >= tB ? ST_POST : ST_HYBRID);
+    if (st == ST_AUTO && qq.multi) {
+      // conjunctive query: the rule looks at the estimated count of objects passing both
+      // ranges, Y times the fraction of the second attribute's sample inside its range
+      const std::vector<int64_t>& sm = V.attr2_sample;
+      const int64_t ns = (int64_t)sm.size();
+      int64_t c2 = 0;
+      for (int64_t j = 0; j < ns; ++j) c2 += sm[j] >= qq.l2 && sm[j] <= qq.h2;
+      const int64_t yj = Y * c2;
+      st = (Y <= tA || yj <= tA * ns) ? ST_PRE : (yj >= tB * ns ? ST_POST : ST_HYBRID);
+    } else if (st == ST_AUTO) {
+      st = Y <= tA ? ST_PRE : (Y >= tB ? ST_POST : ST_HYBRID);
+    }
     cnt[C_STRAT] = st;
     cnt[C_LO] = qq.lo;
     cnt[C_HI] = qq.hi;
@@ -1354,6 +1368,11 @@ int orc_set_attr2(void* h, const int64_t* attr2, int64_t n) {
     }
     a[i] = attr2[V.ext[i]];
   }
+  std::vector<int64_t> srt(a);
+  std::sort(srt.begin(), srt.end());
+  const int64_t ns = std::min<int64_t>(n, 2048);
+  V.attr2_sample.resize(ns);
+  for (int64_t j = 0; j < ns; ++j) V.attr2_sample[j] = srt[(size_t)(j * n / ns)];
   V.attr2.swap(a);
   return 0;
 }

@@ -1,6 +1,7 @@
 // C ABI: index residency (load, upload, free, save) and the search entry points.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -328,12 +329,21 @@ int unify_set_attr2(unify_index_t ix, const int64_t* attr2, int64_t n) {
     }
     a[i] = attr2[ext[i]];
   }
+  // sorted sample for the plan's selectivity estimate: the value at rank floor(j n / ns)
+  // of the sorted second attributes, j < ns = min(n, 2048)
+  const int64_t ns = std::min<int64_t>(N, 2048);
+  std::vector<int64_t> srt(a);
+  std::sort(srt.begin(), srt.end());
+  std::vector<int64_t> smp((size_t)ns);
+  for (int64_t j = 0; j < ns; ++j) smp[j] = srt[(size_t)(j * N / ns)];
   void* p = nullptr;
-  if (hipMalloc(&p, sizeof(int64_t) * (size_t)std::max<int64_t>(N, 1)) != hipSuccess) {
+  if (hipMalloc(&p, sizeof(int64_t) * (size_t)(std::max<int64_t>(N, 1) + ns)) != hipSuccess) {
     set_error("device allocation failed (second attribute)");
     return UNIFY_ENOMEM;
   }
-  if (hipMemcpy(p, a.data(), sizeof(int64_t) * (size_t)N, hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemcpy(p, a.data(), sizeof(int64_t) * (size_t)N, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(static_cast<int64_t*>(p) + std::max<int64_t>(N, 1), smp.data(), sizeof(int64_t) * (size_t)ns,
+                hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(p);
     set_error("host-to-device copy failed");
     return UNIFY_EDEVICE;
@@ -352,6 +362,8 @@ int unify_set_attr2(unify_index_t ix, const int64_t* attr2, int64_t n) {
   }
   ix->allocs.push_back(p);
   ix->dv.attr2 = static_cast<const int64_t*>(p);
+  ix->dv.attr2_sample = static_cast<const int64_t*>(p) + std::max<int64_t>(N, 1);
+  ix->dv.n2s = (int32_t)ns;
   return UNIFY_OK;
 }
 

@@ -1436,6 +1436,8 @@ int insert_impl(unify_index_t ix, const float* vectors, const int64_t* attr, con
   nv.vec_scale = nullptr;
   nv.vec_eps = nullptr;
   nv.attr2 = nullptr;  // a second attribute is set again for the grown index
+  nv.attr2_sample = nullptr;
+  nv.n2s = 0;
   nv.precision = UNIFY_FP32;
   const int precision = dv.precision;
   rl.unlock();

@@ -114,6 +114,7 @@ __device__ int64_t upper_bound_i64(const int64_t* a, int64_t n, int64_t x) {
 }
 
 __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t* __restrict__ h,
+                       const int64_t* __restrict__ l2, const int64_t* __restrict__ h2,
                        const int8_t* __restrict__ strat_in, int64_t nq, int64_t tauA, int64_t tauB,
                        int32_t k, int32_t chunk, QPlan* __restrict__ plan, int8_t* __restrict__ out_strat,
                        int64_t* __restrict__ out_ids, float* __restrict__ out_dist,
@@ -142,7 +143,20 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
   const int64_t Y = hi - lo;
   int s = strat_in ? (int)strat_in[q] : UNIFY_AUTO;
   if (s < UNIFY_AUTO || s > UNIFY_POST) s = UNIFY_AUTO;
-  if (s == UNIFY_AUTO) s = Y <= tauA ? UNIFY_PRE : (Y >= tauB ? UNIFY_POST : UNIFY_HYBRID);
+  if (s == UNIFY_AUTO) {
+    if (l2 && ix.n2s > 0) {
+      // conjunctive query: the objects passing both ranges are estimated as Y times the
+      // fraction c2 / n2s of the second attribute's sample inside its range
+      const int64_t a2 = l2[q], b2 = h2[q];
+      const int64_t c2 = a2 <= b2 ? upper_bound_i64(ix.attr2_sample, ix.n2s, b2) -
+                                        lower_bound_i64(ix.attr2_sample, ix.n2s, a2)
+                                  : 0;
+      const int64_t yj = Y * c2;
+      s = (Y <= tauA || yj <= tauA * ix.n2s) ? UNIFY_PRE : (yj >= tauB * ix.n2s ? UNIFY_POST : UNIFY_HYBRID);
+    } else {
+      s = Y <= tauA ? UNIFY_PRE : (Y >= tauB ? UNIFY_POST : UNIFY_HYBRID);
+    }
+  }
   QPlan P;
   P.lo = (int32_t)lo;
   P.hi = (int32_t)hi;
@@ -649,7 +663,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
 // the kernel's ranking store, for which this is the fallback when it is not FP32).
 template <int NG, int PREC>
 __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
-                         Sec sec, int& al, Counters& cnt) {
+                         int& al, Counters& cnt) {
   const int lane = lane_id();
   const int k = A.k;
   al = 0;
@@ -660,12 +674,49 @@ __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[N
     eval_keys<NG, UNIFY_FP32, (PREC != UNIFY_FP32 ? SHALLOW : STREAM)>(A.ix, qv, cntv,
                                                                       [&](int i) { return base + i; }, L.bkeys);
     __syncthreads();
-    const u64 key = lane < cntv && sec_ok(A, sec, base + lane) ? L.bkeys[lane] : KEY_MAX;
+    const u64 key = lane < cntv ? L.bkeys[lane] : KEY_MAX;
     const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
     list_insert(L.ann, al, k, key < T ? key : KEY_MAX);
     __syncthreads();
   }
   cnt.ndist += P.hi - P.lo;
+}
+
+// Strategy A for a conjunctive query: the slice's second attributes are tested
+// first, and the objects that pass are gathered (up to a wavefront's worth) and
+// scored with the FP32 distance.
+template <int NG, int PREC>
+__device__ void pre_scan_multi(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P, Sec sec,
+                               int& al, Counters& cnt) {
+  const int lane = lane_id();
+  const int k = A.k;
+  al = 0;
+  for (int blk = 0; blk * WAVE < k; ++blk) L.ann[blk * WAVE + lane] = KEY_MAX;
+  int nb = 0;  // gathered ids in L.bkeys[0, nb)
+  auto flush = [&]() {
+    __syncthreads();
+    eval_keys<NG, UNIFY_FP32, (PREC != UNIFY_FP32 ? SHALLOW : STREAM)>(
+        A.ix, qv, nb, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
+    __syncthreads();
+    const u64 key = lane < nb ? L.bkeys[lane] : KEY_MAX;
+    const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
+    list_insert(L.ann, al, k, key < T ? key : KEY_MAX);
+    __syncthreads();
+    cnt.ndist += nb;
+    nb = 0;
+  };
+  __syncthreads();
+  for (int base = P.lo; base < P.hi; base += WAVE) {
+    const int32_t v = base + lane;
+    const bool pass = v < P.hi && sec_ok(A, sec, v);
+    const u64 pm = ballot(pass);
+    const int c = __popcll(pm);
+    if (c == 0) continue;
+    if (nb + c > WAVE) flush();
+    if (pass) L.bkeys[nb + rank_in(pm)] = (uint32_t)v;
+    nb += c;
+  }
+  if (nb > 0) flush();
 }
 
 // Bounds on sqrt(s), s = the canonical FP32 distance of an object, from st =
@@ -696,8 +747,8 @@ __device__ __forceinline__ void root_bounds(float st, float eps, const SearchArg
 // threshold are re-scored in FP32.  Returns false when cand cannot hold the
 // qualifying objects (the caller then runs the FP32 scan).
 template <int NG, int PREC>
-__device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
-                              Sec sec, int& al, Counters& cnt) {
+__device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P, int& al,
+                              Counters& cnt) {
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
   const int k = A.k;
@@ -710,7 +761,7 @@ __device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&
     __syncthreads();
     cnt.ndist += cntv;
     float lb = 0.f, ub = 0.f;
-    const bool have = lane < cntv && sec_ok(A, sec, base + lane);
+    const bool have = lane < cntv;
     if (have) root_bounds(key_dist(L.bkeys[lane]), ix.vec_eps[base + lane], A, lb, ub);
     const int32_t v = base + lane;
     const u64 uk = have ? make_key(ub, v) : KEY_MAX;
@@ -853,9 +904,11 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
     Pc.hi = min(P.hi, Pc.lo + P.clen);
     // a low-precision scan whose bounds cannot settle its top k is redone in FP32
     bool fell = false;
-    if (PREC == UNIFY_FP32 || !pre_scan_lowp<NG, PREC>(A, L, qv, Pc, sec, al, cnt)) {
+    if (A.l2) {
+      pre_scan_multi<NG, PREC>(A, L, qv, Pc, sec, al, cnt);
+    } else if (PREC == UNIFY_FP32 || !pre_scan_lowp<NG, PREC>(A, L, qv, Pc, al, cnt)) {
       fell = PREC != UNIFY_FP32;
-      pre_scan<NG, PREC>(A, L, qv, Pc, sec, al, cnt);
+      pre_scan<NG, PREC>(A, L, qv, Pc, al, cnt);
     }
     if (P.nch > 1) {
       pre_store_chunk(A, L, q, P, chunk, al, cnt, fell);
@@ -1354,7 +1407,8 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, unify_index_
   const unsigned pb = 256;
   const int64_t nq = X.nq;
   if (ev) HIP_OK(hipEventRecord(ev[0], st));
-  hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, X.dv, X.l, X.h, X.strategy, nq,
+  hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, X.dv, X.l, X.h, X.A.l2, X.A.h2,
+                     X.strategy, nq,
                      X.R.tauA, X.R.tauB, X.R.k, X.R.pre_chunk, X.S.plan, X.out_strategy, X.out_ids, X.out_dist,
                      X.out_stats);
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((4 * nq + pb - 1) / pb)), dim3(pb), 0, st, X.S.qacc, 4 * nq, 0);

@@ -40,6 +40,8 @@ struct DevIndex {
   const int32_t* adjU;       // [R][S][MU]
   const int32_t* glistU;     // [R][GC]
   const int64_t* attr2;      // [n] second attribute (conjunctive queries), or null
+  const int64_t* attr2_sample;  // [n2s] sorted sample of attr2 (selectivity estimates)
+  int32_t n2s;
 };
 
 // Per-query plan written by the plan kernel.

@@ -48,11 +48,12 @@ def test_parity_conjunctive(c1, precision, strategy):
     try:
         Q, L, H, L2, H2 = _dev(W.queries, W.l, W.h, l2, h2)
         for ef, p, chunk in ((48, 1, 0), (64, 2, 64)):
-            rid, rd = ix.search(W.queries, W.l, W.h, 10, ef, p=p, strategy=strategy, l2=l2, h2=h2)
-            ids, dist, _, st = g.search(Q, L, H, 10, ef, beam_p=p, strategy=None if strategy == hsig.AUTO else strategy,
+            rid, rd, rc = ix.search(W.queries, W.l, W.h, 10, ef, p=p, strategy=strategy, l2=l2, h2=h2, counters=True)
+            ids, dist, srun, st = g.search(Q, L, H, 10, ef, beam_p=p, strategy=None if strategy == hsig.AUTO else strategy,
                                         stats=True, pre_chunk=chunk, l2=L2, h2=H2)
             torch.cuda.synchronize()
             assert (st.cpu().numpy()[:, 3] != 2).all()
+            assert np.array_equal(srun.cpu().numpy().astype(np.int64), rc[:, hsig.STRAT])
             gid, gd = ids.cpu().numpy(), dist.cpu().numpy()
             bad = np.nonzero((gid != rid).any(1) | (gd.view(np.uint32) != rd.view(np.uint32)).any(1))[0]
             assert bad.size == 0, f"ef={ef} p={p} chunk={chunk}: {bad.size} rows differ, first {bad[:5]}"

@@ -78,3 +78,25 @@ def test_empty_second_range_and_errors(multi, small_workload):
     fresh = hsig.Index.build(W.base[:300], W.attr[:300], W.level_u[:300], 4, 8, 32)
     with pytest.raises(ValueError):
         fresh.search(W.queries[:2], W.l[:2], W.h[:2], 10, 32, l2=l2[:2], h2=h2[:2])
+
+
+def test_strategy_rule_uses_joint_estimate(multi):
+    """The rule for conjunctive queries compares Y * c2 / ns with tau_A and tau_B (c2 of
+    the ns sample values of the second attribute lie in its range): a second range that
+    admits everything keeps the single-attribute choice, an empty one makes every query
+    a pre-filter scan, and a narrow one never turns a query into a post-filter search."""
+    ix, W, a2, l2, h2 = multi
+    nq = len(W.queries)
+    _, _, c0 = ix.search(W.queries, W.l, W.h, 10, 32, counters=True)
+    lo, hi = np.full(nq, a2.min()), np.full(nq, a2.max())
+    _, _, c1 = ix.search(W.queries, W.l, W.h, 10, 32, counters=True, l2=lo, h2=hi)
+    assert np.array_equal(c0[:, hsig.STRAT], c1[:, hsig.STRAT])
+    _, _, ce = ix.search(W.queries, W.l, W.h, 10, 32, counters=True, l2=hi, h2=lo)
+    Y = ce[:, hsig.HI] - ce[:, hsig.LO]
+    assert (ce[Y > 0, hsig.STRAT] == hsig.PRE).all()
+    srt = np.sort(a2)
+    narrow_l = np.full(nq, srt[len(srt) // 2])
+    narrow_h = np.full(nq, srt[len(srt) // 2 + len(srt) // 100])  # about 1% of the objects
+    _, _, cn = ix.search(W.queries, W.l, W.h, 10, 32, counters=True, l2=narrow_l, h2=narrow_h)
+    assert (cn[:, hsig.STRAT] != hsig.POST).all()
+    assert (cn[c0[:, hsig.STRAT] == hsig.PRE, hsig.STRAT] == hsig.PRE).all()
