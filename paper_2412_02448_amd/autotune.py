@@ -75,28 +75,27 @@ def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256),
         for m in ms:
             if m > index.S * index.M:
                 continue
+            pending = list(ps)  # beam widths still below the target at the efs tried so far
             for ef in efs:
-                if ef < k:
+                if ef < k or not pending:
                     continue
-                ids, _, _ = index.search(Q, L, H, k, ef, m=m, tau_a=ta, tau_b=tb)
-                torch.cuda.synchronize()
-                rec = recall_at_k(ids.cpu().numpy(), truth)
-                if rec < target:
-                    table.append(Setting(m, ef, 1, rec, 0.0, ta, tb))
-                    continue
-                for p in ps:
+                for p in list(pending):
                     kw = dict(m=m, beam_p=p, tau_a=ta, tau_b=tb)
-                    index.search(Q, L, H, k, ef, **kw)
+                    ids, _, _ = index.search(Q, L, H, k, ef, **kw)
                     torch.cuda.synchronize()
+                    rec = recall_at_k(ids.cpu().numpy(), truth)  # beam width changes the results
+                    if rec < target:
+                        table.append(Setting(m, ef, p, rec, 0.0, ta, tb))
+                        continue
                     t = time.perf_counter()
                     for _ in range(reps):
                         index.search(Q, L, H, k, ef, **kw)
                     torch.cuda.synchronize()
                     qps = Q.shape[0] * reps / (time.perf_counter() - t)
                     table.append(Setting(m, ef, p, rec, qps, ta, tb))
+                    pending.remove(p)  # larger ef only costs more once the target is met
                     if log:
                         log(f"tune tau=({ta}, {tb}) m={m} ef={ef} p={p}: recall {rec:.4f}, {qps:,.0f} QPS")
-                break  # larger ef only costs more once the target is met
     ok = [s for s in table if s.recall >= target and s.qps > 0]
     best = None
     if ok:

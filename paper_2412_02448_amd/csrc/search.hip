@@ -62,18 +62,26 @@ struct SearchArgs {
   uint32_t* tags;         // [nslots][n] visited epochs, one row per persistent wave
   uint32_t* epochs;       // [nslots] last epoch used by each row
   int64_t nslots;
-  const int64_t* l2;      // conjunctive queries: inclusive range on the second attribute
-  const int64_t* h2;      // per query, or null
+  const struct ConjArgs* conj;  // conjunctive queries (written by the plan kernel), or null
+};
+
+// Second attribute and per-query inclusive ranges of a conjunctive search.  The
+// search kernel reaches them through one pointer, read where a test is made, so
+// single-attribute searches hold no extra registers.
+struct ConjArgs {
+  const int64_t* attr2;
+  const int64_t* l2;
+  const int64_t* h2;
 };
 
 // The second-attribute test of a conjunctive query (always true for others).
-// Only the query index is kept: its range is read where the test is made, so
-// single-attribute searches hold no extra registers.
 struct Sec {
   int32_t q;
 };
 __device__ __forceinline__ bool sec_ok(const SearchArgs& A, Sec s, int32_t v) {
-  return !A.l2 || (A.ix.attr2[v] >= A.l2[s.q] && A.ix.attr2[v] <= A.h2[s.q]);
+  if (!A.conj) return true;
+  const ConjArgs c = *A.conj;
+  return c.attr2[v] >= c.l2[s.q] && c.attr2[v] <= c.h2[s.q];
 }
 
 constexpr uint32_t HASH_EMPTY = 0xFFFFFFFFu;
@@ -115,7 +123,7 @@ __device__ int64_t upper_bound_i64(const int64_t* a, int64_t n, int64_t x) {
 
 __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t* __restrict__ h,
                        const int64_t* __restrict__ l2, const int64_t* __restrict__ h2,
-                       const int8_t* __restrict__ strat_in, int64_t nq, int64_t tauA, int64_t tauB,
+                       ConjArgs* __restrict__ conj, const int8_t* __restrict__ strat_in, int64_t nq, int64_t tauA, int64_t tauB,
                        int32_t k, int32_t chunk, QPlan* __restrict__ plan, int8_t* __restrict__ out_strat,
                        int64_t* __restrict__ out_ids, float* __restrict__ out_dist,
                        int32_t* __restrict__ out_stats) {
@@ -126,6 +134,7 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
   const int64_t ns = (ix.n + stride - 1) / stride;
   for (int64_t j = threadIdx.x; j < ns; j += blockDim.x) samp[j] = ix.attr[j * stride];
   __syncthreads();
+  if (conj && blockIdx.x == 0 && threadIdx.x == 0) *conj = ConjArgs{ix.attr2, l2, h2};
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
   const int64_t lq = l[q], hq = h[q];
@@ -692,8 +701,37 @@ __device__ void pre_scan_multi(const SearchArgs& A, const Lds& L, const float4 (
   const int k = A.k;
   al = 0;
   for (int blk = 0; blk * WAVE < k; ++blk) L.ann[blk * WAVE + lane] = KEY_MAX;
-  int nb = 0;  // gathered ids in L.bkeys[0, nb)
-  auto flush = [&]() {
+  __syncthreads();
+  if constexpr (PREC == UNIFY_FP8E4M3) {
+    // (the FP8 kernel's register allocation does not absorb the gathering loop below:
+    // it scores every object of the slice and drops those failing the test)
+    for (int base = P.lo; base < P.hi; base += WAVE) {
+      const int cntv = min(WAVE, P.hi - base);
+      eval_keys<NG, UNIFY_FP32, SHALLOW>(A.ix, qv, cntv, [&](int i) { return base + i; }, L.bkeys);
+      __syncthreads();
+      const u64 key = lane < cntv && sec_ok(A, sec, base + lane) ? L.bkeys[lane] : KEY_MAX;
+      const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
+      list_insert(L.ann, al, k, key < T ? key : KEY_MAX);
+      __syncthreads();
+    }
+    cnt.ndist += P.hi - P.lo;
+    return;
+  }
+  int base = P.lo;
+  while (true) {
+    // gather up to a wavefront's worth of passing ids into L.bkeys
+    int nb = 0;
+    while (base < P.hi) {
+      const int32_t v = base + lane;
+      const bool pass = v < P.hi && sec_ok(A, sec, v);
+      const u64 pm = ballot(pass);
+      const int c = __popcll(pm);
+      if (nb + c > WAVE) break;  // this block starts the next batch
+      if (pass) L.bkeys[nb + rank_in(pm)] = (uint32_t)v;
+      nb += c;
+      base += WAVE;
+    }
+    if (nb == 0) break;
     __syncthreads();
     eval_keys<NG, UNIFY_FP32, (PREC != UNIFY_FP32 ? SHALLOW : STREAM)>(
         A.ix, qv, nb, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
@@ -703,20 +741,7 @@ __device__ void pre_scan_multi(const SearchArgs& A, const Lds& L, const float4 (
     list_insert(L.ann, al, k, key < T ? key : KEY_MAX);
     __syncthreads();
     cnt.ndist += nb;
-    nb = 0;
-  };
-  __syncthreads();
-  for (int base = P.lo; base < P.hi; base += WAVE) {
-    const int32_t v = base + lane;
-    const bool pass = v < P.hi && sec_ok(A, sec, v);
-    const u64 pm = ballot(pass);
-    const int c = __popcll(pm);
-    if (c == 0) continue;
-    if (nb + c > WAVE) flush();
-    if (pass) L.bkeys[nb + rank_in(pm)] = (uint32_t)v;
-    nb += c;
   }
-  if (nb > 0) flush();
 }
 
 // Bounds on sqrt(s), s = the canonical FP32 distance of an object, from st =
@@ -904,7 +929,7 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
     Pc.hi = min(P.hi, Pc.lo + P.clen);
     // a low-precision scan whose bounds cannot settle its top k is redone in FP32
     bool fell = false;
-    if (A.l2) {
+    if (A.conj) {
       pre_scan_multi<NG, PREC>(A, L, qv, Pc, sec, al, cnt);
     } else if (PREC == UNIFY_FP32 || !pre_scan_lowp<NG, PREC>(A, L, qv, Pc, al, cnt)) {
       fell = PREC != UNIFY_FP32;
@@ -1296,6 +1321,7 @@ struct Launch {
   const float* queries;
   int64_t nq;
   const int64_t *l, *h;
+  const int64_t *l2 = nullptr, *h2 = nullptr;  // conjunctive searches
   const int8_t* strategy;
   int64_t* out_ids;
   float* out_dist;
@@ -1355,8 +1381,10 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   A.out_ids = out_ids;
   A.out_dist = out_dist;
   A.out_stats = out_stats;
-  A.l2 = l2;
-  A.h2 = h2;
+  // the counters block holds 4 counters, then (conjunctive searches) the ConjArgs
+  A.conj = l2 ? reinterpret_cast<const ConjArgs*>(X.S.counters + 16) : nullptr;
+  X.l2 = l2;
+  X.h2 = h2;
   A.plan = X.S.plan;
   A.tags = ix->tags;
   A.epochs = ix->epochs;
@@ -1407,8 +1435,8 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, unify_index_
   const unsigned pb = 256;
   const int64_t nq = X.nq;
   if (ev) HIP_OK(hipEventRecord(ev[0], st));
-  hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, X.dv, X.l, X.h, X.A.l2, X.A.h2,
-                     X.strategy, nq,
+  hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, X.dv, X.l, X.h, X.l2, X.h2,
+                     const_cast<ConjArgs*>(X.A.conj), X.strategy, nq,
                      X.R.tauA, X.R.tauB, X.R.k, X.R.pre_chunk, X.S.plan, X.out_strategy, X.out_ids, X.out_dist,
                      X.out_stats);
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((4 * nq + pb - 1) / pb)), dim3(pb), 0, st, X.S.qacc, 4 * nq, 0);
