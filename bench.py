@@ -13,7 +13,8 @@ and re-scored in FP32), (m, ef, beam width) is tuned on 10,000 held-out queries
 of the same recipe for recall@10 >= 0.95 against the exact answer (the
 pre-filter scan forced on every query), then the batch is timed.  The headline
 value is the fastest store whose recall on the benchmark queries reaches the
-target.  The JSON line also reports every store, each strategy timed
+target (stores within 2% of the fastest are a tie, which the most accurate of
+them wins).  The JSON line also reports every store, each strategy timed
 separately, the roofline of the search kernel (algorithmic bytes from the
 kernel's own counters / its HIP-event duration) and the CPU oracle's HSIG
 search on the same index as a baseline.
@@ -206,7 +207,12 @@ def main():
             f"({by_prec[prec]['rerun_queries']} queries)")
 
     ok = [p for p in precs if by_prec[p]["recall@10"] >= args.recall_target]
-    head = max(ok or precs, key=lambda p: by_prec[p]["qps"] if ok else by_prec[p]["recall@10"])
+    if ok:
+        # stores within 2% of the fastest are within the timing noise: the most accurate of them
+        top = max(by_prec[p]["qps"] for p in ok)
+        head = max((p for p in ok if by_prec[p]["qps"] >= 0.98 * top), key=lambda p: by_prec[p]["recall@10"])
+    else:
+        head = max(precs, key=lambda p: by_prec[p]["recall@10"])
     H0 = by_prec[head]
     m, ef, bp, ta, tb, vc = H0["m"], H0["ef"], H0["beam_p"], H0["tau_a"], H0["tau_b"], H0["visit_cap"]
     index.set_precision(head)

@@ -672,7 +672,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
 // the kernel's ranking store, for which this is the fallback when it is not FP32).
 template <int NG, int PREC>
 __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
-                         int& al, Counters& cnt) {
+                         Sec sec, int& al, Counters& cnt) {
   const int lane = lane_id();
   const int k = A.k;
   al = 0;
@@ -683,7 +683,7 @@ __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[N
     eval_keys<NG, UNIFY_FP32, (PREC != UNIFY_FP32 ? SHALLOW : STREAM)>(A.ix, qv, cntv,
                                                                       [&](int i) { return base + i; }, L.bkeys);
     __syncthreads();
-    const u64 key = lane < cntv ? L.bkeys[lane] : KEY_MAX;
+    const u64 key = lane < cntv && sec_ok(A, sec, base + lane) ? L.bkeys[lane] : KEY_MAX;
     const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
     list_insert(L.ann, al, k, key < T ? key : KEY_MAX);
     __syncthreads();
@@ -702,21 +702,6 @@ __device__ void pre_scan_multi(const SearchArgs& A, const Lds& L, const float4 (
   al = 0;
   for (int blk = 0; blk * WAVE < k; ++blk) L.ann[blk * WAVE + lane] = KEY_MAX;
   __syncthreads();
-  if constexpr (PREC == UNIFY_FP8E4M3) {
-    // (the FP8 kernel's register allocation does not absorb the gathering loop below:
-    // it scores every object of the slice and drops those failing the test)
-    for (int base = P.lo; base < P.hi; base += WAVE) {
-      const int cntv = min(WAVE, P.hi - base);
-      eval_keys<NG, UNIFY_FP32, SHALLOW>(A.ix, qv, cntv, [&](int i) { return base + i; }, L.bkeys);
-      __syncthreads();
-      const u64 key = lane < cntv && sec_ok(A, sec, base + lane) ? L.bkeys[lane] : KEY_MAX;
-      const u64 T = al == k ? L.ann[k - 1] : KEY_MAX;
-      list_insert(L.ann, al, k, key < T ? key : KEY_MAX);
-      __syncthreads();
-    }
-    cnt.ndist += P.hi - P.lo;
-    return;
-  }
   int base = P.lo;
   while (true) {
     // gather up to a wavefront's worth of passing ids into L.bkeys
@@ -928,12 +913,16 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
     Pc.lo = P.lo + chunk * P.clen;
     Pc.hi = min(P.hi, Pc.lo + P.clen);
     // a low-precision scan whose bounds cannot settle its top k is redone in FP32
+    // conjunctive queries: the gathering scan where the kernel's registers absorb a
+    // second scan loop; elsewhere the plain scan (one call site) scores every object
+    // and drops those failing the second test
+    constexpr bool GATHER = NG <= 4 && PREC != UNIFY_FP8E4M3;
     bool fell = false;
-    if (A.conj) {
+    if (GATHER && A.conj) {
       pre_scan_multi<NG, PREC>(A, L, qv, Pc, sec, al, cnt);
-    } else if (PREC == UNIFY_FP32 || !pre_scan_lowp<NG, PREC>(A, L, qv, Pc, al, cnt)) {
-      fell = PREC != UNIFY_FP32;
-      pre_scan<NG, PREC>(A, L, qv, Pc, al, cnt);
+    } else if (PREC == UNIFY_FP32 || A.conj || !pre_scan_lowp<NG, PREC>(A, L, qv, Pc, al, cnt)) {
+      fell = PREC != UNIFY_FP32 && !A.conj;
+      pre_scan<NG, PREC>(A, L, qv, Pc, sec, al, cnt);
     }
     if (P.nch > 1) {
       pre_store_chunk(A, L, q, P, chunk, al, cnt, fell);
