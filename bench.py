@@ -171,10 +171,10 @@ def main():
         t0 = time.time()
         ms_grid = (args.m,) if args.m else None
         efs_grid = (args.ef,) if args.ef else (16, 24, 32, 48, 64, 128, 256)
-        ps_grid = (args.p,) if args.p else (2, 4, 8)
+        ps_grid = (args.p,) if args.p else (2, 3, 4, 6, 8)
         if not args.m:
             Mi = index.M
-            ms_grid = (Mi // 2, (3 * Mi) // 4, Mi, (3 * Mi) // 2, 2 * Mi)
+            ms_grid = (Mi // 2, (3 * Mi) // 4, Mi, (3 * Mi) // 2, 2 * Mi, 3 * Mi)
         kw_t = {"taus": ((args.tau_a, args.tau_b),)} if args.tau_a else {}
         # a small margin above the target on the held-out queries keeps the benchmark
         # queries above it too

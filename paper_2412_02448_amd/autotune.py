@@ -36,16 +36,18 @@ class Setting:
 
 
 def recall_at_k(ids: np.ndarray, truth: np.ndarray) -> float:
-    """Mean over queries of |found & exact| / |exact| (Eq. 1; |exact| = min(k, |R|))."""
-    r = np.empty(len(ids))
-    for i in range(len(ids)):
-        t = truth[i][truth[i] >= 0]
-        if t.size == 0:
-            r[i] = 1.0
-            continue
-        f = ids[i][ids[i] >= 0]
-        r[i] = np.intersect1d(f, t, assume_unique=True).size / t.size
-    return float(r.mean())
+    """Mean over queries of |found & exact| / |exact| (Eq. 1; |exact| = min(k, |R|)).
+    Rows hold distinct ids padded with -1; a query with no exact answer counts 1."""
+    if len(ids) == 0:
+        return 1.0
+    valid = truth >= 0
+    hit = np.empty(len(ids), np.int64)
+    step = max(1, (1 << 24) // max(1, truth.shape[1] * ids.shape[1]))  # rows per block of comparisons
+    for a in range(0, len(ids), step):
+        t, f = truth[a:a + step], ids[a:a + step]
+        hit[a:a + step] = ((t[:, :, None] == f[:, None, :]).any(2) & valid[a:a + step]).sum(1)
+    n = valid.sum(1)
+    return float(np.where(n > 0, hit / np.maximum(n, 1), 1.0).mean())
 
 
 def exact_answers(index, Q, L, H, k):
