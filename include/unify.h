@@ -228,6 +228,19 @@ int unify_search_multi(unify_index_t index, const float* queries, int64_t nq, co
                        float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* hip_stream);
 
 /*
+ * Disjunctive two-attribute queries (the paper's multi-attribute extension,
+ * approach 1): with one index per attribute over the same objects, search each
+ * with its own range and merge the two [nq][k] result lists of every query here.
+ * The merge keeps the k smallest (distance, external id) pairs, an object found
+ * by both searches once (it carries the same canonical FP32 distance in both).
+ * All arrays are device memory in the layout unify_search writes (ascending,
+ * -1 / +inf padded); out_* may not alias the inputs.  Enqueued on hip_stream.
+ * Errors: UNIFY_EINVAL (k < 1, nq < 0, null arrays), UNIFY_EDEVICE.
+ */
+int unify_merge_or(const int64_t* ids_a, const float* dist_a, const int64_t* ids_b, const float* dist_b,
+                   int64_t nq, int32_t k, int64_t* out_ids, float* out_dist, void* hip_stream);
+
+/*
  * Durations of the kernels of the last unify_search* call on this index that set
  * UNIFY_FLAG_TIMING, from HIP events recorded on that call's stream:
  *   plan_ms     the plan and work-list kernels;

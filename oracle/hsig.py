@@ -307,3 +307,32 @@ class Index:
         cnt = lib().orc_layer_search(self._h, _p(q), ep, layer, ef, int(hybrid), a, b, c, int(filter),
                                      l, h, _p(ids), _p(dist))
         return ids[:cnt], dist[:cnt]
+
+
+def merge_or(ids_a, dist_a, ids_b, dist_b):
+    """Disjunctive two-attribute queries (the paper's multi-attribute extension,
+    approach 1): the results of one index per attribute, each searched with its own
+    range, merged per query.  Both lists ascend by distance (-1 / +inf padded); the
+    merged list takes the smaller distance first (ties: the smaller id), and an id
+    already taken at the same distance (the same object from the other list) is
+    skipped.  Returns the first k of the merged list, padded."""
+    ids_a, ids_b = np.asarray(ids_a), np.asarray(ids_b)
+    dist_a, dist_b = np.asarray(dist_a, np.float32), np.asarray(dist_b, np.float32)
+    nq, k = ids_a.shape
+    oi = np.full((nq, k), -1, np.int64)
+    od = np.full((nq, k), np.inf, np.float32)
+    for q in range(nq):
+        a = [(float(d), int(i)) for d, i in zip(dist_a[q], ids_a[q]) if i >= 0]
+        b = [(float(d), int(i)) for d, i in zip(dist_b[q], ids_b[q]) if i >= 0]
+        out = []
+        while len(out) < k and (a or b):
+            if a and (not b or a[0] <= b[0]):
+                d, i = a.pop(0)
+            else:
+                d, i = b.pop(0)
+            if any(dd == d and ii == i for dd, ii in out):
+                continue
+            out.append((d, i))
+        for t, (d, i) in enumerate(out):
+            oi[q, t], od[q, t] = i, d
+    return oi, od

@@ -58,6 +58,7 @@ SIGNATURES = {
     "unify_set_precision": (_I32, [_P, _I32]),
     "unify_insert": (_I32, [_P, _P, _P, _P, _I64]),
     "unify_set_attr2": (_I32, [_P, _P, _I64]),
+    "unify_merge_or": (_I32, [_P, _P, _P, _P, _I64, _I32, _P, _P, _P]),
     "unify_search_multi": (_I32, [_P, _P, _I64, _P, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "unify_batch_create": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "unify_server_create": (_I32, [_P, _P, _P]),
@@ -101,6 +102,25 @@ def validate_index_file(path: str) -> dict:
     _check(load_library().unify_validate_index_file(path.encode(), C.byref(n), C.byref(d), C.byref(S),
                                                     C.byref(M)))
     return {"n": n.value, "d": d.value, "S": S.value, "M": M.value}
+
+
+def merge_or(a, b, stream=None):
+    """Disjunctive query results: a and b are (ids, dist) of the same queries searched on two
+    indexes over the same objects (one per attribute, each with its range); returns the k
+    nearest distinct objects of the two lists per query, as new device tensors."""
+    import torch
+    ia, da = a[0], a[1]
+    ib, db = b[0], b[1]
+    if ia.shape != ib.shape or da.shape != ia.shape or db.shape != ia.shape or ia.dim() != 2:
+        raise ValueError("both results must be [nq, k] ids and distances")
+    for t, dt in ((ia, torch.int64), (ib, torch.int64), (da, torch.float32), (db, torch.float32)):
+        if t.dtype != dt or not t.is_contiguous() or t.device != ia.device:
+            raise ValueError("ids int64 and dist float32, contiguous, on one device")
+    oi, od = torch.empty_like(ia), torch.empty_like(da)
+    s = stream if stream is not None else torch.cuda.current_stream(ia.device)
+    _check(load_library().unify_merge_or(_ptr(ia), _ptr(da), _ptr(ib), _ptr(db), ia.shape[0], ia.shape[1],
+                                         _ptr(oi), _ptr(od), s.cuda_stream))
+    return oi, od
 
 
 def _ptr(t) -> int:

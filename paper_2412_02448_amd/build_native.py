@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libunify.so")
-SOURCES = ["api.hip", "search.hip", "quant.hip", "serve.hip", "build.hip", "index_file.cpp"]
+SOURCES = ["api.hip", "search.hip", "quant.hip", "serve.hip", "build.hip", "merge.hip", "index_file.cpp"]
 ARCH = os.environ.get("UNIFY_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
