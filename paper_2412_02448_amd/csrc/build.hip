@@ -1439,11 +1439,11 @@ int insert_impl(unify_index_t ix, const float* vectors, const int64_t* attr, con
   nv.attr2_sample = nullptr;
   nv.n2s = 0;
   nv.precision = UNIFY_FP32;
-  const int precision = dv.precision;
   rl.unlock();
 
   // swap between searches: wait for every search enqueued on the old version
   std::unique_lock<std::shared_mutex> wl(ix->version_mu);
+  const int precision = ix->dv.precision;  // as the caller last set it
   if (ix->last_search) BHIP(hipEventSynchronize(ix->last_search));
   BHIP(hipDeviceSynchronize());
   for (void* p : ix->allocs)
