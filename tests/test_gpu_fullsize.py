@@ -1,0 +1,76 @@
+"""Parity at the benchmark's full size: the 1M x 128 mixed-range workload, the
+GPU-built index, the benchmark's launch configuration (10,000 queries in one
+call, BF16 store, m = 64, ef = 16, p = 4, tau = (0.01, 0.5), split pre-filter
+scans) -- against the oracle on a sample of the queries (the oracle reads the
+same index file and searches those queries one by one), and against properties
+that hold for every query at any size: pre-filter rows equal the exact answer,
+every returned object is in range with its exact FP32 distance, rows ascend."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import hsig
+from synth import workloads as w
+
+
+@pytest.fixture(scope="module")
+def full(tmp_path_factory):
+    import torch
+    import paper_2412_02448_amd as u
+    assert torch.cuda.is_available()
+    spec = w.SPECS["mixed1m"]
+    print("[fixture] GPU build mixed1m (1M x 128)", flush=True)
+    W = w.make(spec, base_seed=0)
+    g = u.Index.build(W.base, W.attr, W.level_u, spec.S, spec.M, spec.ef_cons, device=0, precision="bf16")
+    dev = torch.device("cuda", 0)
+    Q, L, H = (torch.from_numpy(a).to(dev) for a in (W.queries, W.l, W.h))
+    ids, dist, strat, st = g.search(Q, L, H, 10, 16, m=64, beam_p=4, tau_a=0.01, tau_b=0.5, stats=True)
+    torch.cuda.synchronize()
+    out = [t.cpu().numpy() for t in (ids, dist, strat, st)]
+    path = str(tmp_path_factory.mktemp("full") / "mixed1m.uix")
+    print("[fixture] saving the index for the oracle", flush=True)
+    g.save(path)
+    g.close()
+    return W, out, path
+
+
+def test_sampled_queries_equal_oracle(full):
+    W, (ids, dist, strat, st), path = full
+    print("[case] oracle reads the 1M index", flush=True)
+    ref = hsig.Index.read(path)
+    ref.set_store(hsig.BF16, 4)
+    sample = np.arange(0, len(W.queries), 37)
+    rid, rd, rc = ref.search(W.queries[sample], W.l[sample], W.h[sample], 10, 16, m=64, p=4, tau_a=0.01,
+                             tau_b=0.5, counters=True)
+    assert (st[:, 3] != 2).all()
+    assert np.array_equal(strat[sample].astype(np.int64), rc[:, hsig.STRAT])
+    assert np.array_equal(ids[sample], rid)
+    assert np.array_equal(dist[sample].view(np.uint32), rd.view(np.uint32))
+    # every strategy is in the sample
+    assert set(rc[:, hsig.STRAT].tolist()) == {hsig.PRE, hsig.HYBRID, hsig.POST}
+
+
+def test_properties_of_every_row(full):
+    W, (ids, dist, strat, st), path = full
+    order = np.lexsort((np.arange(len(W.attr)), W.attr))
+    srt = W.attr[order]
+    for i in range(len(W.queries)):
+        row = ids[i][ids[i] >= 0]
+        a = W.attr[row]
+        assert np.all((a >= W.l[i]) & (a <= W.h[i])), i
+        assert np.all(np.diff(dist[i][: len(row)]) >= 0), i
+        if i % 10 == 0:  # exact FP32 distances of the returned objects
+            d32 = np.array([hsig.dist32(W.queries[i], W.base[e]) for e in row], np.float32)
+            assert np.array_equal(d32, dist[i][: len(row)]), i
+        if strat[i] == hsig.PRE and i % 5 == 0:  # pre-filter rows are the exact answer
+            lo, hi = np.searchsorted(srt, W.l[i], "left"), np.searchsorted(srt, W.h[i], "right")
+            idx = order[lo:hi]
+            dd = ((W.base[idx].astype(np.float64) - W.queries[i].astype(np.float64)) ** 2).sum(1)
+            o = np.lexsort((idx, dd))
+            top = idx[o[:10]]
+            # the same set unless the 10th and 11th exact distances tie within FP32 rounding
+            if len(o) <= 10 or dd[o[10]] - dd[o[9]] > 1e-5 * dd[o[10]]:
+                assert sorted(row.tolist()) == sorted(top.tolist()), i
