@@ -177,7 +177,7 @@ def test_deterministic(c1):
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("d", [96, 960])
+@pytest.mark.parametrize("d", [4, 96, 200, 260, 960, 2048])  # every kernel width: 2, 4, 8, 15 and 32 groups
 def test_parity_other_dimensions(tmp_path, d):
     spec = w.scaled(w.SPECS["hybrid10k"], n=3000, nq=40, d=d, S=4, M=8, ef_cons=40)
     W, ix, g = _build(spec, 3, str(tmp_path / f"d{d}.uix"))
