@@ -204,14 +204,15 @@ def test_fp8_every_code(tmp_path):
     g.close()
 
 
+@pytest.mark.parametrize("d", [200, 260, 960, 2048])
 @pytest.mark.parametrize("name,prec", PRECS)
-def test_parity_low_precision_d960(tmp_path, name, prec):
-    """The GIST-like width (960 = 15 groups of 64): one 16-lane group per vector
-    with 15 rounds of groups, for both copies."""
+def test_parity_low_precision_d960(tmp_path, name, prec, d):
+    """Wider rows than the 1M workload's, for both copies: the kernels for 4, 8, 15 and
+    32 groups of 64 elements (960 is the GIST-like width)."""
     import paper_2412_02448_amd as u
-    spec = w.scaled(w.SPECS["gist1m"], n=2500, nq=60, S=4, M=8, ef_cons=40)
+    spec = w.scaled(w.SPECS["gist1m"], n=2500, nq=60, S=4, M=8, ef_cons=40, d=d)
     W = w.make(spec, base_seed=9)
-    print(f"[case] d=960 {name}", flush=True)
+    print(f"[case] d={d} {name}", flush=True)
     ix = hsig.Index.build(W.base, W.attr, W.level_u, spec.S, spec.M, spec.ef_cons, seed=9)
     path = str(tmp_path / "g.uix")
     ix.write(path)
