@@ -485,7 +485,7 @@ def insert_bench(args, spec, W, Q, L, H, k, m, ef, bp, ta, tb, vc, prec, build_s
     """The insertion experiment's shape on the mixed1m objects: an index of the first
     200k, then four insertions of 200k each.  Per round: insertion time, then QPS and
     recall@10 (against the exact answer over the objects present) at the headline
-    setting.  The last round holds the same 1M objects as the single build."""
+    setting.  After the last insertion the index holds the same 1M objects as the single build."""
     import numpy as np
     import torch
 
