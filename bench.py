@@ -574,9 +574,31 @@ def serve_bench(args, index, spec, W, m, ef, bp, ta, tb, vc, prec):
         rows.append(row)
         log(f"serving {row['offered_qps']}: {row['achieved_qps']:,.0f} QPS, p50 {row['p50_ms']} ms, "
             f"p99 {row['p99_ms']} ms, {batches} batches, identical {row['equal_to_batch_search']}")
+    # k = 100 (the other result size of the serving workload), ef = 128
+    k2, ef2, cnt = 100, 128, 20_000
+    ref2 = index.search(torch.from_numpy(q[:cnt]).to(dev), torch.from_numpy(l[:cnt]).to(dev),
+                        torch.from_numpy(h[:cnt]).to(dev), k2, ef2, m=m, beam_p=bp, tau_a=ta, tau_b=tb,
+                        visit_cap=vc)[0].cpu().numpy()
+    k100 = []
+    for rate in (10_000, 100_000):
+        arrive = np.cumsum(rng.exponential(1.0 / rate, cnt))
+        srv = u.Server(index, k2, ef2, max_batch=4096, inflight=2, m=m, beam_p=bp, tau_a=ta, tau_b=tb,
+                       visit_cap=vc)
+        t0 = time.perf_counter()
+        ids, _, lat = srv.wait(srv.submit(q[:cnt], l[:cnt], h[:cnt], arrive_s=arrive), timeout_s=120)
+        wall = time.perf_counter() - t0
+        _, batches, _ = srv.stats()
+        srv.close()
+        row = {"k": k2, "ef": ef2, "offered_qps": rate, "requests": cnt, "achieved_qps": round(cnt / wall, 1),
+               "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "batches": batches,
+               "equal_to_batch_search": bool(np.array_equal(ids, ref2))}
+        k100.append(row)
+        log(f"serving k=100 at {rate}/s: {row['achieved_qps']:,.0f} QPS, p50 {row['p50_ms']} ms, "
+            f"p99 {row['p99_ms']} ms, identical {row['equal_to_batch_search']}")
     return {"workload": f"mixed1m index ({prec} store, m={m} ef={ef} p={bp} tau=({ta}, {tb})), k={k}, "
                         f"serving range mix",
-            "max_batch": 4096, "inflight": 2, "rates": rows}
+            "max_batch": 4096, "inflight": 2, "rates": rows, "k100": k100}
 
 
 def batch100k(args, prec):

@@ -111,3 +111,25 @@ def test_concurrent_streams_equal_serial(c1):
     for o in outs:
         assert np.array_equal(o.cpu().numpy(), ref)
     g.close()
+
+
+def test_served_k100_equals_batch(c1):
+    """The serving workload's other result size: k = 100."""
+    W, ix, path = c1
+    torch = _torch()
+    import paper_2412_02448_amd as u
+    print("[case] serve k=100", flush=True)
+    g = u.Index.load(path, device=0)
+    dev = torch.device("cuda", 0)
+    n = 300
+    srv = u.Server(g, 100, 128, max_batch=64, inflight=2, m=16, beam_p=2)
+    arrive = np.sort(np.random.default_rng(2).uniform(0, 0.02, n))
+    ids, dist, lat = srv.wait(srv.submit(W.queries[:n], W.l[:n], W.h[:n], arrive_s=arrive), timeout_s=60)
+    srv.close()
+    ref = g.search(torch.from_numpy(W.queries[:n]).to(dev), torch.from_numpy(W.l[:n]).to(dev),
+                   torch.from_numpy(W.h[:n]).to(dev), 100, 128, m=16, beam_p=2)
+    assert np.array_equal(ids, ref[0].cpu().numpy())
+    assert np.array_equal(dist.view(np.uint32), ref[1].cpu().numpy().view(np.uint32))
+    oid, od = ix.search(W.queries[:n], W.l[:n], W.h[:n], 100, 128, m=16, p=2)
+    assert np.array_equal(oid, ids)
+    g.close()
