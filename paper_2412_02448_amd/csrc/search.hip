@@ -94,7 +94,7 @@ constexpr uint32_t HASH_EMPTY = 0xFFFFFFFFu;
 constexpr int WAVES_PER_SIMD_FP32 = 3, WAVES_PER_SIMD_LOW = 4, BF16_ROUNDS = 4;
 constexpr int PRE_NCH_MAX = 8;      // chunks per pre-filter scan at most
 constexpr int PLAN_SAMPLES = 2048;  // sorted attributes staged in LDS by the plan kernel
-constexpr int PRE_SPLIT_KMAX = 32;  // larger k scans its slice in one wavefront
+constexpr int PRE_SPLIT_KMAX = 128;  // larger k scans its slice in one wavefront
 
 // ---------------------------------------------------------------------------
 // Plan: the range becomes an id interval [lo, hi) (the skip-list walk of
@@ -1068,19 +1068,19 @@ __global__ void __launch_bounds__(64, NG > 4 ? 1 : (PREC == UNIFY_FP32 ? WAVES_P
 }
 
 // Outputs of the split pre-filter scans: one wavefront per query merges its
-// chunks' top-k lists (k <= 32) and writes the k results and the counters.
+// chunks' top-k lists (k <= PRE_SPLIT_KMAX) and writes the k results and the counters.
 __global__ void __launch_bounds__(256) k_pre_merge(DevIndex ix, const QPlan* __restrict__ plan, int64_t nq, int k,
                                                    const u64* __restrict__ part, const int32_t* __restrict__ qacc,
                                                    int64_t* __restrict__ out_ids, float* __restrict__ out_dist,
                                                    int32_t* __restrict__ out_stats) {
-  __shared__ u64 lists[4][WAVE];
+  __shared__ u64 lists[4][PRE_SPLIT_KMAX];
   const int lane = lane_id();
   const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (q >= nq) return;  // uniform per wavefront
   const QPlan P = plan[q];
   if (P.strat != UNIFY_PRE || P.nch <= 1) return;
   u64* lst = lists[threadIdx.x >> 6];
-  lst[lane] = KEY_MAX;
+  for (int t = lane; t < PRE_SPLIT_KMAX; t += WAVE) lst[t] = KEY_MAX;
   int al = 0;
   const u64* all = part + (int64_t)P.pbase * k;
   const int tot = P.nch * k;
@@ -1090,10 +1090,10 @@ __global__ void __launch_bounds__(256) k_pre_merge(DevIndex ix, const QPlan* __r
     const u64 T = al == k ? lst[k - 1] : KEY_MAX;
     list_insert(lst, al, k, key < T ? key : KEY_MAX);
   }
-  if (lane < k) {
-    const u64 key = lane < al ? lst[lane] : KEY_MAX;
-    out_ids[q * k + lane] = key != KEY_MAX ? ix.ext[key_id(key)] : -1;
-    out_dist[q * k + lane] = key != KEY_MAX ? key_dist(key) : __builtin_inff();
+  for (int t = lane; t < k; t += WAVE) {
+    const u64 key = t < al ? lst[t] : KEY_MAX;
+    out_ids[q * k + t] = key != KEY_MAX ? ix.ext[key_id(key)] : -1;
+    out_dist[q * k + t] = key != KEY_MAX ? key_dist(key) : __builtin_inff();
   }
   if (out_stats && lane == 0) {
     int32_t* st = out_stats + q * 8;

@@ -111,7 +111,7 @@ def test_parity_split_pre_filter(c1, chunk):
     """Pre-filter scans split into chunks on several wavefronts and merged."""
     W, ix, g = c1
     print(f"[case] split pre-filter chunk={chunk}", flush=True)
-    for k in (1, 10, 32, 33):
+    for k in (1, 10, 32, 33, 100, 128, 129):
         for strategy in (hsig.PRE, hsig.AUTO):
             ref = ix.search(W.queries, W.l, W.h, k, max(k, 40), strategy=strategy)
             got = gpu_search(g, W, k, max(k, 40), strategy=None if strategy == hsig.AUTO else strategy,
