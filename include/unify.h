@@ -83,8 +83,9 @@ typedef struct {
   int32_t rerank_mult;  /* BF16/FP8 stores: FP32 rerank of the best rerank_mult * k
                            graph results; default 4 */
   int32_t cand_cap;     /* on-chip candidate entries per query, a power of two in
-                           [64, 4096]; default 512.  Queries that need more are re-run
-                           with a larger array (same results). */
+                           [64, 4096]; default the larger of 512 and 8 * ef rounded up to
+                           a power of two.  Queries that need more are re-run with a
+                           larger array (same results). */
   double tau_a_frac;    /* tau_A = floor(tau_a_frac * n); default 0.01 (Sec. 6.2) */
   double tau_b_frac;    /* tau_B = ceil(tau_b_frac * n); default 0.5 (Sec. 6.2) */
   uint32_t flags;       /* UNIFY_FLAG_* bits, 0 for none */
@@ -92,7 +93,7 @@ typedef struct {
                            [256, 16384]; default 1024 for the FP32 store, 512 for BF16 /
                            FP8 (more wavefronts fit; larger visited sets spill to HBM,
                            same results) */
-  int32_t pre_chunk;    /* pre-filter scans with k <= 32 split their slice into chunks of
+  int32_t pre_chunk;    /* pre-filter scans with k <= 128 split their slice into chunks of
                            about this many objects (at most 8 chunks), scanned by different
                            wavefronts and merged exactly; default 2048, minimum 64 */
 } unify_params;

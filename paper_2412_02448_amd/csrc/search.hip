@@ -1185,7 +1185,12 @@ int resolve(unify_index_t ix, int64_t nq, int32_t k, int32_t ef, const unify_par
   R.p = P.beam_p > 0 ? P.beam_p : 1;
   const double ta = P.tau_a_frac > 0 ? P.tau_a_frac : 0.01;
   const double tb = P.tau_b_frac > 0 ? P.tau_b_frac : 0.5;
-  R.ccap = P.cand_cap > 0 ? P.cand_cap : 512;
+  // candidate array: 512 entries, or 8 ef rounded up to a power of two for longer lists (a
+  // hybrid search keeps out-of-range objects in it; at ef = 128, 512 entries sent 1.5% of the
+  // serving workload's queries to the larger-capacity re-run, which then ended the batch)
+  R.ccap = 512;
+  while (R.ccap < 8 * ef) R.ccap *= 2;
+  if (P.cand_cap > 0) R.ccap = P.cand_cap;
   R.hcap = P.visit_cap > 0 ? P.visit_cap : (dv.precision == UNIFY_FP32 ? 1024 : 512);
   R.rerank = P.rerank_mult > 0 ? P.rerank_mult : 4;
   R.pre_chunk = P.pre_chunk > 0 ? P.pre_chunk : 2048;
