@@ -21,12 +21,13 @@ def test_tuner_reports_true_recall(tmp_path):
     dev = torch.device("cuda", 0)
     Q, L, H = (torch.from_numpy(a).to(dev) for a in (W.queries, W.l, W.h))
     best, table = autotune.tune(g, Q, L, H, 10, 0.9, ms=(8, 16), efs=(16, 32, 64), ps=(1, 4),
-                                taus=((0.01, 0.5), (0.005, 0.3)), reps=2)
+                                taus=((0.01, 0.5), (0.005, 0.3)), pre_chunks=(64, 512), reps=2)
     assert best is not None and best.recall >= 0.9
     truth = autotune.exact_answers(g, Q, L, H, 10)
+    assert {s.pre_chunk for s in table} >= {64, 512}
     for s in table:
         ids, _, _ = g.search(Q, L, H, 10, s.ef, **dict(s.kwargs(), visit_cap=0))
         assert autotune.recall_at_k(ids.cpu().numpy(), truth) == pytest.approx(s.recall, abs=0)
-    ok = [s for s in table if s.recall >= 0.9 and s.qps > 0 and s.visit_cap == 0]
-    assert best.qps >= 0.98 * max(s.qps for s in ok) or best.visit_cap != 0
+    ok = [s for s in table if s.recall >= 0.9 and s.qps > 0 and s.visit_cap == 0 and s.pre_chunk == 0]
+    assert best.qps >= 0.98 * max(s.qps for s in ok) or best.visit_cap != 0 or best.pre_chunk != 0
     g.close()
