@@ -6,7 +6,8 @@ segments and M = 32 (built on the GPU), 10,000 queries from the same mixture
 with range fraction log-uniform in [1e-3, 1], k = 10.  One step = one search of
 the whole 10,000-query batch with the range-aware strategy (plan, pre-filter
 scans, hybrid and post-filter searches, FP32 rerank), inputs already resident
-in HBM.
+in HBM, run as one replay of the captured launch sequence (unify_batch_run); the
+same step through per-call launches (unify_search) is reported beside it.
 
 For each vector store (FP32, and BF16 / FP8 E4M3 copies ranked in low precision
 and re-scored in FP32), (m, ef, beam width) is tuned on 10,000 held-out queries
@@ -226,9 +227,25 @@ def main():
     log("recall@10 by ef: " + ", ".join(f"ef={e}: {r:.4f}" for e, r in recalls.items()))
 
     # ---- timed region of the headline: K steps of the whole path ----
-    sec, out = timed(m, ef, bp, ta=ta, tb=tb, vc=vc)
+    # A step is one replay of the captured launch sequence (plan, work list, search, merge,
+    # re-run) over the resident batch; the same step through per-call launches is reported
+    # beside it.
+    sec_eager, out_eager = timed(m, ef, bp, ta=ta, tb=tb, vc=vc)
+    batch = u.Batch(index, Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
+    for _ in range(args.warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t) / args.steps
+    out = (batch.ids, batch.dist)
+    same = bool(torch.equal(batch.ids, out_eager[0]))
+    batch.close()  # the output tensors stay
     qps = nq / sec
-    log(f"auto ({head}): {qps:,.0f} QPS ({sec * 1e3:.3f} ms/step)")
+    log(f"auto ({head}): {qps:,.0f} QPS ({sec * 1e3:.3f} ms/step) as a graph replay; "
+        f"{nq / sec_eager:,.0f} QPS ({sec_eager * 1e3:.3f} ms/step) through per-call launches; same ids {same}")
     per_strategy = {}
     for name, sv in (("pre", u.PRE), ("hybrid", u.HYBRID), ("post", u.POST)):
         s, o = timed(m, ef, bp, sv, steps=max(1, args.steps // 2 + 1), warmup=1, ta=ta, tb=tb, vc=vc)
@@ -335,6 +352,8 @@ def main():
                    "recall_by_ef": {str(e): round(r, 4) for e, r in recalls.items()},
                    "strategy_mix": {"pre": int(mix[1]), "hybrid": int(mix[2]), "post": int(mix[3])},
                    "build_s": round(build_s, 1)},
+        "eager": {"qps": round(nq / sec_eager, 1), "ms_per_step": round(sec_eager * 1e3, 4),
+                  "same_ids_as_graph": same},
         "by_precision": by_prec,
         "per_strategy": per_strategy,
         "hybrid_selection": selection,
