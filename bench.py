@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--no-insert", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--wide-n", type=int, default=250_000, help="objects of the 960-wide workload")
+    ap.add_argument("--wide-M", type=int, default=0, help="chunk capacity of the 960-wide index (0: the recipe's)")
     ap.add_argument("--cpu-queries", type=int, default=0, help="queries in the CPU sample (0: all)")
     return ap.parse_args()
 
@@ -377,7 +378,7 @@ def wide_bench(args):
     import paper_2412_02448_amd as u
     from paper_2412_02448_amd import autotune
     from synth import workloads as w
-    spec = w.scaled(w.SPECS["gist1m"], n=args.wide_n)
+    spec = w.scaled(w.SPECS["gist1m"], n=args.wide_n, **({"M": args.wide_M} if args.wide_M else {}))
     dev = torch.device("cuda", 0)
     t0 = time.time()
     W = w.make(spec, base_seed=0)
@@ -395,7 +396,8 @@ def wide_bench(args):
                        f"range fraction log-uniform [1e-3, 1], k={k}"}
     for prec in ("fp32", "bf16", "fp8"):
         index.set_precision(prec)
-        best, table = autotune.tune(index, Qc, Lc, Hc, k, args.recall_target, efs=(32, 64, 128))
+        best, table = autotune.tune(index, Qc, Lc, Hc, k, args.recall_target, efs=(32, 64, 128, 256),
+                                    ms=(index.M, (3 * index.M) // 2, 2 * index.M, 3 * index.M, 4 * index.M))
         if best is None:
             best = max(table, key=lambda s: s.recall)
         m, ef, bp, ta, tb, vc = best.m, best.ef, best.beam_p, best.tau_a, best.tau_b, best.visit_cap
