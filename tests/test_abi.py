@@ -76,3 +76,37 @@ def test_validate_rejects_out_of_range_edge(tmp_path):
     with pytest.raises(u.UnifyError) as e:
         u.validate_index_file(p)
     assert e.value.code == -74 and "adjacency" in str(e.value)
+
+
+def test_entry_points_reject_bad_arguments_on_the_host():
+    """Argument checks that run before any device call: every entry point answers a
+    null handle or an out-of-range size with UNIFY_EINVAL (-22) and a message, and the
+    free functions accept null."""
+    import ctypes as C
+
+    import paper_2412_02448_amd as u
+    lib = u.load_library()
+    EINVAL = -22
+    null = None
+    assert lib.unify_search(null, null, 1, null, null, 10, 10, null, null, null, null, null, null) == EINVAL
+    assert lib.unify_search_ex(null, null, 1, null, null, 10, 10, null, null, null, null, null, null, null) == EINVAL
+    assert lib.unify_search_multi(null, null, 1, null, null, null, null, 10, 10, null, null, null, null, null, null,
+                                  null) == EINVAL
+    assert lib.unify_insert(null, null, null, null, 5) == EINVAL
+    assert lib.unify_set_attr2(null, null, 5) == EINVAL
+    assert lib.unify_set_precision(null, 1) == EINVAL
+    assert lib.unify_index_info(null, null, null, null, null, null) == EINVAL
+    assert lib.unify_save_index(null, b"/nonexistent") == EINVAL
+    assert lib.unify_batch_run(null, null) == EINVAL
+    assert lib.unify_server_create(null, null, null) == EINVAL
+    assert lib.unify_server_submit(null, 1, null, null, null, null, null, null) == EINVAL
+    assert lib.unify_server_wait(null, 1, null, null, null, null, 1.0) == EINVAL
+    assert lib.unify_server_stats(null, null, null, null) == EINVAL
+    # the merge checks its sizes before launching anything
+    buf = (C.c_int64 * 4)()
+    assert lib.unify_merge_or(buf, buf, buf, buf, 1, 0, buf, buf, null) == EINVAL
+    assert lib.unify_merge_or(buf, buf, buf, buf, -1, 2, buf, buf, null) == EINVAL
+    assert lib.unify_merge_or(null, null, null, null, 0, 2, null, null, null) == 0  # nothing to merge
+    assert lib.unify_last_error()  # a message is left
+    for free in (lib.unify_free_index, lib.unify_batch_free, lib.unify_server_free):
+        assert free(null) == 0
