@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--wide-n", type=int, default=250_000, help="objects of the 960-wide workload")
     ap.add_argument("--wide-M", type=int, default=0, help="chunk capacity of the 960-wide index (0: the recipe's)")
+    ap.add_argument("--wide-efc", type=int, default=0, help="efCons of the 960-wide index (0: the recipe's)")
     ap.add_argument("--cpu-queries", type=int, default=0, help="queries in the CPU sample (0: all)")
     return ap.parse_args()
 
@@ -378,7 +379,12 @@ def wide_bench(args):
     import paper_2412_02448_amd as u
     from paper_2412_02448_amd import autotune
     from synth import workloads as w
-    spec = w.scaled(w.SPECS["gist1m"], n=args.wide_n, **({"M": args.wide_M} if args.wide_M else {}))
+    over = {}
+    if args.wide_M:
+        over["M"] = args.wide_M
+    if args.wide_efc:
+        over["ef_cons"] = args.wide_efc
+    spec = w.scaled(w.SPECS["gist1m"], n=args.wide_n, **over)
     dev = torch.device("cuda", 0)
     t0 = time.time()
     W = w.make(spec, base_seed=0)
@@ -392,7 +398,7 @@ def wide_bench(args):
     cq, cl, ch, _ = w.more_queries(spec, W.attr, 1000, base_seed=0, stream=1)
     Qc, Lc, Hc = (torch.from_numpy(a).to(dev) for a in (cq, cl, ch))
     out = {"workload": f"gist-like: n={spec.n} d={d} (512-centre mixture, sigma 0.2), attribute uniform in "
-                       f"[0, 2^31), HSIG S={spec.S} M={spec.M} built on GPU ({build_s:.0f}s); {nq} queries, "
+                       f"[0, 2^31), HSIG S={spec.S} M={spec.M} efCons={spec.ef_cons} built on GPU ({build_s:.0f}s); {nq} queries, "
                        f"range fraction log-uniform [1e-3, 1], k={k}"}
     for prec in ("fp32", "bf16", "fp8"):
         index.set_precision(prec)

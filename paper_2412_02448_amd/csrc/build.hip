@@ -41,7 +41,7 @@ namespace {
 constexpr int KT_R = 128;  // rows per candidate block
 constexpr int KT_C = 64;   // candidate columns per tile
 constexpr int KT_D = 64;   // dimensions per staged slice
-constexpr int KC = 128;    // candidate list capacity per (object, segment)
+constexpr int KC = 256;    // candidate list capacity per (object, segment): efCons up to 256
 constexpr int CAPR = 256;  // nearest candidates kept before a prune
 
 __global__ void b_gather(const float* __restrict__ X, int d, const int32_t* __restrict__ nodes, int64_t nl,
