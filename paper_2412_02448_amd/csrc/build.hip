@@ -10,7 +10,7 @@
 // This builder produces the same structure for all objects at once, layer by
 // layer:
 //   1. candidates: the exact K nearest objects of segment j for every object
-//      (one tiled distance pass per segment, K = min(efCons, 128));
+//      (one tiled distance pass per segment, K = min(efCons, 256));
 //   2. forward chunks: Prune(v, candidates, M);
 //   3. reverse edges: every forward edge v -> o (v in segment i) offers v to
 //      chunk i of o; a chunk that then holds more than M objects is re-pruned;
