@@ -194,13 +194,13 @@ def main():
         torch.cuda.synchronize()
         pre_ms, search_ms, rerun_ms = index.last_timing()
         st = stats.cpu().numpy().astype(np.int64)
-        first = st[:, 3] == 0
+        first = (st[:, 3] & 0xFF) == 0
         bts = int(bytes_per_query(st, d, k, prec)[first].sum())
         by_prec[prec] = {
             "qps": round(nq / sec, 1), "ms_per_step": round(sec * 1e3, 4), "recall@10": round(rec, 4),
             "m": m, "ef": ef, "beam_p": bp, "tau_a": ta, "tau_b": tb, "visit_cap": vc, "search_launch_ms": round(search_ms, 4),
             "plan_ms": round(pre_ms, 4), "rerun_launch_ms": round(rerun_ms, 4),
-            "rerun_queries": int((st[:, 3] == 1).sum()), "failed_queries": int((st[:, 3] == 2).sum()),
+            "rerun_queries": int(((st[:, 3] & 0xFF) == 1).sum()), "failed_queries": int(((st[:, 3] & 0xFF) == 2).sum()),
             "bytes_per_launch": bts, "achieved_GBps": round(bts / (search_ms * 1e-3) / 1e9, 1),
             "fp32_rescores_per_query": round(float(st[:, 2].mean()), 2),
             "same_ids_as_stats_call": bool((ids == out[0]).all().item()),
@@ -270,7 +270,7 @@ def main():
     torch.cuda.synchronize()
     pre_ms, search_ms, rerun_ms = index.last_timing()
     st = stats.cpu().numpy().astype(np.int64)
-    first = st[:, 3] == 0
+    first = (st[:, 3] & 0xFF) == 0
     bytes_first = int(bytes_per_query(st, d, k, head)[first].sum())
     achieved = bytes_first / (search_ms * 1e-3) / 1e9
     mix = np.bincount(np.maximum(st[:, 5], 0), minlength=4)
@@ -279,7 +279,7 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(head, m, ef, bp, ta, tb, vc), "bytes_per_launch": bytes_first,
                 "launch_ms": round(search_ms, 4), "rerun_launch_ms": round(rerun_ms, 4),
-                "rerun_queries": int((st[:, 3] == 1).sum()), "failed_queries": int((st[:, 3] == 2).sum())}
+                "rerun_queries": int(((st[:, 3] & 0xFF) == 1).sum()), "failed_queries": int(((st[:, 3] & 0xFF) == 2).sum())}
     ids_np = ids.cpu().numpy()
     for sname, sv in (("pre", 1), ("hybrid", 2), ("post", 3)):
         sel = np.nonzero(st[:, 5] == sv)[0]
@@ -419,7 +419,7 @@ def wide_bench(args):
         torch.cuda.synchronize()
         search_ms = index.last_timing()[1]
         st = st.cpu().numpy().astype(np.int64)
-        b = int(bytes_per_query(st, d, k, prec)[st[:, 3] == 0].sum())
+        b = int(bytes_per_query(st, d, k, prec)[(st[:, 3] & 0xFF) == 0].sum())
         ids = o[0].cpu().numpy()
         rec = float(np.mean([len(set(ids[i][ids[i] >= 0]) & set(truth[i][truth[i] >= 0]))
                              / max(1, (truth[i] >= 0).sum()) if (truth[i] >= 0).any() else 1.0
@@ -784,7 +784,7 @@ def profile_run(args, index, Q, L, H, k, spec, nq, build_s, prec):
     torch.cuda.synchronize()
     pre_ms, search_ms, rerun_ms = index.last_timing()
     st = stats.cpu().numpy().astype(np.int64)
-    b = int(bytes_per_query(st, spec.d, k, prec)[st[:, 3] == 0].sum())
+    b = int(bytes_per_query(st, spec.d, k, prec)[(st[:, 3] & 0xFF) == 0].sum())
     print(json.dumps({"profile_run": True, "store": prec, "m": m, "ef": ef, "beam_p": bp, "tau_a": ta, "tau_b": tb,
                       "visit_cap": vc, "qps": round(nq / sec, 1),
                       "ms_per_step": round(sec * 1e3, 4), "search_launch_ms": round(search_ms, 4),

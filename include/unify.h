@@ -75,20 +75,23 @@ enum {
                                m nearest, instead of the first ceil(m / S') of each chunk (S2) */
 };
 
-/* Search parameters.  Zero in a field selects its default. */
+/* Search parameters.  Zero in a field selects its default.  The first six fields
+ * are the search's own parameters (m and the strategy thresholds of Sec. 4.2 and
+ * Sec. 5.2, plus the beam width and rerank depth of this implementation); the
+ * fields after `flags` size on-chip structures and never change a result. */
 typedef struct {
   int32_t m;            /* neighbours examined per expansion in the hybrid search,
                            ceil(m / S') from each active chunk (Sec. 4.2); default M0 */
   int32_t beam_p;       /* candidates expanded together per step, 1..8; default 1 (= Alg. 7) */
   int32_t rerank_mult;  /* BF16/FP8 stores: FP32 rerank of the best rerank_mult * k
                            graph results; default 4 */
+  double tau_a_frac;    /* tau_A = floor(tau_a_frac * n); default 0.01 (Sec. 5.2) */
+  double tau_b_frac;    /* tau_B = ceil(tau_b_frac * n); default 0.5 (Sec. 5.2) */
+  uint32_t flags;       /* UNIFY_FLAG_* bits, 0 for none */
   int32_t cand_cap;     /* on-chip candidate entries per query, a power of two in
                            [64, 4096]; default the larger of 512 and 8 * ef rounded up to
                            a power of two.  Queries that need more are re-run with a
                            larger array (same results). */
-  double tau_a_frac;    /* tau_A = floor(tau_a_frac * n); default 0.01 (Sec. 6.2) */
-  double tau_b_frac;    /* tau_B = ceil(tau_b_frac * n); default 0.5 (Sec. 6.2) */
-  uint32_t flags;       /* UNIFY_FLAG_* bits, 0 for none */
   int32_t visit_cap;    /* on-chip visited-cache entries per query, a power of two in
                            [256, 16384]; default 1024 for the FP32 store, 512 for BF16 /
                            FP8 (more wavefronts fit; larger visited sets spill to HBM,
@@ -99,8 +102,11 @@ typedef struct {
 } unify_params;
 
 /*
- * Reads an index file (format: little-endian; see the package documentation) and
- * makes it resident on HIP device `device`.  precision selects the store the graph
+ * Reads an index file holding an HSIG as Sec. 4.1 lays it out (per layer, one
+ * chunk of at most M neighbours per segment for every object; the global-edge
+ * bitmap of Alg. 5; objects in attribute order, the order the layer-0 skip list
+ * walks) and makes it resident on HIP device `device`.  File format:
+ * little-endian, see the package documentation.  precision selects the store the graph
  * searches read (UNIFY_FP32, UNIFY_BF16, UNIFY_FP8E4M3); the FP32 store is always
  * resident for the pre-filter scan and the rerank.  The file's tables are checked
  * (checksum, sizes, every adjacency entry in range); on any failure *out is left
@@ -157,7 +163,10 @@ int unify_validate_index_file(const char* path, int64_t* n, int32_t* d, int32_t*
 /* Writes a resident index to `path` in the index file format. */
 int unify_save_index(unify_index_t index, const char* path);
 
-/* Sizes of a resident index (host outputs; any may be NULL).  levels = top layer + 1. */
+/* Sizes of a resident index (host outputs; any may be NULL), in the notation of
+ * Sec. 4.1 and Table 1: n objects of dimension d, S segments, chunk capacity M,
+ * levels = top layer + 1 (the layer count of the hierarchy, Alg. 6's L + 1).
+ * UNIFY_EINVAL for a null index. */
 int unify_index_info(unify_index_t index, int64_t* n, int32_t* d, int32_t* S, int32_t* M,
                      int32_t* levels);
 
@@ -169,11 +178,14 @@ int unify_index_info(unify_index_t index, int64_t* n, int32_t* d, int32_t* S, in
  *   ef            result-list size of the graph searches; k <= ef <= 256 when any
  *                 query runs the hybrid or post-filter search
  *   strategy      device, [nq] int8 per-query strategy (UNIFY_AUTO .. UNIFY_POST),
- *                 or NULL for UNIFY_AUTO on every query
+ *                 or NULL for UNIFY_AUTO on every query.  The values are read on the
+ *                 device, so an unknown one cannot fail the call: its row is padded
+ *                 and out_strategy reports -2 for it
  *   params        host, or NULL for defaults
  *   out_ids       device, [nq][k] int64
  *   out_dist      device, [nq][k] float32
- *   out_strategy  device, [nq] int8 strategy actually run, or NULL
+ *   out_strategy  device, [nq] int8 strategy actually run (-1: empty range, -2:
+ *                 unknown requested strategy), or NULL
  *   hip_stream    hipStream_t to enqueue on, or NULL
  * nq = 0 is a no-op.  Scratch space is allocated by the library per call.
  * Calls may come from several threads and streams: the search kernels of
@@ -188,13 +200,16 @@ int unify_search(unify_index_t index, const float* queries, int64_t nq, const in
 /*
  * unify_search plus per-query counters:
  *   out_stats  device, [nq][8] int32: [0] distance evaluations, [1] expansions,
- *              [2] FP32 re-scores of a BF16 / FP8 search, [3] status (0 = answered
- *              in the first search pass, 1 = re-run: with larger on-chip lists for a
- *              graph search, by the FP32 scan for a low-precision pre-filter scan whose
- *              bounds could not settle the result, 2 = capacity exceeded even then: the
- *              row is padded), [4] adjacency entries read, [5] strategy run (-1 for an
- *              empty range), [6] Y = objects in range, [7] active segments (hybrid only,
- *              else 0).
+ *              [2] FP32 re-scores of a BF16 / FP8 search, [3] status in bits 0-7
+ *              (0 = answered in the first search pass, 1 = re-run: with larger on-chip
+ *              lists for a graph search, by the FP32 scan for a low-precision pre-filter
+ *              scan whose bounds could not settle the result, 2 = capacity exceeded even
+ *              then: the row is padded, 3 = the requested strategy is not one of
+ *              UNIFY_AUTO..UNIFY_POST: the row is padded) and flag bits above: bit 8 =
+ *              a layer search's visited set outgrew the on-chip cache and continued in
+ *              HBM (same results), [4] adjacency entries read, [5] strategy run (-1 for
+ *              an empty range, -2 for an unknown requested strategy), [6] Y = objects in
+ *              range, [7] active segments (hybrid only, else 0).
  */
 int unify_search_ex(unify_index_t index, const float* queries, int64_t nq, const int64_t* l,
                     const int64_t* h, int32_t k, int32_t ef, const int8_t* strategy,
@@ -332,7 +347,11 @@ int unify_server_stats(unify_server_t server, int64_t* completed, int64_t* batch
 /* Serves every submitted request, stops the worker and frees the server (NULL accepted). */
 int unify_server_free(unify_server_t server);
 
-/* Frees the index and its device memory.  NULL is accepted. */
+/* Frees an index returned by unify_load_index or unify_build_index and all device
+ * memory it holds (tables, low-precision copies, visited-set memory).  Waits for the
+ * searches enqueued on it.  Batches and servers over it must be freed first.  Not a
+ * step of the method: the handle's lifetime under the ownership rule above.  NULL is
+ * accepted. */
 int unify_free_index(unify_index_t index);
 
 /* Message of the last failure on the calling thread (never NULL). */

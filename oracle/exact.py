@@ -6,7 +6,7 @@ The plain definitions the search approximates, in FP64:
   return the k objects of R nearest to q, all of R when |R| < k.  Ties in
   distance are broken by the smaller identifier (the definition's strict "<"
   leaves tied sets open); squared Euclidean distance gives the same order as
-  Euclidean distance (Sec. 6.1).
+  Euclidean distance (Sec. 5.1).
 * recall (Eq. 1): |kNN' intersect kNN| / min(k, |R|); 1 when R is empty.
 
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark may

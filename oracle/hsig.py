@@ -19,7 +19,7 @@ _LIB = os.path.join(_HERE, "liboracle_hsig.so")
 
 AUTO, PRE, HYBRID, POST = 0, 1, 2, 3
 # per-query counters written by search(): see the C_* enum in hsig_ref.cpp
-NDIST, NEXP, NVISIT0, MAXCAND, MAXLIVE, STRAT, LO, HI, NRERANK, NCOUNT = range(10)
+NDIST, NEXP, NVISIT0, MAXCAND, MAXLIVE, STRAT, LO, HI, NRERANK, ENTRY, NCOUNT = range(11)
 FP32, BF16, FP8E4M3 = 0, 1, 2
 
 

@@ -62,16 +62,23 @@
 // Pins (tests/test_oracle_*.py): Definition 1 and Eq. 1 by hand examples and a
 // library routine; dist32 by exact integer cases, a crafted rounding case and
 // the FP64 error bound; the level law P(level >= l) = M^-l; Prune by hand-built
-// cases; Example 2's segments; S = 1 HSIG = HNSW (Alg. 3) edge for edge;
-// single-segment inclusiveness = 1 and > 80% on 1..8 segments (Sec. 6.4);
-// layer search with ef >= n = brute force over the reachable set; pre-filter =
-// exact k-NN; the skip-list walk = the attribute slice; the beam form at p = 1
-// = the sequential loop; the BF16 and E4M3 roundings against a library's
-// conversions, every E4M3 code's value, and a low-precision search on vectors
-// both formats hold exactly = the FP32 search.  Parity unpinned: the exact set of global-edge marks
-// that GlobalEdgeMasking leaves (only its invariants are checked: at most M
-// marks per node and layer, each mark an existing chunk edge), and the exact
-// graph the full build produces on realistic inputs (no printed graph exists).
+// cases; Example 2's segments; the S = 1 build against an independent HNSW
+// (Alg. 1 and Alg. 3 written separately in the tests) edge for edge; a
+// six-object, two-segment build traced by hand through Alg. 4-6 (forward and
+// reverse edges, the re-prune of an overflowing chunk, every global-edge mark,
+// a mark dropped with its edge); the whole build (chunks, marks, entries)
+// against an independent HSIGInsert on integer grids full of distance ties; the
+// hybrid entry rule on an index whose two segments share the top level;
+// single-segment inclusiveness = 1 and > 80% on 1..8 segments (Sec. 5.4);
+// Theorem 1 on this code's exact range search; layer search with ef >= n =
+// brute force over the reachable set; pre-filter = exact k-NN; the skip-list
+// walk = the attribute slice; the beam form at p = 1 = the sequential loop; the
+// BF16 and E4M3 roundings against a library's conversions, every E4M3 code's
+// value, and a low-precision search on vectors both formats hold exactly = the
+// FP32 search.  Parity unpinned: none of the build's steps; the graphs of the
+// large synthetic workloads are checked only by invariants and recall (no
+// printed graph exists), which is enough for search parity because the GPU and
+// this code search the same file.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -91,7 +98,7 @@ typedef std::pair<float, int> FI;   // (FP32 distance, internal id): search-side
 // Distances
 // ---------------------------------------------------------------------------
 
-// Squared Euclidean distance in FP64 (the paper uses Euclidean distance, Sec. 6.1).
+// Squared Euclidean distance in FP64 (the paper uses Euclidean distance, Sec. 5.1).
 double dist64(const float* a, const float* b, int d) {
   double s = 0.0;
   for (int t = 0; t < d; ++t) {
@@ -126,7 +133,7 @@ float dist32(const float* q, const float* x, int d) {
 
 // ---------------------------------------------------------------------------
 // Low-precision copies of the vectors (an extension for bandwidth-bound
-// hardware; the paper computes plain Euclidean distances, Sec. 6.1).  A graph
+// hardware; the paper computes plain Euclidean distances, Sec. 5.1).  A graph
 // search may rank objects by distances to rounded copies and then re-score its
 // best results with the exact FP32 distance.  Each rounding below is written as
 // "pick the nearest representable value" over the format's value set, which is
@@ -526,7 +533,7 @@ struct View {
   std::vector<float> XS;
   int rerank = 0;
   // A second attribute per object (internal order; empty when not set) for
-  // conjunctive two-attribute queries (Sec. 6.5's extension, approach 1).
+  // conjunctive two-attribute queries (the multi-attribute discussion of Sec. 5.9, approach 1).
   std::vector<int64_t> attr2;
   // sorted sample of attr2 for the strategy rule: the value at rank floor(j n / ns)
   // of the sorted attr2, j < ns = min(n, 2048)
@@ -809,7 +816,7 @@ int read_view(const char* path, View& V) {
 // ---------------------------------------------------------------------------
 
 enum { ST_AUTO = 0, ST_PRE = 1, ST_HYBRID = 2, ST_POST = 3 };
-enum { C_NDIST = 0, C_NEXP, C_NVISIT0, C_MAXCAND, C_MAXLIVE, C_STRAT, C_LO, C_HI, C_NRERANK, C_NCOUNT };
+enum { C_NDIST = 0, C_NEXP, C_NVISIT0, C_MAXCAND, C_MAXLIVE, C_STRAT, C_LO, C_HI, C_NRERANK, C_ENTRY, C_NCOUNT };
 
 struct Query {
   const View* V;
@@ -1032,6 +1039,7 @@ struct Searcher {
       if (best.second < 0 || kj < best) best = kj;
     }
     int ep = best.second;
+    Q.cnt[C_ENTRY] = ep;  // the entry the rule chose (internal id), for the tests
     for (int l = top; l >= 1; --l) ep = layer_seq(Q, true, false, ep, l, 1, stamp, cur)[0].second;
     std::vector<FI> ann = (p == 1 && !batch_form) ? layer_seq(Q, true, true, ep, 0, ef, stamp, cur)
                                                   : layer_beam(Q, true, true, ep, ef, p, stamp, cur);
@@ -1305,6 +1313,7 @@ int orc_search(void* h, const float* Q, int64_t nq, const int64_t* L, const int6
   for (int64_t i = 0; i < nq; ++i) {
     int64_t* cnt = counters ? counters + i * C_NCOUNT : dummy.data();
     for (int t = 0; t < C_NCOUNT; ++t) cnt[t] = 0;
+    cnt[C_ENTRY] = -1;
     Query qq;
     qq.V = &V;
     qq.q = Q + (size_t)i * V.d;

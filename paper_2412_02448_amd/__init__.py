@@ -36,9 +36,15 @@ class UnifyError(RuntimeError):
 
 
 class _Params(C.Structure):
-    _fields_ = [("m", C.c_int32), ("beam_p", C.c_int32), ("rerank_mult", C.c_int32), ("cand_cap", C.c_int32),
+    _fields_ = [("m", C.c_int32), ("beam_p", C.c_int32), ("rerank_mult", C.c_int32),
                 ("tau_a_frac", C.c_double), ("tau_b_frac", C.c_double), ("flags", C.c_uint32),
-                ("visit_cap", C.c_int32), ("pre_chunk", C.c_int32)]
+                ("cand_cap", C.c_int32), ("visit_cap", C.c_int32), ("pre_chunk", C.c_int32)]
+
+
+def _params(m=0, beam_p=0, rerank_mult=0, tau_a=0.0, tau_b=0.0, flags=0, cand_cap=0, visit_cap=0,
+            pre_chunk=0) -> _Params:
+    return _Params(m=m, beam_p=beam_p, rerank_mult=rerank_mult, tau_a_frac=tau_a, tau_b_frac=tau_b, flags=flags,
+                   cand_cap=cand_cap, visit_cap=visit_cap, pre_chunk=pre_chunk)
 
 
 _lib = None
@@ -265,7 +271,7 @@ class Index:
         else:
             ids, dist, ost, sts = out
         flags = (FLAG_TIMING if timing else 0) | (FLAG_SELECT_S1 if select_s1 else 0)
-        prm = _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, flags, visit_cap, pre_chunk)
+        prm = _params(m, beam_p, rerank_mult, tau_a, tau_b, flags, cand_cap, visit_cap, pre_chunk)
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         lib = load_library()
         if (l2 is None) != (h2 is None):
@@ -313,7 +319,7 @@ class Batch:
         self.dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
         self.strategy_run = torch.empty((nq,), dtype=torch.int8, device=dev)
         self.stats = torch.empty((nq, 8), dtype=torch.int32, device=dev) if stats else None
-        prm = _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, FLAG_SELECT_S1 if select_s1 else 0, visit_cap,
+        prm = _params(m, beam_p, rerank_mult, tau_a, tau_b, FLAG_SELECT_S1 if select_s1 else 0, cand_cap, visit_cap,
                       pre_chunk)
         torch.cuda.synchronize(dev)  # the tensors above exist before the capture reads their addresses
         self._b = C.c_void_p()
@@ -355,7 +361,7 @@ class Server:
         self.index, self.k = index, k
         flags = FLAG_SELECT_S1 if select_s1 else 0
         cfg = _ServerConfig(k, ef, max_batch, inflight, max_wait_s,
-                            _Params(m, beam_p, rerank_mult, cand_cap, tau_a, tau_b, flags, visit_cap, pre_chunk))
+                            _params(m, beam_p, rerank_mult, tau_a, tau_b, flags, cand_cap, visit_cap, pre_chunk))
         self._s = C.c_void_p()
         _check(load_library().unify_server_create(index._h, C.byref(cfg), C.byref(self._s)))
 

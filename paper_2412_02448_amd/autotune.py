@@ -1,6 +1,6 @@
 """Search-parameter tuning for a resident index.
 
-The paper sets its search parameters by sweeping them (Sec. 6.6: ef and m trade
+The paper sets its search parameters by sweeping them (Sec. 5.7: ef and m trade
 recall for speed; Sec. 4.2: tau_A and tau_B come from sample queries).  This
 tuner does the same on the GPU: for sample queries with known exact answers
 (the pre-filter scan forced on every sample query gives them), it measures

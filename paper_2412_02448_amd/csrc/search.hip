@@ -95,6 +95,8 @@ constexpr int WAVES_PER_SIMD_FP32 = 3, WAVES_PER_SIMD_LOW = 4, BF16_ROUNDS = 4;
 constexpr int PRE_NCH_MAX = 8;      // chunks per pre-filter scan at most
 constexpr int PLAN_SAMPLES = 2048;  // sorted attributes staged in LDS by the plan kernel
 constexpr int PRE_SPLIT_KMAX = 128;  // larger k scans its slice in one wavefront
+constexpr int STRAT_INVALID = -2;    // out_strategy of a row whose requested strategy is unknown
+constexpr int STATUS_INVALID = 3;    // its status counter
 
 // ---------------------------------------------------------------------------
 // Plan: the range becomes an id interval [lo, hi) (the skip-list walk of
@@ -149,9 +151,12 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
     hi = b0 + upper_bound_i64(ix.attr + b0, b1 - b0, hq);
     if (hi < lo) hi = lo;
   }
-  const int64_t Y = hi - lo;
+  int64_t Y = hi - lo;
   int s = strat_in ? (int)strat_in[q] : UNIFY_AUTO;
-  if (s < UNIFY_AUTO || s > UNIFY_POST) s = UNIFY_AUTO;
+  // a strategy outside AUTO..POST is not run: the row is padded and reported as
+  // strategy STRAT_INVALID with status 3
+  const bool bad = s < UNIFY_AUTO || s > UNIFY_POST;
+  if (bad) Y = 0;
   if (s == UNIFY_AUTO) {
     if (l2 && ix.n2s > 0) {
       // conjunctive query: the objects passing both ranges are estimated as Y times the
@@ -189,10 +194,14 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
     }
     if (out_stats) {
       for (int t = 0; t < 8; ++t) out_stats[q * 8 + t] = 0;
+      if (bad) {
+        out_stats[q * 8 + 3] = STATUS_INVALID;
+        out_stats[q * 8 + 5] = STRAT_INVALID;
+      }
     }
   }
   plan[q] = P;
-  if (out_strat) out_strat[q] = (int8_t)s;
+  if (out_strat) out_strat[q] = (int8_t)(bad ? STRAT_INVALID : s);
 }
 
 // Work list, longest work first so that the persistent waves finish together:
@@ -448,7 +457,9 @@ __device__ __forceinline__ void wave_fence() {
 
 struct Counters {
   int32_t ndist = 0, nexp = 0, nrerank = 0, nadj = 0;
+  int32_t spill = 0;  // a layer search's visited set left the LDS cache for the HBM tag row
 };
+constexpr int32_t STAT_SPILL_BIT = 0x100;  // status counter flag: the visited set spilled to HBM
 
 // One layer of the search (Alg. 1 / Alg. 7 with beam width p).  On return, the
 // ann list holds `al` keys ascending.  Returns false on capacity overflow.
@@ -665,6 +676,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
     }
     if (overflow) break;
   }
+  if (tagged) cnt.spill = 1;
   return !__any(overflow);
 }
 
@@ -1029,7 +1041,7 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
     st[0] = cnt.ndist;
     st[1] = cnt.nexp;
     st[2] = cnt.nrerank;
-    st[3] = ok ? status : 2;
+    st[3] = (ok ? status : 2) | (cnt.spill ? STAT_SPILL_BIT : 0);
     st[4] = cnt.nadj;
     st[5] = P.strat;
     st[6] = P.hi - P.lo;

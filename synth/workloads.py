@@ -5,8 +5,8 @@ query ranges and the uniform variates an index build consumes.  It holds none
 of the search or build arithmetic, so both the oracle and the HIP path can use
 it without sharing any of the method.
 
-Shapes follow the paper's workloads (Section 6.1, Table 1: SIFT1M-like 1M x 128,
-GIST1M-like 1M x 960; Section 6.7: the 10M scalability point).  The real
+Shapes follow the paper's workloads (Section 5.1, Table 1: SIFT1M-like 1M x 128,
+GIST1M-like 1M x 960; Section 5.8: the 10M scalability point).  The real
 datasets are not available; Gaussian mixtures stand in for them:
 
 * centres ~ N(0, I_d), mixture weights uniform, point = centre + sigma * N(0, I_d);

@@ -110,3 +110,26 @@ def test_entry_points_reject_bad_arguments_on_the_host():
     assert lib.unify_last_error()  # a message is left
     for free in (lib.unify_free_index, lib.unify_batch_free, lib.unify_server_free):
         assert free(null) == 0
+
+
+def test_params_struct_matches_header():
+    """The binding's parameter struct has the header's fields in the header's order, and
+    the search's own parameters (m, beam width, rerank depth, the two strategy thresholds,
+    flags) come first, so a caller compiled against that six-field prefix keeps working."""
+    import ctypes as C
+
+    import paper_2412_02448_amd as u
+    src = open(os.path.join(ROOT, "include", "unify.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{(.*?)\} unify_params;", src, flags=re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        typ, names = decl.split(None, 1)
+        fields += [(n.strip(), typ) for n in names.split(",")]
+    ctype = {"int32_t": C.c_int32, "uint32_t": C.c_uint32, "double": C.c_double}
+    assert [(n, ctype[t]) for n, t in fields] == list(u._Params._fields_)
+    assert [n for n, _ in fields[:6]] == ["m", "beam_p", "rerank_mult", "tau_a_frac", "tau_b_frac", "flags"]
+    assert u._Params.tau_a_frac.offset == 16 and u._Params.flags.offset == 32

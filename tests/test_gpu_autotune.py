@@ -1,4 +1,4 @@
-"""The search-parameter tuner (Sec. 6.6's sweep, Sec. 4.2's thresholds from
+"""The search-parameter tuner (Sec. 5.7's sweep, Sec. 4.2's thresholds from
 sample queries): every setting it reports carries the recall that setting
 actually reaches (beam width included), and the one it returns is the fastest
 of those meeting the target, up to its 2% tie rule."""

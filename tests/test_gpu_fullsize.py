@@ -53,7 +53,7 @@ def test_sampled_queries_equal_oracle(full):
     sample = np.arange(0, len(W.queries), 37)
     rid, rd, rc = ref.search(W.queries[sample], W.l[sample], W.h[sample], 10, 16, m=64, p=4, tau_a=0.01,
                              tau_b=0.5, counters=True)
-    assert (st[:, 3] != 2).all()
+    assert ((st[:, 3] & 0xFF) != 2).all()
     assert np.array_equal(strat[sample].astype(np.int64), rc[:, hsig.STRAT])
     assert np.array_equal(ids[sample], rid)
     assert np.array_equal(dist[sample].view(np.uint32), rd.view(np.uint32))

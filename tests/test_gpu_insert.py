@@ -90,7 +90,7 @@ def test_parity_on_grown_index(grown, strategy):
     ids, dist, _, st = g.search(Q, L, H, 10, 48, beam_p=2, strategy=None if strategy == hsig.AUTO else strategy,
                                 stats=True)
     torch.cuda.synchronize()
-    assert (st.cpu().numpy()[:, 3] != 2).all()
+    assert ((st.cpu().numpy()[:, 3] & 0xFF) != 2).all()
     assert np.array_equal(ids.cpu().numpy(), rid)
     assert np.array_equal(dist.cpu().numpy().view(np.uint32), rd.view(np.uint32))
 

@@ -52,7 +52,7 @@ def test_parity_conjunctive(c1, precision, strategy):
             ids, dist, srun, st = g.search(Q, L, H, 10, ef, beam_p=p, strategy=None if strategy == hsig.AUTO else strategy,
                                         stats=True, pre_chunk=chunk, l2=L2, h2=H2)
             torch.cuda.synchronize()
-            assert (st.cpu().numpy()[:, 3] != 2).all()
+            assert ((st.cpu().numpy()[:, 3] & 0xFF) != 2).all()
             assert np.array_equal(srun.cpu().numpy().astype(np.int64), rc[:, hsig.STRAT])
             gid, gd = ids.cpu().numpy(), dist.cpu().numpy()
             bad = np.nonzero((gid != rid).any(1) | (gd.view(np.uint32) != rd.view(np.uint32)).any(1))[0]

@@ -157,7 +157,7 @@ def test_edge_cases(small_index, small_workload):
 
 
 def test_recall_grows_with_ef(small_index, small_workload):
-    # Sec. 6.6: recall rises with ef (m fixed); here averaged over all queries.
+    # Sec. 5.7: recall rises with ef (m fixed); here averaged over all queries.
     W = small_workload
     rec = []
     for ef in (10, 20, 40, 80):
