@@ -1,7 +1,8 @@
 """Parity at the benchmark's full size: the 1M x 128 mixed-range workload, the
 GPU-built index, the benchmark's launch configuration (10,000 queries in one
 call, BF16 store, m = 64, ef = 16, p = 4, tau = (0.01, 0.5), split pre-filter
-scans; per-call launches and graph replays give the same rows) -- against the oracle on a sample of the queries (the oracle reads the
+scans; per-call launches and graph replays give the same rows; the FP32 and FP8
+stores at their own settings) -- against the oracle on a sample of the queries (the oracle reads the
 same index file and searches those queries one by one), and against properties
 that hold for every query at any size: pre-filter rows equal the exact answer,
 every returned object is in range with its exact FP32 distance, rows ascend."""
@@ -14,6 +15,10 @@ pytestmark = pytest.mark.gpu
 
 from oracle import hsig
 from synth import workloads as w
+
+
+# store -> the search setting the benchmark tunes for it on this workload
+STORES = {"fp32": dict(m=96, beam_p=8, tau_a=0.005, tau_b=0.3), "fp8": dict(m=64, beam_p=4, tau_a=0.01, tau_b=0.5)}
 
 
 @pytest.fixture(scope="module")
@@ -38,6 +43,14 @@ def full(tmp_path_factory):
         assert np.array_equal(b.ids.cpu().numpy(), out[0])
         assert np.array_equal(b.dist.cpu().numpy().view(np.uint32), out[1].view(np.uint32))
     b.close()
+    # the FP32 and FP8 stores at their own benchmark settings
+    others = {}
+    for name, kw in STORES.items():
+        g.set_precision(name)
+        res = g.search(Q, L, H, 10, 16, stats=True, **kw)
+        torch.cuda.synchronize()
+        others[name] = [t.cpu().numpy() for t in res]
+    out.append(others)
     path = str(tmp_path_factory.mktemp("full") / "mixed1m.uix")
     print("[fixture] saving the index for the oracle", flush=True)
     g.save(path)
@@ -46,7 +59,7 @@ def full(tmp_path_factory):
 
 
 def test_sampled_queries_equal_oracle(full):
-    W, (ids, dist, strat, st), path = full
+    W, (ids, dist, strat, st, _), path = full
     print("[case] oracle reads the 1M index", flush=True)
     ref = hsig.Index.read(path)
     ref.set_store(hsig.BF16, 4)
@@ -62,7 +75,7 @@ def test_sampled_queries_equal_oracle(full):
 
 
 def test_properties_of_every_row(full):
-    W, (ids, dist, strat, st), path = full
+    W, (ids, dist, strat, st, _), path = full
     order = np.lexsort((np.arange(len(W.attr)), W.attr))
     srt = W.attr[order]
     for i in range(len(W.queries)):
@@ -82,3 +95,24 @@ def test_properties_of_every_row(full):
             # the same set unless the 10th and 11th exact distances tie within FP32 rounding
             if len(o) <= 10 or dd[o[10]] - dd[o[9]] > 1e-5 * dd[o[10]]:
                 assert sorted(row.tolist()) == sorted(top.tolist()), i
+
+
+@pytest.mark.parametrize("name", list(STORES))
+def test_sampled_queries_equal_oracle_other_stores(full, name):
+    """The FP32 store (the parity target of the plain search) and the FP8 store on the
+    same 1M index and sample, each at its benchmark setting."""
+    W, (*_, others), path = full
+    ids, dist, strat, st = others[name]
+    kw = STORES[name]
+    print(f"[case] oracle reads the 1M index, {name} store", flush=True)
+    ref = hsig.Index.read(path)
+    if name == "fp8":
+        ref.set_store(hsig.FP8E4M3, 4)
+    sample = np.arange(0, len(W.queries), 37)
+    rid, rd, rc = ref.search(W.queries[sample], W.l[sample], W.h[sample], 10, 16, m=kw["m"], p=kw["beam_p"],
+                             tau_a=kw["tau_a"], tau_b=kw["tau_b"], counters=True)
+    assert ((st[:, 3] & 0xFF) != 2).all()
+    assert np.array_equal(strat[sample].astype(np.int64), rc[:, hsig.STRAT])
+    assert np.array_equal(ids[sample], rid)
+    assert np.array_equal(dist[sample].view(np.uint32), rd.view(np.uint32))
+    assert set(rc[:, hsig.STRAT].tolist()) == {hsig.PRE, hsig.HYBRID, hsig.POST}

@@ -225,3 +225,21 @@ def test_parity_low_precision_d960(tmp_path, name, prec, d):
         assert np.array_equal(ref[0], gid) and np.array_equal(ref[1].view(np.uint32), gd.view(np.uint32)), strategy
     g.close()
 
+
+
+@pytest.mark.parametrize("name,prec", PRECS)
+def test_lowp_pre_scan_falls_back_to_fp32(c1, name, prec):
+    """k = 64 with a 64-entry candidate buffer: the low-precision scan's bounds admit
+    more than 64 objects, so the scan (whole slices, and chunks of split slices) is
+    redone with the FP32 store (status 1); every row is still the exact answer."""
+    W, ix, path = c1
+    import paper_2412_02448_amd as u
+    g = u.Index.load(path, device=0, precision=name)
+    for chunk in (4096, 256):
+        print(f"[case] {name} pre-scan fallback chunk={chunk}", flush=True)
+        gid, gd, _, gst = gpu_search(g, W.queries, W.l, W.h, 64, 64, hsig.PRE, cand_cap=64, pre_chunk=chunk)
+        ref = ix.search(W.queries, W.l, W.h, 64, 64, strategy=hsig.PRE)
+        assert np.array_equal(ref[0], gid) and np.array_equal(ref[1].view(np.uint32), gd.view(np.uint32))
+        assert ((gst[:, 3] & 0xFF) == 1).any(), "no scan fell back"
+        assert ((gst[:, 3] & 0xFF) != 2).all()
+    g.close()

@@ -186,3 +186,47 @@ def test_parity_other_dimensions(tmp_path, d):
         ref = ix.search(W.queries, W.l, W.h, 10, 32, strategy=strategy)
         got = gpu_search(g, W, 10, 32, strategy=None if strategy == hsig.AUTO else strategy)
         assert_parity(ref, got, f"d={d} strategy={strategy}")
+
+
+@pytest.mark.parametrize("p", [1, 4])
+@pytest.mark.parametrize("strategy", [hsig.HYBRID, hsig.POST, hsig.AUTO])
+def test_parity_small_capacities(c1, strategy, p):
+    """A 64-entry candidate array and a 256-entry visited cache: graph searches outgrow
+    the candidate array (the query is abandoned and re-run by the second launch with a
+    larger one: status 1) or the visited cache (the visited set continues in the wave's
+    HBM tag row: flag bit 8).  Both paths are reached here and every row still equals
+    the oracle's."""
+    W, ix, g = c1
+    print(f"[case] small capacities strategy={strategy} p={p}", flush=True)
+    ref = ix.search(W.queries, W.l, W.h, 10, 64, p=p, strategy=strategy)
+    got = gpu_search(g, W, 10, 64, strategy=None if strategy == hsig.AUTO else strategy, beam_p=p,
+                     cand_cap=64, visit_cap=256)
+    assert_parity(ref, got, f"small capacities strategy={strategy} p={p}")
+    st = got[3]
+    graph = np.isin(st[:, 5], [hsig.HYBRID, hsig.POST])
+    assert graph.any()
+    assert ((st[:, 3] & 0xFF) == 1)[graph].any(), "no query reached the re-run launch"
+    assert ((st[:, 3] & 0x100) != 0)[graph].any(), "no visited set spilled to HBM"
+
+
+def test_unknown_strategy_rows(c1):
+    """Strategies outside AUTO..POST are read on the device: their rows are padded and
+    reported as strategy -2 with status 3; the other rows are searched as usual."""
+    W, ix, g = c1
+    torch = _torch()
+    dev = torch.device("cuda", 0)
+    print("[case] unknown strategies", flush=True)
+    nq = len(W.queries)
+    s = np.zeros(nq, np.int8)
+    s[::7] = 4
+    s[3::11] = -1
+    s[5::13] = 127
+    bad = (s < 0) | (s > 3)
+    Q, l, h = (torch.from_numpy(a).to(dev) for a in (W.queries, W.l, W.h))
+    ids, dist, ost, st = g.search(Q, l, h, 10, 64, strategy=torch.from_numpy(s).to(dev), stats=True)
+    torch.cuda.synchronize()
+    ids, dist, ost, st = (t.cpu().numpy() for t in (ids, dist, ost, st))
+    assert (ids[bad] == -1).all() and np.isinf(dist[bad]).all()
+    assert (ost[bad] == -2).all() and (st[bad, 3] == 3).all() and (st[bad, 5] == -2).all()
+    rid, rd = ix.search(W.queries[~bad], W.l[~bad], W.h[~bad], 10, 64)
+    assert np.array_equal(ids[~bad], rid) and np.array_equal(dist[~bad].view(np.uint32), rd.view(np.uint32))
