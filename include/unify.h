@@ -217,6 +217,27 @@ int unify_search_ex(unify_index_t index, const float* queries, int64_t nq, const
                     int8_t* out_strategy, int32_t* out_stats, void* hip_stream);
 
 /*
+ * unify_search_ex for callers that cannot allocate: code under HIP graph capture,
+ * serving loops that must not call hipMalloc, harnesses that forbid allocation.
+ * Arguments, results and errors are those of unify_search_ex (UNIFY_FLAG_TIMING is
+ * ignored).  The call allocates no device, pinned or host memory: the per-call
+ * scratch (query plans, the work list, partial lists of split pre-filter scans)
+ * lives in one static device array of 32 MiB that every GPU the library runs on
+ * holds until the process ends, and the visited-set memory was allocated when the
+ * index became resident.  A call needing more scratch than the array holds (about
+ * nq * (64 * k + 120) bytes when k <= 128, nq * 120 bytes otherwise) fails with
+ * UNIFY_EINVAL before launching anything: split the batch.  Every call on one GPU
+ * uses the same array, which keeps the last call's contents (each call writes what
+ * it reads).  Calls on one index are ordered on the device (each waits for the
+ * previous one's kernels); calls on two indexes of one GPU that overlap on the
+ * device race on the array and return wrong results: the caller serialises them.
+ */
+int unify_search_ex_noalloc(unify_index_t index, const float* queries, int64_t nq, const int64_t* l,
+                            const int64_t* h, int32_t k, int32_t ef, const int8_t* strategy,
+                            const unify_params* params, int64_t* out_ids, float* out_dist,
+                            int8_t* out_strategy, int32_t* out_stats, void* hip_stream);
+
+/*
  * Second attribute for conjunctive two-attribute queries (the paper's
  * multi-attribute extension, approach 1: the HSIG stays built on the first
  * attribute; the filter also tests the second).

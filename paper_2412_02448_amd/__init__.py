@@ -59,6 +59,7 @@ SIGNATURES = {
     "unify_index_info": (_I32, [_P, _P, _P, _P, _P, _P]),
     "unify_search": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P]),
     "unify_search_ex": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "unify_search_ex_noalloc": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "unify_last_timing": (_I32, [_P, _P, _P, _P]),
     "unify_copy_store": (_I32, [_P, _I32, _P, _P, _P, _P]),
     "unify_set_precision": (_I32, [_P, _I32]),

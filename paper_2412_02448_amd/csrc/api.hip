@@ -19,6 +19,9 @@ int search_multi_impl(unify_index_t ix, const float* queries, int64_t nq, const 
                       const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef, const int8_t* strategy,
                       const unify_params* prm, int64_t* out_ids, float* out_dist, int8_t* out_strategy,
                       int32_t* out_stats, void* stream);
+int search_impl_noalloc(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                        int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
+                        float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream);
 
 namespace {
 thread_local std::string g_error;
@@ -119,7 +122,9 @@ int make_resident(HostIndex&& H, int device, int precision, unify_index_t* out) 
   up(H.adjU, &dv.adjU);
   up(gU, &dv.glistU);
   if (rc == UNIFY_OK) rc = quantize_store(ix, precision);
+  if (rc == UNIFY_OK) rc = ensure_tags(ix);
   if (rc != UNIFY_OK) {
+    if (ix->last_search) (void)hipEventDestroy(ix->last_search);
     for (void* p : ix->allocs) (void)hipFree(p);
     delete ix;
     return rc;
@@ -295,6 +300,14 @@ int unify_search_ex(unify_index_t ix, const float* queries, int64_t nq, const in
                     float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* hip_stream) {
   return search_impl(ix, queries, nq, l, h, k, ef, strategy, params, out_ids, out_dist, out_strategy, out_stats,
                      hip_stream);
+}
+
+int unify_search_ex_noalloc(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                            int32_t k, int32_t ef, const int8_t* strategy, const unify_params* params,
+                            int64_t* out_ids, float* out_dist, int8_t* out_strategy, int32_t* out_stats,
+                            void* hip_stream) {
+  return search_impl_noalloc(ix, queries, nq, l, h, k, ef, strategy, params, out_ids, out_dist, out_strategy,
+                             out_stats, hip_stream);
 }
 
 int unify_search_multi(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,

@@ -1457,7 +1457,8 @@ int insert_impl(unify_index_t ix, const float* vectors, const int64_t* attr, con
   ix->dv = nv;
   ix->host = std::move(H);
   ++ix->version;
-  return quantize_store(ix, precision);
+  const int rc = quantize_store(ix, precision);
+  return rc == UNIFY_OK ? ensure_tags(ix) : rc;
 }
 
 }  // namespace unify

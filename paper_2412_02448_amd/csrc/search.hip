@@ -36,7 +36,41 @@
 #include "unify_internal.h"
 #include "wave.h"
 
+// Scratch of the allocation-free entry point (plans, work list and partial
+// lists of one call): one array in every GPU's memory from the moment the code
+// object is loaded until the process ends.  Host code never passes this name to
+// a kernel (on the host it is only a stand-in); it uses the device address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
 namespace unify {
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[MAX_DEVICES] = {};  // device address of `scratch` on each device
+
+// The address of `scratch` on `device` (the current device), looked up once.
+int noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= MAX_DEVICES) {
+    set_error("device ordinal out of range");
+    return UNIFY_EINVAL;
+  }
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return UNIFY_EDEVICE;
+    }
+    g_noalloc_ptr[device] = p;
+  }
+  *out = g_noalloc_ptr[device];
+  return UNIFY_OK;
+}
+}  // namespace
 
 struct SearchArgs {
   DevIndex ix;
@@ -1226,8 +1260,14 @@ int resolve(unify_index_t ix, int64_t nq, int32_t k, int32_t ef, const unify_par
   return UNIFY_OK;
 }
 
-// Visited tags: one row of n epochs per persistent wave, kept with the index.
+}  // namespace
+
+// Visited tags: one row of n epochs per persistent wave, kept with the index,
+// and the event that orders the search kernels of successive calls.  Made when
+// the index becomes resident (load, build, insertion), so that searches need no
+// allocation of their own.
 int ensure_tags(unify_index_t ix) {
+  if (!ix->last_search) HIP_OK(hipEventCreateWithFlags(&ix->last_search, hipEventDisableTiming));
   if (ix->tags) return UNIFY_OK;
   const DevIndex& dv = ix->dv;
   HIP_OK(hipDeviceGetAttribute(&ix->cus, hipDeviceAttributeMultiprocessorCount, ix->device));
@@ -1258,6 +1298,8 @@ int ensure_tags(unify_index_t ix) {
   ix->allocs.push_back(e);
   return UNIFY_OK;
 }
+
+namespace {
 
 // Per-call device scratch: plans, work list (graph queries and pre-filter
 // chunks), chunk of each entry, fallback list, counters, per-query merge
@@ -1296,7 +1338,9 @@ struct Pass {
   unsigned grid;
 };
 
-int prepare_pass(unify_index_t ix, KernelFn fn, size_t lds, int64_t nq, Pass& out) {
+// cache = false: the occupancy found is not added to the index's table (the
+// allocation-free entry point keeps host memory unchanged too).
+int prepare_pass(unify_index_t ix, KernelFn fn, size_t lds, int64_t nq, Pass& out, bool cache = true) {
   const auto key = std::make_pair(reinterpret_cast<const void*>(fn), lds);
   auto it = ix->occupancy.find(key);
   int per_cu = 0;
@@ -1306,7 +1350,7 @@ int prepare_pass(unify_index_t ix, KernelFn fn, size_t lds, int64_t nq, Pass& ou
     HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), 64, lds));
-    ix->occupancy[key] = per_cu;
+    if (cache) ix->occupancy[key] = per_cu;
   }
   if (per_cu < 1) {
     set_error("search kernel does not fit on a compute unit");
@@ -1342,7 +1386,7 @@ struct Launch {
 int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, int64_t nq, const int64_t* l,
                    const int64_t* h, const int8_t* strategy, int64_t* out_ids, float* out_dist,
                    int8_t* out_strategy, int32_t* out_stats, void* scratch, Launch& X,
-                   const int64_t* l2 = nullptr, const int64_t* h2 = nullptr) {
+                   const int64_t* l2 = nullptr, const int64_t* h2 = nullptr, bool cache = true) {
   const DevIndex& dv = ix->dv;
   X.dv = dv;
   X.queries = queries;
@@ -1425,11 +1469,12 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   X.B = B;
   const bool s1 = (R.flags & UNIFY_FLAG_SELECT_S1) != 0;
   int rc = prepare_pass(ix, kernel_for<0>(dv.d, dv.precision, s1),
-                        lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap, A.sel_cap), nq, X.p0);
+                        lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap, A.sel_cap), nq, X.p0, cache);
   // the re-run pass holds the few queries that overflowed: a small grid launches faster
   if (rc == UNIFY_OK)
     rc = prepare_pass(ix, kernel_for<1>(dv.d, dv.precision, s1),
-                      lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap, B.sel_cap), std::min<int64_t>(nq, 512), X.p1);
+                      lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap, B.sel_cap), std::min<int64_t>(nq, 512), X.p1,
+                      cache);
   return rc;
 }
 
@@ -1437,9 +1482,17 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
 // sequence can be captured into a HIP graph.  ev: 4 events to record, or null.
 // order: the index whose previous search kernels the search kernels must follow
 // (null inside a graph capture, where the caller orders the replay instead).
-int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, unify_index_t order = nullptr) {
+// whole = true: the plan and work-list kernels wait too (their scratch is
+// shared with the previous call's search kernels).
+int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, unify_index_t order = nullptr,
+                   bool whole = false) {
   const unsigned pb = 256;
   const int64_t nq = X.nq;
+  std::unique_lock<std::mutex> g;
+  if (order) {
+    g = std::unique_lock<std::mutex>(order->order_mu);
+    if (whole && order->last_search) HIP_OK(hipStreamWaitEvent(st, order->last_search, 0));
+  }
   if (ev) HIP_OK(hipEventRecord(ev[0], st));
   hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, X.dv, X.l, X.h, X.l2, X.h2,
                      const_cast<ConjArgs*>(X.A.conj), X.strategy, nq,
@@ -1450,9 +1503,7 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, unify_index_
                      X.S.counters);
   HIP_OK(hipGetLastError());
   if (ev) HIP_OK(hipEventRecord(ev[1], st));
-  std::unique_lock<std::mutex> g;
-  if (order) {
-    g = std::unique_lock<std::mutex>(order->order_mu);
+  if (order && !whole) {
     if (!order->last_search) HIP_OK(hipEventCreateWithFlags(&order->last_search, hipEventDisableTiming));
     else HIP_OK(hipStreamWaitEvent(st, order->last_search, 0));
   }
@@ -1565,6 +1616,48 @@ int search_impl_scratch(unify_index_t ix, const float* queries, int64_t nq, cons
   Launch X;
   rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, X);
   if (rc == UNIFY_OK) rc = enqueue_launch(X, reinterpret_cast<hipStream_t>(stream), nullptr, ix);
+  return rc;
+}
+
+size_t noalloc_scratch_bytes() { return NOALLOC_SCRATCH_BYTES; }
+
+// unify_search_ex over the static scratch array: no allocation of any kind.
+int search_impl_noalloc(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
+                        int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
+                        float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream) {
+  if (!ix) {
+    set_error("null index");
+    return UNIFY_EINVAL;
+  }
+  std::shared_lock<std::shared_mutex> version(ix->version_mu);
+  Resolved R;
+  int rc = resolve(ix, nq, k, ef, prm, R);
+  if (rc != UNIFY_OK) return rc;
+  R.flags &= ~(uint32_t)UNIFY_FLAG_TIMING;  // timing events would be created on first use
+  if (nq == 0) return UNIFY_OK;
+  if (!queries || !l || !h || !out_ids || !out_dist) {
+    set_error("null buffer");
+    return UNIFY_EINVAL;
+  }
+  const size_t need = search_scratch_bytes(nq, k);
+  if (need > NOALLOC_SCRATCH_BYTES) {
+    set_error("unify_search_ex_noalloc: " + std::to_string(nq) + " queries with k = " + std::to_string(k) +
+              " need " + std::to_string(need) + " bytes of scratch, more than the static " +
+              std::to_string(NOALLOC_SCRATCH_BYTES) + "; split the batch");
+    return UNIFY_EINVAL;
+  }
+  if (!ix->tags || !ix->last_search) {
+    set_error("the index has no visited-set memory");
+    return UNIFY_EINVAL;
+  }
+  HIP_OK(hipSetDevice(ix->device));
+  void* scratch = nullptr;
+  rc = noalloc_scratch(ix->device, &scratch);
+  if (rc != UNIFY_OK) return rc;
+  Launch X;
+  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, X,
+                      nullptr, nullptr, false);
+  if (rc == UNIFY_OK) rc = enqueue_launch(X, reinterpret_cast<hipStream_t>(stream), nullptr, ix, true);
   return rc;
 }
 

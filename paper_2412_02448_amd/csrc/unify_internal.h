@@ -81,6 +81,10 @@ void set_error(const std::string& msg);
 // resident vectors and its error bounds when it is not resident yet.
 int quantize_store(unify_index_t ix, int precision);
 
+// Allocates the index's visited-set memory and its search-ordering event if
+// they are not there yet (called when an index version becomes resident).
+int ensure_tags(unify_index_t ix);
+
 }  // namespace unify
 
 struct unify_index {
@@ -88,7 +92,7 @@ struct unify_index {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // timing: before the plan, after the work
                                                             // list, after the search, after the re-run
   bool timed = false;
-  uint32_t* tags = nullptr;    // visited epochs [nslots][n], allocated at the first search
+  uint32_t* tags = nullptr;    // visited epochs [nslots][n], allocated when the index becomes resident
   uint32_t* epochs = nullptr;  // [nslots]
   int64_t nslots = 0;
   const float* eps_of[3] = {nullptr, nullptr, nullptr};  // error bounds of the resident BF16 / FP8 copies
