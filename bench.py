@@ -35,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+HOST_SHARE = 16  # host cores that go with one GPU of the box
 METRIC = "QPS @ recall@10≥0.95, 1M×128 mixed ranges, FP32 vs BF16/FP8; HBM GB/s"
 PRECISIONS = ("fp32", "bf16", "fp8")
 DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}
@@ -74,6 +75,12 @@ def parse():
     ap.add_argument("--wide-M", type=int, default=0, help="chunk capacity of the 960-wide index (0: the recipe's)")
     ap.add_argument("--wide-efc", type=int, default=0, help="efCons of the 960-wide index (0: the recipe's)")
     ap.add_argument("--cpu-queries", type=int, default=0, help="queries in the CPU sample (0: all)")
+    ap.add_argument("--wpq", type=int, default=0, help="wavefronts per heavy graph search (0: the library default)")
+    ap.add_argument("--heavy", type=int, default=0, help="heavy graph searches per batch (0: the library default)")
+    ap.add_argument("--inflight", type=int, default=2, help="serving slots in flight")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="development/profiling run: build the index, then only the serving section with one "
+                         "store (--precisions) and --m/--ef/--p (no tuning); prints the serving record")
     return ap.parse_args()
 
 
@@ -123,6 +130,15 @@ def main():
     cp_dst = torch.empty_like(cp_src)
     cp_dst.copy_(cp_src)
 
+    if args.serving_only:
+        if not (args.m and args.ef and args.p and len(precs) == 1):
+            print("--serving-only needs --m, --ef, --p and one store in --precisions", file=sys.stderr)
+            sys.exit(2)
+        index.set_precision(precs[0])
+        rec = serve_bench(args, index, spec, W, args.m, args.ef, args.p, 0.01, 0.5, 0, precs[0])
+        print(json.dumps({"serving": rec}), flush=True)
+        return
+
     if args.profile_run:
         if not (args.m and args.ef and args.p and len(precs) == 1):
             print("--profile-run needs --m, --ef, --p and one store in --precisions", file=sys.stderr)
@@ -156,7 +172,11 @@ def main():
     Lc = torch.from_numpy(cl).to(dev)
     Hc = torch.from_numpy(ch).to(dev)
 
+    coop = {"waves_per_query": args.wpq, "heavy_queries": args.heavy}
+
     def timed(m, ef, bp, strategy=None, steps=args.steps, warmup=args.warmup, ta=0.01, tb=0.5, vc=0, **kw):
+        # cooperative searches do not run selection S1
+        kw = {**({} if kw.get("select_s1") else coop), **kw}
         out = None
         for _ in range(warmup):
             out = index.search(Q, L, H, k, ef, strategy=strategy, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, **kw)
@@ -169,6 +189,7 @@ def main():
 
     # ---- every store: tune on held-out queries, then K timed steps of the batch ----
     by_prec = {}
+    store_rows = {}  # store -> (ids, dist) of the timed batch, scored against FP64 in the CPU leg
     for prec in precs:
         index.set_precision(prec)
         t0 = time.time()
@@ -179,6 +200,16 @@ def main():
             Mi = index.M
             ms_grid = (Mi // 2, (3 * Mi) // 4, Mi, (3 * Mi) // 2, 2 * Mi, 3 * Mi)
         kw_t = {"taus": ((args.tau_a, args.tau_b),)} if args.tau_a else {}
+        cal = None
+        if not args.tau_a:
+            # Sec. 4.2: base objects as sample queries with random ranges, the three strategies
+            # timed per cardinality bucket; the turning points join the tuner's threshold grid
+            rs = np.random.default_rng(41)
+            sample = W.base[rs.choice(len(W.base), 8192, replace=False)]
+            cal = autotune.calibrate_tau(index, sample, W.attr, k, 32, args.recall_target, m=2 * index.M, beam_p=4,
+                                         log=lambda s, p=prec: log(f"[{p}] {s}"))
+            log(f"[{prec}] calibrated tau = ({cal.tau_a:.6f}, {cal.tau_b:.6f})")
+            kw_t = {"taus": ((cal.tau_a, cal.tau_b), (0.01, 0.5), (0.01, 0.3), (0.005, 0.3), (0.01, 0.2))}
         # a small margin above the target on the held-out queries keeps the benchmark
         # queries above it too
         best, table = autotune.tune(index, Qc, Lc, Hc, k, args.recall_target + TUNE_MARGIN, ms=ms_grid,
@@ -190,11 +221,15 @@ def main():
             f"tau=({ta}, {tb})")
         sec, out = timed(m, ef, bp, ta=ta, tb=tb, vc=vc)
         rec = recall_of(out[0])
-        ids, _, _, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True, timing=True)
+        store_rows[prec] = (out[0].cpu().numpy(), out[1].cpu().numpy())
+        ids, _, _, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True,
+                                        timing=True, **coop)
         torch.cuda.synchronize()
-        pre_ms, search_ms, rerun_ms = index.last_timing()
+        pre_ms, _, rerun_ms = index.last_timing()
+        ph = index.last_timing_phases()
+        search_ms = ph["search"]
         st = stats.cpu().numpy().astype(np.int64)
-        first = (st[:, 3] & 0xFF) == 0
+        first = ((st[:, 3] & 0xFF) == 0) & ~tile_rows(st)
         bts = int(bytes_per_query(st, d, k, prec)[first].sum())
         by_prec[prec] = {
             "qps": round(nq / sec, 1), "ms_per_step": round(sec * 1e3, 4), "recall@10": round(rec, 4),
@@ -204,6 +239,14 @@ def main():
             "bytes_per_launch": bts, "achieved_GBps": round(bts / (search_ms * 1e-3) / 1e9, 1),
             "fp32_rescores_per_query": round(float(st[:, 2].mean()), 2),
             "same_ids_as_stats_call": bool((ids == out[0]).all().item()),
+            "phases_ms": {kk: round(v, 4) for kk, v in ph.items()},
+            "tile_scan": tile_roofline(st, ph, d, k, prec, spec.n),
+            "tau_calibration": None if cal is None else {
+                "tau_a": round(cal.tau_a, 6), "tau_b": round(cal.tau_b, 6), "setting": "k=10 ef=32 m=2M p=4",
+                "chosen": bool(abs(ta - cal.tau_a) < 1e-12 and abs(tb - cal.tau_b) < 1e-12),
+                "buckets": [{"y": [a, b], "recall": [round(cal.recall[s_][i], 3) for s_ in ("pre", "hybrid", "post")],
+                             "us_per_query": [round(cal.us_per_query[s_][i], 3) for s_ in ("pre", "hybrid", "post")]}
+                            for i, (a, b) in enumerate(zip(cal.y_lo, cal.y_hi))]},
         }
         log(f"[{prec}] {nq / sec:,.0f} QPS ({sec * 1e3:.3f} ms/step), recall@10 {rec:.4f}; search kernel "
             f"{search_ms:.3f} ms, {by_prec[prec]['achieved_GBps']} GB/s algorithmic, rerun {rerun_ms:.3f} ms "
@@ -233,7 +276,7 @@ def main():
     # re-run) over the resident batch; the same step through per-call launches is reported
     # beside it.
     sec_eager, out_eager = timed(m, ef, bp, ta=ta, tb=tb, vc=vc)
-    batch = u.Batch(index, Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
+    batch = u.Batch(index, Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, **coop)
     for _ in range(args.warmup):
         batch.run()
     torch.cuda.synchronize()
@@ -266,20 +309,28 @@ def main():
             for e in (16, 32, 64, 128)))
 
     # ---- roofline of the search kernel: counters of one more (identical) call ----
-    ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True, timing=True)
+    ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True,
+                                           timing=True, **coop)
     torch.cuda.synchronize()
-    pre_ms, search_ms, rerun_ms = index.last_timing()
+    pre_ms, _, rerun_ms = index.last_timing()
+    phases = index.last_timing_phases()
+    search_ms = phases["search"]
     st = stats.cpu().numpy().astype(np.int64)
-    first = (st[:, 3] & 0xFF) == 0
+    first = ((st[:, 3] & 0xFF) == 0) & ~tile_rows(st)
     bytes_first = int(bytes_per_query(st, d, k, head)[first].sum())
     achieved = bytes_first / (search_ms * 1e-3) / 1e9
+    copy_gbs = copy_peak(torch, dev)
+    log(f"device copy: {copy_gbs:,.0f} GB/s (read + write)")
     mix = np.bincount(np.maximum(st[:, 5], 0), minlength=4)
     kern = f"k_search<*, {KCODE[head]}, 0, false>"
     roofline = {"bound": "hbm", "kernel": f"{kern} (first pass)", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(head, m, ef, bp, ta, tb, vc), "bytes_per_launch": bytes_first,
                 "launch_ms": round(search_ms, 4), "rerun_launch_ms": round(rerun_ms, 4),
-                "rerun_queries": int(((st[:, 3] & 0xFF) == 1).sum()), "failed_queries": int(((st[:, 3] & 0xFF) == 2).sum())}
+                "measured_copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                "rerun_queries": int(((st[:, 3] & 0xFF) == 1).sum()), "failed_queries": int(((st[:, 3] & 0xFF) == 2).sum()),
+                "phases_ms": {kk: round(v, 4) for kk, v in phases.items()}}
+    roofline_tile = tile_roofline(st, phases, d, k, head, spec.n)
     ids_np = ids.cpu().numpy()
     for sname, sv in (("pre", 1), ("hybrid", 2), ("post", 3)):
         sel = np.nonzero(st[:, 5] == sv)[0]
@@ -335,12 +386,19 @@ def main():
 
     # ---- CPU baseline: the oracle's HSIG search on the same index ----
     cpu = None
+    fp64 = None
     if not args.no_cpu_baseline:
         try:
             cpu = cpu_baseline(args, W, index, ids_np, k, ef, m, bp, ta, tb, nq, head)
         except Exception as e:  # the GPU line is still reported
             log(f"CPU baseline failed: {e!r}")
             cpu = {"value": None, "unit": "queries/s", "cores": 0, "kind": "oracle", "sample": f"failed: {e!r}"}
+        try:
+            store_rows["headline_graph_replay"] = (out[0].cpu().numpy(), out[1].cpu().numpy())
+            fp64 = fp64_scoring(W, truth, store_rows, k, st[:, 6])
+        except Exception as e:  # the GPU line is still reported
+            log(f"FP64 scoring failed: {e!r}")
+            fp64 = {"failed": repr(e)}
     line = {
         "metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True, "scaling": "weak",
@@ -351,6 +409,7 @@ def main():
                    "n": spec.n, "d": d, "nq": nq, "k": k, "store": head, "ef": ef, "m": m, "beam_p": bp,
                    "tau_a": ta, "tau_b": tb, "visit_cap": vc,
                    "recall@10": round(recall_of(out[0]), 4),
+                   "recall@10_vs_fp64_sample": (fp64 or {}).get("headline_graph_replay", {}).get("recall@10"),
                    "recall_by_ef": {str(e): round(r, 4) for e, r in recalls.items()},
                    "strategy_mix": {"pre": int(mix[1]), "hybrid": int(mix[2]), "post": int(mix[3])},
                    "build_s": round(build_s, 1)},
@@ -360,6 +419,8 @@ def main():
         "per_strategy": per_strategy,
         "hybrid_selection": selection,
         "roofline": roofline,
+        "roofline_tile_scan": roofline_tile,
+        "fp64_check": fp64,
         "batch100k": b100,
         "wide960": wide,
         "insertion": ins,
@@ -368,6 +429,111 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def tile_rows(st):
+    """Rows answered by the matrix-core pre-filter scan (stats[4] = its super-block records)."""
+    return (st[:, 5] == 1) & (st[:, 4] > 0)
+
+
+def tile_roofline(st, ph, d, k, prec, n):
+    """The matrix-core pre-filter scan: its kernel time (HIP events around it), the products
+    it runs on the matrix cores, and the bytes of the super-blocks it reads.  Every super-block
+    a record names is read once per group of up to 16 queries; the per-query algorithmic
+    bytes (Y d b summed over the queries) are reported beside them."""
+    import numpy as np
+    rows = tile_rows(st)
+    if not rows.any():
+        return None
+    b = {"fp32": 4, "bf16": 2, "fp8": 1}[prec]
+    row_b = d * b + 4 + (4 if prec != "fp32" else 0) + (4 if prec == "fp8" else 0)  # + norm, eps, scale
+    Y = st[rows, 6].astype(np.int64)
+    alg_bytes = int((Y * d * b).sum())
+    # products: each (query, object in range) pair is one d-long dot product; BF16 inputs run it twice
+    # (the query in two parts)
+    alg_flop = int((Y * 2 * d).sum()) * (2 if prec != "fp32" else 1)
+    ms = ph["tile_scan"]
+    peak = 2500.0 if prec != "fp32" else 157.3
+    tf = alg_flop / (ms * 1e-3) / 1e12 if ms > 0 else None
+    return {"bound": "hbm", "kernel": f"k_tile_scan<{KCODE[prec]}>", "launch_ms": round(ms, 4),
+            "setup_ms": round(ph["tile_setup"], 4), "final_ms": round(ph["tile_final"], 4),
+            "queries": int(rows.sum()), "records": int(st[rows, 4].sum()),
+            "per_query_bytes": alg_bytes, "per_query_GBps": round(alg_bytes / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
+            "row_bytes": row_b, "mfma_flop": alg_flop, "mfma_TFLOPs": round(tf, 2) if tf else None,
+            "mfma_peak_TFLOPs": peak, "mfma_frac": round(tf / peak, 5) if tf else None,
+            "fp32_rescores_per_query": round(float(st[rows, 2].mean()), 2)}
+
+
+def copy_peak(torch, dev):
+    """Device-to-device copy bandwidth (bytes read + written per second), the achievable
+    HBM rate beside the 8 TB/s specification."""
+    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for _ in range(10):
+        b.copy_(a)
+    s1.record()
+    torch.cuda.synchronize()
+    gbs = 10 * 2 * a.numel() / (s0.elapsed_time(s1) * 1e-3) / 1e9
+    del a, b
+    return gbs
+
+
+def fp64_scoring(W, truth_gpu, rows, k, Ysize, nsample=1000):
+    """Part of the CPU leg: the exact FP64 answer (Definition 1, the oracle's brute force) of a
+    fixed sample of queries spread over all range sizes (every (nq / nsample)-th query in order of
+    Y), recall@10 of each store's rows against it (Eq. 1), the relative error of every returned
+    distance against the FP64 distance of the same object, and how often the GPU's exact scan
+    (the recall truth of the rest of the line) returns the FP64 answer."""
+    import concurrent.futures as cf
+
+    import numpy as np
+    from oracle import exact
+    nq = len(W.queries)
+    order = np.argsort(Ysize, kind="stable")
+    sample = np.sort(order[np.linspace(0, nq - 1, min(nsample, nq)).astype(np.int64)])
+    ext = np.arange(len(W.attr), dtype=np.int64)
+    perm = np.lexsort((ext, W.attr))
+    Xs, As, Es = W.base[perm], W.attr[perm], ext[perm]
+    t0 = time.time()
+    ncpu = min(HOST_SHARE, len(os.sched_getaffinity(0)))
+
+    def one(i):
+        ids, dd, size = exact.rfknn_sorted(Xs, As, W.queries[i], W.l[i], W.h[i], k, Es)
+        return ids, dd, size
+    with cf.ThreadPoolExecutor(max_workers=ncpu) as pool:
+        res = list(pool.map(one, sample))
+    truth_s = time.time() - t0
+    log(f"FP64 exact answers of {len(sample)} sample queries: {truth_s:.1f}s on {ncpu} threads")
+    X64 = W.base.astype(np.float64)
+    out = {"sample": f"{len(sample)} of the {nq} queries, every {nq // len(sample)}-th in order of range size "
+                     f"(Y from {int(Ysize[sample].min())} to {int(Ysize[sample].max())})",
+           "truth_s": round(truth_s, 1), "threads": ncpu}
+    agree = 0
+    for j, i in enumerate(sample):
+        t = truth_gpu[i][truth_gpu[i] >= 0]
+        agree += int(np.array_equal(t, res[j][0]))
+    out["gpu_exact_scan_equals_fp64"] = round(agree / len(sample), 4)
+    for name, (ids, dist) in rows.items():
+        rec, errs = [], []
+        for j, i in enumerate(sample):
+            tid, _, size = res[j]
+            rec.append(exact.recall(ids[i], tid, k, size))
+            got = ids[i] >= 0
+            if got.any():
+                e = ids[i][got]
+                d64 = ((X64[e] - W.queries[i].astype(np.float64)) ** 2).sum(1)
+                nz = d64 > 0
+                errs.append(np.abs(dist[i][got][nz].astype(np.float64) - d64[nz]) / d64[nz])
+        errs = np.concatenate(errs) if errs else np.zeros(1)
+        out[name] = {"recall@10": round(float(np.mean(rec)), 4), "dist_rel_err_max": float(errs.max()),
+                     "dist_rel_err_mean": float(errs.mean())}
+        log(f"FP64 check {name}: recall@10 {np.mean(rec):.4f}, distance error max {errs.max():.2e} "
+            f"mean {errs.mean():.2e}")
+    return out
 
 
 def wide_bench(args):
@@ -582,10 +748,14 @@ def serve_bench(args, index, spec, W, m, ef, bp, ta, tb, vc, prec):
                        ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)[0].cpu().numpy()
     rng = np.random.default_rng(12)
     rows = []
+    limits = None
     for rate in (10_000, 100_000, 1_000_000, None):
         cnt = n if rate is None or rate >= 100_000 else 20_000
         arrive = np.zeros(cnt) if rate is None else np.cumsum(rng.exponential(1.0 / rate, cnt))
-        srv = u.Server(index, k, ef, max_batch=4096, inflight=2, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
+        srv = u.Server(index, k, ef, max_batch=4096, inflight=args.inflight, m=m, beam_p=bp, tau_a=ta, tau_b=tb,
+                       visit_cap=vc)
+        b_, r_, m_ = srv.limits()
+        limits = {"max_batch": b_, "visit_rows_per_slot": r_, "device_MB": round(m_ / 2 ** 20, 1)}
         t0 = time.perf_counter()
         tickets = srv.submit(q[:cnt], l[:cnt], h[:cnt], arrive_s=arrive)
         ids, _, lat = srv.wait(tickets, timeout_s=120)
@@ -609,7 +779,7 @@ def serve_bench(args, index, spec, W, m, ef, bp, ta, tb, vc, prec):
     k100 = []
     for rate in (10_000, 100_000):
         arrive = np.cumsum(rng.exponential(1.0 / rate, cnt))
-        srv = u.Server(index, k2, ef2, max_batch=4096, inflight=2, m=m, beam_p=bp, tau_a=ta, tau_b=tb,
+        srv = u.Server(index, k2, ef2, max_batch=4096, inflight=args.inflight, m=m, beam_p=bp, tau_a=ta, tau_b=tb,
                        visit_cap=vc)
         t0 = time.perf_counter()
         ids, _, lat = srv.wait(srv.submit(q[:cnt], l[:cnt], h[:cnt], arrive_s=arrive), timeout_s=120)
@@ -625,7 +795,7 @@ def serve_bench(args, index, spec, W, m, ef, bp, ta, tb, vc, prec):
             f"p99 {row['p99_ms']} ms, identical {row['equal_to_batch_search']}")
     return {"workload": f"mixed1m index ({prec} store, m={m} ef={ef} p={bp} tau=({ta}, {tb})), k={k}, "
                         f"serving range mix",
-            "max_batch": 4096, "inflight": 2, "rates": rows, "k100": k100}
+            "max_batch": 4096, "inflight": args.inflight, "admitted": limits, "rates": rows, "k100": k100}
 
 
 def batch100k(args, prec):
@@ -715,7 +885,8 @@ def cpu_baseline(args, W, index, ids, k, ef, m, bp, ta, tb, nq, prec):
         t0 = time.time()
         ref.set_store({"bf16": hsig.BF16, "fp8": hsig.FP8E4M3}[prec], 4)
         log(f"oracle {prec} copy ({time.time() - t0:.1f}s)")
-    ncpu = min(16, len(os.sched_getaffinity(0)))
+    naff = len(os.sched_getaffinity(0))
+    ncpu = min(HOST_SHARE, naff)  # this GPU's share of the host's cores
     sample = np.arange(min(args.cpu_queries, nq)) if args.cpu_queries else np.arange(nq)
     parts = np.array_split(sample, ncpu)
     res = [None] * ncpu
@@ -738,10 +909,29 @@ def cpu_baseline(args, W, index, ids, k, ef, m, bp, ta, tb, nq, prec):
         if passes == 1:
             cpu_ids = np.concatenate(res)
             agree = float(np.mean([np.array_equal(cpu_ids[i], ids[i]) for i in range(len(sample))]))
+    # one thread over a fixed 2,000-query slice of the same batch (the strategy mix of the whole)
+    one = sample[:: max(1, len(sample) // 2000)]
+    t0 = time.perf_counter()
+    ref.search(W.queries[one], W.l[one], W.h[one], k, ef, m=m, p=bp, tau_a=ta, tau_b=tb)
+    one_s = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     cpu = {"value": round(passes * len(sample) / cpu_s, 1), "unit": "queries/s", "cores": ncpu, "kind": "oracle",
-           "sample": f"{passes} passes over {len(sample)} of the {nq} queries ({cpu_s:.1f} s), auto strategy, "
-                     f"{prec} store, ef={ef}, m={m}, p={bp}, tau=({ta}, {tb}), same index; {agree:.4f} of them return the GPU's ids"}
-    log(f"CPU oracle: {cpu['value']:,.0f} QPS on {ncpu} threads ({cpu_s:.1f}s), id agreement {agree:.4f}")
+           "sample": f"{passes} passes over {len(sample)} of the {nq} queries ({cpu_s:.1f} s) on {ncpu} threads "
+                     f"(the GPU's share of the host; the affinity mask holds {naff} cores), auto strategy, {prec} "
+                     f"store, ef={ef}, m={m}, p={bp}, tau=({ta}, {tb}), same index; {agree:.4f} of them return the "
+                     f"GPU's ids",
+           "affinity_cores": naff,
+           "cpu_model": model, "single_thread_qps": round(len(one) / one_s, 1),
+           "single_thread_sample": f"every {max(1, len(sample) // 2000)}-th query, {len(one)} queries"}
+    log(f"CPU oracle: {cpu['value']:,.0f} QPS on {ncpu} threads ({cpu_s:.1f}s), id agreement {agree:.4f}; "
+        f"1 thread {cpu['single_thread_qps']:,.0f} QPS; {model}")
     return cpu
 
 

@@ -70,9 +70,14 @@ enum {
 /* Bits of unify_params.flags. */
 enum {
   UNIFY_FLAG_TIMING = 1,    /* record HIP events around the search kernels; see unify_last_timing */
-  UNIFY_FLAG_SELECT_S1 = 2  /* hybrid neighbour selection S1 (Sec. 4.2): rank every entry of the
-                               active chunks by its distance to the expanded object and take the
-                               m nearest, instead of the first ceil(m / S') of each chunk (S2) */
+  UNIFY_FLAG_SELECT_S1 = 2,  /* hybrid neighbour selection S1 (Sec. 4.2): rank every entry of the
+                                active chunks by its distance to the expanded object and take the
+                                m nearest, instead of the first ceil(m / S') of each chunk (S2) */
+  UNIFY_FLAG_PRE_WAVE_SCAN = 4,  /* strategy A by one scan per query and wavefront instead of the
+                                    shared matrix-core scan (same results) */
+  UNIFY_FLAG_SERIAL_PHASES = 8   /* run the matrix-core scan before the graph-search kernel instead
+                                    of beside it on a second stream (same results; each phase's
+                                    timing is then its own) */
 };
 
 /* Search parameters.  Zero in a field selects its default.  The first six fields
@@ -99,6 +104,11 @@ typedef struct {
   int32_t pre_chunk;    /* pre-filter scans with k <= 128 split their slice into chunks of
                            about this many objects (at most 8 chunks), scanned by different
                            wavefronts and merged exactly; default 2048, minimum 64 */
+  int32_t waves_per_query;  /* 1 (default), 2 or 4: wavefronts that run each heavy graph
+                               search together (same results; not with selection S1) */
+  int32_t heavy_queries;    /* graph searches of a batch run that way at most: the first in the
+                               work list, which starts with the narrowest hybrid ranges;
+                               default the number of compute units */
 } unify_params;
 
 /*
@@ -190,7 +200,10 @@ int unify_index_info(unify_index_t index, int64_t* n, int32_t* d, int32_t* S, in
  * nq = 0 is a no-op.  Scratch space is allocated by the library per call.
  * Calls may come from several threads and streams: the search kernels of
  * successive calls on one index run one after another (they share the index's
- * visited-set memory), ordered by an event the library records.
+ * visited-set memory: per resident wavefront, a bitmap of the n objects and a
+ * 32 KiB log, 16 wavefronts per compute unit, made when the index becomes
+ * resident), ordered by an event the library records.  Serving slots hold
+ * visited memory of their own and run concurrently with these calls.
  */
 int unify_search(unify_index_t index, const float* queries, int64_t nq, const int64_t* l,
                  const int64_t* h, int32_t k, int32_t ef, const int8_t* strategy,
@@ -207,7 +220,12 @@ int unify_search(unify_index_t index, const float* queries, int64_t nq, const in
  *              then: the row is padded, 3 = the requested strategy is not one of
  *              UNIFY_AUTO..UNIFY_POST: the row is padded) and flag bits above: bit 8 =
  *              a layer search's visited set outgrew the on-chip cache and continued in
- *              HBM (same results), [4] adjacency entries read, [5] strategy run (-1 for
+ *              HBM (same results), bit 9 = several wavefronts ran the graph search
+ *              together (waves_per_query; such a search keeps its visited set in HBM,
+ *              and which searches run so can differ between calls), [4] adjacency
+ *              entries read (a pre-filter row answered
+ *              by the matrix-core scan: the super-blocks its slice spans; 0 when it was
+ *              scanned per wavefront), [5] strategy run (-1 for
  *              an empty range, -2 for an unknown requested strategy), [6] Y = objects in
  *              range, [7] active segments (hybrid only, else 0).
  */
@@ -279,14 +297,28 @@ int unify_merge_or(const int64_t* ids_a, const float* dist_a, const int64_t* ids
 
 /*
  * Durations of the kernels of the last unify_search* call on this index that set
- * UNIFY_FLAG_TIMING, from HIP events recorded on that call's stream:
- *   plan_ms     the plan and work-list kernels;
- *   search_ms   the main search launch (graph searches and pre-filter scans);
+ * UNIFY_FLAG_TIMING, from HIP events recorded on that call's streams:
+ *   plan_ms     everything before the graph-search kernel: plan and work list (and,
+ *               with UNIFY_FLAG_SERIAL_PHASES, the matrix-core pre-filter scan);
+ *   search_ms   the graph-search launch (graph searches and the pre-filter scans that
+ *               run per wavefront), by default concurrent with the matrix-core scan,
+ *               until both have finished, and the merge of split scans;
  *   rerun_ms    the launch that re-runs queries whose on-chip lists overflowed.
  * Waits for the events to complete.  Outputs are host pointers, any may be NULL.
  * Returns UNIFY_EINVAL when no timed search has been issued.
  */
 int unify_last_timing(unify_index_t index, float* plan_ms, float* search_ms, float* rerun_ms);
+
+/*
+ * The same, phase by phase: out_ms (host, n entries, 1 <= n <= 7) receives in order
+ * the plan and work list; the matrix-core scan's set-up (query split, super-block
+ * lists); its scan kernel; its results (FP32 re-scores); the graph-search kernel;
+ * the merge of split scans (with, by default, the wait for the matrix-core scan,
+ * which runs beside the graph search); the re-run.  Phases that did not run last
+ * 0 ms.  The graph-search phase starts after the work list (after the matrix-core
+ * scan with UNIFY_FLAG_SERIAL_PHASES).
+ */
+int unify_last_timing_ex(unify_index_t index, float* out_ms, int32_t n);
 
 /*
  * Selects the store later searches on this index rank by (UNIFY_FP32, UNIFY_BF16,
@@ -335,11 +367,16 @@ int unify_batch_free(unify_batch_t batch);  /* NULL is accepted */
  * Serving: continuous batching over a resident index (one worker thread per
  * server).  Requests are submitted from host memory with an arrival time; the
  * worker admits the requests that have arrived into a batch whenever one of
- * its `inflight` slots is free (each slot holds pinned staging, device buffers
- * and scratch for max_batch queries, allocated at creation, so admission is
- * bounded by slot memory and no allocation happens while serving), searches it
- * on the slot's stream and completes the requests when the slot's event fires.
- * Every request's result is the one unify_search returns for it alone.
+ * its `inflight` slots is free, searches it on the slot's stream and completes
+ * the requests when the slot's event fires.  Each slot holds pinned staging,
+ * device buffers and scratch for a batch and its own visited-set memory, all
+ * allocated at creation (again only after an insertion grows the index), so
+ * the search kernels of different slots run concurrently on the device.
+ * Admission is by device memory: the batch size (at most max_batch), then the
+ * visited rows of each slot (at most one per resident wavefront of the device),
+ * halve until `inflight` slots fit mem_budget bytes; unify_server_limits
+ * reports the outcome.  Every request's result is the one unify_search returns
+ * for it alone.
  */
 typedef struct unify_server* unify_server_t;
 typedef struct {
@@ -349,6 +386,8 @@ typedef struct {
   double max_wait_s;      /* a partial batch waits until its oldest request has waited this
                              long (0: it launches as soon as a slot is free) */
   unify_params params;    /* search parameters (flags ignored) */
+  int64_t mem_budget;     /* device bytes the slots may hold; 0: half the free device memory.
+                             UNIFY_ENOMEM when it holds no slots of 64 queries and 64 rows */
 } unify_server_config;
 
 int unify_server_create(unify_index_t index, const unify_server_config* config, unify_server_t* out);
@@ -363,6 +402,10 @@ int unify_server_submit(unify_server_t server, int64_t n, const float* queries, 
  * be NULL.  UNIFY_EIO on time-out.  Results stay retrievable until the server is freed. */
 int unify_server_wait(unify_server_t server, int64_t n, const int64_t* tickets, int64_t* ids, float* dist,
                       double* latency_s, double timeout_s);
+/* The admission the memory budget allowed: requests per batch, visited rows per slot,
+ * and the device bytes all slots hold (any pointer may be NULL). */
+int unify_server_limits(unify_server_t server, int64_t* max_batch, int64_t* visit_rows,
+                        int64_t* device_bytes);
 /* Requests completed, batches launched, and seconds with at least one batch in flight. */
 int unify_server_stats(unify_server_t server, int64_t* completed, int64_t* batches, double* busy_s);
 /* Serves every submitted request, stops the worker and frees the server (NULL accepted). */

@@ -19,6 +19,8 @@ __all__ = ["Index", "UnifyError", "AUTO", "PRE", "HYBRID", "POST", "FP32", "BF16
 AUTO, PRE, HYBRID, POST = 0, 1, 2, 3
 FLAG_TIMING = 1
 FLAG_SELECT_S1 = 2
+FLAG_PRE_WAVE_SCAN = 4
+FLAG_SERIAL_PHASES = 8
 FP32, BF16, FP8E4M3 = 0, 1, 2
 _PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8E4M3, "fp8e4m3": FP8E4M3}
 
@@ -38,13 +40,15 @@ class UnifyError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("m", C.c_int32), ("beam_p", C.c_int32), ("rerank_mult", C.c_int32),
                 ("tau_a_frac", C.c_double), ("tau_b_frac", C.c_double), ("flags", C.c_uint32),
-                ("cand_cap", C.c_int32), ("visit_cap", C.c_int32), ("pre_chunk", C.c_int32)]
+                ("cand_cap", C.c_int32), ("visit_cap", C.c_int32), ("pre_chunk", C.c_int32),
+                ("waves_per_query", C.c_int32), ("heavy_queries", C.c_int32)]
 
 
 def _params(m=0, beam_p=0, rerank_mult=0, tau_a=0.0, tau_b=0.0, flags=0, cand_cap=0, visit_cap=0,
-            pre_chunk=0) -> _Params:
+            pre_chunk=0, waves_per_query=0, heavy_queries=0) -> _Params:
     return _Params(m=m, beam_p=beam_p, rerank_mult=rerank_mult, tau_a_frac=tau_a, tau_b_frac=tau_b, flags=flags,
-                   cand_cap=cand_cap, visit_cap=visit_cap, pre_chunk=pre_chunk)
+                   cand_cap=cand_cap, visit_cap=visit_cap, pre_chunk=pre_chunk, waves_per_query=waves_per_query,
+                   heavy_queries=heavy_queries)
 
 
 _lib = None
@@ -61,6 +65,7 @@ SIGNATURES = {
     "unify_search_ex": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "unify_search_ex_noalloc": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "unify_last_timing": (_I32, [_P, _P, _P, _P]),
+    "unify_last_timing_ex": (_I32, [_P, _P, _I32]),
     "unify_copy_store": (_I32, [_P, _I32, _P, _P, _P, _P]),
     "unify_set_precision": (_I32, [_P, _I32]),
     "unify_insert": (_I32, [_P, _P, _P, _P, _I64]),
@@ -71,6 +76,7 @@ SIGNATURES = {
     "unify_server_create": (_I32, [_P, _P, _P]),
     "unify_server_submit": (_I32, [_P, _I64, _P, _P, _P, _P, _P, _P]),
     "unify_server_wait": (_I32, [_P, _I64, _P, _P, _P, _P, C.c_double]),
+    "unify_server_limits": (_I32, [_P, _P, _P, _P]),
     "unify_server_stats": (_I32, [_P, _P, _P, _P]),
     "unify_server_free": (_I32, [_P]),
     "unify_batch_run": (_I32, [_P, _P]),
@@ -127,6 +133,9 @@ def merge_or(a, b, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream(ia.device)
     _check(load_library().unify_merge_or(_ptr(ia), _ptr(da), _ptr(ib), _ptr(db), ia.shape[0], ia.shape[1],
                                          _ptr(oi), _ptr(od), s.cuda_stream))
+    if s != torch.cuda.current_stream(ia.device):
+        for t in (ia, da, ib, db, oi, od):
+            t.record_stream(s)  # in use on s until it passes this point
     return oi, od
 
 
@@ -212,8 +221,12 @@ class Index:
         else:
             raise UnifyError(-22, "the index has no low-precision store")
         eps = torch.empty(self.n, dtype=torch.float32, device=dev)
-        st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
-        _check(load_library().unify_copy_store(self._h, prec, _ptr(codes), _ptr(sc), _ptr(eps), st))
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        _check(load_library().unify_copy_store(self._h, prec, _ptr(codes), _ptr(sc), _ptr(eps), s.cuda_stream))
+        if s != torch.cuda.current_stream(dev):
+            for t in (codes, sc, eps):
+                if t is not None:
+                    t.record_stream(s)  # in use on s until it passes this point
         return codes, sc, eps
 
     def save(self, path: str) -> None:
@@ -236,17 +249,28 @@ class Index:
         _check(load_library().unify_last_timing(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
 
+    def last_timing_phases(self) -> dict:
+        """Per-phase milliseconds of the last search issued with timing=True (waits for it)."""
+        t = (C.c_float * 7)()
+        _check(load_library().unify_last_timing_ex(self._h, t, 7))
+        names = ("plan", "tile_setup", "tile_scan", "tile_final", "search", "merge", "rerun")
+        return {nm: float(v) for nm, v in zip(names, t)}
+
     def search(self, queries, l, h, k: int, ef: int, strategy=None, m: int = 0, beam_p: int = 1,
                rerank_mult: int = 0, tau_a: float = 0.0, tau_b: float = 0.0, stats: bool = False,
                out=None, stream=None, timing: bool = False, cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0,
-               select_s1: bool = False, l2=None, h2=None):
+               select_s1: bool = False, l2=None, h2=None, wave_scan: bool = False, waves_per_query: int = 0,
+               heavy_queries: int = 0, serial_phases: bool = False):
         """Enqueues a search on the current stream (or `stream`) and returns torch tensors.
 
         queries: cuda float32 [nq, d]; l, h: cuda int64 [nq] (inclusive); strategy: None (auto),
         an int for every query, or a cuda int8 [nq] tensor.  select_s1: hybrid neighbour selection S1
         (the m entries of the active chunks nearest the expanded object) instead of S2 (the first
         ceil(m / S') of each chunk).  l2, h2: cuda int64 [nq] inclusive ranges on the second
-        attribute (conjunctive query; set_attr2 first).  Returns (ids, dist, strategy[, stats]).
+        attribute (conjunctive query; set_attr2 first).  wave_scan: pre-filter scans per
+        wavefront instead of the shared matrix-core scan (same results).  serial_phases: the
+        matrix-core scan before the graph search rather than beside it (same results; for
+        timing each phase alone).  Returns (ids, dist, strategy[, stats]).
         """
         import torch
         dev = torch.device("cuda", self.device)
@@ -271,8 +295,10 @@ class Index:
             sts = torch.empty((nq, 8), dtype=torch.int32, device=dev) if stats else None
         else:
             ids, dist, ost, sts = out
-        flags = (FLAG_TIMING if timing else 0) | (FLAG_SELECT_S1 if select_s1 else 0)
-        prm = _params(m, beam_p, rerank_mult, tau_a, tau_b, flags, cand_cap, visit_cap, pre_chunk)
+        flags = ((FLAG_TIMING if timing else 0) | (FLAG_SELECT_S1 if select_s1 else 0)
+                 | (FLAG_PRE_WAVE_SCAN if wave_scan else 0) | (FLAG_SERIAL_PHASES if serial_phases else 0))
+        prm = _params(m, beam_p, rerank_mult, tau_a, tau_b, flags, cand_cap, visit_cap, pre_chunk, waves_per_query,
+                      heavy_queries)
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         lib = load_library()
         if (l2 is None) != (h2 is None):
@@ -291,6 +317,12 @@ class Index:
             rc = lib.unify_search(self._h, _ptr(queries), nq, _ptr(l), _ptr(h), k, ef, _ptr(st), C.byref(prm),
                                   _ptr(ids), _ptr(dist), _ptr(ost), s.cuda_stream)
         _check(rc)
+        if s != torch.cuda.current_stream(dev):
+            # the kernels use these tensors on `s`: the caching allocator must not hand their
+            # memory out again before that stream has passed this point
+            for t in (queries, l, h, st, ids, dist, ost, sts, l2, h2):
+                if t is not None:
+                    t.record_stream(s)
         return (ids, dist, ost, sts) if stats else (ids, dist, ost)
 
 
@@ -303,7 +335,9 @@ class Batch:
 
     def __init__(self, index: Index, queries, l, h, k: int, ef: int, strategy=None, stats: bool = False,
                  m: int = 0, beam_p: int = 1, rerank_mult: int = 0, tau_a: float = 0.0, tau_b: float = 0.0,
-                 cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0, select_s1: bool = False):
+                 cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0, select_s1: bool = False,
+                 wave_scan: bool = False, waves_per_query: int = 0, heavy_queries: int = 0,
+                 serial_phases: bool = False):
         import torch
         dev = torch.device("cuda", index.device)
         nq = queries.shape[0]
@@ -320,8 +354,10 @@ class Batch:
         self.dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
         self.strategy_run = torch.empty((nq,), dtype=torch.int8, device=dev)
         self.stats = torch.empty((nq, 8), dtype=torch.int32, device=dev) if stats else None
-        prm = _params(m, beam_p, rerank_mult, tau_a, tau_b, FLAG_SELECT_S1 if select_s1 else 0, cand_cap, visit_cap,
-                      pre_chunk)
+        flags = ((FLAG_SELECT_S1 if select_s1 else 0) | (FLAG_PRE_WAVE_SCAN if wave_scan else 0)
+                 | (FLAG_SERIAL_PHASES if serial_phases else 0))
+        prm = _params(m, beam_p, rerank_mult, tau_a, tau_b, flags, cand_cap, visit_cap, pre_chunk, waves_per_query,
+                      heavy_queries)
         torch.cuda.synchronize(dev)  # the tensors above exist before the capture reads their addresses
         self._b = C.c_void_p()
         _check(load_library().unify_batch_create(index._h, _ptr(queries), nq, _ptr(l), _ptr(h), k, ef,
@@ -347,22 +383,25 @@ class Batch:
 
 class _ServerConfig(C.Structure):
     _fields_ = [("k", C.c_int32), ("ef", C.c_int32), ("max_batch", C.c_int32), ("inflight", C.c_int32),
-                ("max_wait_s", C.c_double), ("params", _Params)]
+                ("max_wait_s", C.c_double), ("params", _Params), ("mem_budget", C.c_int64)]
 
 
 class Server:
     """Continuous-batching server over a resident index (the library's worker
-    thread admits arrived requests into batches of at most max_batch whenever
-    one of `inflight` slots is free).  Requests come from host arrays."""
+    thread admits arrived requests into batches whenever one of `inflight`
+    slots is free; each slot has its own visited memory, so slots overlap on the
+    device; the batch size and visited rows fit mem_budget bytes, 0 = half the
+    free device memory).  Requests come from host arrays."""
 
     def __init__(self, index: Index, k: int, ef: int, max_batch: int = 4096, inflight: int = 2,
                  max_wait_s: float = 0.0, m: int = 0, beam_p: int = 1, rerank_mult: int = 0, tau_a: float = 0.0,
                  tau_b: float = 0.0, cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0,
-                 select_s1: bool = False):
+                 select_s1: bool = False, waves_per_query: int = 0, heavy_queries: int = 0, mem_budget: int = 0):
         self.index, self.k = index, k
         flags = FLAG_SELECT_S1 if select_s1 else 0
         cfg = _ServerConfig(k, ef, max_batch, inflight, max_wait_s,
-                            _params(m, beam_p, rerank_mult, tau_a, tau_b, flags, cand_cap, visit_cap, pre_chunk))
+                            _params(m, beam_p, rerank_mult, tau_a, tau_b, flags, cand_cap, visit_cap, pre_chunk,
+                                    waves_per_query, heavy_queries), int(mem_budget))
         self._s = C.c_void_p()
         _check(load_library().unify_server_create(index._h, C.byref(cfg), C.byref(self._s)))
 
@@ -392,6 +431,12 @@ class Server:
         _check(load_library().unify_server_wait(self._s, n, t.ctypes.data, ids.ctypes.data, dist.ctypes.data,
                                                 lat.ctypes.data, float(timeout_s)))
         return ids, dist, lat
+
+    def limits(self):
+        """(requests per batch, visited rows per slot, device bytes of the slots) the budget admitted."""
+        b, r, m = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(load_library().unify_server_limits(self._s, C.byref(b), C.byref(r), C.byref(m)))
+        return b.value, r.value, m.value
 
     def stats(self):
         """(requests completed, batches launched, seconds with a batch in flight)."""

@@ -143,3 +143,116 @@ def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256),
             if qps > 1.03 * best.qps:
                 best = cand
     return best, table
+
+
+# ---------------------------------------------------------------------------
+# Calibration of the strategy thresholds (Sec. 4.2, "Range-aware Strategy
+# Selection"): objects sampled from the base set serve as queries, each with a
+# random range; the samples run under each of the three strategies, and at a
+# recall target the two turning points -- where pre-filtering stops beating the
+# hybrid search and where post-filtering starts to -- give tau_A and tau_B.
+# On the GPU a query's latency is not observable alone, so the samples are
+# grouped into buckets of similar cardinality Y and each bucket is timed as
+# one batch per strategy: its per-query time is the batch time over its size.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Calibration:
+    tau_a: float          # fraction of n: pre-filtering when Y <= tau_a * n
+    tau_b: float          # fraction of n: post-filtering when Y >= tau_b * n
+    y_lo: list            # per bucket: smallest and largest Y of its samples
+    y_hi: list
+    recall: dict          # strategy name -> per-bucket recall@k
+    us_per_query: dict    # strategy name -> per-bucket microseconds per query
+
+
+def sample_ranges(attr, nsamp: int, rng, f_min: float = None):
+    """Random ranges over the base attributes: Y = round(f n) consecutive objects in
+    attribute order, f log-uniform in [f_min, 1] (f_min = 1/n by default), start
+    uniform.  Returns inclusive bounds (l, h) and Y per sample."""
+    a = np.sort(np.asarray(attr, np.int64))
+    n = len(a)
+    f_min = 1.0 / n if f_min is None else f_min
+    f = np.exp(rng.uniform(np.log(f_min), 0.0, nsamp))
+    y = np.clip(np.rint(f * n).astype(np.int64), 1, n)
+    start = (rng.random(nsamp) * (n - y + 1)).astype(np.int64)
+    l, h = a[start], a[start + y - 1]
+    # equal attribute values make a range hold a few more objects than asked
+    ylo = np.searchsorted(a, l, "left")
+    yhi = np.searchsorted(a, h, "right")
+    return l, h, yhi - ylo
+
+
+def turning_points(y_lo, y_hi, recall, us, target: float, n: int):
+    """tau_A and tau_B (fractions of n) from per-bucket records, buckets ascending in Y.
+    A strategy counts in a bucket only when its recall reaches the target; pre-
+    filtering wins a bucket when it counts and the hybrid search does not or is not
+    faster, post-filtering likewise.  tau_A ends the run of buckets from the smallest
+    Y that pre-filtering wins; tau_B starts the run of buckets up to the largest Y
+    that post-filtering wins, and is never below tau_A."""
+    nb = len(y_lo)
+
+    def wins(s, b):
+        ok = recall[s][b] >= target
+        hy = recall["hybrid"][b] >= target
+        return ok and (not hy or us[s][b] <= us["hybrid"][b])
+
+    a = 0
+    while a < nb and wins("pre", a):
+        a += 1
+    b = nb
+    while b > a and wins("post", b - 1):
+        b -= 1
+    # half an object of margin, so that floor(tau_A n) and ceil(tau_B n) land on the edges
+    # (and a tau_A for "no pre-filter zone" stays positive: zero selects the default)
+    tau_a = (y_hi[a - 1] + 0.5 if a > 0 else 0.5) / n
+    tau_b = (y_lo[b] - 0.5) / n if b < nb else 1.0
+    tau_b = max(tau_b, tau_a)
+    return min(tau_a, 1.0), min(tau_b, 1.0)
+
+
+def calibrate_tau(index, queries, attr, k: int, ef: int, target: float, m: int = 0, beam_p: int = 1,
+                  buckets: int = 16, per_bucket: int = 512, reps: int = 5, seed: int = 0, log=None):
+    """Sec. 4.2's threshold calibration on the GPU.  queries: host float32 [s, d], objects
+    sampled from the base set (s >= buckets * per_bucket rows are used, cycling if fewer);
+    attr: the base attributes (host int64 [n]).  Runs every bucket of samples under the
+    forced pre-filter, hybrid and post-filter strategies with (k, ef, m, beam_p), scores
+    recall@k against the exact answers (the FP32 pre-filter scan), and returns a
+    Calibration whose tau_a, tau_b are the turning points at the target."""
+    import torch
+    from . import HYBRID, POST, PRE
+    rng = np.random.default_rng(seed)
+    n = len(attr)
+    ns = buckets * per_bucket
+    l, h, y = sample_ranges(attr, ns, rng)
+    order = np.argsort(y, kind="stable")
+    q = np.asarray(queries, np.float32)
+    q = q[np.arange(ns) % len(q)]
+    dev = torch.device("cuda", index.device)
+    y_lo, y_hi = [], []
+    rec = {"pre": [], "hybrid": [], "post": []}
+    us = {"pre": [], "hybrid": [], "post": []}
+    for bkt in range(buckets):
+        sel = order[bkt * per_bucket:(bkt + 1) * per_bucket]
+        Q = torch.from_numpy(np.ascontiguousarray(q[sel])).to(dev)
+        L = torch.from_numpy(np.ascontiguousarray(l[sel])).to(dev)
+        H = torch.from_numpy(np.ascontiguousarray(h[sel])).to(dev)
+        truth = exact_answers(index, Q, L, H, k)
+        y_lo.append(int(y[sel].min()))
+        y_hi.append(int(y[sel].max()))
+        for name, st in (("pre", PRE), ("hybrid", HYBRID), ("post", POST)):
+            kw = dict(strategy=st, m=m, beam_p=beam_p)
+            ids, _, _ = index.search(Q, L, H, k, ef, **kw)
+            torch.cuda.synchronize()
+            rec[name].append(recall_at_k(ids.cpu().numpy(), truth))
+            t = time.perf_counter()
+            for _ in range(reps):
+                index.search(Q, L, H, k, ef, **kw)
+            torch.cuda.synchronize()
+            us[name].append((time.perf_counter() - t) / (reps * len(sel)) * 1e6)
+        if log:
+            log(f"calibrate Y in [{y_lo[-1]}, {y_hi[-1]}]: recall pre/hybrid/post "
+                f"{rec['pre'][-1]:.3f}/{rec['hybrid'][-1]:.3f}/{rec['post'][-1]:.3f}, us/query "
+                f"{us['pre'][-1]:.3f}/{us['hybrid'][-1]:.3f}/{us['post'][-1]:.3f}")
+    ta, tb = turning_points(y_lo, y_hi, rec, us, target, n)
+    return Calibration(ta, tb, y_lo, y_hi, rec, us)

@@ -122,9 +122,9 @@ int make_resident(HostIndex&& H, int device, int precision, unify_index_t* out) 
   up(H.adjU, &dv.adjU);
   up(gU, &dv.glistU);
   if (rc == UNIFY_OK) rc = quantize_store(ix, precision);
-  if (rc == UNIFY_OK) rc = ensure_tags(ix);
+  if (rc == UNIFY_OK) rc = ensure_pool(ix);
   if (rc != UNIFY_OK) {
-    if (ix->last_search) (void)hipEventDestroy(ix->last_search);
+    pool_free(ix->pool);
     for (void* p : ix->allocs) (void)hipFree(p);
     delete ix;
     return rc;
@@ -361,10 +361,10 @@ int unify_set_attr2(unify_index_t ix, const int64_t* attr2, int64_t n) {
     set_error("host-to-device copy failed");
     return UNIFY_EDEVICE;
   }
-  // searches enqueued before may still read the previous array
-  if (ix->last_search && hipEventSynchronize(ix->last_search) != hipSuccess) {
+  // searches enqueued before (on any visited pool) may still read the previous array
+  if (hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(p);
-    set_error("hipEventSynchronize failed");
+    set_error("hipDeviceSynchronize failed");
     return UNIFY_EDEVICE;
   }
   void* old = const_cast<int64_t*>(ix->dv.attr2);
@@ -380,25 +380,38 @@ int unify_set_attr2(unify_index_t ix, const int64_t* attr2, int64_t n) {
   return UNIFY_OK;
 }
 
-int unify_last_timing(unify_index_t ix, float* plan_ms, float* search_ms, float* rerun_ms) {
+int unify_last_timing_ex(unify_index_t ix, float* out_ms, int32_t n) {
   if (!ix || !ix->timed) {
     set_error("no timed search on this index");
     return UNIFY_EINVAL;
   }
-  if (hipSetDevice(ix->device) != hipSuccess || hipEventSynchronize(ix->ev[3]) != hipSuccess) {
+  if (!out_ms || n < 1 || n > 7) {
+    set_error("unify_last_timing_ex: out_ms needs 1..7 entries");
+    return UNIFY_EINVAL;
+  }
+  if (hipSetDevice(ix->device) != hipSuccess || hipEventSynchronize(ix->ev[7]) != hipSuccess) {
     set_error("hipEventSynchronize failed");
     return UNIFY_EDEVICE;
   }
-  float a = 0.f, b = 0.f, c = 0.f;
-  if (hipEventElapsedTime(&a, ix->ev[0], ix->ev[1]) != hipSuccess ||
-      hipEventElapsedTime(&b, ix->ev[1], ix->ev[2]) != hipSuccess ||
-      hipEventElapsedTime(&c, ix->ev[2], ix->ev[3]) != hipSuccess) {
-    set_error("hipEventElapsedTime failed");
-    return UNIFY_EDEVICE;
+  for (int i = 0; i < n; ++i) {
+    // the graph-search phase starts after the work list when the matrix-core scan ran beside it
+    const int from = (i == 4 && ix->timed_side) ? 1 : i;
+    if (hipEventElapsedTime(&out_ms[i], ix->ev[from], ix->ev[i + 1]) != hipSuccess) {
+      set_error("hipEventElapsedTime failed");
+      return UNIFY_EDEVICE;
+    }
   }
-  if (plan_ms) *plan_ms = a;
-  if (search_ms) *search_ms = b;
-  if (rerun_ms) *rerun_ms = c;
+  return UNIFY_OK;
+}
+
+int unify_last_timing(unify_index_t ix, float* plan_ms, float* search_ms, float* rerun_ms) {
+  float t[7];
+  const int rc = unify_last_timing_ex(ix, t, 7);
+  if (rc != UNIFY_OK) return rc;
+  const bool side = ix->timed_side;
+  if (plan_ms) *plan_ms = side ? t[0] : t[0] + t[1] + t[2] + t[3];
+  if (search_ms) *search_ms = t[4] + t[5];
+  if (rerun_ms) *rerun_ms = t[6];
   return UNIFY_OK;
 }
 
@@ -417,6 +430,7 @@ int unify_batch_free(unify_batch_t b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->scratch) (void)hipFree(b->scratch);
+  free_side(b->side);
   delete b;
   return UNIFY_OK;
 }
@@ -426,7 +440,7 @@ int unify_free_index(unify_index_t ix) {
   (void)hipSetDevice(ix->device);
   for (hipEvent_t e : ix->ev)
     if (e) (void)hipEventDestroy(e);
-  if (ix->last_search) (void)hipEventDestroy(ix->last_search);
+  pool_free(ix->pool);
   for (void* p : ix->allocs)
     if (p) (void)hipFree(p);
   delete ix;

@@ -1444,21 +1444,18 @@ int insert_impl(unify_index_t ix, const float* vectors, const int64_t* attr, con
   // swap between searches: wait for every search enqueued on the old version
   std::unique_lock<std::shared_mutex> wl(ix->version_mu);
   const int precision = ix->dv.precision;  // as the caller last set it
-  if (ix->last_search) BHIP(hipEventSynchronize(ix->last_search));
-  BHIP(hipDeviceSynchronize());
+  BHIP(hipDeviceSynchronize());  // every search, on any visited pool
   for (void* p : ix->allocs)
     if (p) (void)hipFree(p);
   ix->allocs = V.ptrs;
   V.keep = true;
-  ix->tags = nullptr;
-  ix->epochs = nullptr;
-  ix->nslots = 0;
   for (auto& e : ix->eps_of) e = nullptr;
+  for (auto& e : ix->nrm_of) e = nullptr;
   ix->dv = nv;
   ix->host = std::move(H);
   ++ix->version;
   const int rc = quantize_store(ix, precision);
-  return rc == UNIFY_OK ? ensure_tags(ix) : rc;
+  return rc == UNIFY_OK ? ensure_pool(ix) : rc;  // rows for the new size
 }
 
 }  // namespace unify

@@ -13,9 +13,14 @@ namespace {
 
 constexpr int QW = 4;  // rows (one wavefront each) per 256-thread block
 
-// FP8 scale of a row: max_t |x_t| / 448, 1 for a zero row.  The division is
-// done in FP64 and rounded to FP32, which gives the correctly rounded FP32
-// quotient (FP64 carries more than twice FP32's significand plus two bits).
+// FP8 scale of a row: max_t |x_t| / 448, 1 for a zero row, by correctly rounded
+// FP32 division (the device default for `/`), as are the quotients x_t / s.
+// eps_v bounds ||copy_v - x_v||: each difference e_t = back_t - x_t is exact in
+// FP32 (the two values lie within a factor of two of each other, or one is
+// zero), and the sum of the e_t^2 passes through at most d / 64 + 7 roundings
+// to nearest (products, a lane's sum, six shuffle additions), so widening the
+// root of the computed sum by 2^-18 relative covers them for d <= 2048; 1e-21
+// covers squares that underflow.  An exact copy gets 0.
 template <int PREC>
 __global__ void __launch_bounds__(256) k_quant(const float* __restrict__ vec, int64_t n, int d,
                                                uint16_t* __restrict__ bf, uint8_t* __restrict__ f8,
@@ -29,9 +34,10 @@ __global__ void __launch_bounds__(256) k_quant(const float* __restrict__ vec, in
     float mx = 0.0f;
     for (int t = lane; t < d; t += 64) mx = fmaxf(mx, fabsf(x[t]));
     for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-    if (mx > 0.0f) s = (float)((double)mx / 448.0);
+    if (mx > 0.0f) s = mx / 448.0f;
   }
-  double e2 = 0.0;
+  float e2 = 0.0f;
+  bool nz = false;  // some difference is not zero (its square may underflow)
   for (int t = lane; t < d; t += 64) {
     const float xt = x[t];
     float back;
@@ -40,20 +46,67 @@ __global__ void __launch_bounds__(256) k_quant(const float* __restrict__ vec, in
       bf[v * d + t] = (uint16_t)c;
       back = bf16_to_f32(c);
     } else {
-      const float y = (float)((double)xt / (double)s);
-      const uint32_t c = f32_to_e4m3(y);
+      const uint32_t c = f32_to_e4m3(xt / s);
       f8[v * d + t] = (uint8_t)c;
       back = fp8_value(c, s);
     }
-    const double e = (double)back - (double)xt;  // exact in FP64
-    e2 += e * e;
+    const float e = back - xt;  // exact
+    e2 = __builtin_fmaf(e, e, e2);
+    nz = nz || e != 0.0f;
   }
   for (int o = 32; o >= 1; o >>= 1) e2 += __shfl_xor(e2, o, 64);
+  nz = __ballot(nz) != 0;
   if (lane == 0) {
     if constexpr (PREC == UNIFY_FP8E4M3) scale[v] = s;
-    // FP64 rounding of the sum and the root is far below 2^-30 relative
-    eps[v] = __double2float_ru(sqrt(e2) * (1.0 + 0x1p-30));
+    eps[v] = nz ? __builtin_sqrtf(e2) * (1.0f + 0x1p-18f) + 1e-21f : 0.0f;  // 0 exactly for an exact copy
   }
+}
+
+// Squared norm of every row of the store PREC (as the searches decode it),
+// in FP32 by fused multiply-adds: the norm-expansion scan bounds its error by
+// (d + 8) u times the exact value.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_rownorm(DevIndex ix, float* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * QW + (threadIdx.x >> 6);
+  if (v >= ix.n) return;  // uniform per wavefront
+  const int d = ix.d;
+  float acc = 0.0f;
+  for (int t = lane; t < d; t += 64) {
+    float x;
+    if constexpr (PREC == UNIFY_FP32) x = ix.vec[v * d + t];
+    else if constexpr (PREC == UNIFY_BF16) x = bf16_to_f32(ix.vec_bf16[v * d + t]);
+    else x = fp8_value(ix.vec_fp8[v * d + t], ix.vec_scale[v]);
+    acc = __builtin_fmaf(x, x, acc);
+  }
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) out[v] = acc;
+}
+
+// The squared row norms of the store `precision` (built the first time), made
+// the ones later searches read.  Synchronous.
+int store_norms(unify_index_t ix, int precision) {
+  DevIndex& dv = ix->dv;
+  if (!ix->nrm_of[precision] && dv.n > 0) {
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(float) * dv.n) != hipSuccess) {
+      set_error("device allocation failed (row norms)");
+      return UNIFY_ENOMEM;
+    }
+    ix->allocs.push_back(p);
+    const dim3 grid((unsigned)((dv.n + QW - 1) / QW));
+    if (precision == UNIFY_BF16) hipLaunchKernelGGL(k_rownorm<UNIFY_BF16>, grid, dim3(256), 0, 0, dv, (float*)p);
+    else if (precision == UNIFY_FP8E4M3)
+      hipLaunchKernelGGL(k_rownorm<UNIFY_FP8E4M3>, grid, dim3(256), 0, 0, dv, (float*)p);
+    else hipLaunchKernelGGL(k_rownorm<UNIFY_FP32>, grid, dim3(256), 0, 0, dv, (float*)p);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      set_error("row-norm kernel failed");
+      return UNIFY_EDEVICE;
+    }
+    ix->nrm_of[precision] = (const float*)p;
+  }
+  dv.vec_nrm = ix->nrm_of[precision];
+  return UNIFY_OK;
 }
 
 }  // namespace
@@ -68,7 +121,7 @@ int quantize_store(unify_index_t ix, int precision) {
   if (have) {
     dv.precision = precision;
     dv.vec_eps = ix->eps_of[precision];
-    return UNIFY_OK;
+    return store_norms(ix, precision);
   }
   const size_t cells = (size_t)dv.n * dv.d;
   auto alloc = [&](size_t bytes, void** p) {
@@ -103,7 +156,7 @@ int quantize_store(unify_index_t ix, int precision) {
   ix->eps_of[precision] = (const float*)ep;
   dv.precision = precision;
   dv.vec_eps = (const float*)ep;
-  return UNIFY_OK;
+  return store_norms(ix, precision);
 }
 
 }  // namespace unify

@@ -93,10 +93,15 @@ struct SearchArgs {
   int32_t* next;          // work counter
   int32_t* fb_list;       // queries abandoned by the first pass
   int32_t* fb_count;
-  uint32_t* tags;         // [nslots][n] visited epochs, one row per persistent wave
-  uint32_t* epochs;       // [nslots] last epoch used by each row
+  uint32_t* vrows;        // [nslots][vstride] visited rows, one per persistent wave
+  int64_t vstride;        // words of a row: the bitmap (bwords) then the log (VLOG_CAP)
+  int64_t bwords;         // words of a row's bitmap (ceil(n / 32), padded)
   int64_t nslots;
   const struct ConjArgs* conj;  // conjunctive queries (written by the plan kernel), or null
+  // cooperative searches: heavy queries work[0, *nheavy), their counter, first visited row
+  const int32_t* nheavy;
+  int32_t* mw_next;
+  int64_t mw_row0;
 };
 
 // Second attribute and per-query inclusive ranges of a conjunctive search.  The
@@ -129,6 +134,12 @@ constexpr int WAVES_PER_SIMD_FP32 = 3, WAVES_PER_SIMD_LOW = 4, BF16_ROUNDS = 4;
 constexpr int PRE_NCH_MAX = 8;      // chunks per pre-filter scan at most
 constexpr int PLAN_SAMPLES = 2048;  // sorted attributes staged in LDS by the plan kernel
 constexpr int PRE_SPLIT_KMAX = 128;  // larger k scans its slice in one wavefront
+// Matrix-core pre-filter scan (see k_tile_scan).
+constexpr int TILE_ROWS = 256;  // objects per super-block
+constexpr int TILE_Q = 16;      // queries per matrix tile (the MFMA M dimension)
+constexpr int TILE_KMAX = 32;   // larger k scans per wavefront
+constexpr int TILE_DMAX = 512;  // wider rows scan per wavefront (the tile's queries stay in LDS)
+constexpr int TILE_PAIRS_PER_QUERY = 6;  // record budget per query of a batch (beyond it: per-wave scans)
 constexpr int STRAT_INVALID = -2;    // out_strategy of a row whose requested strategy is unknown
 constexpr int STATUS_INVALID = 3;    // its status counter
 
@@ -160,8 +171,8 @@ __device__ int64_t upper_bound_i64(const int64_t* a, int64_t n, int64_t x) {
 __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t* __restrict__ h,
                        const int64_t* __restrict__ l2, const int64_t* __restrict__ h2,
                        ConjArgs* __restrict__ conj, const int8_t* __restrict__ strat_in, int64_t nq, int64_t tauA, int64_t tauB,
-                       int32_t k, int32_t chunk, QPlan* __restrict__ plan, int8_t* __restrict__ out_strat,
-                       int64_t* __restrict__ out_ids, float* __restrict__ out_dist,
+                       int32_t k, int32_t chunk, int32_t tile_on, QPlan* __restrict__ plan,
+                       int8_t* __restrict__ out_strat, int64_t* __restrict__ out_ids, float* __restrict__ out_dist,
                        int32_t* __restrict__ out_stats) {
   // every stride-th sorted attribute in LDS: the binary searches then touch HBM
   // only inside one stride-long window
@@ -212,6 +223,8 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
   P.nch = 1;
   P.clen = (int32_t)Y;
   P.pbase = 0;
+  P.tsb = 0;
+  P.tbase = 0;
   if (Y > 0) {
     P.a = (int32_t)(upper_bound_i64(ix.seg_start, ix.S + 1, lo) - 1);
     P.b = (int32_t)(upper_bound_i64(ix.seg_start, ix.S + 1, hi - 1) - 1);
@@ -220,6 +233,8 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
       P.nch = (int32_t)std::min<int64_t>(PRE_NCH_MAX, (Y + chunk - 1) / chunk);
       P.clen = (int32_t)((Y + P.nch - 1) / P.nch);
     }
+    // a candidate for the matrix-core scan (the work list decides within its record budget)
+    if (s == UNIFY_PRE && tile_on && !l2) P.tsb = (int32_t)((hi - 1) / TILE_ROWS - lo / TILE_ROWS + 1);
   } else {
     P.strat = -1;
     for (int t = 0; t < k; ++t) {
@@ -250,20 +265,47 @@ __device__ __forceinline__ int graph_bucket(const QPlan& P) {
   return P.strat == UNIFY_HYBRID ? lg : 32 + lg;
 }
 
-__global__ void k_worklist(QPlan* __restrict__ plan, int64_t nq, int64_t n, int32_t* __restrict__ work,
-                           int32_t* __restrict__ wchunk,
-                           int32_t* __restrict__ counters /* nwork, next, fb_count, fb_next */) {
+__global__ void k_worklist(QPlan* __restrict__ plan, int64_t nq, int64_t n, int64_t pcap, int32_t heavy_cap,
+                           int32_t* __restrict__ work, int32_t* __restrict__ wchunk,
+                           int32_t* __restrict__ counters /* nwork, next, fb_count, fb_next, -, tile items,
+                                                             heavy, heavy next */) {
   constexpr int NB = 1024, NG = 64;
   __shared__ int32_t spart[1024];
+  __shared__ int64_t tpart[1024];
   __shared__ int32_t bucket[NB];
   __shared__ int32_t gbucket[NG];
   const int t = threadIdx.x, T = blockDim.x;
   for (int b = t; b < NB; b += T) bucket[b] = 0;
   if (t < NG) gbucket[t] = 0;
+  // records of the matrix-core scan: each thread's candidates in its own query order,
+  // threads in order (a deterministic assignment); a query whose records would pass
+  // pcap is scanned per wavefront instead
+  int64_t tc = 0;
+  for (int64_t q = t; q < nq; q += T) {
+    const QPlan P = plan[q];
+    if (P.strat == UNIFY_PRE && P.tsb > 0) tc += P.tsb;
+  }
+  tpart[t] = tc;
   __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {
+    const int64_t v = t >= off ? tpart[t - off] : 0;
+    __syncthreads();
+    tpart[t] += v;
+    __syncthreads();
+  }
+  int64_t tcur = tpart[t] - tc;
   int32_t sc = 0;
   for (int64_t q = t; q < nq; q += T) {  // interleaved, so that plan reads coalesce
-    const QPlan P = plan[q];
+    QPlan P = plan[q];
+    if (P.strat == UNIFY_PRE && P.tsb > 0) {
+      if (tcur + P.tsb <= pcap) {
+        plan[q].tbase = (int32_t)tcur;
+        tcur += P.tsb;
+        continue;
+      }
+      plan[q].tsb = 0;
+      P.tsb = 0;
+    }
     if (P.strat == UNIFY_HYBRID || P.strat == UNIFY_POST) {
       atomicAdd(&gbucket[graph_bucket(P)], 1);
     } else if (P.strat == UNIFY_PRE) {
@@ -297,7 +339,7 @@ __global__ void k_worklist(QPlan* __restrict__ plan, int64_t nq, int64_t n, int3
       const int32_t w = atomicSub(&gbucket[graph_bucket(P)], 1) - 1;
       work[w] = (int32_t)q;
       wchunk[w] = 0;
-    } else if (P.strat == UNIFY_PRE) {
+    } else if (P.strat == UNIFY_PRE && P.tsb == 0) {
       for (int j = 0; j < P.nch; ++j) {
         const int b = (int)((int64_t)(P.lo + j * P.clen) * NB / n);
         const int32_t w = atomicSub(&bucket[b], 1) - 1;
@@ -311,10 +353,15 @@ __global__ void k_worklist(QPlan* __restrict__ plan, int64_t nq, int64_t n, int3
     }
   }
   if (t == 0) {
+    // the first heavy_cap graph searches (the narrowest hybrid ranges first) go to the
+    // cooperative kernel; the one-wavefront kernel starts after them
+    const int32_t nheavy = min(nbeam, heavy_cap);
     counters[0] = nbeam + nchunks;
-    counters[1] = 0;
+    counters[1] = nheavy;
     counters[2] = 0;
     counters[3] = 0;
+    counters[6] = nheavy;
+    counters[7] = 0;
   }
 }
 
@@ -439,11 +486,25 @@ struct Lds {
 
 // Visited set of one layer search.  An 8-way set-associative cache of ids in
 // LDS is exact while no set has overflowed ("local" mode: a miss proves the id
-// new).  When an insert finds its set full, the wave writes every cached id and
-// the overflowing ones to its HBM tag row (tag == epoch means visited) and
-// switches to "tagged" mode: a cache miss then reads the tag.  Only this wave
-// uses its tag row; workgroup-scope fences order its own stores and loads.
+// new).  When an insert finds its set full, the wave sets the bits of every
+// cached id and of the overflowing ones in its HBM visited row and switches to
+// "tagged" mode: a cache miss then sets the id's bit, and the bit's old value
+// says whether it was visited.  A row is a bitmap of n bits, all clear between
+// layer searches, followed by a log of the bitmap words the layer search made
+// non-zero, which it clears at its end (the whole bitmap if the log overflowed).
+// Only this wave (workgroup) uses its row; workgroup-scope fences order its own
+// stores and loads.
 constexpr int VWAYS = 8;
+constexpr int VLOG_CAP = 8192;  // logged words per row
+
+struct VRow {
+  uint32_t* bits;  // [bwords]
+  uint32_t* log;   // [VLOG_CAP]
+};
+__device__ __forceinline__ VRow vrow_of(const SearchArgs& A, int64_t slot) {
+  uint32_t* r = A.vrows + slot * A.vstride;
+  return VRow{r, r + A.bwords};
+}
 
 __device__ __forceinline__ uint32_t* cache_set(uint32_t* cache, int setbits, int32_t v) {
   const uint32_t set = ((uint32_t)v * 2654435761u) >> (32 - setbits);
@@ -473,15 +534,49 @@ __device__ __forceinline__ bool visit_local(uint32_t* cache, int setbits, int32_
   return true;
 }
 
-// Tagged mode: the tag row is authoritative, the cache only saves reads.  The
-// exchange lets exactly one lane of a batch claim an id the batch holds twice.
-__device__ __forceinline__ bool visit_tagged(uint32_t* cache, int setbits, uint32_t* tags, uint32_t epoch,
-                                             int32_t v) {
+// Sets v's bit in the bitmap: true when it was clear.  `fresh`: the word was
+// zero before (exactly one lane of those that set bits in it sees that), so its
+// index belongs in the log.
+__device__ __forceinline__ bool mark_bit(uint32_t* bits, int32_t v, bool& fresh) {
+  const uint32_t m = 1u << ((uint32_t)v & 31u);
+  const uint32_t old =
+      __hip_atomic_fetch_or(bits + ((uint32_t)v >> 5), m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  fresh = old == 0u;
+  return (old & m) == 0u;
+}
+
+// Tagged mode: the bitmap is authoritative, the cache only saves reads.  The
+// atomic OR lets exactly one lane of a batch claim an id the batch holds twice.
+__device__ __forceinline__ bool visit_tagged(uint32_t* cache, int setbits, uint32_t* bits, int32_t v,
+                                             bool& fresh) {
   uint32_t* base = cache_set(cache, setbits, v);
+  fresh = false;
   if (cache_hit(base, v)) return false;
-  if (__hip_atomic_exchange(tags + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == epoch) return false;
+  if (!mark_bit(bits, v, fresh)) return false;
   base[(uint32_t)v & (VWAYS - 1)] = (uint32_t)v;
   return true;
+}
+
+// Appends the words that `fresh` lanes made non-zero to the log (one wavefront;
+// nlog counts past VLOG_CAP once it overflows).
+__device__ __forceinline__ void log_words(const VRow& R, int& nlog, bool fresh, int32_t v) {
+  const u64 fm = ballot(fresh);
+  if (fresh) {
+    const int i = nlog + rank_in(fm);
+    if (i < VLOG_CAP) R.log[i] = (uint32_t)v >> 5;
+  }
+  nlog += __popcll(fm);
+}
+
+// Leaves the bitmap all clear again: the logged words, or every word when the
+// log overflowed.  Thread t of nt; the caller orders these stores before the
+// row's next use.
+__device__ __forceinline__ void clear_row(const VRow& R, int nlog, int64_t bwords, int t, int nt) {
+  if (nlog <= VLOG_CAP) {
+    for (int i = t; i < nlog; i += nt) R.bits[R.log[i]] = 0u;
+  } else {
+    for (int64_t i = t; i < bwords; i += nt) R.bits[i] = 0u;
+  }
 }
 
 __device__ __forceinline__ void wave_fence() {
@@ -489,28 +584,42 @@ __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Orders one wavefront's LDS writes before its later reads by other lanes, in a
+// block of several independent wavefronts (no block barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The LDS sync of code one wavefront runs: a block barrier where the block is that
+// wavefront (WS = false), a wavefront-level one where other wavefronts of the block
+// run other code (WS = true).
+template <bool WS>
+__device__ __forceinline__ void lsync() {
+  if constexpr (WS) wave_lds_sync();
+  else __syncthreads();
+}
+
 struct Counters {
   int32_t ndist = 0, nexp = 0, nrerank = 0, nadj = 0;
   int32_t spill = 0;  // a layer search's visited set left the LDS cache for the HBM tag row
+  int32_t coop = 0;   // the query ran as a cooperative (several-wavefront) search
 };
 constexpr int32_t STAT_SPILL_BIT = 0x100;  // status counter flag: the visited set spilled to HBM
+constexpr int32_t STAT_COOP_BIT = 0x200;   // status counter flag: a cooperative search
 
 // One layer of the search (Alg. 1 / Alg. 7 with beam width p).  On return, the
 // ann list holds `al` keys ascending.  Returns false on capacity overflow.
 template <int NG, int PREC, bool S1 = false>
 __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
                              Sec sec, bool hybrid, bool filter, int c, int32_t ep, u64 ep_key, int layer, int efl,
-                             int p, int& al, Counters& cnt, uint32_t* tags, uint32_t& epoch) {
+                             int p, int& al, Counters& cnt, const VRow& R) {
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
   int hbits = 0;
   while ((1 << hbits) < A.hcap) ++hbits;
-  // a fresh epoch per layer search; the row is cleared if the counter wraps
-  if (++epoch == 0) {
-    for (int64_t i = lane; i < ix.n; i += WAVE) tags[i] = 0u;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    epoch = 1;
-  }
+  int nlog = 0;  // tagged mode: words logged in R
   for (int i = lane; i < A.hcap; i += WAVE) L.hash[i] = HASH_EMPTY;
   __syncthreads();
   const int setbits = hbits - 3;  // hcap / VWAYS sets
@@ -647,19 +756,24 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
         const int e = base + lane;
         const int32_t v = e < ntot ? (int32_t)(uint32_t)L.bkeys[e] : -1;
         __syncthreads();  // this block is read before new ids are written over it
-        bool isnew = false, full = false;
+        bool isnew = false, full = false, fresh = false;
         if (v >= 0) {
-          isnew = tagged ? visit_tagged(L.hash, setbits, tags, epoch, v)
+          isnew = tagged ? visit_tagged(L.hash, setbits, R.bits, v, fresh)
                          : visit_local(L.hash, setbits, v, full);
         }
+        if (tagged) log_words(R, nlog, fresh, v);
         if (!tagged && __any(full)) {
-          // switch to tagged mode: record every visited id in the tag row
+          // switch to tagged mode: set the bit of every visited id in the row
           for (int i = lane; i < A.hcap; i += WAVE) {
             const uint32_t id = L.hash[i];
-            if (id != HASH_EMPTY) tags[id] = epoch;
+            bool fr = false;
+            if (id != HASH_EMPTY) (void)mark_bit(R.bits, (int32_t)id, fr);
+            log_words(R, nlog, fr, (int32_t)id);
           }
           // an id that found its set full may appear twice in the batch: one lane claims it
-          if (full) isnew = __hip_atomic_exchange(tags + v, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != epoch;
+          bool fr = false;
+          if (full) isnew = mark_bit(R.bits, v, fr);
+          log_words(R, nlog, fr, v);
           tagged = true;
         }
         if (tagged) wave_fence();
@@ -710,7 +824,12 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
     }
     if (overflow) break;
   }
-  if (tagged) cnt.spill = 1;
+  if (tagged) {
+    cnt.spill = 1;
+    wave_fence();  // the log's stores before their loads
+    clear_row(R, nlog, A.bwords, lane, WAVE);
+    wave_fence();  // the clears before the row's next atomics
+  }
   return !__any(overflow);
 }
 
@@ -877,7 +996,7 @@ __device__ bool pre_scan_lowp(const SearchArgs& A, const Lds& L, const float4 (&
 // Graph search results over a BF16 / FP8 copy: the first rerank * k in-range
 // entries of ann (ascending by the copy's distance) are re-scored with the FP32
 // distance into a sorted list of k in L.cand.  Returns that list's length.
-template <int NG>
+template <int NG, bool WS = false>
 __device__ int rerank_graph(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P,
                             Sec sec, int al, bool post, Counters& cnt) {
   const int lane = lane_id();
@@ -885,7 +1004,7 @@ __device__ int rerank_graph(const SearchArgs& A, const Lds& L, const float4 (&qv
   const int R = A.rerank * k;
   int rl = 0, taken = 0;
   for (int blk = 0; blk * WAVE < k; ++blk) L.cand[blk * WAVE + lane] = KEY_MAX;
-  __syncthreads();
+  lsync<WS>();
   for (int base = 0; base < al && taken < R; base += WAVE) {
     const int t = base + lane;
     const u64 key = t < al ? L.ann[t] : KEY_MAX;
@@ -896,15 +1015,15 @@ __device__ int rerank_graph(const SearchArgs& A, const Lds& L, const float4 (&qv
     const u64 um = ballot(keep);
     const int nb = __popcll(um);
     if (nb == 0) continue;
-    __syncthreads();
+    lsync<WS>();
     if (keep) L.bkeys[rank_in(um)] = (uint32_t)id;
-    __syncthreads();
+    lsync<WS>();
     eval_keys<NG, UNIFY_FP32, SHALLOW>(A.ix, qv, nb, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
-    __syncthreads();
+    lsync<WS>();
     const u64 nk = lane < nb ? L.bkeys[lane] : KEY_MAX;
     const u64 T = rl == k ? L.cand[k - 1] : KEY_MAX;
     list_insert(L.cand, rl, k, nk < T ? nk : KEY_MAX);
-    __syncthreads();
+    lsync<WS>();
     taken += nb;
     cnt.nrerank += nb;
   }
@@ -929,11 +1048,60 @@ __device__ void pre_store_chunk(const SearchArgs& A, const Lds& L, int32_t q, co
   }
 }
 
+// Outputs of one query (one wavefront): hybrid / pre take the first k; post keeps
+// in-range entries in order.  Graph results over a low-precision copy come
+// re-scored and filtered.
+template <int NG, int PREC, bool WS = false>
+__device__ void write_result(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P, Sec sec,
+                             int32_t q, int al, bool ok, int status, bool hybrid, Counters& cnt) {
+  const DevIndex& ix = A.ix;
+  const int lane = lane_id();
+  const int kout = A.k;
+  const u64* res = L.ann;
+  bool post_filter = P.strat == UNIFY_POST;
+  if (PREC != UNIFY_FP32 && P.strat != UNIFY_PRE && ok && al > 0) {
+    al = rerank_graph<NG, WS>(A, L, qv, P, sec, al, post_filter, cnt);
+    res = L.cand;
+    post_filter = false;
+  }
+  int written = 0;
+  for (int base = 0; base < al && written < kout; base += WAVE) {
+    const int t = base + lane;
+    const u64 key = t < al ? res[t] : KEY_MAX;
+    const int32_t id = key_id(key);
+    const bool keep = key != KEY_MAX && (!post_filter || (id >= P.lo && id < P.hi && sec_ok(A, sec, id)));
+    const u64 km = ballot(keep);
+    const int pos = written + rank_in(km);
+    if (keep && pos < kout) {
+      A.out_ids[(int64_t)q * kout + pos] = ix.ext[id];
+      A.out_dist[(int64_t)q * kout + pos] = key_dist(key);
+    }
+    written += __popcll(km);
+  }
+  written = min(written, kout);
+  if (!ok) written = 0;
+  for (int t = written + lane; t < kout; t += WAVE) {
+    A.out_ids[(int64_t)q * kout + t] = -1;
+    A.out_dist[(int64_t)q * kout + t] = __builtin_inff();
+  }
+  if (A.out_stats && lane == 0) {
+    int32_t* st = A.out_stats + (int64_t)q * 8;
+    st[0] = cnt.ndist;
+    st[1] = cnt.nexp;
+    st[2] = cnt.nrerank;
+    st[3] = (ok ? status : 2) | (cnt.spill ? STAT_SPILL_BIT : 0) | (cnt.coop ? STAT_COOP_BIT : 0);
+    st[4] = cnt.nadj;
+    st[5] = P.strat;
+    st[6] = P.hi - P.lo;
+    st[7] = hybrid ? P.b - P.a + 1 : 0;
+  }
+}
+
+
 __device__ __forceinline__ bool ne_missing(int top) { return top < 0; }
 
 template <int NG, int PREC, bool S1 = false>
-__device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chunk, uint32_t* tags,
-                          uint32_t& epoch) {
+__device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chunk, const VRow& R) {
   const DevIndex& ix = A.ix;
   const int lane = lane_id();
   const QPlan P = A.plan[q];
@@ -952,7 +1120,6 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
   int al = 0;
   bool ok = true;
   const bool hybrid = P.strat == UNIFY_HYBRID;
-  int kout = A.k;
   int status = A.pass;
   if (P.strat == UNIFY_PRE) {
     QPlan Pc = P;  // this chunk of the slice
@@ -1018,15 +1185,13 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
       __syncthreads();
     }
     for (int layer = top; layer >= 1 && ok; --layer) {
-      ok = layer_search<NG, PREC, S1>(A, L, qv, P, sec, hybrid, false, c, ep, ep_key, layer, 1, 1, al, cnt, tags,
-                                      epoch);
+      ok = layer_search<NG, PREC, S1>(A, L, qv, P, sec, hybrid, false, c, ep, ep_key, layer, 1, 1, al, cnt, R);
       ep_key = L.ann[0];
       ep = key_id(ep_key);
       __syncthreads();
     }
     if (ok)
-      ok = layer_search<NG, PREC, S1>(A, L, qv, P, sec, hybrid, hybrid, c, ep, ep_key, 0, A.ef, A.p, al, cnt, tags,
-                                      epoch);
+      ok = layer_search<NG, PREC, S1>(A, L, qv, P, sec, hybrid, hybrid, c, ep, ep_key, 0, A.ef, A.p, al, cnt, R);
     if (ne_missing(top)) {
       al = 0;
       ok = true;
@@ -1041,45 +1206,354 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
       return;
     }
   }
-  // outputs: hybrid / pre take the first k; post keeps in-range entries in order.
-  // Graph results over a low-precision copy come re-scored and filtered.
-  const u64* res = L.ann;
-  bool post_filter = P.strat == UNIFY_POST;
-  if (PREC != UNIFY_FP32 && P.strat != UNIFY_PRE && ok && al > 0) {
-    al = rerank_graph<NG>(A, L, qv, P, sec, al, post_filter, cnt);
-    res = L.cand;
-    post_filter = false;
+  write_result<NG, PREC>(A, L, qv, P, sec, q, al, ok, status, hybrid, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// Cooperative graph search: MW wavefronts of one workgroup run one query.  The
+// longest searches of a batch (the hybrid searches of the narrowest ranges, at
+// the head of the work list) bound a step; spreading each step's adjacency
+// gather, visited checks and distance evaluations over MW wavefronts shortens
+// them.  Wavefront 0 pops the candidates and admits the evaluated keys by the
+// rule of the one-wavefront search (so the same ann list results); the visited
+// set is the workgroup's HBM tag row from the start (the LDS cache only saves
+// reads), so whichever wavefront meets an id first claims it by one atomic
+// exchange.  Three workgroup barriers per step.
+// ---------------------------------------------------------------------------
+struct LdsMW {
+  u64* ann;
+  u64* cand;
+  uint32_t* hash;
+  u64* bkeys;   // entry and result stages (wavefront 0)
+  u64* nbuf;    // per wavefront: its new ids, then their keys
+  int32_t* sh;  // broadcast slots
+};
+enum { SH_NPOP = 8, SH_POPPED = 9 /* 8 slots */, SH_CL = 17, SH_AL = 18, SH_OVER = 19, SH_EP = 20, SH_TOP = 21,
+       SH_W = 22, SH_EPKEY = 24 /* 2 slots */, SH_NLOG = 26, SH_SLOTS = 27 };
+
+// LDS bytes of a cooperative search's workgroup (besides the broadcast slots).
+__host__ __device__ inline size_t lds_bytes_mw(int ef_blocks, int ccap, int hcap, int nbr_cap, int mw) {
+  return sizeof(u64) * ((size_t)ef_blocks * WAVE + ccap + nbr_cap + nbr_cap + (size_t)mw * WAVE) +
+         sizeof(uint32_t) * hcap;
+}
+
+template <int NG, int PREC, int MW>
+__device__ bool layer_search_mw(const SearchArgs& A, const LdsMW& L, const float4 (&qv)[NG], const QPlan& P,
+                                Sec sec, bool hybrid, bool filter, int c, int32_t ep, u64 ep_key, int layer,
+                                int efl, int p, int& al, Counters& cnt, const VRow& R) {
+  const DevIndex& ix = A.ix;
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6, tid = threadIdx.x;
+  constexpr int NT = 64 * MW;
+  int hbits = 0;
+  while ((1 << hbits) < A.hcap) ++hbits;
+  const int setbits = hbits - 3;
+  for (int i = tid; i < A.hcap; i += NT) L.hash[i] = HASH_EMPTY;
+  __syncthreads();
+  if (tid == 0) {
+    bool fresh = false;
+    (void)mark_bit(R.bits, ep, fresh);
+    R.log[0] = (uint32_t)ep >> 5;
+    L.sh[SH_NLOG] = 1;
+    L.hash[cache_set(L.hash, setbits, ep) - L.hash] = (uint32_t)ep;
+    L.cand[0] = ep_key;
   }
-  int written = 0;
-  for (int base = 0; base < al && written < kout; base += WAVE) {
-    const int t = base + lane;
-    const u64 key = t < al ? res[t] : KEY_MAX;
-    const int32_t id = key_id(key);
-    const bool keep = key != KEY_MAX && (!post_filter || (id >= P.lo && id < P.hi && sec_ok(A, sec, id)));
-    const u64 km = ballot(keep);
-    const int pos = written + rank_in(km);
-    if (keep && pos < kout) {
-      A.out_ids[(int64_t)q * kout + pos] = ix.ext[id];
-      A.out_dist[(int64_t)q * kout + pos] = key_dist(key);
+  int cl = 1;
+  const bool ep_in = !filter || (ep >= P.lo && ep < P.hi && sec_ok(A, sec, ep));
+  if (wv == 0) L.ann[lane] = (ep_in && lane == 0) ? ep_key : KEY_MAX;
+  al = ep_in ? 1 : 0;
+  bool overflow = false;
+  __syncthreads();
+
+  const int mc = layer == 0 ? ix.M0 : ix.MU;
+  const int Sa = P.b - P.a + 1;
+  const int per_node = hybrid ? Sa * min(c, mc) : ix.GC;
+  const int cc = min(c, mc);
+  const int32_t* table = hybrid ? (layer == 0 ? ix.adj0 : ix.adjU) : (layer == 0 ? ix.glist0 : ix.glistU);
+  const int64_t max_steps = ix.n + 2;
+  int64_t steps = 0;
+  while (true) {
+    if (++steps > max_steps) {
+      overflow = true;
+      break;
     }
-    written += __popcll(km);
+    const bool full = al == efl;
+    const u64 T = full ? L.ann[efl - 1] : KEY_MAX;
+    // wavefront 0 pops up to p candidates that pass the stopping test
+    if (wv == 0) {
+      int npop = 0;
+      for (int t = 0; t < p; ++t) {
+        u64 best = KEY_MAX;
+        int bidx = -1;
+        for (int i = lane; i < cl; i += WAVE) {
+          const u64 kk = L.cand[i];
+          if (kk < best) {
+            best = kk;
+            bidx = i;
+          }
+        }
+        const u64 mn = wave_min64(best);
+        if (mn == KEY_MAX || (full && mn > T)) break;
+        const u64 who = ballot(best == mn);
+        const int src = __ffsll((unsigned long long)who) - 1;
+        const int idx = __shfl(bidx, src, WAVE);
+        if (lane == src) L.cand[idx] = KEY_MAX;
+        if (lane == 0) L.sh[SH_POPPED + t] = key_id(mn);
+        ++npop;
+        wave_lds_sync();
+      }
+      if (lane == 0) L.sh[SH_NPOP] = npop;
+    }
+    __syncthreads();
+    const int npop = L.sh[SH_NPOP];
+    if (npop == 0) break;
+    cnt.nexp += npop;
+    cnt.nadj += npop * per_node;
+    // this wavefront's share of the entries, [e0, e1); its new ids go to nbuf[e0 ..]
+    const int ntot = npop * per_node;
+    const int share = (ntot + MW * WAVE - 1) / (MW * WAVE) * WAVE;
+    const int e0 = wv * share, e1 = min(ntot, e0 + share);
+    int64_t rowbase = 0;  // lane t < npop: first entry of popped[t]'s row
+    if (lane < npop) {
+      const int32_t o = L.sh[SH_POPPED + lane];
+      const int64_t r = layer == 0 ? (int64_t)o : (int64_t)ix.uprow[o] + layer - 1;
+      rowbase = r * (hybrid ? (int64_t)ix.S * mc : (int64_t)ix.GC);
+    }
+    u64* mine = L.nbuf + e0;
+    int nnw = 0;
+    constexpr int GB = 8;
+    for (int b0 = e0; b0 < e1; b0 += GB * WAVE) {
+      int32_t vv[GB];
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
+        const int e = b0 + u * WAVE + lane;
+        const int t = e / per_node, tt = e - t * per_node;
+        const int64_t rb = (int64_t)shfl64((u64)rowbase, min(t, WAVE - 1));
+        vv[u] = e < e1 ? (hybrid ? table[rb + (int64_t)(P.a + tt / cc) * mc + tt % cc] : table[rb + tt]) : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
+        const int32_t v = vv[u];
+        bool fresh = false;
+        const bool isnew = v >= 0 && visit_tagged(L.hash, setbits, R.bits, v, fresh);
+        // the words this wavefront made non-zero go to the shared log
+        const u64 fm = ballot(fresh);
+        if (fm) {
+          int b = 0;
+          if (lane == 0) b = atomicAdd(&L.sh[SH_NLOG], __popcll(fm));
+          b = __shfl(b, 0, WAVE);
+          const int i = b + rank_in(fm);
+          if (fresh && i < VLOG_CAP) R.log[i] = (uint32_t)v >> 5;
+        }
+        const u64 nm = ballot(isnew);
+        if (isnew) mine[nnw + rank_in(nm)] = (uint32_t)v;
+        nnw += __popcll(nm);
+      }
+    }
+    wave_lds_sync();
+    if (nnw > 0) eval_keys<NG, PREC>(ix, qv, nnw, [&](int i) { return key_id(mine[i]); }, mine);
+    if (lane == 0) L.sh[wv] = nnw;
+    __syncthreads();
+    // wavefront 0 admits every wavefront's keys against the threshold from before this step
+    if (wv == 0) {
+      for (int w2 = 0; w2 < MW && !overflow; ++w2) {
+        const int nn = L.sh[w2];
+        cnt.ndist += nn;
+        const u64* theirs = L.nbuf + w2 * share;
+        for (int base = 0; base < nn; base += WAVE) {
+          const int tt = base + lane;
+          const u64 key = tt < nn ? theirs[tt] : KEY_MAX;
+          const bool adm = key != KEY_MAX && key < T;
+          const u64 am = ballot(adm);
+          const int na = __popcll(am);
+          if (na == 0) continue;
+          if (cl + na > A.ccap) {
+            // compact: drop tombstones and keys that can no longer be expanded
+            const u64 W = al == efl ? L.ann[efl - 1] : KEY_MAX;
+            int ncl = 0;
+            for (int i0 = 0; i0 < cl; i0 += WAVE) {
+              const int i = i0 + lane;
+              const u64 kk = i < cl ? L.cand[i] : KEY_MAX;
+              const bool keep = kk != KEY_MAX && kk <= W;
+              const u64 km = ballot(keep);
+              wave_lds_sync();
+              if (keep) L.cand[ncl + rank_in(km)] = kk;
+              ncl += __popcll(km);
+              wave_lds_sync();
+            }
+            cl = ncl;
+            if (cl + na > A.ccap) {
+              overflow = true;
+              break;
+            }
+          }
+          if (adm) L.cand[cl + rank_in(am)] = key;
+          cl += na;
+          const int32_t id = key_id(key);
+          const bool in_r = adm && (!filter || (id >= P.lo && id < P.hi && sec_ok(A, sec, id)));
+          list_insert(L.ann, al, efl, in_r ? key : KEY_MAX);
+          wave_lds_sync();
+        }
+      }
+      if (lane == 0) {
+        L.sh[SH_CL] = cl;
+        L.sh[SH_AL] = al;
+        L.sh[SH_OVER] = overflow ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    if (wv != 0) {
+      cl = L.sh[SH_CL];
+      al = L.sh[SH_AL];
+      overflow = L.sh[SH_OVER] != 0;
+    }
+    if (overflow) break;
   }
-  written = min(written, kout);
-  if (!ok) written = 0;
-  for (int t = written + lane; t < kout; t += WAVE) {
-    A.out_ids[(int64_t)q * kout + t] = -1;
-    A.out_dist[(int64_t)q * kout + t] = __builtin_inff();
+  cnt.spill = 1;  // the visited set lives in the row
+  __syncthreads();  // every wavefront's bits and log entries before the clear
+  clear_row(R, L.sh[SH_NLOG], A.bwords, tid, NT);
+  __syncthreads();  // the clears before the row's next use
+  return !overflow;
+}
+
+template <int NG, int PREC, int MW>
+__device__ void run_query_mw(const SearchArgs& A, const LdsMW& L, int32_t q, const VRow& R) {
+  const DevIndex& ix = A.ix;
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  const QPlan P = A.plan[q];
+  const Sec sec{q};
+  float4 qv[NG];
+  {
+    const int s = lane & 15, G = ix.d >> 2;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const int g = s + 16 * i;
+      qv[i] = g < G ? *reinterpret_cast<const float4*>(A.Q + (int64_t)q * ix.d + 4 * g)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   }
-  if (A.out_stats && lane == 0) {
-    int32_t* st = A.out_stats + (int64_t)q * 8;
-    st[0] = cnt.ndist;
-    st[1] = cnt.nexp;
-    st[2] = cnt.nrerank;
-    st[3] = (ok ? status : 2) | (cnt.spill ? STAT_SPILL_BIT : 0);
-    st[4] = cnt.nadj;
-    st[5] = P.strat;
-    st[6] = P.hi - P.lo;
-    st[7] = hybrid ? P.b - P.a + 1 : 0;
+  Counters cnt;
+  cnt.coop = 1;
+  int al = 0;
+  const bool hybrid = P.strat == UNIFY_HYBRID;
+  const int Sa = P.b - P.a + 1;
+  const int c = (A.m + Sa - 1) / Sa;
+  // entry (wavefront 0): for the hybrid search the entry of the active segment with the
+  // highest top level (ties: nearer, then smaller id), else the global entry
+  if (wv == 0) {
+    int32_t ep = -1;
+    int top = -1;
+    u64 ep_key = KEY_MAX;
+    if (hybrid) {
+      for (int j = P.a; j <= P.b; ++j)
+        if (ix.seg_entry[j] >= 0) top = max(top, ix.seg_maxlevel[j]);
+      int ne = 0;
+      for (int j0 = P.a; j0 <= P.b; j0 += WAVE) {
+        const int j = j0 + lane;
+        const bool is = j <= P.b && ix.seg_entry[j] >= 0 && ix.seg_maxlevel[j] == top;
+        const u64 mk = ballot(is);
+        if (is) L.bkeys[ne + rank_in(mk)] = (uint32_t)ix.seg_entry[j];
+        ne += __popcll(mk);
+      }
+      wave_lds_sync();
+      eval_keys<NG, PREC>(ix, qv, ne, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
+      wave_lds_sync();
+      cnt.ndist += ne;
+      const u64 kk = lane < ne ? L.bkeys[lane] : KEY_MAX;
+      ep_key = wave_min64(kk);
+      ep = key_id(ep_key);
+      if (ne == 0) top = -1;
+    } else {
+      top = ix.L;
+      ep = ix.gentry;
+      L.bkeys[0] = (uint32_t)ep;
+      wave_lds_sync();
+      eval_keys<NG, PREC>(ix, qv, 1, [&](int i) { return key_id(L.bkeys[i]); }, L.bkeys);
+      wave_lds_sync();
+      ep_key = L.bkeys[0];
+      cnt.ndist += 1;
+    }
+    if (lane == 0) {
+      L.sh[SH_EP] = ep;
+      L.sh[SH_TOP] = top;
+      L.sh[SH_EPKEY] = (int32_t)(uint32_t)ep_key;
+      L.sh[SH_EPKEY + 1] = (int32_t)(uint32_t)(ep_key >> 32);
+    }
+  }
+  __syncthreads();
+  int32_t ep = L.sh[SH_EP];
+  const int top = L.sh[SH_TOP];
+  u64 ep_key = ((u64)(uint32_t)L.sh[SH_EPKEY + 1] << 32) | (uint32_t)L.sh[SH_EPKEY];
+  __syncthreads();
+  bool ok = true;
+  for (int layer = top; layer >= 1 && ok; --layer) {
+    ok = layer_search_mw<NG, PREC, MW>(A, L, qv, P, sec, hybrid, false, c, ep, ep_key, layer, 1, 1, al, cnt, R);
+    ep_key = L.ann[0];
+    ep = key_id(ep_key);
+    __syncthreads();
+  }
+  if (ok && top >= 0)
+    ok = layer_search_mw<NG, PREC, MW>(A, L, qv, P, sec, hybrid, hybrid, c, ep, ep_key, 0, A.ef, A.p, al, cnt, R);
+  if (top < 0) {  // no entry among the active segments: nothing to search
+    al = 0;
+    ok = true;
+  }
+  if (!ok && A.pass == 0) {
+    if (threadIdx.x == 0) {
+      const int32_t slot = atomicAdd(A.fb_count, 1);
+      A.fb_list[slot] = q;
+    }
+    return;
+  }
+  if (wv == 0) {
+    Lds Lw;
+    Lw.ann = L.ann;
+    Lw.cand = L.cand;
+    Lw.hash = L.hash;
+    Lw.bkeys = L.bkeys;
+    Lw.sel = nullptr;
+    write_result<NG, PREC, true>(A, Lw, qv, P, sec, q, al, ok, A.pass, hybrid, cnt);
+  }
+}
+
+// Persistent cooperative searches: first the heavy queries (the head of the work
+// list, work[0, nheavy)), then queries of the shared remainder, with the
+// one-wavefront kernel.  Workgroup g owns visited row mw_row0 + g.
+template <int NG, int PREC, int MW>
+__global__ void __launch_bounds__(64 * MW) k_search_mw(SearchArgs A) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int32_t sh[SH_SLOTS];
+  LdsMW L;
+  unsigned char* p = lds_raw;
+  L.ann = reinterpret_cast<u64*>(p);
+  p += sizeof(u64) * A.ef_blocks * WAVE;
+  L.cand = reinterpret_cast<u64*>(p);
+  p += sizeof(u64) * A.ccap;
+  L.bkeys = reinterpret_cast<u64*>(p);
+  p += sizeof(u64) * A.nbr_cap;
+  L.nbuf = reinterpret_cast<u64*>(p);
+  p += sizeof(u64) * (A.nbr_cap + MW * WAVE);
+  L.hash = reinterpret_cast<uint32_t*>(p);
+  L.sh = sh;
+  const int32_t nwork = *A.nwork, nheavy = *A.nheavy;
+  const VRow R = vrow_of(A, A.mw_row0 + blockIdx.x);  // the workgroup's visited row
+  bool heavy = true;  // thread 0's view
+  while (true) {
+    if (threadIdx.x == 0) {
+      int32_t w = nwork;
+      if (heavy) {
+        w = atomicAdd(A.mw_next, 1);
+        if (w >= nheavy) heavy = false;
+      }
+      if (!heavy) w = atomicAdd(A.next, 1);
+      sh[SH_W] = w;
+    }
+    __syncthreads();
+    const int32_t w = sh[SH_W];
+    __syncthreads();
+    if (w >= nwork) break;
+    run_query_mw<NG, PREC, MW>(A, L, A.work[w], R);
+    __syncthreads();
   }
 }
 
@@ -1098,19 +1572,15 @@ __global__ void __launch_bounds__(64, NG > 4 ? 1 : (PREC == UNIFY_FP32 ? WAVES_P
   p += sizeof(u64) * A.sel_cap;
   L.hash = reinterpret_cast<uint32_t*>(p);
   const int32_t nwork = *A.nwork;
-  // this wave's visited tags; the epoch persists across launches in A.epochs
-  const int64_t slot = blockIdx.x;
-  uint32_t* tags = A.tags + slot * A.ix.n;
-  uint32_t epoch = __hip_atomic_load(&A.epochs[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const VRow R = vrow_of(A, blockIdx.x);  // this wave's visited row
   while (true) {
     int32_t w = 0;
     if (lane_id() == 0) w = atomicAdd(A.next, 1);
     w = __shfl(w, 0, WAVE);
     if (w >= nwork) break;
-    run_query<NG, PREC, S1>(A, L, A.work[w], A.wchunk ? A.wchunk[w] : 0, tags, epoch);
+    run_query<NG, PREC, S1>(A, L, A.work[w], A.wchunk ? A.wchunk[w] : 0, R);
     __syncthreads();
   }
-  if (lane_id() == 0) __hip_atomic_store(&A.epochs[slot], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Outputs of the split pre-filter scans: one wavefront per query merges its
@@ -1124,7 +1594,7 @@ __global__ void __launch_bounds__(256) k_pre_merge(DevIndex ix, const QPlan* __r
   const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (q >= nq) return;  // uniform per wavefront
   const QPlan P = plan[q];
-  if (P.strat != UNIFY_PRE || P.nch <= 1) return;
+  if (P.strat != UNIFY_PRE || P.nch <= 1 || P.tsb > 0) return;  // tsb > 0: the matrix-core scan answers it
   u64* lst = lists[threadIdx.x >> 6];
   for (int t = lane; t < PRE_SPLIT_KMAX; t += WAVE) lst[t] = KEY_MAX;
   int al = 0;
@@ -1155,6 +1625,519 @@ __global__ void __launch_bounds__(256) k_pre_merge(DevIndex ix, const QPlan* __r
 }
 
 // ---------------------------------------------------------------------------
+// Strategy A on the matrix cores.  The pre-filter queries of a batch share the
+// attribute-sorted store: a super-block of TILE_ROWS consecutive objects is read
+// once for up to 16 of the queries whose slices touch it, and the distance of
+// every (query, object) pair is formed by the norm expansion
+//   s~ = ||x~||^2 - 2 q . x~ + ||q||^2
+// with the products q . x~ on MFMA (BF16 inputs for the BF16 and FP8 stores, the
+// query split into two BF16 parts; FP32 inputs for the FP32 store), accumulated
+// in FP32.  s~ only selects: with a bound E on its error, eps_v on the copy's
+// error and the relative error g of the canonical FP32 distance, every object
+// gets [lb, ub] around the root of its canonical distance.  Within a
+// super-block the objects with lb <= min(k-th smallest ub of the block, the
+// smallest such value any block of the query has published) are recorded; the
+// k-th smallest ub over a query's records is the k-th smallest over its slice
+// (each of those k objects is recorded by its block), and every object of the
+// exact top k has lb <= that value.  k_tile_final re-scores the recorded
+// objects below it with the canonical FP32 distance, so the result is exactly
+// the FP32 scan's.  A query whose records overflow is scanned in FP32 instead.
+// ---------------------------------------------------------------------------
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+
+struct TileArgs {
+  DevIndex ix;
+  const QPlan* plan;
+  const float* Q;
+  int64_t nq;
+  int32_t k, kcq;
+  uint32_t* qhl;        // [nq][d] BF16 split of each query: high part | low part << 16
+  float4* qinfo;        // [nq] (||q||^2, ||q||, bound on ||q - (hi + lo)||, 0)
+  uint32_t* tglob;      // [nq] smallest published block threshold (FP32 bits)
+  int32_t* cnt_sb;      // [nsb] queries per super-block, then the fill cursor
+  int32_t* fill_sb;     // [nsb]
+  int32_t* off_sb;      // [nsb + 1] first list entry of each super-block
+  int32_t* ioff;        // [nsb + 1] first work item of each super-block
+  int32_t* list;        // [pcap] queries of each super-block
+  int32_t* item_sb;     // [pcap] super-block of each work item
+  int32_t* rec_cnt;     // [pcap] objects recorded per (query, super-block), kcq + 1 = overflow
+  u64* rec_key;         // [pcap][kcq] (lb bits << 32) | id
+  float* rec_ub;        // [pcap][kcq] ub of the same object
+  int32_t* counters;    // [6]: work items of the scan
+  int64_t nsb;
+  float cE, bA, bB, bC, bD;
+};
+
+// Queries of the matrix-core scan: the BF16 split, norms and error bound of each
+// query, its threshold, and the count of queries per super-block.
+__global__ void __launch_bounds__(256) k_tile_prep(TileArgs T) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= T.nq) return;  // uniform per wavefront
+  const QPlan P = T.plan[q];
+  if (P.strat != UNIFY_PRE || P.tsb == 0) return;
+  const int sb0 = P.lo / TILE_ROWS;
+  for (int j = lane; j < P.tsb; j += WAVE) atomicAdd(&T.cnt_sb[sb0 + j], 1);
+  const int d = T.ix.d;
+  const float* qq = T.Q + q * d;
+  float n2 = 0.0f, e2 = 0.0f;
+  for (int t = lane; t < d; t += WAVE) {
+    const float x = qq[t];
+    n2 = __builtin_fmaf(x, x, n2);
+    if (T.ix.precision != UNIFY_FP32) {
+      // q = hi + lo + res, each step exact: a value minus its nearest BF16 is exact in FP32
+      const uint32_t hi = f32_to_bf16(x);
+      const float r = x - bf16_to_f32(hi);
+      const uint32_t lo = f32_to_bf16(r);
+      const float res = r - bf16_to_f32(lo);
+      T.qhl[q * d + t] = hi | (lo << 16);
+      e2 = __builtin_fmaf(res, res, e2);
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    n2 += __shfl_xor(n2, o, WAVE);
+    e2 += __shfl_xor(e2, o, WAVE);
+  }
+  if (lane == 0) {
+    // the sum of squares passes through at most d / 64 + 7 roundings: 2^-18 covers them
+    const float eq = T.ix.precision == UNIFY_FP32 ? 0.0f : __builtin_sqrtf(e2) * (1.0f + 0x1p-18f) + 1e-21f;
+    T.qinfo[q] = make_float4(n2, __builtin_sqrtf(n2), eq, 0.0f);
+    T.tglob[q] = 0x7F800000u;  // +inf
+  }
+}
+
+// Offsets of the super-blocks' query lists and of their work items (one item =
+// one super-block and up to TILE_Q of its queries).  One block.
+__global__ void __launch_bounds__(1024) k_tile_index(TileArgs T) {
+  __shared__ int32_t sa[1024], sb[1024];
+  const int t = threadIdx.x, NT = blockDim.x;
+  const int64_t per = (T.nsb + NT - 1) / NT;
+  const int64_t b0 = std::min<int64_t>(T.nsb, t * per), b1 = std::min<int64_t>(T.nsb, b0 + per);
+  int32_t ca = 0, ci = 0;
+  for (int64_t b = b0; b < b1; ++b) {
+    const int32_t c = T.cnt_sb[b];
+    ca += c;
+    ci += (c + TILE_Q - 1) / TILE_Q;
+  }
+  sa[t] = ca;
+  sb[t] = ci;
+  __syncthreads();
+  for (int off = 1; off < NT; off <<= 1) {
+    const int32_t va = t >= off ? sa[t - off] : 0, vb = t >= off ? sb[t - off] : 0;
+    __syncthreads();
+    sa[t] += va;
+    sb[t] += vb;
+    __syncthreads();
+  }
+  int32_t pa = sa[t] - ca, pi = sb[t] - ci;
+  for (int64_t b = b0; b < b1; ++b) {
+    const int32_t c = T.cnt_sb[b];
+    T.off_sb[b] = pa;
+    T.ioff[b] = pi;
+    T.fill_sb[b] = 0;
+    const int ni = (c + TILE_Q - 1) / TILE_Q;
+    for (int j = 0; j < ni; ++j) T.item_sb[pi + j] = (int32_t)b;
+    pa += c;
+    pi += ni;
+  }
+  if (t == NT - 1) {
+    T.off_sb[T.nsb] = sa[t];
+    T.ioff[T.nsb] = sb[t];
+    T.counters[5] = sb[t];
+  }
+}
+
+// Every query of the matrix-core scan joins the list of each super-block it touches.
+__global__ void __launch_bounds__(256) k_tile_fill(TileArgs T) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= T.nq) return;
+  const QPlan P = T.plan[q];
+  if (P.strat != UNIFY_PRE || P.tsb == 0) return;
+  const int sb0 = P.lo / TILE_ROWS;
+  for (int j = lane; j < P.tsb; j += WAVE) {
+    const int b = sb0 + j;
+    T.list[T.off_sb[b] + atomicAdd(&T.fill_sb[b], 1)] = (int32_t)q;
+  }
+}
+
+// k-th smallest (1-based, k <= count of values below +inf) of the 4 values per
+// lane, as FP32 bits (non-negative values order as their bits): the largest x
+// with fewer than k values below it, built from the top bit down.
+__device__ __forceinline__ uint32_t kth_smallest4(const uint32_t (&u)[4], int k) {
+  uint32_t pre = 0;
+  for (int bit = 30; bit >= 0; --bit) {
+    const uint32_t c = pre | (1u << bit);
+    int below = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) below += __popcll(ballot(u[i] < c));
+    if (below < k) pre = c;
+  }
+  return pre;
+}
+
+// One workgroup of 4 wavefronts per work item; PREC = the store in use.
+// Wavefront w contracts the item's queries with rows 64 w .. 64 w + 63 of the
+// super-block and selects for queries w, w + 4, ...  LDS: the queries as MFMA
+// A operands, then lb / ub of every (query, object) of the super-block.
+constexpr int TILE_WAVES = 4;
+template <int PREC>
+__global__ void __launch_bounds__(64 * TILE_WAVES) k_tile_scan(TileArgs T) {
+  extern __shared__ __align__(16) unsigned char tile_lds[];
+  const int lane = lane_id(), wv = threadIdx.x >> 6, tid = threadIdx.x;
+  constexpr int NT = 64 * TILE_WAVES;
+  const int d = T.ix.d;
+  const int stride = d + 8;  // padded row (elements) of the staged queries
+  // A operands: BF16 stores: hi and lo parts, u16 [TILE_Q][stride] each; FP32: f32 [TILE_Q][stride]
+  uint16_t* ahi = reinterpret_cast<uint16_t*>(tile_lds);
+  uint16_t* alo = ahi + TILE_Q * stride;
+  float* af = reinterpret_cast<float*>(tile_lds);
+  float* LB = reinterpret_cast<float*>(tile_lds + (size_t)TILE_Q * stride * 4);
+  float* UB = LB + TILE_Q * TILE_ROWS;
+  __shared__ int32_t s_q[TILE_Q], s_lo[TILE_Q], s_hi[TILE_Q], s_pair[TILE_Q];
+  __shared__ float4 s_info[TILE_Q];
+  const int nitems = T.counters[5];
+  const int n = (int)T.ix.n;
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int sb = T.item_sb[item];
+    const int g = item - T.ioff[sb];
+    const int qb = T.off_sb[sb] + g * TILE_Q;
+    const int nqg = min(TILE_Q, T.off_sb[sb + 1] - qb);
+    if (tid < TILE_Q) {
+      if (tid < nqg) {
+        const int32_t q = T.list[qb + tid];
+        const QPlan P = T.plan[q];
+        s_q[tid] = q;
+        s_lo[tid] = P.lo;
+        s_hi[tid] = P.hi;
+        s_pair[tid] = P.tbase + (sb - P.lo / TILE_ROWS);
+        s_info[tid] = T.qinfo[q];
+      } else {
+        s_q[tid] = -1;
+        s_lo[tid] = s_hi[tid] = 0;
+      }
+    }
+    for (int idx = tid; idx < TILE_Q * TILE_ROWS; idx += NT) {
+      LB[idx] = __builtin_inff();
+      UB[idx] = __builtin_inff();
+    }
+    __syncthreads();
+    // stage the queries, 4 elements per load (zero rows beyond nqg)
+    {
+      constexpr int MAXV = TILE_Q * TILE_DMAX / 4 / NT;  // loads per thread at most
+      const int nvec = TILE_Q * d / 4;
+      uint4 wv4[MAXV];
+#pragma unroll
+      for (int j = 0; j < MAXV; ++j) {
+        const int v = tid + j * NT;
+        const int m = v / (d / 4), t4 = v - m * (d / 4);
+        const int q = v < nvec ? s_q[m] : -1;
+        if constexpr (PREC == UNIFY_FP32)
+          wv4[j] = q >= 0 ? *reinterpret_cast<const uint4*>(T.Q + (int64_t)q * d + 4 * t4) : make_uint4(0, 0, 0, 0);
+        else
+          wv4[j] = q >= 0 ? *reinterpret_cast<const uint4*>(T.qhl + (int64_t)q * d + 4 * t4) : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < MAXV; ++j) {
+        const int v = tid + j * NT;
+        if (v >= nvec) break;
+        const int m = v / (d / 4), t = 4 * (v - m * (d / 4));
+        if constexpr (PREC == UNIFY_FP32) {
+          *reinterpret_cast<uint4*>(af + m * stride + t) = wv4[j];
+        } else {
+          const uint4 w = wv4[j];
+          *reinterpret_cast<uint2*>(ahi + m * stride + t) =
+              make_uint2((w.x & 0xFFFFu) | (w.y << 16), (w.z & 0xFFFFu) | (w.w << 16));
+          *reinterpret_cast<uint2*>(alo + m * stride + t) =
+              make_uint2((w.x >> 16) | (w.y & 0xFFFF0000u), (w.z >> 16) | (w.w & 0xFFFF0000u));
+        }
+      }
+    }
+    __syncthreads();
+    const int mrow = lane & 15, kq = lane >> 4;  // MFMA lane roles: row / column, k quarter
+    {
+      const int r0 = sb * TILE_ROWS + wv * 64;
+      bool cover = false;
+      if (lane < nqg) cover = s_lo[lane] < r0 + 64 && s_hi[lane] > r0;
+      if (r0 < n && __any(cover)) {
+        f32x4_t acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        if constexpr (PREC == UNIFY_FP32) {
+          // 16x16x4 FP32 MFMA: a k-step of 16 elements = 4 instructions; lane (n, kq) holds
+          // elements 16 s + 4 kq .. + 3 of object n and of query n (as the A row).  Loads of
+          // 4 k-steps are issued before their products.
+          for (int s0 = 0; s0 < d / 16; s0 += 4) {
+            float4 x[4][4];
+#pragma unroll
+            for (int ss = 0; ss < 4; ++ss)
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                const int row = r0 + 16 * t + mrow, s = s0 + ss;
+                x[ss][t] = (row < n && s < d / 16)
+                               ? *reinterpret_cast<const float4*>(T.ix.vec + (int64_t)row * d + 16 * s + 4 * kq)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+              }
+#pragma unroll
+            for (int ss = 0; ss < 4; ++ss) {
+              if (s0 + ss >= d / 16) break;
+              const float4 qa = *reinterpret_cast<const float4*>(af + mrow * stride + 16 * (s0 + ss) + 4 * kq);
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa.x, x[ss][t].x, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa.y, x[ss][t].y, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa.z, x[ss][t].z, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa.w, x[ss][t].w, acc[t], 0, 0, 0);
+              }
+            }
+          }
+        } else {
+          // 16x16x32 BF16 MFMA: a k-step of 32 elements; lane (n, kq) holds elements
+          // 32 s + 8 kq .. + 7 of object n and of query n (A); the query in two parts.
+          // Loads of 4 k-steps are issued before their products.
+          for (int s0 = 0; s0 < d / 32; s0 += 4) {
+            uint4 x[4][4];
+#pragma unroll
+            for (int ss = 0; ss < 4; ++ss)
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                const int row = r0 + 16 * t + mrow, s = s0 + ss;
+                const bool in = row < n && s < d / 32;
+                if constexpr (PREC == UNIFY_BF16) {
+                  x[ss][t] = in ? *reinterpret_cast<const uint4*>(T.ix.vec_bf16 + (int64_t)row * d + 32 * s + 8 * kq)
+                                : make_uint4(0u, 0u, 0u, 0u);
+                } else {
+                  const uint2 w = in ? *reinterpret_cast<const uint2*>(T.ix.vec_fp8 + (int64_t)row * d + 32 * s + 8 * kq)
+                                     : make_uint2(0u, 0u);
+                  x[ss][t] = make_uint4(w.x, w.y, 0u, 0u);
+                }
+              }
+#pragma unroll
+            for (int ss = 0; ss < 4; ++ss) {
+              if (s0 + ss >= d / 32) break;
+              const int s = s0 + ss;
+              const bf16x8_t qh = *reinterpret_cast<const bf16x8_t*>(ahi + mrow * stride + 32 * s + 8 * kq);
+              const bf16x8_t ql = *reinterpret_cast<const bf16x8_t*>(alo + mrow * stride + 32 * s + 8 * kq);
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                bf16x8_t xb;
+                if constexpr (PREC == UNIFY_BF16) {
+                  xb = __builtin_bit_cast(bf16x8_t, x[ss][t]);
+                } else {
+                  // E4M3 codes decode exactly to BF16 (3 significand bits, exponents 2^-9 .. 2^8)
+                  uint32_t h[4];
+#pragma unroll
+                  for (int c = 0; c < 2; ++c) {
+                    const uint32_t word = c == 0 ? x[ss][t].x : x[ss][t].y;
+                    const auto f0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)word, false);
+                    const auto f1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)word, true);
+                    h[2 * c] = (__float_as_uint(f0[0]) >> 16) | (__float_as_uint(f0[1]) & 0xFFFF0000u);
+                    h[2 * c + 1] = (__float_as_uint(f1[0]) >> 16) | (__float_as_uint(f1[1]) & 0xFFFF0000u);
+                  }
+                  xb = __builtin_bit_cast(bf16x8_t, make_uint4(h[0], h[1], h[2], h[3]));
+                }
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qh, xb, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ql, xb, acc[t], 0, 0, 0);
+              }
+            }
+          }
+        }
+        // lane holds, for tile t, the products of queries 4 kq + i with object r0 + 16 t + mrow
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int row = r0 + 16 * t + mrow;
+          float nrm = 0.f, eps = 0.f, sc = 1.f;
+          if (row < n) {
+            nrm = T.ix.vec_nrm[row];
+            if (PREC != UNIFY_FP32) eps = T.ix.vec_eps[row];
+            if (PREC == UNIFY_FP8E4M3) sc = T.ix.vec_scale[row];
+          }
+          const float xn = __builtin_sqrtf(nrm);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int m = 4 * kq + i;
+            if (m >= nqg || row < s_lo[m] || row >= s_hi[m]) continue;
+            const float4 qi = s_info[m];
+            const float dot = PREC == UNIFY_FP8E4M3 ? acc[t][i] * sc : acc[t][i];
+            const float st = __builtin_fmaf(-2.0f, dot, nrm) + qi.x;
+            const float xs = xn + qi.y;
+            const float E = __builtin_fmaf(T.cE * xs, xs, __builtin_fmaf(2.0000019f * xn, qi.z, 1e-30f));
+            const float rl = __builtin_sqrtf(fmaxf(st - E, 0.0f));
+            const float rh = __builtin_sqrtf(st + E);
+            const float l = __builtin_fmaf(rl, T.bA, -__builtin_fmaf(eps, T.bB, 1e-18f));
+            const int col = wv * 64 + 16 * t + mrow;
+            LB[m * TILE_ROWS + col] = l > 0.0f ? l : 0.0f;
+            UB[m * TILE_ROWS + col] = __builtin_fmaf(rh, T.bC, __builtin_fmaf(eps, T.bD, 1e-18f));
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // per query (wavefront w takes queries w, w + 4, ...): block threshold, records,
+    // published threshold
+    for (int m = wv; m < nqg; m += TILE_WAVES) {
+      uint32_t u[4];
+      float lb[4];
+      int valid = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float ub = UB[m * TILE_ROWS + 64 * c + lane];
+        u[c] = __float_as_uint(ub);
+        lb[c] = LB[m * TILE_ROWS + 64 * c + lane];
+        valid += __popcll(ballot(ub != __builtin_inff()));
+      }
+      const int32_t q = s_q[m];
+      const uint32_t tloc = valid >= T.k ? kth_smallest4(u, T.k) : 0x7F800000u;
+      const uint32_t tg = __hip_atomic_load(&T.tglob[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const float thr = __uint_as_float(min(tloc, tg));
+      const int64_t pair = s_pair[m];
+      int cnt = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bool e = u[c] != 0x7F800000u && lb[c] <= thr;
+        const u64 em = ballot(e);
+        const int pos = cnt + rank_in(em);
+        if (e && pos < T.kcq) {
+          const int32_t id = sb * TILE_ROWS + 64 * c + lane;
+          T.rec_key[pair * T.kcq + pos] = make_key(lb[c], id);
+          T.rec_ub[pair * T.kcq + pos] = __uint_as_float(u[c]);
+        }
+        cnt += __popcll(em);
+      }
+      if (lane == 0) {
+        T.rec_cnt[pair] = min(cnt, T.kcq + 1);
+        if (tloc < tg) atomicMin(&T.tglob[q], tloc);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Results of the matrix-core scan: one wavefront per query.  The k-th smallest ub
+// over the query's records, then the canonical FP32 distance of every recorded
+// object whose lb is not above it; the plain FP32 scan when a record overflowed.
+// The records of a query are contiguous; they are read 4 entries per lane per
+// round (all loads of a round issued together).
+template <int NG>
+__global__ void __launch_bounds__(256) k_tile_final(TileArgs T, int64_t* __restrict__ out_ids,
+                                                    float* __restrict__ out_dist, int32_t* __restrict__ out_stats) {
+  __shared__ u64 lists[4][WAVE];  // list_insert works on whole 64-entry blocks
+  __shared__ u64 bk[4][WAVE];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 4 + w;
+  if (q >= T.nq) return;  // uniform per wavefront
+  const QPlan P = T.plan[q];
+  if (P.strat != UNIFY_PRE || P.tsb == 0) return;
+  const DevIndex& ix = T.ix;
+  const int k = T.k, kcq = T.kcq;
+  u64* lst = lists[w];
+  u64* keys = bk[w];
+  float4 qv[NG];
+  {
+    const int s = lane & 15, G = ix.d >> 2;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const int g = s + 16 * i;
+      qv[i] = g < G ? *reinterpret_cast<const float4*>(T.Q + q * ix.d + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  constexpr int U = 4;
+  const int64_t first = (int64_t)P.tbase * kcq;
+  const int total = P.tsb * kcq;
+  lst[lane] = KEY_MAX;
+  int al = 0;
+  bool over = false;
+  // pass 1: the k smallest ub
+  for (int b0 = 0; b0 < total && !over; b0 += U * WAVE) {
+    u64 rk[U];
+    float ru[U];
+    int rc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = b0 + u * WAVE + lane;
+      rc[u] = e < total ? T.rec_cnt[P.tbase + e / kcq] : 0;
+      rk[u] = e < total ? T.rec_key[first + e] : KEY_MAX;
+      ru[u] = e < total ? T.rec_ub[first + e] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = b0 + u * WAVE + lane;
+      over = over || __any(rc[u] > kcq);
+      const bool valid = e < total && (e % kcq) < rc[u];
+      const u64 key = valid ? make_key(ru[u], key_id(rk[u])) : KEY_MAX;
+      const u64 Tk = al == k ? lst[k - 1] : KEY_MAX;
+      list_insert(lst, al, k, key < Tk ? key : KEY_MAX);
+      wave_lds_sync();
+    }
+  }
+  const float thr = al == k ? key_dist(lst[k - 1]) : __builtin_inff();
+  int32_t nres = 0;
+  wave_lds_sync();
+  lst[lane] = KEY_MAX;
+  al = 0;
+  if (!over) {
+    // pass 2: canonical FP32 distances of the objects whose lb is not above thr
+    for (int b0 = 0; b0 < total; b0 += U * WAVE) {
+      u64 rk[U];
+      int rc[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = b0 + u * WAVE + lane;
+        rc[u] = e < total ? T.rec_cnt[P.tbase + e / kcq] : 0;
+        rk[u] = e < total ? T.rec_key[first + e] : KEY_MAX;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = b0 + u * WAVE + lane;
+        const bool use = e < total && (e % kcq) < rc[u] && key_dist(rk[u]) <= thr;
+        const u64 um = ballot(use);
+        const int nb = __popcll(um);
+        if (nb == 0) continue;
+        if (use) keys[rank_in(um)] = (uint32_t)key_id(rk[u]);
+        wave_lds_sync();
+        eval_keys<NG, UNIFY_FP32, STREAM>(ix, qv, nb, [&](int x) { return key_id(keys[x]); }, keys);
+        wave_lds_sync();
+        const u64 key = lane < nb ? keys[lane] : KEY_MAX;
+        const u64 Tk = al == k ? lst[k - 1] : KEY_MAX;
+        list_insert(lst, al, k, key < Tk ? key : KEY_MAX);
+        wave_lds_sync();
+        nres += nb;
+      }
+    }
+  } else {
+    for (int base = P.lo; base < P.hi; base += WAVE) {
+      const int cntv = min(WAVE, P.hi - base);
+      eval_keys<NG, UNIFY_FP32, STREAM>(ix, qv, cntv, [&](int x) { return base + x; }, keys);
+      wave_lds_sync();
+      const u64 key = lane < cntv ? keys[lane] : KEY_MAX;
+      const u64 Tk = al == k ? lst[k - 1] : KEY_MAX;
+      list_insert(lst, al, k, key < Tk ? key : KEY_MAX);
+      wave_lds_sync();
+    }
+    nres = P.hi - P.lo;
+  }
+  for (int t = lane; t < k; t += WAVE) {
+    const u64 key = t < al ? lst[t] : KEY_MAX;
+    out_ids[q * k + t] = key != KEY_MAX ? ix.ext[key_id(key)] : -1;
+    out_dist[q * k + t] = key != KEY_MAX ? key_dist(key) : __builtin_inff();
+  }
+  if (out_stats && lane == 0) {
+    int32_t* st = out_stats + q * 8;
+    st[0] = P.hi - P.lo;
+    st[1] = 0;
+    st[2] = nres;
+    st[3] = over ? 1 : 0;
+    st[4] = P.tsb;  // records of the matrix-core scan (adjacency entries for graph searches)
+    st[5] = UNIFY_PRE;
+    st[6] = P.hi - P.lo;
+    st[7] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
@@ -1165,6 +2148,8 @@ size_t lds_bytes(int ef_blocks, int ccap, int hcap, int nbr_cap, int sel_cap = 0
 }
 
 typedef void (*KernelFn)(SearchArgs);
+typedef void (*KernelFnT)(TileArgs);
+typedef void (*FinalFn)(TileArgs, int64_t*, float*, int32_t*);
 
 template <int PREC, int PASS, bool S1>
 KernelFn pick_kernel(int d) {
@@ -1189,6 +2174,26 @@ KernelFn kernel_for(int d, int prec, bool s1 = false) {
   return s1 ? kernel_for_sel<PASS, true>(d, prec) : kernel_for_sel<PASS, false>(d, prec);
 }
 
+template <int PREC, int MW>
+KernelFn pick_mw(int d) {
+  const int ng = (d + 63) / 64;
+  if (ng <= 2) return k_search_mw<2, PREC, MW>;
+  if (ng <= 4) return k_search_mw<4, PREC, MW>;
+  if (ng <= 8) return k_search_mw<8, PREC, MW>;
+  if (ng <= 15) return k_search_mw<15, PREC, MW>;
+  if (ng <= 32) return k_search_mw<32, PREC, MW>;
+  return nullptr;
+}
+
+template <int MW>
+KernelFn mw_for_prec(int d, int prec) {
+  if (prec == UNIFY_BF16) return pick_mw<UNIFY_BF16, MW>(d);
+  if (prec == UNIFY_FP8E4M3) return pick_mw<UNIFY_FP8E4M3, MW>(d);
+  return pick_mw<UNIFY_FP32, MW>(d);
+}
+
+KernelFn kernel_mw(int d, int prec, int mw) { return mw == 4 ? mw_for_prec<4>(d, prec) : mw_for_prec<2>(d, prec); }
+
 #define HIP_OK(x)                                                            \
   do {                                                                       \
     hipError_t e_ = (x);                                                     \
@@ -1203,6 +2208,10 @@ struct Resolved {
   int32_t k, ef, m, p, ccap, hcap, rerank, pre_chunk;
   int64_t tauA, tauB;
   uint32_t flags;
+  bool tile;    // pre-filter scans may run on the matrix cores
+  int32_t kcq;  // objects one (query, super-block) record holds
+  int32_t wpq;    // wavefronts per heavy graph search (1: no cooperative kernel)
+  int32_t heavy;  // heavy graph searches per batch at most
 };
 
 int resolve(unify_index_t ix, int64_t nq, int32_t k, int32_t ef, const unify_params* prm, Resolved& R) {
@@ -1239,13 +2248,17 @@ int resolve(unify_index_t ix, int64_t nq, int32_t k, int32_t ef, const unify_par
   if (P.cand_cap > 0) R.ccap = P.cand_cap;
   R.hcap = P.visit_cap > 0 ? P.visit_cap : (dv.precision == UNIFY_FP32 ? 1024 : 512);
   R.rerank = P.rerank_mult > 0 ? P.rerank_mult : 4;
+  R.wpq = P.waves_per_query > 0 ? P.waves_per_query : 1;
+  R.heavy = P.heavy_queries > 0 ? P.heavy_queries : ix->cus;
   R.pre_chunk = P.pre_chunk > 0 ? P.pre_chunk : 2048;
   R.flags = P.flags;
   if (R.m > dv.S * dv.M0 || R.p > 8 || ta > 1.0 || tb > 1.0 || R.ccap < 64 || R.ccap > 4096 ||
       (R.ccap & (R.ccap - 1)) || R.hcap < 256 || R.hcap > 16384 || (R.hcap & (R.hcap - 1)) || R.rerank > 256 ||
-      R.pre_chunk < 64) {
+      R.pre_chunk < 64 || (R.wpq != 1 && R.wpq != 2 && R.wpq != 4) || P.heavy_queries < 0 ||
+      ((R.flags & UNIFY_FLAG_SELECT_S1) && R.wpq > 1)) {
     set_error("params out of range (m <= S*M0, beam_p <= 8, tau fractions <= 1, cand_cap and visit_cap powers "
-              "of two in [64, 4096] and [256, 16384], rerank_mult <= 256, pre_chunk >= 64)");
+              "of two in [64, 4096] and [256, 16384], rerank_mult <= 256, pre_chunk >= 64, waves_per_query 1, 2 "
+              "or 4 and not with selection S1, heavy_queries >= 0)");
     return UNIFY_EINVAL;
   }
   // the FP32 rerank of a low-precision search builds its k results in the candidate array
@@ -1253,6 +2266,13 @@ int resolve(unify_index_t ix, int64_t nq, int32_t k, int32_t ef, const unify_par
     while (R.ccap < k) R.ccap *= 2;
   R.tauA = (int64_t)std::floor(ta * (double)dv.n);
   R.tauB = (int64_t)std::ceil(tb * (double)dv.n);
+  // the matrix-core scan: k <= TILE_KMAX, d <= TILE_DMAX, whole MFMA k-steps (16 elements
+  // for FP32, 32 for BF16 / FP8 rows), the store's row norms resident
+  R.tile = !(R.flags & UNIFY_FLAG_PRE_WAVE_SCAN) && k <= TILE_KMAX && dv.d <= TILE_DMAX && dv.vec_nrm &&
+           dv.d % (dv.precision == UNIFY_FP32 ? 16 : 32) == 0 && dv.n < (int64_t(1) << 31);
+  // records hold the block's k smallest upper bounds and the few objects whose bounds
+  // overlap them; FP8 bounds are wider
+  R.kcq = (2 * k + 12 + 7) / 8 * 8 * (dv.precision == UNIFY_FP8E4M3 ? 2 : 1);
   if (!kernel_for<0>(dv.d, dv.precision)) {
     set_error("unsupported dimension");
     return UNIFY_EINVAL;
@@ -1262,41 +2282,79 @@ int resolve(unify_index_t ix, int64_t nq, int32_t k, int32_t ef, const unify_par
 
 }  // namespace
 
-// Visited tags: one row of n epochs per persistent wave, kept with the index,
-// and the event that orders the search kernels of successive calls.  Made when
-// the index becomes resident (load, build, insertion), so that searches need no
+// The side stream of the cooperative kernel, the visited rows and the event
+// that orders the search kernels using them.  The index's pool is made when the
+// index becomes resident (load, build, insertion), so that searches need no
 // allocation of their own.
-int ensure_tags(unify_index_t ix) {
-  if (!ix->last_search) HIP_OK(hipEventCreateWithFlags(&ix->last_search, hipEventDisableTiming));
-  if (ix->tags) return UNIFY_OK;
-  const DevIndex& dv = ix->dv;
-  HIP_OK(hipDeviceGetAttribute(&ix->cus, hipDeviceAttributeMultiprocessorCount, ix->device));
+int make_side(SideStream& s) {
+  for (hipStream_t* t : {&s.stream, &s.tstream})
+    if (!*t) HIP_OK(hipStreamCreateWithFlags(t, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&s.fork, &s.join, &s.tfork, &s.tjoin})
+    if (!*e) HIP_OK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  return UNIFY_OK;
+}
+
+void free_side(SideStream& s) {
+  for (hipEvent_t e : {s.fork, s.join, s.tfork, s.tjoin})
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t t : {s.stream, s.tstream})
+    if (t) (void)hipStreamDestroy(t);
+  s = SideStream{};
+}
+
+namespace {
+int64_t bitmap_words(int64_t n) { return ((n + 31) / 32 + 63) / 64 * 64; }
+}  // namespace
+
+size_t pool_row_bytes(int64_t n) { return sizeof(uint32_t) * (size_t)(bitmap_words(n) + VLOG_CAP); }
+
+int pool_ensure(VisitPool& p, int64_t n) {
+  if (!p.last) HIP_OK(hipEventCreateWithFlags(&p.last, hipEventDisableTiming));
+  if (make_side(p.side) != UNIFY_OK) return UNIFY_EDEVICE;
+  if (p.rows && p.n == n) return UNIFY_OK;
+  if (p.rows) {
+    HIP_OK(hipEventSynchronize(p.last));
+    HIP_OK(hipFree(p.rows));
+    p.rows = nullptr;
+    p.nrows = 0;
+  }
   size_t free_b = 0, total_b = 0;
   HIP_OK(hipMemGetInfo(&free_b, &total_b));
-  int64_t slots = (int64_t)ix->cus * 16;
-  const int64_t fit = (int64_t)(free_b / 4 / (sizeof(uint32_t) * (size_t)dv.n));
-  if (slots > fit) slots = fit;
-  if (slots < 1) {
-    set_error("no device memory for the visited tags");
+  const size_t rb = pool_row_bytes(n);
+  const int64_t fit = (int64_t)(free_b / 4 / rb);
+  const int64_t rows = std::min<int64_t>(std::max<int64_t>(p.max_rows, 1), fit);
+  void* r = nullptr;
+  if (rows < 1 || hipMalloc(&r, rb * (size_t)rows) != hipSuccess) {
+    set_error("no device memory for the visited rows");
     return UNIFY_ENOMEM;
   }
-  void* t = nullptr;
-  void* e = nullptr;
-  if (hipMalloc(&t, sizeof(uint32_t) * (size_t)dv.n * slots) != hipSuccess ||
-      hipMalloc(&e, sizeof(uint32_t) * slots) != hipSuccess) {
-    if (t) (void)hipFree(t);
-    set_error("no device memory for the visited tags");
-    return UNIFY_ENOMEM;
-  }
-  HIP_OK(hipMemset(t, 0, sizeof(uint32_t) * (size_t)dv.n * slots));
-  HIP_OK(hipMemset(e, 0, sizeof(uint32_t) * slots));
+  HIP_OK(hipMemset(r, 0, rb * (size_t)rows));
   HIP_OK(hipDeviceSynchronize());
-  ix->tags = static_cast<uint32_t*>(t);
-  ix->epochs = static_cast<uint32_t*>(e);
-  ix->nslots = slots;
-  ix->allocs.push_back(t);
-  ix->allocs.push_back(e);
+  p.rows = static_cast<uint32_t*>(r);
+  p.nrows = rows;
+  p.bwords = bitmap_words(n);
+  p.stride = p.bwords + VLOG_CAP;
+  p.n = n;
   return UNIFY_OK;
+}
+
+void pool_free(VisitPool& p) {
+  if (p.last) {
+    (void)hipEventSynchronize(p.last);
+    (void)hipEventDestroy(p.last);
+  }
+  if (p.rows) (void)hipFree(p.rows);
+  free_side(p.side);
+  p.rows = nullptr;
+  p.last = nullptr;
+  p.nrows = 0;
+  p.n = -1;
+}
+
+int ensure_pool(unify_index_t ix) {
+  if (!ix->cus) HIP_OK(hipDeviceGetAttribute(&ix->cus, hipDeviceAttributeMultiprocessorCount, ix->device));
+  if (!ix->pool.max_rows) ix->pool.max_rows = (int64_t)ix->cus * 16;
+  return pool_ensure(ix->pool, ix->dv.n);
 }
 
 namespace {
@@ -1308,27 +2366,80 @@ struct Scratch {
   QPlan* plan;
   int32_t *work, *wchunk, *fb, *counters, *qacc;
   u64* part;
+  // matrix-core pre-filter scan (pcap = 0: none)
+  int64_t pcap, nsb;
+  uint32_t *qhl, *tglob;
+  float4* qinfo;
+  int32_t *cnt_sb, *fill_sb, *off_sb, *ioff, *list, *item_sb, *rec_cnt;
+  u64* rec_key;
+  float* rec_ub;
 };
 
 size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 
-size_t scratch_layout(int64_t nq, int k, void* base, Scratch* S) {
+// Device scratch of one search of nq queries; pcap records for the matrix-core
+// scan (0: none), each of kcq objects.  Returns the bytes; fills S when given.
+size_t scratch_layout(const DevIndex& dv, int64_t nq, int k, int64_t pcap, int kcq, void* base, Scratch* S) {
   const int64_t wcap = nq * PRE_NCH_MAX;
   const size_t plan_b = up256(sizeof(QPlan) * nq), work_b = up256(sizeof(int32_t) * wcap),
                fb_b = up256(sizeof(int32_t) * nq), acc_b = up256(sizeof(int32_t) * 4 * nq),
                part_b = k <= PRE_SPLIT_KMAX ? up256(sizeof(u64) * (size_t)wcap * k) : 0;
+  const int64_t nsb = (dv.n + TILE_ROWS - 1) / TILE_ROWS;
+  size_t qhl_b = 0, info_b = 0, tg_b = 0, sb_b = 0, sb1_b = 0, list_b = 0, rc_b = 0, rk_b = 0, ru_b = 0;
+  if (pcap > 0) {
+    qhl_b = dv.precision != UNIFY_FP32 ? up256(sizeof(uint32_t) * (size_t)nq * dv.d) : 0;
+    info_b = up256(sizeof(float4) * nq);
+    tg_b = up256(sizeof(uint32_t) * nq);
+    sb_b = up256(sizeof(int32_t) * nsb);
+    sb1_b = up256(sizeof(int32_t) * (nsb + 1));
+    list_b = up256(sizeof(int32_t) * pcap);
+    rc_b = list_b;
+    rk_b = up256(sizeof(u64) * (size_t)pcap * kcq);
+    ru_b = up256(sizeof(float) * (size_t)pcap * kcq);
+  }
   if (S) {
     char* sp = static_cast<char*>(base);
     S->plan = reinterpret_cast<QPlan*>(sp);
     S->work = reinterpret_cast<int32_t*>(sp += plan_b);
     S->wchunk = reinterpret_cast<int32_t*>(sp += work_b);
     S->fb = reinterpret_cast<int32_t*>(sp += work_b);
-    S->counters = reinterpret_cast<int32_t*>(sp += fb_b);  // nwork, next, fb_count, fb_next
+    S->counters = reinterpret_cast<int32_t*>(sp += fb_b);  // nwork, next, fb_count, fb_next, -, tile items
     S->qacc = reinterpret_cast<int32_t*>(sp += 256);
-    S->part = part_b ? reinterpret_cast<u64*>(sp += acc_b) : nullptr;
+    sp += acc_b;
+    S->part = part_b ? reinterpret_cast<u64*>(sp) : nullptr;
+    sp += part_b;
+    S->pcap = pcap;
+    S->nsb = nsb;
+    S->qhl = qhl_b ? reinterpret_cast<uint32_t*>(sp) : nullptr;
+    sp += qhl_b;
+    S->qinfo = reinterpret_cast<float4*>(sp);
+    sp += info_b;
+    S->tglob = reinterpret_cast<uint32_t*>(sp);
+    sp += tg_b;
+    S->cnt_sb = reinterpret_cast<int32_t*>(sp);
+    sp += sb_b;
+    S->fill_sb = reinterpret_cast<int32_t*>(sp);
+    sp += sb_b;
+    S->off_sb = reinterpret_cast<int32_t*>(sp);
+    sp += sb1_b;
+    S->ioff = reinterpret_cast<int32_t*>(sp);
+    sp += sb1_b;
+    S->list = reinterpret_cast<int32_t*>(sp);
+    sp += list_b;
+    S->item_sb = reinterpret_cast<int32_t*>(sp);
+    sp += list_b;
+    S->rec_cnt = reinterpret_cast<int32_t*>(sp);
+    sp += rc_b;
+    S->rec_key = reinterpret_cast<u64*>(sp);
+    sp += rk_b;
+    S->rec_ub = reinterpret_cast<float*>(sp);
   }
-  return plan_b + 2 * work_b + fb_b + 256 + acc_b + part_b;
+  return plan_b + 2 * work_b + fb_b + 256 + acc_b + part_b + qhl_b + info_b + tg_b + 2 * sb_b + 2 * sb1_b +
+         2 * list_b + rc_b + rk_b + ru_b;
 }
+
+// Records of the matrix-core scan for a batch of nq queries.
+int64_t tile_pcap(const Resolved& R, int64_t nq) { return R.tile ? TILE_PAIRS_PER_QUERY * nq + 64 : 0; }
 
 // A launch configuration of the persistent search kernel, prepared outside any
 // stream capture: dynamic LDS size set on the function, grid from occupancy.
@@ -1340,7 +2451,8 @@ struct Pass {
 
 // cache = false: the occupancy found is not added to the index's table (the
 // allocation-free entry point keeps host memory unchanged too).
-int prepare_pass(unify_index_t ix, KernelFn fn, size_t lds, int64_t nq, Pass& out, bool cache = true) {
+int prepare_pass(unify_index_t ix, KernelFn fn, size_t lds, int64_t nq, int64_t row_cap, Pass& out,
+                 bool cache = true, int reserve = 0, int block = 64) {
   const auto key = std::make_pair(reinterpret_cast<const void*>(fn), lds);
   auto it = ix->occupancy.find(key);
   int per_cu = 0;
@@ -1349,15 +2461,16 @@ int prepare_pass(unify_index_t ix, KernelFn fn, size_t lds, int64_t nq, Pass& ou
   } else {
     HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
-    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), 64, lds));
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), block, lds));
     if (cache) ix->occupancy[key] = per_cu;
   }
   if (per_cu < 1) {
     set_error("search kernel does not fit on a compute unit");
     return UNIFY_EDEVICE;
   }
-  int64_t grid = (int64_t)per_cu * ix->cus;
-  grid = std::min<int64_t>(grid, ix->nslots);
+  // reserve: wavefronts per compute unit left for a kernel running beside this one
+  int64_t grid = (int64_t)std::max(1, per_cu - reserve) * ix->cus;
+  grid = std::min<int64_t>(grid, row_cap);
   grid = std::min<int64_t>(grid, nq);
   out.fn = fn;
   out.lds = lds;
@@ -1379,14 +2492,22 @@ struct Launch {
   int32_t* out_stats;
   Resolved R;
   Scratch S;
-  SearchArgs A, B;  // first pass, re-run pass
-  Pass p0, p1;
+  SearchArgs A, B, C;  // first pass, re-run pass, cooperative searches
+  Pass p0, p1, pc;
+  bool mw = false;
+  // matrix-core pre-filter scan
+  bool tile = false;
+  TileArgs T;
+  KernelFnT scan_fn = nullptr;
+  FinalFn final_fn = nullptr;
+  size_t scan_lds = 0;
+  unsigned scan_grid = 0;
 };
 
 int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, int64_t nq, const int64_t* l,
                    const int64_t* h, const int8_t* strategy, int64_t* out_ids, float* out_dist,
-                   int8_t* out_strategy, int32_t* out_stats, void* scratch, Launch& X,
-                   const int64_t* l2 = nullptr, const int64_t* h2 = nullptr, bool cache = true) {
+                   int8_t* out_strategy, int32_t* out_stats, void* scratch, int64_t pcap, const VisitPool& pool,
+                   Launch& X, const int64_t* l2 = nullptr, const int64_t* h2 = nullptr, bool cache = true) {
   const DevIndex& dv = ix->dv;
   X.dv = dv;
   X.queries = queries;
@@ -1399,7 +2520,8 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   X.out_strategy = out_strategy;
   X.out_stats = out_stats;
   X.R = R;
-  scratch_layout(nq, R.k, scratch, &X.S);
+  if (l2) pcap = 0;  // conjunctive scans test the second attribute: per wavefront
+  scratch_layout(dv, nq, R.k, pcap, R.kcq, scratch, &X.S);
   const int S = dv.S;
   const int per_node = std::max(std::min(R.m + S - 1, S * std::max(dv.M0, dv.MU)), dv.GC);
   SearchArgs A{};
@@ -1436,9 +2558,10 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   X.l2 = l2;
   X.h2 = h2;
   A.plan = X.S.plan;
-  A.tags = ix->tags;
-  A.epochs = ix->epochs;
-  A.nslots = ix->nslots;
+  A.vrows = pool.rows;
+  A.vstride = pool.stride;
+  A.bwords = pool.bwords;
+  A.nslots = pool.nrows;
   // first pass: modest LDS per wave for occupancy
   A.ccap = R.ccap;
   A.hcap = R.hcap;
@@ -1451,6 +2574,9 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   A.next = X.S.counters + 1;
   A.fb_list = X.S.fb;
   A.fb_count = X.S.counters + 2;
+  A.nheavy = X.S.counters + 6;
+  A.mw_next = X.S.counters + 7;
+  A.mw_row0 = 0;
   // second pass over the abandoned queries with the largest LDS that fits
   int maxlds = 0;
   if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) != hipSuccess)
@@ -1468,57 +2594,165 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   X.A = A;
   X.B = B;
   const bool s1 = (R.flags & UNIFY_FLAG_SELECT_S1) != 0;
+  X.tile = pcap > 0;
+  if (X.tile) {
+    TileArgs T{};
+    T.ix = dv;
+    T.plan = X.S.plan;
+    T.Q = queries;
+    T.nq = nq;
+    T.k = R.k;
+    T.kcq = R.kcq;
+    T.qhl = X.S.qhl;
+    T.qinfo = X.S.qinfo;
+    T.tglob = X.S.tglob;
+    T.cnt_sb = X.S.cnt_sb;
+    T.fill_sb = X.S.fill_sb;
+    T.off_sb = X.S.off_sb;
+    T.ioff = X.S.ioff;
+    T.list = X.S.list;
+    T.item_sb = X.S.item_sb;
+    T.rec_cnt = X.S.rec_cnt;
+    T.rec_key = X.S.rec_key;
+    T.rec_ub = X.S.rec_ub;
+    T.counters = X.S.counters;
+    T.nsb = X.S.nsb;
+    // bounds of the norm expansion: |s~ - ||x~ - q||^2| <= cE (||x~|| + ||q||)^2 + 2 ||x~|| eq,
+    // cE = 3 (d + 8) u covering the products' accumulation (two parts of the query), both
+    // norms and the two additions; g and the constants as for the low-precision scan
+    const int G = dv.d / 4;
+    const double u = std::ldexp(1.0, -24), w = std::ldexp(1.0, -20);
+    const double nr = 4.0 * ((G + 15) / 16) + 6.0, g = nr * u / (1.0 - nr * u);
+    T.cE = (float)(3.0 * (dv.d + 8) * u * (1.0 + w));
+    T.bA = (float)(std::sqrt(1.0 - g) * (1.0 - w));
+    T.bB = (float)(std::sqrt(1.0 - g) * (1.0 + w));
+    T.bC = (float)(std::sqrt(1.0 + g) * (1.0 + w));
+    T.bD = T.bC;
+    X.T = T;
+    X.scan_fn = dv.precision == UNIFY_BF16 ? k_tile_scan<UNIFY_BF16>
+                : dv.precision == UNIFY_FP8E4M3 ? k_tile_scan<UNIFY_FP8E4M3> : k_tile_scan<UNIFY_FP32>;
+    const int ng = (dv.d + 63) / 64;
+    X.final_fn = ng <= 2 ? k_tile_final<2> : (ng <= 4 ? k_tile_final<4> : k_tile_final<8>);
+    X.scan_lds = (size_t)TILE_Q * (dv.d + 8) * 4 + 2 * (size_t)TILE_Q * TILE_ROWS * sizeof(float);
+    HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(X.scan_fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)X.scan_lds));
+    int per_cu = 0;
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(X.scan_fn),
+                                                        64 * TILE_WAVES, X.scan_lds));
+    X.scan_grid = (unsigned)std::max(1, std::max(1, per_cu) * ix->cus);
+  }
+  // cooperative searches of the heavy queries: one workgroup of wpq wavefronts per compute
+  // unit, beside the one-wavefront kernel, whose grid leaves them room
+  X.mw = R.wpq > 1 && R.heavy > 0;
+  int reserve = 0;
+  int64_t row_cap = pool.nrows;
+  if (X.mw) {
+    SearchArgs C = A;
+    C.ccap = std::max(A.ccap, 1024);
+    C.hcap = std::max(A.hcap, 2048);
+    KernelFn fc = kernel_mw(dv.d, dv.precision, R.wpq);
+    if (!fc) {
+      set_error("unsupported dimension");
+      return UNIFY_EINVAL;
+    }
+    const size_t lc = lds_bytes_mw(C.ef_blocks, C.ccap, C.hcap, C.nbr_cap, R.wpq);
+    const int64_t gc = std::min<int64_t>(ix->cus, std::max<int64_t>(1, pool.nrows / 8));
+    C.mw_row0 = pool.nrows - gc;  // the last gc visited rows
+    HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(fc), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lc));
+    X.pc = Pass{fc, lc, (unsigned)gc};
+    X.C = C;
+    reserve = R.wpq;
+    row_cap = C.mw_row0;
+  }
   int rc = prepare_pass(ix, kernel_for<0>(dv.d, dv.precision, s1),
-                        lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap, A.sel_cap), nq, X.p0, cache);
+                        lds_bytes(A.ef_blocks, A.ccap, A.hcap, A.nbr_cap, A.sel_cap), nq, row_cap, X.p0, cache,
+                        reserve);
   // the re-run pass holds the few queries that overflowed: a small grid launches faster
   if (rc == UNIFY_OK)
     rc = prepare_pass(ix, kernel_for<1>(dv.d, dv.precision, s1),
-                      lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap, B.sel_cap), std::min<int64_t>(nq, 512), X.p1,
-                      cache);
+                      lds_bytes(B.ef_blocks, B.ccap, B.hcap, B.nbr_cap, B.sel_cap), std::min<int64_t>(nq, 512),
+                      pool.nrows, X.p1, cache);
   return rc;
 }
 
 // Kernel launches only (no allocation, no memset, no synchronisation), so the
-// sequence can be captured into a HIP graph.  ev: 4 events to record, or null.
-// order: the index whose previous search kernels the search kernels must follow
-// (null inside a graph capture, where the caller orders the replay instead).
-// whole = true: the plan and work-list kernels wait too (their scratch is
-// shared with the previous call's search kernels).
-int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, unify_index_t order = nullptr,
-                   bool whole = false) {
+// sequence can be captured into a HIP graph.  ev: 8 events to record, or null.
+// order: the visited pool whose previous search kernels the search kernels must
+// follow (null inside a graph capture, where the caller orders the replay
+// instead).  whole = true: the plan and work-list kernels wait too (their
+// scratch is shared with the previous call's search kernels).
+int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, const SideStream& side,
+                   VisitPool* order = nullptr, bool whole = false) {
   const unsigned pb = 256;
   const int64_t nq = X.nq;
   std::unique_lock<std::mutex> g;
   if (order) {
-    g = std::unique_lock<std::mutex>(order->order_mu);
-    if (whole && order->last_search) HIP_OK(hipStreamWaitEvent(st, order->last_search, 0));
+    g = std::unique_lock<std::mutex>(order->mu);
+    if (whole) HIP_OK(hipStreamWaitEvent(st, order->last, 0));
   }
+  const unsigned qb4 = (unsigned)((nq + 3) / 4);
   if (ev) HIP_OK(hipEventRecord(ev[0], st));
   hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, X.dv, X.l, X.h, X.l2, X.h2,
                      const_cast<ConjArgs*>(X.A.conj), X.strategy, nq,
-                     X.R.tauA, X.R.tauB, X.R.k, X.R.pre_chunk, X.S.plan, X.out_strategy, X.out_ids, X.out_dist,
-                     X.out_stats);
+                     X.R.tauA, X.R.tauB, X.R.k, X.R.pre_chunk, (int32_t)X.tile, X.S.plan, X.out_strategy,
+                     X.out_ids, X.out_dist, X.out_stats);
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((4 * nq + pb - 1) / pb)), dim3(pb), 0, st, X.S.qacc, 4 * nq, 0);
-  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, X.S.plan, nq, X.dv.n, X.S.work, X.S.wchunk,
-                     X.S.counters);
+  if (X.tile)
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((X.S.nsb + pb - 1) / pb)), dim3(pb), 0, st, X.S.cnt_sb,
+                       X.S.nsb, 0);
+  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, X.S.plan, nq, X.dv.n, X.S.pcap,
+                     (int32_t)(X.mw ? X.R.heavy : 0), X.S.work, X.S.wchunk, X.S.counters);
   HIP_OK(hipGetLastError());
   if (ev) HIP_OK(hipEventRecord(ev[1], st));
-  if (order && !whole) {
-    if (!order->last_search) HIP_OK(hipEventCreateWithFlags(&order->last_search, hipEventDisableTiming));
-    else HIP_OK(hipStreamWaitEvent(st, order->last_search, 0));
+  // the matrix-core scan: its own queries and scratch, beside the graph search
+  // (on the side stream) unless the phases run one after another
+  const bool tside = X.tile && !(X.R.flags & UNIFY_FLAG_SERIAL_PHASES);
+  hipStream_t ts = st;
+  if (tside) {
+    HIP_OK(hipEventRecord(side.tfork, st));
+    HIP_OK(hipStreamWaitEvent(side.tstream, side.tfork, 0));
+    ts = side.tstream;
+  }
+  if (X.tile) {
+    hipLaunchKernelGGL(k_tile_prep, dim3(qb4), dim3(256), 0, ts, X.T);
+    hipLaunchKernelGGL(k_tile_index, dim3(1), dim3(1024), 0, ts, X.T);
+    hipLaunchKernelGGL(k_tile_fill, dim3(qb4), dim3(256), 0, ts, X.T);
+    if (ev) HIP_OK(hipEventRecord(ev[2], ts));
+    hipLaunchKernelGGL(X.scan_fn, dim3(X.scan_grid), dim3(64 * TILE_WAVES), X.scan_lds, ts, X.T);
+    if (ev) HIP_OK(hipEventRecord(ev[3], ts));
+    hipLaunchKernelGGL(X.final_fn, dim3(qb4), dim3(256), 0, ts, X.T, X.out_ids, X.out_dist, X.out_stats);
+    HIP_OK(hipGetLastError());
+    if (ev) HIP_OK(hipEventRecord(ev[4], ts));
+    if (tside) HIP_OK(hipEventRecord(side.tjoin, ts));
+  } else if (ev) {
+    for (int i = 2; i <= 4; ++i) HIP_OK(hipEventRecord(ev[i], st));
+  }
+  if (order && !whole) HIP_OK(hipStreamWaitEvent(st, order->last, 0));
+  if (X.mw) {
+    // the cooperative kernel on the side stream, concurrently with the one-wavefront kernel
+    HIP_OK(hipEventRecord(side.fork, st));
+    HIP_OK(hipStreamWaitEvent(side.stream, side.fork, 0));
+    hipLaunchKernelGGL(X.pc.fn, dim3(X.pc.grid), dim3(64 * X.R.wpq), X.pc.lds, side.stream, X.C);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(side.join, side.stream));
   }
   hipLaunchKernelGGL(X.p0.fn, dim3(X.p0.grid), dim3(64), X.p0.lds, st, X.A);
   HIP_OK(hipGetLastError());
+  if (X.mw) HIP_OK(hipStreamWaitEvent(st, side.join, 0));
+  if (ev) HIP_OK(hipEventRecord(ev[5], st));
+  // the merge and the re-run follow the matrix-core scan (its FP32 fallbacks join the re-run)
+  if (tside) HIP_OK(hipStreamWaitEvent(st, side.tjoin, 0));
   if (X.S.part) {
-    hipLaunchKernelGGL(k_pre_merge, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, X.dv, X.S.plan, nq, X.R.k,
+    hipLaunchKernelGGL(k_pre_merge, dim3(qb4), dim3(256), 0, st, X.dv, X.S.plan, nq, X.R.k,
                        X.S.part, X.S.qacc, X.out_ids, X.out_dist, X.out_stats);
     HIP_OK(hipGetLastError());
   }
-  if (ev) HIP_OK(hipEventRecord(ev[2], st));
+  if (ev) HIP_OK(hipEventRecord(ev[6], st));
   hipLaunchKernelGGL(X.p1.fn, dim3(X.p1.grid), dim3(64), X.p1.lds, st, X.B);
   HIP_OK(hipGetLastError());
-  if (order) HIP_OK(hipEventRecord(order->last_search, st));
-  if (ev) HIP_OK(hipEventRecord(ev[3], st));
+  if (order) HIP_OK(hipEventRecord(order->last, st));
+  if (ev) HIP_OK(hipEventRecord(ev[7], st));
   return UNIFY_OK;
 }
 
@@ -1550,20 +2784,22 @@ int search_common(unify_index_t ix, const float* queries, int64_t nq, const int6
   if (nq == 0) return UNIFY_OK;
   HIP_OK(hipSetDevice(ix->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  rc = ensure_tags(ix);
+  rc = ensure_pool(ix);
   if (rc != UNIFY_OK) return rc;
   const bool timing = (R.flags & UNIFY_FLAG_TIMING) != 0;
   if (timing) {
-    for (int e = 0; e < 4; ++e)
-      if (!ix->ev[e]) HIP_OK(hipEventCreate(&ix->ev[e]));
+    for (hipEvent_t& e : ix->ev)
+      if (!e) HIP_OK(hipEventCreate(&e));
     ix->timed = true;
   }
   void* scratch = nullptr;
-  HIP_OK(hipMallocAsync(&scratch, scratch_layout(nq, k, nullptr, nullptr), st));
+  const int64_t pcap = l2 ? 0 : tile_pcap(R, nq);
+  HIP_OK(hipMallocAsync(&scratch, scratch_layout(ix->dv, nq, k, pcap, R.kcq, nullptr, nullptr), st));
   Launch X;
-  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, X,
-                      l2, h2);
-  if (rc == UNIFY_OK) rc = enqueue_launch(X, st, timing ? ix->ev : nullptr, ix);
+  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, pcap,
+                      ix->pool, X, l2, h2);
+  if (timing) ix->timed_side = X.tile && !(R.flags & UNIFY_FLAG_SERIAL_PHASES);
+  if (rc == UNIFY_OK) rc = enqueue_launch(X, st, timing ? ix->ev : nullptr, ix->pool.side, &ix->pool);
   if (hipFreeAsync(scratch, st) != hipSuccess && rc == UNIFY_OK) rc = UNIFY_EDEVICE;
   return rc;
 }
@@ -1589,14 +2825,21 @@ int search_multi_impl(unify_index_t ix, const float* queries, int64_t nq, const 
 }
 
 
-size_t search_scratch_bytes(int64_t nq, int32_t k) { return scratch_layout(nq, k, nullptr, nullptr); }
+// Scratch of a search of nq queries with parameters prm on index ix (0 when they are invalid).
+size_t search_scratch_bytes(unify_index_t ix, int64_t nq, int32_t k, int32_t ef, const unify_params* prm) {
+  Resolved R;
+  if (resolve(ix, nq, k, ef, prm, R) != UNIFY_OK) return 0;
+  return scratch_layout(ix->dv, nq, k, tile_pcap(R, nq), R.kcq, nullptr, nullptr);
+}
 
 // unify_search with caller-provided scratch (at least search_scratch_bytes(nq, k)
-// bytes of device memory), for loops that must not allocate per call.
+// bytes of device memory) and visited pool (null: the index's), for loops that
+// must not allocate per call.  A caller's pool is (re)made here for the current
+// index size.
 int search_impl_scratch(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
                         int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
                         float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* scratch,
-                        size_t scratch_bytes, void* stream) {
+                        size_t scratch_bytes, VisitPool* pool, void* stream) {
   if (!ix) {
     set_error("null index");
     return UNIFY_EINVAL;
@@ -1606,16 +2849,23 @@ int search_impl_scratch(unify_index_t ix, const float* queries, int64_t nq, cons
   int rc = resolve(ix, nq, k, ef, prm, R);
   if (rc != UNIFY_OK) return rc;
   if (nq == 0) return UNIFY_OK;
-  if (!queries || !l || !h || !out_ids || !out_dist || !scratch || scratch_bytes < search_scratch_bytes(nq, k)) {
+  // the record budget of the matrix-core scan shrinks to what the scratch holds
+  int64_t pcap = tile_pcap(R, nq);
+  while (pcap > 0 && scratch_layout(ix->dv, nq, k, pcap, R.kcq, nullptr, nullptr) > scratch_bytes) pcap /= 2;
+  if (!queries || !l || !h || !out_ids || !out_dist || !scratch ||
+      scratch_bytes < scratch_layout(ix->dv, nq, k, pcap, R.kcq, nullptr, nullptr)) {
     set_error("null buffer or scratch too small");
     return UNIFY_EINVAL;
   }
   HIP_OK(hipSetDevice(ix->device));
-  rc = ensure_tags(ix);
+  rc = ensure_pool(ix);
   if (rc != UNIFY_OK) return rc;
+  if (!pool) pool = &ix->pool;
+  else if ((rc = pool_ensure(*pool, ix->dv.n)) != UNIFY_OK) return rc;
   Launch X;
-  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, X);
-  if (rc == UNIFY_OK) rc = enqueue_launch(X, reinterpret_cast<hipStream_t>(stream), nullptr, ix);
+  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, pcap,
+                      *pool, X);
+  if (rc == UNIFY_OK) rc = enqueue_launch(X, reinterpret_cast<hipStream_t>(stream), nullptr, pool->side, pool);
   return rc;
 }
 
@@ -1639,14 +2889,16 @@ int search_impl_noalloc(unify_index_t ix, const float* queries, int64_t nq, cons
     set_error("null buffer");
     return UNIFY_EINVAL;
   }
-  const size_t need = search_scratch_bytes(nq, k);
+  int64_t pcap = tile_pcap(R, nq);
+  while (pcap > 0 && scratch_layout(ix->dv, nq, k, pcap, R.kcq, nullptr, nullptr) > NOALLOC_SCRATCH_BYTES) pcap /= 2;
+  const size_t need = scratch_layout(ix->dv, nq, k, pcap, R.kcq, nullptr, nullptr);
   if (need > NOALLOC_SCRATCH_BYTES) {
     set_error("unify_search_ex_noalloc: " + std::to_string(nq) + " queries with k = " + std::to_string(k) +
               " need " + std::to_string(need) + " bytes of scratch, more than the static " +
               std::to_string(NOALLOC_SCRATCH_BYTES) + "; split the batch");
     return UNIFY_EINVAL;
   }
-  if (!ix->tags || !ix->last_search) {
+  if (!ix->pool.rows || ix->pool.n != ix->dv.n || !ix->pool.last) {
     set_error("the index has no visited-set memory");
     return UNIFY_EINVAL;
   }
@@ -1655,9 +2907,10 @@ int search_impl_noalloc(unify_index_t ix, const float* queries, int64_t nq, cons
   rc = noalloc_scratch(ix->device, &scratch);
   if (rc != UNIFY_OK) return rc;
   Launch X;
-  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, X,
-                      nullptr, nullptr, false);
-  if (rc == UNIFY_OK) rc = enqueue_launch(X, reinterpret_cast<hipStream_t>(stream), nullptr, ix, true);
+  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, pcap,
+                      ix->pool, X, nullptr, nullptr, false);
+  if (rc == UNIFY_OK)
+    rc = enqueue_launch(X, reinterpret_cast<hipStream_t>(stream), nullptr, ix->pool.side, &ix->pool, true);
   return rc;
 }
 
@@ -1683,7 +2936,7 @@ int batch_create(unify_index_t ix, const float* queries, int64_t nq, const int64
   }
   R.flags &= ~(uint32_t)UNIFY_FLAG_TIMING;
   HIP_OK(hipSetDevice(ix->device));
-  rc = ensure_tags(ix);
+  rc = ensure_pool(ix);
   if (rc != UNIFY_OK) return rc;
   unify_batch_t b = new unify_batch();
   b->ix = ix;
@@ -1693,20 +2946,24 @@ int batch_create(unify_index_t ix, const float* queries, int64_t nq, const int64
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->scratch) (void)hipFree(b->scratch);
+    free_side(b->side);
     delete b;
     return code;
   };
-  if (hipMalloc(&b->scratch, scratch_layout(nq, k, nullptr, nullptr)) != hipSuccess)
+  if (make_side(b->side) != UNIFY_OK) return fail(UNIFY_EDEVICE, "side stream creation failed");
+  const int64_t pcap = tile_pcap(R, nq);
+  if (hipMalloc(&b->scratch, scratch_layout(ix->dv, nq, k, pcap, R.kcq, nullptr, nullptr)) != hipSuccess)
     return fail(UNIFY_ENOMEM, "device allocation failed (batch scratch)");
   Launch X;
-  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, b->scratch, X);
+  rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, b->scratch,
+                      pcap, ix->pool, X);
   if (rc != UNIFY_OK) return fail(rc, "batch preparation failed");
   hipStream_t cs = nullptr;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
     return fail(UNIFY_EDEVICE, "hipStreamCreate failed");
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    rc = enqueue_launch(X, cs, nullptr);
+    rc = enqueue_launch(X, cs, nullptr, b->side);
     const hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
     if (e2 != hipSuccess) e = e2;
   }
@@ -1731,11 +2988,10 @@ int batch_run(unify_batch_t b, void* stream) {
     set_error("the index changed (objects were inserted) after this batch was created: create it again");
     return UNIFY_EINVAL;
   }
-  std::lock_guard<std::mutex> g(ix->order_mu);
-  if (!ix->last_search) HIP_OK(hipEventCreateWithFlags(&ix->last_search, hipEventDisableTiming));
-  else HIP_OK(hipStreamWaitEvent(st, ix->last_search, 0));
+  std::lock_guard<std::mutex> g(ix->pool.mu);
+  HIP_OK(hipStreamWaitEvent(st, ix->pool.last, 0));
   HIP_OK(hipGraphLaunch(b->exec, st));
-  HIP_OK(hipEventRecord(ix->last_search, st));
+  HIP_OK(hipEventRecord(ix->pool.last, st));
   return UNIFY_OK;
 }
 

@@ -1,10 +1,12 @@
 // Serving: continuous batching of range-filtered k-NN requests over a resident
 // index.  Requests carry an arrival time; a worker thread admits the requests
-// that have arrived into a batch whenever one of its in-flight slots is free
-// (a slot owns pinned host staging, device buffers and scratch for max_batch
-// queries, so admission is bounded by slot memory), launches the search on the
-// slot's stream and harvests finished slots by their events.  Per-query
-// results do not depend on which other queries share a batch.
+// that have arrived into a batch whenever one of its in-flight slots is free,
+// launches the search on the slot's stream and harvests finished slots by their
+// events.  A slot owns pinned host staging, device buffers, scratch and its own
+// visited pool, so the search kernels of different slots run concurrently on
+// the device.  The batch size and the pool rows are chosen at creation so that
+// the slots fit a device-memory budget.  Per-query results do not depend on
+// which other queries share a batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,6 +15,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -23,16 +26,18 @@ namespace unify {
 int search_impl_scratch(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
                         int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
                         float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* scratch,
-                        size_t scratch_bytes, void* stream);
-size_t search_scratch_bytes(int64_t nq, int32_t k);
+                        size_t scratch_bytes, VisitPool* pool, void* stream);
+size_t search_scratch_bytes(unify_index_t ix, int64_t nq, int32_t k, int32_t ef, const unify_params* prm);
 }  // namespace unify
 
 using Clock = std::chrono::steady_clock;
 
 struct unify_server {
   unify_index_t ix = nullptr;
-  unify_server_config cfg{};
+  unify_server_config cfg{};  // cfg.max_batch: the batch size the budget admits
   int d = 0;
+  int64_t visit_rows = 0;    // rows of each slot's visited pool
+  int64_t device_bytes = 0;  // device memory the slots hold
 
   struct Slot {
     hipStream_t stream = nullptr;
@@ -50,6 +55,7 @@ struct unify_server {
     float* ddist = nullptr;
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    std::unique_ptr<unify::VisitPool> pool;  // the visited rows of this slot's searches
     std::vector<int64_t> tickets;  // requests of the batch in flight, empty when free
   };
   std::vector<Slot> slots;
@@ -81,9 +87,20 @@ struct unify_server {
 
 namespace {
 
+// Device bytes of a slot's query and result buffers for B queries.
+size_t io_bytes(int64_t B, int d, int k) {
+  const size_t parts[] = {sizeof(float) * B * d, sizeof(int64_t) * B, sizeof(int64_t) * B, (size_t)B,
+                          sizeof(int64_t) * B * k, sizeof(float) * B * k};
+  size_t total = 0;
+  for (size_t p : parts) total += (p + 255) / 256 * 256;
+  return total;
+}
+
 int slot_init(unify_server* S, unify_server::Slot& s) {
   const int64_t B = S->cfg.max_batch;
   const int k = S->cfg.k, d = S->d;
+  s.pool = std::make_unique<unify::VisitPool>();
+  s.pool->max_rows = S->visit_rows;
   if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
     return UNIFY_EDEVICE;
@@ -99,9 +116,13 @@ int slot_init(unify_server* S, unify_server::Slot& s) {
     off[i] = total;
     total += (parts[i] + 255) / 256 * 256;
   }
-  s.scratch_bytes = unify::search_scratch_bytes(B, k);
+  s.scratch_bytes = unify::search_scratch_bytes(S->ix, B, k, S->cfg.ef, &S->cfg.params);
+  if (s.scratch_bytes == 0) return UNIFY_EINVAL;
   if (hipMalloc(&s.dmem, total) != hipSuccess || hipMalloc(&s.scratch, s.scratch_bytes) != hipSuccess)
     return UNIFY_ENOMEM;
+  const int rc = unify::pool_ensure(*s.pool, S->ix->dv.n);
+  if (rc != UNIFY_OK) return rc;
+  S->device_bytes += (int64_t)(total + s.scratch_bytes) + s.pool->nrows * (int64_t)unify::pool_row_bytes(s.pool->n);
   char* b = static_cast<char*>(s.dmem);
   s.dq = reinterpret_cast<float*>(b + off[0]);
   s.dl = reinterpret_cast<int64_t*>(b + off[1]);
@@ -118,6 +139,7 @@ void slot_free(unify_server::Slot& s) {
     if (p) (void)hipHostFree(p);
   if (s.dmem) (void)hipFree(s.dmem);
   if (s.scratch) (void)hipFree(s.scratch);
+  if (s.pool) unify::pool_free(*s.pool);
   if (s.done) (void)hipEventDestroy(s.done);
   if (s.stream) (void)hipStreamDestroy(s.stream);
 }
@@ -144,7 +166,7 @@ int slot_launch(unify_server* S, unify_server::Slot& s, const std::vector<int64_
       hipMemcpyAsync(s.ds, s.hs, n, hipMemcpyHostToDevice, st) != hipSuccess)
     return UNIFY_EDEVICE;
   int rc = unify::search_impl_scratch(S->ix, s.dq, n, s.dl, s.dh, k, S->cfg.ef, s.ds, &S->cfg.params, s.dids,
-                                      s.ddist, nullptr, nullptr, s.scratch, s.scratch_bytes, st);
+                                      s.ddist, nullptr, nullptr, s.scratch, s.scratch_bytes, s.pool.get(), st);
   if (rc != UNIFY_OK) return rc;
   if (hipMemcpyAsync(s.hids, s.dids, sizeof(int64_t) * n * k, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipMemcpyAsync(s.hdist, s.ddist, sizeof(float) * n * k, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -251,18 +273,48 @@ int unify_server_create(unify_index_t ix, const unify_server_config* cfg, unify_
   if (c.max_batch <= 0) c.max_batch = 4096;
   if (c.inflight <= 0) c.inflight = 2;
   if (c.k < 1 || c.k > 256 || c.ef < c.k || c.ef > 256 || c.max_batch > (1 << 20) || c.inflight > 8 ||
-      c.max_wait_s < 0) {
-    set_error("unify_server_create: k in [1, 256], ef in [k, 256], max_batch <= 2^20, inflight <= 8, max_wait >= 0");
+      c.max_wait_s < 0 || c.mem_budget < 0) {
+    set_error("unify_server_create: k in [1, 256], ef in [k, 256], max_batch <= 2^20, inflight <= 8, max_wait >= 0, "
+              "mem_budget >= 0");
     return UNIFY_EINVAL;
   }
   if (hipSetDevice(ix->device) != hipSuccess) {
     set_error("hipSetDevice failed");
     return UNIFY_EDEVICE;
   }
+  std::shared_lock<std::shared_mutex> version(ix->version_mu);
+  // admission by memory: each slot holds the buffers and scratch of a batch and a
+  // visited pool (one row per resident wavefront of the device at most); the batch
+  // size, then the rows, halve until `inflight` slots fit the budget
+  int cus = 0;
+  size_t free_b = 0, total_b = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ix->device) != hipSuccess ||
+      hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    set_error("device query failed");
+    return UNIFY_EDEVICE;
+  }
+  const int64_t budget = c.mem_budget > 0 ? c.mem_budget : (int64_t)(free_b / 2);
+  const size_t row = pool_row_bytes(ix->dv.n);
+  int64_t B = c.max_batch, rows = (int64_t)cus * 16;
+  auto slot_bytes = [&](int64_t b, int64_t r) {
+    const size_t sc = search_scratch_bytes(ix, b, c.k, c.ef, &c.params);
+    return sc == 0 ? INT64_MAX : (int64_t)(io_bytes(b, ix->dv.d, c.k) + sc + (size_t)r * row);
+  };
+  if (slot_bytes(1, 1) == INT64_MAX) return UNIFY_EINVAL;  // the parameters (message set)
+  while (B > 64 && slot_bytes(B, rows) > budget / c.inflight) B = (B + 1) / 2;
+  while (rows > 64 && slot_bytes(B, rows) > budget / c.inflight) rows /= 2;
+  if (slot_bytes(B, rows) > budget / c.inflight) {
+    set_error("unify_server_create: the memory budget (" + std::to_string(budget) + " bytes) holds no " +
+              std::to_string(c.inflight) + " slots of " + std::to_string(B) + " queries and " +
+              std::to_string(rows) + " visited rows");
+    return UNIFY_ENOMEM;
+  }
+  c.max_batch = (int32_t)B;
   unify_server* S = new unify_server();
   S->ix = ix;
   S->cfg = c;
   S->d = ix->dv.d;
+  S->visit_rows = rows;
   S->slots.resize(c.inflight);
   for (auto& s : S->slots) {
     const int rc = slot_init(S, s);
@@ -347,6 +399,17 @@ int unify_server_wait(unify_server_t S, int64_t n, const int64_t* tickets, int64
     if (dist) std::memcpy(dist + i * k, S->dist.data() + t * k, sizeof(float) * k);
     if (latency_s) latency_s[i] = S->latency[t];
   }
+  return UNIFY_OK;
+}
+
+int unify_server_limits(unify_server_t S, int64_t* max_batch, int64_t* visit_rows, int64_t* device_bytes) {
+  if (!S) {
+    set_error("null server");
+    return UNIFY_EINVAL;
+  }
+  if (max_batch) *max_batch = S->cfg.max_batch;
+  if (visit_rows) *visit_rows = S->slots.empty() ? 0 : S->slots[0].pool->nrows;
+  if (device_bytes) *device_bytes = S->device_bytes;
   return UNIFY_OK;
 }
 

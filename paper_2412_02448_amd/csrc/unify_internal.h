@@ -35,6 +35,7 @@ struct DevIndex {
   const uint8_t* vec_fp8;    // [n][d] FP8 E4M3 store or null
   const float* vec_scale;    // [n] FP8 scale or null
   const float* vec_eps;      // [n] bound on ||copy - FP32 vector|| of the store in use, or null
+  const float* vec_nrm;      // [n] squared norm of each row of the store in use (FP32)
   const int32_t* adj0;       // [n][S][M0] layer-0 chunks, -1 padded
   const int32_t* glist0;     // [n][GC] layer-0 global (marked) edges, -1 padded
   const int32_t* adjU;       // [R][S][MU]
@@ -52,6 +53,8 @@ struct QPlan {
   int32_t nch;      // pre-filter: chunks the slice is split into (1 = one wavefront)
   int32_t clen;     // pre-filter: objects per chunk (the last one may be shorter)
   int32_t pbase;    // pre-filter, nch > 1: first slot of the query's partial top-k lists
+  int32_t tsb;      // pre-filter by the matrix-core scan: super-blocks its slice touches (0: not)
+  int32_t tbase;    // matrix-core scan: first of the query's tsb candidate records
 };
 
 // Host-side tables of an index (the index file content), internal ids.
@@ -81,26 +84,62 @@ void set_error(const std::string& msg);
 // resident vectors and its error bounds when it is not resident yet.
 int quantize_store(unify_index_t ix, int precision);
 
-// Allocates the index's visited-set memory and its search-ordering event if
-// they are not there yet (called when an index version becomes resident).
-int ensure_tags(unify_index_t ix);
+// Two more streams with their fork and join events: the cooperative search
+// kernel runs on `stream` beside the one-wavefront kernel, the matrix-core
+// pre-filter scan on `tstream` beside both.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t tstream = nullptr;
+  hipEvent_t tfork = nullptr, tjoin = nullptr;
+};
+int make_side(SideStream& s);
+void free_side(SideStream& s);
+
+// Visited-set memory of the graph searches: one row per persistent wavefront (a
+// bitmap of the index's n objects, clear between layer searches, then a log of
+// the bitmap words a layer search set), the event of the last search kernel
+// enqueued on the rows and the side stream of the cooperative kernel.  Searches
+// on one pool are ordered through `last` under `mu`; searches on different
+// pools run concurrently.  The index holds one pool, each serving slot its own.
+struct VisitPool {
+  uint32_t* rows = nullptr;
+  int64_t nrows = 0;     // rows made
+  int64_t max_rows = 0;  // rows wanted (fewer are made when device memory is short)
+  int64_t stride = 0;    // words of a row
+  int64_t bwords = 0;    // words of a row's bitmap
+  int64_t n = -1;        // objects the rows were made for
+  std::mutex mu;
+  hipEvent_t last = nullptr;
+  SideStream side;
+};
+// Bytes of one row for an index of n objects.
+size_t pool_row_bytes(int64_t n);
+// Makes the event, the side stream and max_rows rows for n objects (fewer if a
+// quarter of the free device memory does not hold them), all bits clear; rows
+// made for another n are freed first, once the searches on them have finished.
+int pool_ensure(VisitPool& p, int64_t n);
+// Waits for the pool's searches and frees everything it holds.
+void pool_free(VisitPool& p);
+
+// Makes the index's visited pool (one row per resident wavefront of the device),
+// if it is not there yet for the current index size (called when an index
+// version becomes resident).
+int ensure_pool(unify_index_t ix);
 
 }  // namespace unify
 
 struct unify_index {
   int device = 0;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // timing: before the plan, after the work
-                                                            // list, after the search, after the re-run
+  // timing: before the plan, after the work list, after the matrix-core scan's set-up, after its
+  // scan, after its results, after the search kernel, after the merge, after the re-run
+  hipEvent_t ev[8] = {};
   bool timed = false;
-  uint32_t* tags = nullptr;    // visited epochs [nslots][n], allocated when the index becomes resident
-  uint32_t* epochs = nullptr;  // [nslots]
-  int64_t nslots = 0;
+  bool timed_side = false;  // the timed call ran the matrix-core scan beside the graph search
+  unify::VisitPool pool;  // the visited rows of searches that bring none of their own
   const float* eps_of[3] = {nullptr, nullptr, nullptr};  // error bounds of the resident BF16 / FP8 copies
+  const float* nrm_of[3] = {nullptr, nullptr, nullptr};  // squared row norms of each resident store
   int cus = 0;                                            // compute units of the device
-  // The visited tags are shared by every search on the index: the search
-  // kernels of successive calls are ordered across streams by this event.
-  std::mutex order_mu;
-  hipEvent_t last_search = nullptr;
   // An insertion builds a new version of the tables and swaps it in while no
   // search is being enqueued: entry points that read dv hold version_mu shared,
   // the swap holds it exclusively.  version counts the swaps; insert_mu keeps
@@ -119,6 +158,7 @@ struct unify_batch {
   unify_index_t ix = nullptr;
   uint64_t version = 0;  // the index version the graph was captured on
   void* scratch = nullptr;
+  unify::SideStream side;  // joins the capture when the search forks
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };

@@ -102,6 +102,7 @@ def test_entry_points_reject_bad_arguments_on_the_host():
     assert lib.unify_server_submit(null, 1, null, null, null, null, null, null) == EINVAL
     assert lib.unify_server_wait(null, 1, null, null, null, null, 1.0) == EINVAL
     assert lib.unify_server_stats(null, null, null, null) == EINVAL
+    assert lib.unify_server_limits(null, null, null, null) == EINVAL
     # the merge checks its sizes before launching anything
     buf = (C.c_int64 * 4)()
     assert lib.unify_merge_or(buf, buf, buf, buf, 1, 0, buf, buf, null) == EINVAL
@@ -133,3 +134,22 @@ def test_params_struct_matches_header():
     assert [(n, ctype[t]) for n, t in fields] == list(u._Params._fields_)
     assert [n for n, _ in fields[:6]] == ["m", "beam_p", "rerank_mult", "tau_a_frac", "tau_b_frac", "flags"]
     assert u._Params.tau_a_frac.offset == 16 and u._Params.flags.offset == 32
+
+
+def test_server_config_struct_matches_header():
+    """The binding's server configuration has the header's fields in its order."""
+    import ctypes as C
+
+    import paper_2412_02448_amd as u
+    src = open(os.path.join(ROOT, "include", "unify.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*?)\} unify_server_config;", src, flags=re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        typ, names = decl.split(None, 1)
+        fields += [(n.strip(), typ) for n in names.split(",")]
+    ctype = {"int32_t": C.c_int32, "int64_t": C.c_int64, "double": C.c_double, "unify_params": u._Params}
+    assert [(n, ctype[t]) for n, t in fields] == list(u._ServerConfig._fields_)

@@ -62,7 +62,8 @@ def test_store_matches_oracle_rounding(c1, name, prec):
         assert np.array_equal(sc.cpu().numpy().view(np.uint32), rs.view(np.uint32))
     err = np.sqrt(((back.astype(np.float64) - X) ** 2).sum(1))
     e = eps.cpu().numpy().astype(np.float64)
-    assert np.all(e >= err) and np.all(e <= err * (1 + 1e-6) + 1e-30)
+    # an upper bound, widened by 2^-18 relative (the FP32 sum's roundings) plus 1e-21
+    assert np.all(e >= err) and np.all(e <= err * (1 + 4e-6) + 1e-20)
     g.close()
 
 

@@ -230,3 +230,82 @@ def test_unknown_strategy_rows(c1):
     assert (ost[bad] == -2).all() and (st[bad, 3] == 3).all() and (st[bad, 5] == -2).all()
     rid, rd = ix.search(W.queries[~bad], W.l[~bad], W.h[~bad], 10, 64)
     assert np.array_equal(ids[~bad], rid) and np.array_equal(dist[~bad].view(np.uint32), rd.view(np.uint32))
+
+
+@pytest.mark.parametrize("k", [1, 10, 32])
+def test_matrix_core_scan_equals_wave_scan(c1, k):
+    """The pre-filter scan on the matrix cores (norm expansion on MFMA, then FP32 re-scores of
+    the objects its bounds cannot exclude) returns exactly the per-wavefront FP32 scan's rows
+    and the oracle's; every forced pre-filter row within the record budget took that path."""
+    W, ix, g = c1
+    print(f"[case] matrix-core scan k={k}", flush=True)
+    ref = ix.search(W.queries, W.l, W.h, k, max(k, 16), strategy=hsig.PRE)
+    tile = gpu_search(g, W, k, max(k, 16), strategy=hsig.PRE)
+    wave = gpu_search(g, W, k, max(k, 16), strategy=hsig.PRE, wave_scan=True)
+    assert_parity(ref, tile, f"matrix-core scan k={k}")
+    assert_parity(ref, wave, f"wave scan k={k}")
+    took = tile[3][:, 4] > 0
+    assert took.sum() >= len(W.queries) // 2, took.sum()
+    assert (wave[3][:, 4] == 0).all()
+    # far fewer FP32 evaluations than objects in range
+    assert tile[3][took, 2].sum() < 0.2 * tile[3][took, 6].sum()
+
+
+def test_serial_phases_equal_concurrent(c1):
+    """The matrix-core scan runs beside the graph search on a second stream by default;
+    run before it (UNIFY_FLAG_SERIAL_PHASES), every row is the same, and the oracle's."""
+    W, ix, g = c1
+    print("[case] serial phases vs concurrent", flush=True)
+    ref = ix.search(W.queries, W.l, W.h, 10, 32, m=16, p=2)
+    side = gpu_search(g, W, 10, 32, m=16, beam_p=2)
+    serial = gpu_search(g, W, 10, 32, m=16, beam_p=2, serial_phases=True)
+    assert_parity(ref, side, "concurrent phases")
+    assert_parity(ref, serial, "serial phases")
+    assert (side[3][:, 4][side[2] == hsig.PRE] > 0).any()  # the matrix-core scan ran
+
+
+def test_matrix_core_scan_record_overflow(tmp_path):
+    """Four distinct vectors repeated over 4096 objects: about 64 objects of every super-block
+    tie at the smallest distance, more than a record holds, and those queries are answered
+    by the FP32 scan (status 1) with the (distance, id) order of the oracle."""
+    rng = np.random.default_rng(9)
+    n, d = 4096, 64
+    base = rng.standard_normal((4, d)).astype(np.float32)
+    X = base[rng.integers(0, 4, n)]
+    attr = rng.permutation(n).astype(np.int64)
+    ix = hsig.Index.build(X, attr, 1.0 - rng.random(n), 4, 8, 32)
+    path = str(tmp_path / "ties.uix")
+    ix.write(path)
+    import paper_2412_02448_amd as u
+    g = u.Index.load(path, device=0)
+    nq = 64
+    Q = (base[rng.integers(0, 4, nq)] + 0.01 * rng.standard_normal((nq, d))).astype(np.float32)
+    lo = rng.integers(0, n // 2, nq).astype(np.int64)
+    hi = (lo + rng.integers(300, n // 2, nq)).astype(np.int64)
+    Wq = w.Workload(None, X, attr, Q, lo, hi, None, None)
+    print("[case] matrix-core scan record overflow", flush=True)
+    for k in (1, 10):
+        ref = ix.search(Q, lo, hi, k, 16, strategy=hsig.PRE)
+        got = gpu_search(g, Wq, k, 16, strategy=hsig.PRE)
+        assert_parity(ref, got, f"ties k={k}")
+        assert ((got[3][:, 3] & 0xFF) == 1).any(), "no record overflowed"
+    g.close()
+
+
+@pytest.mark.parametrize("wpq", [2, 4])
+@pytest.mark.parametrize("strategy,p", [(hsig.HYBRID, 1), (hsig.HYBRID, 4), (hsig.POST, 2), (hsig.AUTO, 4)])
+def test_parity_cooperative_search(c1, wpq, strategy, p):
+    """Heavy graph searches run by 2 or 4 wavefronts together (the adjacency gather, the
+    visited checks and the distance evaluations split between them, admissions by one):
+    every row equals the oracle's, for a few heavy queries and for all of them."""
+    W, ix, g = c1
+    print(f"[case] cooperative wpq={wpq} strategy={strategy} p={p}", flush=True)
+    ref = ix.search(W.queries, W.l, W.h, 10, 48, p=p, strategy=strategy)
+    for heavy in (16, 100000):
+        got = gpu_search(g, W, 10, 48, strategy=None if strategy == hsig.AUTO else strategy, beam_p=p,
+                         waves_per_query=wpq, heavy_queries=heavy)
+        assert_parity(ref, got, f"cooperative wpq={wpq} heavy={heavy}")
+        coop = (got[3][:, 3] & 0x200) != 0
+        graph = np.isin(got[3][:, 5], [hsig.HYBRID, hsig.POST])
+        assert coop[graph].sum() >= min(heavy, graph.sum()), (coop.sum(), heavy)
+        assert not coop[~graph].any()

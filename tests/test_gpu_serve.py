@@ -133,3 +133,28 @@ def test_served_k100_equals_batch(c1):
     oid, od = ix.search(W.queries[:n], W.l[:n], W.h[:n], 100, 128, m=16, p=2)
     assert np.array_equal(oid, ids)
     g.close()
+
+
+def test_memory_budget_admission(c1):
+    """A small device-memory budget shrinks the batch size, then each slot's visited
+    rows, until the slots fit; results stay those of the oracle.  A budget that holds
+    no slot is refused."""
+    W, ix, path = c1
+    _torch()
+    import paper_2412_02448_amd as u
+    print("[case] serve under a 12 MB budget", flush=True)
+    g = u.Index.load(path, device=0)
+    with pytest.raises(u.UnifyError):
+        u.Server(g, 10, 40, inflight=3, mem_budget=1 << 16, m=16, beam_p=2)
+    srv = u.Server(g, 10, 40, max_batch=4096, inflight=3, mem_budget=12 << 20, m=16, beam_p=2)
+    batch, rows, nbytes = srv.limits()
+    assert batch == 64 and 1 <= rows <= 128 and 0 < nbytes <= 12 << 20
+    n = len(W.queries)
+    arrive = np.sort(np.random.default_rng(5).uniform(0, 0.02, n))
+    ids, dist, _ = srv.wait(srv.submit(W.queries, W.l, W.h, arrive_s=arrive), timeout_s=60)
+    done, batches, _ = srv.stats()
+    srv.close()
+    assert done == n and batches >= n // 64
+    oid, od = ix.search(W.queries, W.l, W.h, 10, 40, m=16, p=2)
+    assert np.array_equal(oid, ids) and np.array_equal(od.view(np.uint32), dist.view(np.uint32))
+    g.close()
