@@ -375,8 +375,12 @@ int unify_batch_free(unify_batch_t batch);  /* NULL is accepted */
  * Admission is by device memory: the batch size (at most max_batch), then the
  * visited rows of each slot (at most one per resident wavefront of the device),
  * halve until `inflight` slots fit mem_budget bytes; unify_server_limits
- * reports the outcome.  Every request's result is the one unify_search returns
- * for it alone.
+ * reports the outcome.  Each slot runs on one stream (the matrix-core scan before
+ * the graph search; a second stream only for cooperative searches).  Slots overlap
+ * on the device only on different hardware queues: HIP shares GPU_MAX_HW_QUEUES
+ * queues (4 by default) among all streams of a process, in order, so a serving
+ * process with more slots than free queues should raise it.  Every request's
+ * result is the one unify_search returns for it alone.
  */
 typedef struct unify_server* unify_server_t;
 typedef struct {

@@ -2286,11 +2286,17 @@ int resolve(unify_index_t ix, int64_t nq, int32_t k, int32_t ef, const unify_par
 // that orders the search kernels using them.  The index's pool is made when the
 // index becomes resident (load, build, insertion), so that searches need no
 // allocation of their own.
-int make_side(SideStream& s) {
-  for (hipStream_t* t : {&s.stream, &s.tstream})
-    if (!*t) HIP_OK(hipStreamCreateWithFlags(t, hipStreamNonBlocking));
-  for (hipEvent_t* e : {&s.fork, &s.join, &s.tfork, &s.tjoin})
-    if (!*e) HIP_OK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+int make_side(SideStream& s, bool coop, bool tile) {
+  if (coop) {
+    if (!s.stream) HIP_OK(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&s.fork, &s.join})
+      if (!*e) HIP_OK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  }
+  if (tile) {
+    if (!s.tstream) HIP_OK(hipStreamCreateWithFlags(&s.tstream, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&s.tfork, &s.tjoin})
+      if (!*e) HIP_OK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  }
   return UNIFY_OK;
 }
 
@@ -2310,7 +2316,6 @@ size_t pool_row_bytes(int64_t n) { return sizeof(uint32_t) * (size_t)(bitmap_wor
 
 int pool_ensure(VisitPool& p, int64_t n) {
   if (!p.last) HIP_OK(hipEventCreateWithFlags(&p.last, hipEventDisableTiming));
-  if (make_side(p.side) != UNIFY_OK) return UNIFY_EDEVICE;
   if (p.rows && p.n == n) return UNIFY_OK;
   if (p.rows) {
     HIP_OK(hipEventSynchronize(p.last));
@@ -2354,6 +2359,8 @@ void pool_free(VisitPool& p) {
 int ensure_pool(unify_index_t ix) {
   if (!ix->cus) HIP_OK(hipDeviceGetAttribute(&ix->cus, hipDeviceAttributeMultiprocessorCount, ix->device));
   if (!ix->pool.max_rows) ix->pool.max_rows = (int64_t)ix->cus * 16;
+  // the index's side streams exist from the start: the allocation-free call creates nothing
+  if (make_side(ix->pool.side, true, true) != UNIFY_OK) return UNIFY_EDEVICE;
   return pool_ensure(ix->pool, ix->dv.n);
 }
 
@@ -2676,6 +2683,12 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   return rc;
 }
 
+// The matrix-core scan runs on the side stream, beside the graph search.
+bool tile_beside(const Launch& X) { return X.tile && !(X.R.flags & UNIFY_FLAG_SERIAL_PHASES); }
+
+// The side streams a launch uses, made before it is enqueued (or captured).
+int make_side_for(SideStream& s, const Launch& X) { return make_side(s, X.mw, tile_beside(X)); }
+
 // Kernel launches only (no allocation, no memset, no synchronisation), so the
 // sequence can be captured into a HIP graph.  ev: 8 events to record, or null.
 // order: the visited pool whose previous search kernels the search kernels must
@@ -2707,7 +2720,7 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, const SideSt
   if (ev) HIP_OK(hipEventRecord(ev[1], st));
   // the matrix-core scan: its own queries and scratch, beside the graph search
   // (on the side stream) unless the phases run one after another
-  const bool tside = X.tile && !(X.R.flags & UNIFY_FLAG_SERIAL_PHASES);
+  const bool tside = tile_beside(X);
   hipStream_t ts = st;
   if (tside) {
     HIP_OK(hipEventRecord(side.tfork, st));
@@ -2798,7 +2811,8 @@ int search_common(unify_index_t ix, const float* queries, int64_t nq, const int6
   Launch X;
   rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, pcap,
                       ix->pool, X, l2, h2);
-  if (timing) ix->timed_side = X.tile && !(R.flags & UNIFY_FLAG_SERIAL_PHASES);
+  if (timing) ix->timed_side = tile_beside(X);
+  if (rc == UNIFY_OK) rc = make_side_for(ix->pool.side, X);
   if (rc == UNIFY_OK) rc = enqueue_launch(X, st, timing ? ix->ev : nullptr, ix->pool.side, &ix->pool);
   if (hipFreeAsync(scratch, st) != hipSuccess && rc == UNIFY_OK) rc = UNIFY_EDEVICE;
   return rc;
@@ -2865,6 +2879,7 @@ int search_impl_scratch(unify_index_t ix, const float* queries, int64_t nq, cons
   Launch X;
   rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, pcap,
                       *pool, X);
+  if (rc == UNIFY_OK) rc = make_side_for(pool->side, X);
   if (rc == UNIFY_OK) rc = enqueue_launch(X, reinterpret_cast<hipStream_t>(stream), nullptr, pool->side, pool);
   return rc;
 }
@@ -2950,7 +2965,6 @@ int batch_create(unify_index_t ix, const float* queries, int64_t nq, const int64
     delete b;
     return code;
   };
-  if (make_side(b->side) != UNIFY_OK) return fail(UNIFY_EDEVICE, "side stream creation failed");
   const int64_t pcap = tile_pcap(R, nq);
   if (hipMalloc(&b->scratch, scratch_layout(ix->dv, nq, k, pcap, R.kcq, nullptr, nullptr)) != hipSuccess)
     return fail(UNIFY_ENOMEM, "device allocation failed (batch scratch)");
@@ -2958,6 +2972,7 @@ int batch_create(unify_index_t ix, const float* queries, int64_t nq, const int64
   rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, b->scratch,
                       pcap, ix->pool, X);
   if (rc != UNIFY_OK) return fail(rc, "batch preparation failed");
+  if (make_side_for(b->side, X) != UNIFY_OK) return fail(UNIFY_EDEVICE, "side stream creation failed");
   hipStream_t cs = nullptr;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
     return fail(UNIFY_EDEVICE, "hipStreamCreate failed");

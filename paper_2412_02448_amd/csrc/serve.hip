@@ -270,6 +270,9 @@ int unify_server_create(unify_index_t ix, const unify_server_config* cfg, unify_
   }
   unify_server_config c = *cfg;
   c.params.flags &= ~(uint32_t)UNIFY_FLAG_TIMING;  // timing events belong to the index, not to a server
+  // concurrency comes from the slots: each keeps to its one stream (the matrix-core scan
+  // before the graph search), since a process's streams share a few hardware queues
+  c.params.flags |= UNIFY_FLAG_SERIAL_PHASES;
   if (c.max_batch <= 0) c.max_batch = 4096;
   if (c.inflight <= 0) c.inflight = 2;
   if (c.k < 1 || c.k > 256 || c.ef < c.k || c.ef > 256 || c.max_batch > (1 << 20) || c.inflight > 8 ||

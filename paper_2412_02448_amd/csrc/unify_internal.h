@@ -93,7 +93,10 @@ struct SideStream {
   hipStream_t tstream = nullptr;
   hipEvent_t tfork = nullptr, tjoin = nullptr;
 };
-int make_side(SideStream& s);
+// Creates the streams and events a launch needs (the cooperative kernel's, the
+// matrix-core scan's) if they are not there yet: a process shares a few hardware
+// queues among all its streams, so none is made that would stay unused.
+int make_side(SideStream& s, bool coop, bool tile);
 void free_side(SideStream& s);
 
 // Visited-set memory of the graph searches: one row per persistent wavefront (a
