@@ -164,6 +164,24 @@ int unify_insert(unify_index_t index, const float* vectors, const int64_t* attr,
                  int64_t m);
 
 /*
+ * Prune (Sec. 2.2, the neighbour selection of Alg. 4 and Alg. 5) as the GPU builder
+ * runs it, on caller-given candidate lists: for task i, owner owners[i] and
+ * candidates cand[i][0 .. c) (ids into vectors, -1 for none), the candidates are
+ * ordered by (FP32 squared distance to the owner, id), the owner itself and repeated
+ * ids dropped, and each is kept unless an already kept one is strictly nearer to
+ * it than the owner is, until M are kept.  Exposed for callers that assemble
+ * their own candidate lists.
+ *   vectors  device, [n][d] float32 (d % 4 == 0, 4 <= d <= 2048)
+ *   owners   device, [t] int32 ids into vectors
+ *   cand     device, [t][c] int32, 1 <= c <= 256
+ *   out      device, [t][M] int32 kept ids in selection order, -1 padded; 1 <= M <= 64
+ *   hip_stream  stream to enqueue on (scratch is allocated on it), or NULL
+ * Asynchronous; t = 0 is a no-op.  UNIFY_EINVAL for out-of-range sizes or null buffers.
+ */
+int unify_prune(const float* vectors, int64_t n, int32_t d, const int32_t* owners, const int32_t* cand,
+                int64_t t, int32_t c, int32_t M, int32_t* out, void* hip_stream);
+
+/*
  * Reads and checks an index file on the host only (no GPU needed): header,
  * checksum, section sizes and the range of every adjacency entry.  Outputs are
  * host pointers, any may be NULL.  Returns UNIFY_EIO or UNIFY_EFORMAT on failure.

@@ -76,6 +76,7 @@ SIGNATURES = {
     "unify_server_create": (_I32, [_P, _P, _P]),
     "unify_server_submit": (_I32, [_P, _I64, _P, _P, _P, _P, _P, _P]),
     "unify_server_wait": (_I32, [_P, _I64, _P, _P, _P, _P, C.c_double]),
+    "unify_prune": (_I32, [_P, _I64, _I32, _P, _P, _I64, _I32, _I32, _P, _P]),
     "unify_server_limits": (_I32, [_P, _P, _P, _P]),
     "unify_server_stats": (_I32, [_P, _P, _P, _P]),
     "unify_server_free": (_I32, [_P]),
@@ -137,6 +138,27 @@ def merge_or(a, b, stream=None):
         for t in (ia, da, ib, db, oi, od):
             t.record_stream(s)  # in use on s until it passes this point
     return oi, od
+
+
+def prune(vectors, owners, cand, M: int):
+    """The builder's Prune on the GPU: vectors cuda float32 [n, d]; owners cuda int32 [t];
+    cand cuda int32 [t, c] candidate ids (-1: none).  Returns cuda int32 [t, M], the kept ids
+    of each task in selection order, -1 padded."""
+    import torch
+    if vectors.dtype != torch.float32 or vectors.dim() != 2 or not vectors.is_contiguous():
+        raise ValueError("vectors must be a contiguous float32 [n, d] tensor")
+    dev = vectors.device
+    for t_, nd in ((owners, 1), (cand, 2)):
+        if t_.dtype != torch.int32 or t_.dim() != nd or not t_.is_contiguous() or t_.device != dev:
+            raise ValueError("owners int32 [t] and cand int32 [t, c], contiguous, on the vectors' device")
+    t = owners.shape[0]
+    if cand.shape[0] != t:
+        raise ValueError("one candidate row per owner")
+    out = torch.empty((t, M), dtype=torch.int32, device=dev)
+    s = torch.cuda.current_stream(dev)
+    _check(load_library().unify_prune(_ptr(vectors), vectors.shape[0], vectors.shape[1], _ptr(owners), _ptr(cand),
+                                      t, cand.shape[1] if cand.dim() == 2 else 0, M, _ptr(out), s.cuda_stream))
+    return out
 
 
 def _ptr(t) -> int:

@@ -57,9 +57,11 @@ void compact_glist(const std::vector<int32_t>& adj, const std::vector<uint32_t>&
   out.assign((size_t)rows * GC, -1);
   for (int64_t r = 0; r < rows; ++r) {
     int c = 0;
-    for (int pos = 0; pos < S * mc && c < GC; ++pos) {
-      if ((bits[(size_t)r * W + (pos >> 5)] >> (pos & 31)) & 1u) {
-        int32_t t = adj[((size_t)r * S) * mc + pos];
+    for (int w = 0; w < W && c < GC; ++w) {
+      for (uint32_t m = bits[(size_t)r * W + w]; m && c < GC; m &= m - 1) {
+        const int pos = 32 * w + __builtin_ctz(m);
+        if (pos >= S * mc) break;
+        const int32_t t = adj[((size_t)r * S) * mc + pos];
         if (t >= 0) out[(size_t)r * GC + c++] = t;
       }
     }
@@ -449,6 +451,11 @@ int unify_free_index(unify_index_t ix) {
 
 int unify_insert(unify_index_t ix, const float* vectors, const int64_t* attr, const double* level_u, int64_t m) {
   return insert_impl(ix, vectors, attr, level_u, m);
+}
+
+int unify_prune(const float* vectors, int64_t n, int32_t d, const int32_t* owners, const int32_t* cand, int64_t t,
+                int32_t c, int32_t M, int32_t* out, void* hip_stream) {
+  return prune_impl(vectors, n, d, owners, cand, t, c, M, out, hip_stream);
 }
 
 int unify_build_index(const float* vectors, const int64_t* attr, const double* level_u, int64_t n, int32_t d,

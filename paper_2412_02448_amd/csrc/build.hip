@@ -26,9 +26,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <shared_mutex>
 
+#include "lowp.h"
 #include "unify_internal.h"
 #include "wave.h"
 
@@ -212,6 +214,210 @@ __global__ void __launch_bounds__(256) b_knn(KnnArgs A) {
   if (tid < KT_R && lr0 + tid < A.nrows) A.lens[(lr0 + tid) * S + j] = lenr[tid];
 }
 
+// ---------------------------------------------------------------------------
+// Candidates on the matrix cores (rows of at most 256 elements).  The distance
+// of a row to a column is the norm expansion |x|^2 + |y|^2 - 2 x.y over BF16
+// copies of both vectors (the dot product on v_mfma_f32_16x16x32_bf16, FP32
+// accumulation): the squared distance of the rounded points, which only ranks
+// the candidates; Prune recomputes every distance it uses from the FP32
+// vectors.  A workgroup takes 256 rows and one segment: wavefront w holds rows
+// 64 w .. 64 w + 63 as MFMA A operands in registers and streams the segment's
+// columns through LDS, 64 per step (double-buffered).  A candidate enters a
+// row's pending buffer when it is not farther than the row's current K-th
+// candidate; a row with 64 or more pending is merged into its sorted list at
+// the end of the step, the rest at the end, so the threshold tightens as the
+// segment is scanned.  Rows are private to their wavefront: merges need no
+// workgroup barrier.
+// ---------------------------------------------------------------------------
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_b;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_b;
+constexpr int MK_RT = 4;                   // 16-row tiles per wavefront
+constexpr int MK_ROWS = 4 * 16 * MK_RT;    // rows per workgroup
+constexpr int MK_CT = 4;                   // 16-column tiles per step
+constexpr int MK_PC = 128;                 // pending candidates per (row, segment)
+constexpr int MK_DMAX = 256;               // widest rows on this path
+
+// Orders a wavefront's memory operations before its later ones (LDS and global).
+__device__ __forceinline__ void wave_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// BF16 copies of rows [0, nl) of X, zero-padded to dp elements, and their squared norms.
+__global__ void b_bf16_rows(const float* __restrict__ X, int d, int dp, int64_t nl, uint16_t* __restrict__ Xb,
+                            float* __restrict__ xnb) {
+  const int lane = lane_id();
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t r = w0; r < nl; r += nw) {
+    float s = 0.f;
+    for (int t = lane; t < dp; t += WAVE) {
+      const uint32_t b = t < d ? f32_to_bf16(X[r * d + t]) : 0u;
+      Xb[r * dp + t] = (uint16_t)b;
+      const float xb = bf16_to_f32(b);
+      s = __builtin_fmaf(xb, xb, s);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
+    if (lane == 0) xnb[r] = s;
+  }
+}
+
+struct KnnMArgs {
+  const uint16_t* Xb;  // [nl][dp] BF16 rows
+  const float* xnb;    // [nl] their squared norms
+  int dp, S, K;
+  int64_t row0, nrows;
+  const int64_t* sstart;  // [S+1] compact id ranges of the segments
+  u64* lists;             // [nrows][S][KC]
+  int32_t* lens;          // [nrows][S]
+  u64* pend;              // [nrows][S][MK_PC]
+};
+
+__host__ __device__ constexpr size_t knn_mfma_lds(int ks) {
+  return sizeof(uint16_t) * 2 * 64 * (size_t)(32 * ks + 8) + sizeof(float) * MK_ROWS + 2 * sizeof(int32_t) * MK_ROWS;
+}
+
+template <int KS>
+__global__ void __launch_bounds__(256) b_knn_mfma(KnnMArgs A) {
+  extern __shared__ __align__(16) unsigned char knn_lds[];
+  constexpr int stride = 32 * KS + 8;  // staged column (elements), padded against bank conflicts
+  uint16_t* buf0 = reinterpret_cast<uint16_t*>(knn_lds);
+  uint16_t* buf1 = buf0 + 64 * stride;
+  float* tau = reinterpret_cast<float*>(buf1 + 64 * stride);  // per row: its K-th candidate's distance
+  int32_t* pcnt = reinterpret_cast<int32_t*>(tau + MK_ROWS);  // per row: pending candidates
+  int32_t* lenr = pcnt + MK_ROWS;                              // per row: list length
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int j = blockIdx.y, S = A.S, dp = A.dp;
+  const int64_t lr0 = (int64_t)blockIdx.x * MK_ROWS;  // first local row of the workgroup
+  const int64_t c_begin = A.sstart[j], c_end = A.sstart[j + 1];
+  tau[tid] = __builtin_inff();
+  pcnt[tid] = 0;
+  lenr[tid] = 0;
+  const int mrow = lane & 15, kq = lane >> 4;  // MFMA lane roles: row / column, k quarter
+  // A operands: rows 16 rt + mrow of this wavefront, elements 32 s + 8 kq .. + 7
+  bf16x8_b a[MK_RT][KS];
+#pragma unroll
+  for (int rt = 0; rt < MK_RT; ++rt) {
+    const int64_t lr = lr0 + wv * 64 + 16 * rt + mrow;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const uint4 w = lr < A.nrows ? *reinterpret_cast<const uint4*>(A.Xb + (A.row0 + lr) * dp + 32 * s + 8 * kq)
+                                   : make_uint4(0u, 0u, 0u, 0u);
+      a[rt][s] = __builtin_bit_cast(bf16x8_b, w);
+    }
+  }
+  // the lane's output rows: 16 rt + 4 kq + i
+  float xr[MK_RT][4];
+#pragma unroll
+  for (int rt = 0; rt < MK_RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t lr = lr0 + wv * 64 + 16 * rt + 4 * kq + i;
+      xr[rt][i] = lr < A.nrows ? A.xnb[A.row0 + lr] : 0.f;
+    }
+  const int64_t ncol = c_end - c_begin;
+  const int nsteps = (int)((ncol + 63) / 64);
+  // staging: KS chunks of 8 elements per thread and step
+  uint4 st[KS];
+  auto gload = [&](int step) {
+#pragma unroll
+    for (int c = 0; c < KS; ++c) {
+      const int idx = tid + 256 * c, col = idx / (4 * KS), ch = idx - col * (4 * KS);
+      const int64_t gc = c_begin + (int64_t)step * 64 + col;
+      st[c] = gc < c_end ? *reinterpret_cast<const uint4*>(A.Xb + gc * dp + 8 * ch) : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto lstore = [&](uint16_t* b) {
+#pragma unroll
+    for (int c = 0; c < KS; ++c) {
+      const int idx = tid + 256 * c, col = idx / (4 * KS), ch = idx - col * (4 * KS);
+      *reinterpret_cast<uint4*>(b + col * stride + 8 * ch) = st[c];
+    }
+  };
+  if (nsteps > 0) {
+    gload(0);
+    lstore(buf0);
+  }
+  __syncthreads();
+  int32_t* const wp = pcnt + wv * 64;
+  // merges the pending candidates of local row r (of this wavefront) into its list
+  auto merge = [&](int r) {
+    const int64_t lr = lr0 + wv * 64 + r;
+    const int64_t base = lr * S + j;
+    const int cnt = wp[r];
+    int len = lenr[wv * 64 + r];
+    u64 worst = KEY_MAX;
+    for (int b0 = 0; b0 < cnt; b0 += WAVE) {
+      const u64 key = b0 + lane < cnt ? A.pend[base * MK_PC + b0 + lane] : KEY_MAX;
+      worst = glist_insert(A.lists + base * KC, len, A.K, key);
+      wave_order();  // the list's stores before the next batch reads it
+    }
+    if (lane == 0) {
+      lenr[wv * 64 + r] = len;
+      tau[wv * 64 + r] = worst == KEY_MAX ? __builtin_inff() : key_dist(worst);
+      wp[r] = 0;
+    }
+  };
+  for (int step = 0; step < nsteps; ++step) {
+    const uint16_t* cur = (step & 1) ? buf1 : buf0;
+    uint16_t* nxt = (step & 1) ? buf0 : buf1;
+    if (step + 1 < nsteps) gload(step + 1);
+    f32x4_b acc[MK_RT][MK_CT];
+#pragma unroll
+    for (int rt = 0; rt < MK_RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < MK_CT; ++ct) acc[rt][ct] = f32x4_b{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int ct = 0; ct < MK_CT; ++ct) {
+        const bf16x8_b b = *reinterpret_cast<const bf16x8_b*>(cur + (16 * ct + mrow) * stride + 32 * s + 8 * kq);
+#pragma unroll
+        for (int rt = 0; rt < MK_RT; ++rt)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt][s], b, acc[rt][ct], 0, 0, 0);
+      }
+    // filter: lane holds rows 16 rt + 4 kq + i against column 16 ct + mrow of the step
+    const int64_t cb = c_begin + (int64_t)step * 64;
+    float tr[MK_RT][4];
+#pragma unroll
+    for (int rt = 0; rt < MK_RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tr[rt][i] = tau[wv * 64 + 16 * rt + 4 * kq + i];
+#pragma unroll
+    for (int ct = 0; ct < MK_CT; ++ct) {
+      const int64_t col = cb + 16 * ct + mrow;
+      if (col >= c_end) continue;
+      const float xc = A.xnb[col];
+#pragma unroll
+      for (int rt = 0; rt < MK_RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = 16 * rt + 4 * kq + i;  // local row of the wavefront
+          const int64_t lr = lr0 + wv * 64 + r;
+          float dist = __builtin_fmaf(-2.0f, acc[rt][ct][i], xr[rt][i] + xc);
+          dist = dist > 0.f ? dist : 0.f;
+          if (lr < A.nrows && dist <= tr[rt][i] && col != A.row0 + lr) {
+            const int slot = atomicAdd(&wp[r], 1);
+            A.pend[((lr * S + j) * MK_PC) + slot] = make_key(dist, (int32_t)col);
+          }
+        }
+    }
+    wave_order();  // this wavefront's pending stores and counts before the merges read them
+    const bool last = step + 1 == nsteps;
+    u64 need = ballot(wp[lane] >= (last ? 1 : 64));
+    while (need) {
+      const int r = __ffsll((unsigned long long)need) - 1;
+      need &= need - 1;
+      merge(r);
+      wave_order();
+    }
+    if (step + 1 < nsteps) lstore(nxt);
+    __syncthreads();
+  }
+  if (lr0 + tid < A.nrows) A.lens[(lr0 + tid) * S + j] = lenr[tid];
+}
+
 // Generic Prune (Sec. 2.2) of one owner per task, one wavefront per task.
 // Candidates: a_cnt[t] (or a_stride) keys at a + t * a_stride, then b_cnt[t]
 // keys at b + b_off[t]; only the id half of a key is used.  Distances are
@@ -228,7 +434,8 @@ struct PruneArgs {
   int32_t a_stride;
   const int32_t* a_cnt;
   const u64* b;
-  const int64_t* b_off;
+  const int64_t* b_off;    // b_off[t] - b_base: first key of task t in b
+  int64_t b_base;
   const int32_t* b_cnt;
   int32_t Mcap;
   int32_t only_if_over;
@@ -276,7 +483,7 @@ __global__ void __launch_bounds__(64) b_prune(PruneArgs A) {
     __syncthreads();
     const int na = A.a_cnt ? A.a_cnt[t] : A.a_stride;
     const int nb = A.b ? A.b_cnt[t] : 0;
-    const int64_t boff = A.b ? A.b_off[t] : 0;
+    const int64_t boff = A.b ? A.b_off[t] - A.b_base : 0;
     for (int base = 0; base < na + nb; base += WAVE) {
       const int i = base + lane;
       int32_t v = -1;
@@ -390,10 +597,12 @@ __global__ void __launch_bounds__(64) b_prune(PruneArgs A) {
 }
 
 // Reverse edges: every forward edge row -> o (row in segment si) is offered to chunk si of o.
-// Row r of fwd belongs to layer row rows[r] when a row list is given.
+// Row r of fwd belongs to layer row rows[r] when a row list is given.  Only the slots
+// (o * S + si) in [slot_lo, slot_hi) are counted and, with rev, written at off[slot] - base.
 __global__ void b_rev(const u64* __restrict__ fwd, int64_t nrows, int S, int M, const int32_t* __restrict__ segc,
                       int32_t* __restrict__ cnt, const int64_t* __restrict__ off, u64* __restrict__ rev,
-                      const int32_t* __restrict__ rows) {
+                      const int32_t* __restrict__ rows, int64_t slot_lo = 0, int64_t slot_hi = INT64_MAX,
+                      int64_t base = 0) {
   const int64_t total = nrows * S * M;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const u64 kk = fwd[e];
@@ -402,8 +611,37 @@ __global__ void b_rev(const u64* __restrict__ fwd, int64_t nrows, int S, int M, 
     const int64_t row = rows ? (int64_t)rows[r] : r;
     const int32_t o = key_id(kk);
     const int64_t slot = (int64_t)o * S + segc[row];
+    if (slot < slot_lo || slot >= slot_hi) continue;
     const int32_t p = atomicAdd(&cnt[slot], 1);
-    if (rev) rev[off[slot] + p] = make_key(0.f, (int32_t)row);
+    if (rev) rev[off[slot] - base + p] = make_key(0.f, (int32_t)row);
+  }
+}
+
+// Global-edge bits of rows [r0, r0 + nr): bit pos of row r is set when entry pos of
+// its chunks is one of its marks (an id occurs at most once in a row: chunks hold
+// distinct objects of distinct segments).  One wavefront per row.
+__global__ void b_gbits(const u64* __restrict__ fwd, const int32_t* __restrict__ glist, int64_t r0, int64_t nr,
+                        int S, int M, int W, uint32_t* __restrict__ bits) {
+  const int lane = lane_id();
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = w0; i < nr; i += nw) {
+    const int64_t r = r0 + i;
+    const int32_t* mk = glist + r * M;
+    for (int p0 = 0; p0 < W * 32; p0 += WAVE) {
+      const int pos = p0 + lane;
+      bool hit = false;
+      if (pos < S * M) {
+        const u64 kk = fwd[r * S * M + pos];
+        if (kk != KEY_MAX) {
+          const int32_t id = key_id(kk);
+          for (int t = 0; t < M; ++t) hit |= mk[t] == id;
+        }
+      }
+      const u64 m = ballot(hit);
+      if (lane == 0) bits[i * W + p0 / 32] = (uint32_t)m;
+      if (lane == 0 && p0 / 32 + 1 < W) bits[i * W + p0 / 32 + 1] = (uint32_t)(m >> 32);
+    }
   }
 }
 
@@ -562,16 +800,26 @@ PruneFn prune_kernel(int d, int Mcap) {
   return nullptr;
 }
 
-int run_prune(PruneArgs A) {
+int run_prune(PruneArgs A, hipStream_t st = nullptr) {
   PruneFn fn = prune_kernel(A.d, A.Mcap);
   if (!fn) {
     set_error("build: unsupported (d, M) for the GPU builder (d <= 2048, M <= 64)");
     return UNIFY_EINVAL;
   }
   const int64_t grid = std::min<int64_t>(A.ntask, 1 << 20);
-  hipLaunchKernelGGL(fn, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(64), 0, 0, A);
+  hipLaunchKernelGGL(fn, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(64), 0, st, A);
   BHIP(hipGetLastError());
   return UNIFY_OK;
+}
+
+// Candidate ids (-1: none) to keys; kept keys back to ids.
+__global__ void b_ids_to_keys(const int32_t* __restrict__ ids, int64_t cnt, u64* __restrict__ keys) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    keys[i] = ids[i] >= 0 ? make_key(0.f, ids[i]) : KEY_MAX;
+}
+__global__ void b_keys_to_ids(const u64* __restrict__ keys, int64_t cnt, int32_t* __restrict__ ids) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    ids[i] = keys[i] == KEY_MAX ? -1 : key_id(keys[i]);
 }
 
 double now_s() {
@@ -580,9 +828,13 @@ double now_s() {
 
 // Builds one layer over `nodes` (internal ids, ascending).  Outputs, on the
 // host: chunks [nl][S][M] and marks [nl][M] as internal ids (-1 padded).
+// emit(c0, cnt, chunks, bits) receives layer rows c0 .. c0 + cnt - 1 (positions in
+// `nodes`) in order: chunks [cnt][S][M] as internal ids (-1 padded) and their
+// global-edge bits [cnt][ceil(S M / 32)].
+using EmitRows = std::function<void(int64_t, int64_t, const int32_t*, const uint32_t*)>;
 int build_layer(const float* dX, int d, int S, int M, int K, const std::vector<int32_t>& nodes,
-                const std::vector<int64_t>& seg_start, const std::vector<int64_t>& ext,
-                std::vector<int32_t>& chunks_out, std::vector<int32_t>& glist_out, bool verbose) {
+                const std::vector<int64_t>& seg_start, const std::vector<int64_t>& ext, const EmitRows& emit,
+                bool verbose) {
   const int64_t nl = (int64_t)nodes.size();
   DevBuf buf;
   // compact vectors of this layer
@@ -633,18 +885,51 @@ int build_layer(const float* dX, int d, int S, int M, int K, const std::vector<i
 
   // 1-2: candidates and forward chunks, in row chunks
   const int64_t rows_per = std::min<int64_t>(nl, 131072);
+  // rows of at most MK_DMAX elements: candidates on the matrix cores (BF16 copies)
+  const int dp = (d + 31) / 32 * 32;
+  const bool mfma = dp <= MK_DMAX;
   u64* lists = buf.alloc<u64>((size_t)rows_per * S * KC);
   int32_t* lens = buf.alloc<int32_t>((size_t)rows_per * S);
-  u64* pend = buf.alloc<u64>((size_t)rows_per * S * KT_C);
-  if (!lists || !lens || !pend) {
+  u64* pend = mfma ? nullptr : buf.alloc<u64>((size_t)rows_per * S * KT_C);
+  if (!lists || !lens || (!mfma && !pend)) {
     set_error("build: out of device memory");
     return UNIFY_ENOMEM;
+  }
+  uint16_t* Xb = nullptr;
+  float* xnb = nullptr;
+  u64* pendm = nullptr;
+  if (mfma) {
+    Xb = buf.alloc<uint16_t>((size_t)nl * dp);
+    xnb = buf.alloc<float>(nl);
+    pendm = buf.alloc<u64>((size_t)rows_per * S * MK_PC);
+    if (!Xb || !xnb || !pendm) {
+      set_error("build: out of device memory");
+      return UNIFY_ENOMEM;
+    }
+    hipLaunchKernelGGL(b_bf16_rows, dim3(2048), dim3(256), 0, 0, X, d, dp, nl, Xb, xnb);
+    BHIP(hipGetLastError());
   }
   double t0 = now_s();
   for (int64_t r0 = 0; r0 < nl; r0 += rows_per) {
     const int64_t nr = std::min(rows_per, nl - r0);
-    KnnArgs ka{X, xn, d, S, K, r0, nr, dsst, lists, lens, pend};
-    hipLaunchKernelGGL(b_knn, dim3((unsigned)((nr + KT_R - 1) / KT_R), (unsigned)S), dim3(256), 0, 0, ka);
+    if (mfma) {
+      KnnMArgs km{Xb, xnb, dp, S, K, r0, nr, dsst, lists, lens, pendm};
+      const dim3 grid((unsigned)((nr + MK_ROWS - 1) / MK_ROWS), (unsigned)S);
+      const int ks = dp / 32;
+      switch (ks) {
+#define KNN_CASE(KS)                                                                                              \
+  case KS:                                                                                                        \
+    BHIP(hipFuncSetAttribute(reinterpret_cast<const void*>(b_knn_mfma<KS>),                                       \
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)knn_mfma_lds(KS)));                 \
+    hipLaunchKernelGGL(b_knn_mfma<KS>, grid, dim3(256), knn_mfma_lds(KS), 0, km);                                 \
+    break;
+        KNN_CASE(1) KNN_CASE(2) KNN_CASE(3) KNN_CASE(4) KNN_CASE(5) KNN_CASE(6) KNN_CASE(7) KNN_CASE(8)
+#undef KNN_CASE
+      }
+    } else {
+      KnnArgs ka{X, xn, d, S, K, r0, nr, dsst, lists, lens, pend};
+      hipLaunchKernelGGL(b_knn, dim3((unsigned)((nr + KT_R - 1) / KT_R), (unsigned)S), dim3(256), 0, 0, ka);
+    }
     BHIP(hipGetLastError());
     PruneArgs pa{};
     pa.X = X;
@@ -667,9 +952,15 @@ int build_layer(const float* dX, int d, int S, int M, int K, const std::vector<i
   }
   buf.release(lists);
   buf.release(lens);
-  buf.release(pend);
+  if (pend) buf.release(pend);
+  if (mfma) {
+    buf.release(pendm);
+    buf.release(Xb);
+    buf.release(xnb);
+  }
 
-  // 3: reverse edges and re-prune
+  // 3: reverse edges and re-prune, over ranges of owners whose reverse edges fit the
+  // device memory left (at 10M objects and 64 segments they outgrow one buffer)
   int32_t* rcnt = buf.alloc<int32_t>((size_t)nl * S);
   int64_t* roff = buf.alloc<int64_t>((size_t)nl * S + 1);
   if (!rcnt || !roff) {
@@ -677,41 +968,64 @@ int build_layer(const float* dX, int d, int S, int M, int K, const std::vector<i
     return UNIFY_ENOMEM;
   }
   BHIP(hipMemset(rcnt, 0, 4 * (size_t)nl * S));
-  hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nl, S, M, dsegc, rcnt, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nl, S, M, dsegc, rcnt, nullptr, nullptr, nullptr,
+                     (int64_t)0, INT64_MAX, (int64_t)0);
   int rc = scan(buf, rcnt, nl * S, roff);
   if (rc) return rc;
   int64_t total = 0;
   BHIP(hipMemcpy(&total, roff + (size_t)nl * S, 8, hipMemcpyDeviceToHost));
-  u64* rev = buf.alloc<u64>((size_t)std::max<int64_t>(total, 1));
+  size_t free_b = 0, total_b = 0;
+  BHIP(hipMemGetInfo(&free_b, &total_b));
+  const int64_t cap = std::max<int64_t>(std::min<int64_t>(std::max<int64_t>(total, 1),
+                                                           (int64_t)(free_b / 2 / sizeof(u64))),
+                                        (int64_t)S * M * 1024);
+  u64* rev = buf.alloc<u64>((size_t)cap);
   if (!rev) {
     set_error("build: out of device memory");
     return UNIFY_ENOMEM;
   }
-  BHIP(hipMemset(rcnt, 0, 4 * (size_t)nl * S));
-  hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nl, S, M, dsegc, rcnt, roff, rev, nullptr);
-  {
+  int64_t nranges = 0;
+  for (int64_t o0 = 0; o0 < nl;) {
+    // the longest run of owners from o0 whose reverse edges fit, by halving
+    int64_t o1 = nl, lo = 0, hi = 0;
+    BHIP(hipMemcpy(&lo, roff + (size_t)o0 * S, 8, hipMemcpyDeviceToHost));
+    while (true) {
+      BHIP(hipMemcpy(&hi, roff + (size_t)o1 * S, 8, hipMemcpyDeviceToHost));
+      if (hi - lo <= cap || o1 == o0 + 1) break;
+      o1 = o0 + (o1 - o0 + 1) / 2;
+    }
+    if (hi - lo > cap) {
+      set_error("build: the reverse edges of one object exceed the device memory");
+      return UNIFY_ENOMEM;
+    }
+    BHIP(hipMemset(rcnt + (size_t)o0 * S, 0, 4 * (size_t)(o1 - o0) * S));
+    hipLaunchKernelGGL(b_rev, dim3(4096), dim3(256), 0, 0, fwd, nl, S, M, dsegc, rcnt, roff, rev, nullptr, o0 * S,
+                       o1 * S, lo);
     PruneArgs pa{};
     pa.X = X;
     pa.d = d;
-    pa.ntask = nl * S;
-    pa.owner0 = 0;
+    pa.ntask = (o1 - o0) * S;
+    pa.owner0 = o0;
     pa.owner_div = S;
-    pa.a = fwd;
+    pa.a = fwd + (size_t)o0 * S * M;
     pa.a_stride = M;
     pa.b = rev;
-    pa.b_off = roff;
-    pa.b_cnt = rcnt;
+    pa.b_off = roff + (size_t)o0 * S;
+    pa.b_base = lo;
+    pa.b_cnt = rcnt + (size_t)o0 * S;
     pa.Mcap = M;
     pa.only_if_over = 1;
-    pa.out = fwd;  // each task reads its own row before writing it
+    pa.out = fwd + (size_t)o0 * S * M;  // each task reads its own row before writing it
     rc = run_prune(pa);
     if (rc) return rc;
+    BHIP(hipDeviceSynchronize());
+    ++nranges;
+    o0 = o1;
   }
-  BHIP(hipDeviceSynchronize());
   buf.release(rev);
   if (verbose)
-    std::fprintf(stderr, "[build] layer n=%lld: reverse edges %lld (%.1fs)\n", (long long)nl, (long long)total,
-                 now_s() - t0);
+    std::fprintf(stderr, "[build] layer n=%lld: reverse edges %lld in %lld owner ranges (%.1fs)\n", (long long)nl,
+                 (long long)total, (long long)nranges, now_s() - t0);
 
   // 4: global-edge marks
   u64* P = buf.alloc<u64>((size_t)nl * M);
@@ -757,19 +1071,65 @@ int build_layer(const float* dX, int d, int S, int M, int K, const std::vector<i
   if (verbose)
     std::fprintf(stderr, "[build] layer n=%lld: global marks (%.1fs)\n", (long long)nl, now_s() - t0);
 
-  // to the host, as internal ids
-  std::vector<u64> hk((size_t)nl * S * M);
-  BHIP(hipMemcpy(hk.data(), fwd, 8 * hk.size(), hipMemcpyDeviceToHost));
-  chunks_out.resize(hk.size());
-  for (size_t i = 0; i < hk.size(); ++i) chunks_out[i] = hk[i] == KEY_MAX ? -1 : nodes[(int32_t)(uint32_t)hk[i]];
-  glist_out.resize((size_t)nl * M);
-  BHIP(hipMemcpy(glist_out.data(), glist, 4 * glist_out.size(), hipMemcpyDeviceToHost));
-  for (auto& g : glist_out)
-    if (g >= 0) g = nodes[g];
+  // 5: to the host in slices of rows, as internal ids, with the global-edge bits
+  const int W = (S * M + 31) / 32;
+  const int64_t rows_out = std::max<int64_t>(1, std::min<int64_t>(nl, (int64_t)(64 << 20) / ((int64_t)S * M)));
+  uint32_t* dbits = buf.alloc<uint32_t>((size_t)rows_out * W);
+  if (!dbits) {
+    set_error("build: out of device memory");
+    return UNIFY_ENOMEM;
+  }
+  std::vector<u64> hk((size_t)rows_out * S * M);
+  std::vector<int32_t> ch((size_t)rows_out * S * M);
+  std::vector<uint32_t> hb((size_t)rows_out * W);
+  for (int64_t r0 = 0; r0 < nl; r0 += rows_out) {
+    const int64_t nr = std::min(rows_out, nl - r0);
+    hipLaunchKernelGGL(b_gbits, dim3(2048), dim3(256), 0, 0, fwd, glist, r0, nr, S, M, W, dbits);
+    BHIP(hipGetLastError());
+    BHIP(hipMemcpy(hk.data(), fwd + (size_t)r0 * S * M, 8 * (size_t)nr * S * M, hipMemcpyDeviceToHost));
+    BHIP(hipMemcpy(hb.data(), dbits, 4 * (size_t)nr * W, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < (size_t)nr * S * M; ++i) ch[i] = hk[i] == KEY_MAX ? -1 : nodes[(int32_t)(uint32_t)hk[i]];
+    emit(r0, nr, ch.data(), hb.data());
+  }
   return UNIFY_OK;
 }
 
 }  // namespace
+
+// The builder's Prune on caller-given candidate lists (device memory throughout).
+int prune_impl(const float* X, int64_t n, int32_t d, const int32_t* owners, const int32_t* cand, int64_t t,
+               int32_t c, int32_t M, int32_t* out, void* stream) {
+  if (t < 0 || n < 1 || d < 4 || d % 4 || d > 2048 || c < 1 || c > CAPR || M < 1 || M > 64 ||
+      (t > 0 && (!X || !owners || !cand || !out))) {
+    set_error("unify_prune: t >= 0, n >= 1, d % 4 == 0, 4 <= d <= 2048, 1 <= c <= 256, 1 <= M <= 64, "
+              "non-null buffers");
+    return UNIFY_EINVAL;
+  }
+  if (t == 0) return UNIFY_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  void* mem = nullptr;
+  const size_t nin = (size_t)t * c, nout = (size_t)t * M;
+  BHIP(hipMallocAsync(&mem, sizeof(u64) * (nin + nout), st));
+  u64* keys = static_cast<u64*>(mem);
+  u64* okeys = keys + nin;
+  hipLaunchKernelGGL(b_ids_to_keys, dim3(1024), dim3(256), 0, st, cand, (int64_t)nin, keys);
+  PruneArgs pa{};
+  pa.X = X;
+  pa.d = d;
+  pa.ntask = t;
+  pa.owner0 = 0;
+  pa.owner_div = 1;
+  pa.owners = owners;
+  pa.a = keys;
+  pa.a_stride = c;
+  pa.Mcap = M;
+  pa.only_if_over = 0;
+  pa.out = okeys;
+  int rc = run_prune(pa, st);
+  if (rc == UNIFY_OK) hipLaunchKernelGGL(b_keys_to_ids, dim3(1024), dim3(256), 0, st, okeys, (int64_t)nout, out);
+  if (hipFreeAsync(mem, st) != hipSuccess && rc == UNIFY_OK) rc = UNIFY_EDEVICE;
+  return rc;
+}
 
 int build_impl(const float* vectors, const int64_t* attr, const double* level_u, int64_t n, int32_t d, int32_t S,
                int32_t M, int32_t ef_cons, int device, int precision, unify_index_t* out) {
@@ -868,39 +1228,23 @@ int build_impl(const float* vectors, const int64_t* attr, const double* level_u,
   } free_dx{dX};
   BHIP(hipMemcpy(dX, H.vec.data(), H.vec.size() * 4, hipMemcpyHostToDevice));
 
-  auto set_bits = [&](const int32_t* row, const int32_t* marks, uint32_t* bits) {
-    for (int t = 0; t < M; ++t) {
-      if (marks[t] < 0) continue;
-      for (int pos = 0; pos < S * M; ++pos)
-        if (row[pos] == marks[t]) {
-          bits[pos >> 5] |= 1u << (pos & 31);
-          break;
-        }
-    }
-  };
   for (int l = L; l >= 0; --l) {
     std::vector<int32_t> nodes;
     for (int64_t r = 0; r < n; ++r)
       if (H.level[r] >= l) nodes.push_back((int32_t)r);
     if (nodes.size() < 2) continue;
-    std::vector<int32_t> ch, gl;
-    int rc = build_layer(dX, d, S, M, K, nodes, H.seg_start, H.ext, ch, gl, verbose);
-    if (rc) return rc;
-    for (size_t c = 0; c < nodes.size(); ++c) {
-      const int64_t v = nodes[c];
-      int32_t* row;
-      uint32_t* bits;
-      if (l == 0) {
-        row = &H.adj0[(size_t)v * S * M];
-        bits = &H.gbits0[(size_t)v * H.W0];
-      } else {
-        const int64_t ur = H.uprow[v] + l - 1;
-        row = &H.adjU[(size_t)ur * S * M];
-        bits = &H.gbitsU[(size_t)ur * H.WU];
+    auto emit = [&](int64_t c0, int64_t cnt, const int32_t* ch, const uint32_t* bits) {
+      for (int64_t c = c0; c < c0 + cnt; ++c) {
+        const int64_t v = nodes[c];
+        const size_t ur = l == 0 ? (size_t)v : (size_t)(H.uprow[v] + l - 1);
+        int32_t* row = l == 0 ? &H.adj0[ur * S * M] : &H.adjU[ur * S * M];
+        uint32_t* bw = l == 0 ? &H.gbits0[ur * H.W0] : &H.gbitsU[ur * H.WU];
+        std::memcpy(row, ch + (size_t)(c - c0) * S * M, 4 * (size_t)S * M);
+        std::memcpy(bw, bits + (size_t)(c - c0) * H.W0, 4 * (size_t)H.W0);
       }
-      std::memcpy(row, &ch[c * S * M], 4 * (size_t)S * M);
-      set_bits(row, &gl[c * M], bits);
-    }
+    };
+    int rc = build_layer(dX, d, S, M, K, nodes, H.seg_start, H.ext, emit, verbose);
+    if (rc) return rc;
   }
   std::string err;
   int rc = validate_index(H, err);

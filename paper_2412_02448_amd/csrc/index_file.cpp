@@ -12,6 +12,10 @@
 // of ceil(S M / 32) words marking the global (post-filter) edges; bit
 // j * M + r marks entry r of chunk j.  The skip-list successor is implicit:
 // internal ids are ranks in attribute order.
+#include <algorithm>
+#include <atomic>
+#include <thread>
+#include <vector>
 #include <cstdio>
 #include <cstring>
 
@@ -213,21 +217,30 @@ int validate_index(const HostIndex& H, std::string& err) {
     err = "upper-row count mismatch";
     return UNIFY_EFORMAT;
   }
-  // every edge names an object that exists on that layer
-  for (int64_t v = 0; v < n; ++v) {
-    for (int l = 0; l <= H.level[v]; ++l) {
-      const int mc = l == 0 ? H.M0 : H.MU;
-      const int32_t* row = l == 0 ? &H.adj0[(size_t)v * H.S * mc]
-                                  : &H.adjU[(size_t)(H.uprow[v] + l - 1) * H.S * mc];
-      for (int t = 0; t < H.S * mc; ++t) {
-        int32_t x = row[t];
-        if (x == -1) continue;
-        if (x < 0 || x >= n || H.level[x] < l) {
-          err = "adjacency entry out of range";
-          return UNIFY_EFORMAT;
+  // every edge names an object that exists on that layer (object ranges checked in parallel)
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
+                                                                n / 65536 + 1}));
+  std::atomic<bool> bad{false};
+  auto check = [&](int64_t v0, int64_t v1) {
+    for (int64_t v = v0; v < v1 && !bad.load(std::memory_order_relaxed); ++v) {
+      for (int l = 0; l <= H.level[v]; ++l) {
+        const int mc = l == 0 ? H.M0 : H.MU;
+        const int32_t* row = l == 0 ? &H.adj0[(size_t)v * H.S * mc]
+                                    : &H.adjU[(size_t)(H.uprow[v] + l - 1) * H.S * mc];
+        for (int t = 0; t < H.S * mc; ++t) {
+          int32_t x = row[t];
+          if (x == -1) continue;
+          if (x < 0 || x >= n || H.level[x] < l) bad = true;
         }
       }
     }
+  };
+  std::vector<std::thread> pool;
+  for (int i = 0; i < nt; ++i) pool.emplace_back(check, n * i / nt, n * (i + 1) / nt);
+  for (auto& t : pool) t.join();
+  if (bad) {
+    err = "adjacency entry out of range";
+    return UNIFY_EFORMAT;
   }
   return UNIFY_OK;
 }

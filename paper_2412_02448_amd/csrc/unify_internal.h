@@ -172,4 +172,6 @@ int batch_create(unify_index_t ix, const float* queries, int64_t nq, const int64
                  int8_t* out_strategy, int32_t* out_stats, unify_batch_t* out);
 int batch_run(unify_batch_t b, void* stream);
 int insert_impl(unify_index_t ix, const float* vectors, const int64_t* attr, const double* level_u, int64_t m);
+int prune_impl(const float* X, int64_t n, int32_t d, const int32_t* owners, const int32_t* cand, int64_t t,
+               int32_t c, int32_t M, int32_t* out, void* stream);
 }  // namespace unify

@@ -97,6 +97,30 @@ def check_structure(W, F, equi_depth=True):
     assert (adj[:, :, 0] >= 0).mean() > 0.99
 
 
+def test_first_entries_are_segment_nearest(built):
+    """Candidates are ranked on the matrix cores over BF16 copies, and Prune re-scores
+    them in FP32 and always keeps the nearest: the first entry of every chunk is the
+    owner's exact nearest object of that segment (up to distance ties)."""
+    W, g, F = built
+    n, S = F["n"], F["S"]
+    X = F["vec"].astype(np.float64)
+    ss = F["seg_start"]
+    adj = F["adj0"]
+    bad = 0
+    for v in range(0, n, 29):
+        dd = ((X - X[v]) ** 2).sum(1)
+        dd[v] = np.inf
+        for j in range(S):
+            seg = dd[ss[j]:ss[j + 1]]
+            if not np.isfinite(seg).any():
+                continue
+            first = adj[v, j, 0]
+            assert first >= 0
+            if dd[first] > seg.min() * (1 + 1e-6) + 1e-12:
+                bad += 1
+    assert bad == 0, bad
+
+
 def test_recall_against_exact(built):
     import torch
     W, g, F = built
