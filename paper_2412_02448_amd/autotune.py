@@ -30,11 +30,13 @@ class Setting:
     tau_b: float = 0.5
     visit_cap: int = 0  # 0: the library's default
     pre_chunk: int = 0  # 0: the library's default
+    wave_scan: bool = False  # pre-filter scans per wavefront instead of the matrix-core scan
+    waves_per_query: int = 0  # wavefronts of the heaviest graph searches (0: one)
 
     def kwargs(self) -> dict:
         """Search keyword arguments of this setting."""
         return dict(m=self.m, beam_p=self.beam_p, tau_a=self.tau_a, tau_b=self.tau_b, visit_cap=self.visit_cap,
-                    pre_chunk=self.pre_chunk)
+                    pre_chunk=self.pre_chunk, wave_scan=self.wave_scan, waves_per_query=self.waves_per_query)
 
 
 def recall_at_k(ids: np.ndarray, truth: np.ndarray) -> float:
@@ -63,12 +65,14 @@ def exact_answers(index, Q, L, H, k):
 
 def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256), ps=(1, 2, 4),
          taus=((0.01, 0.5), (0.01, 0.3), (0.005, 0.3), (0.01, 0.2)), visit_caps=(512, 1024), pre_chunks=(),
-         reps: int = 10, log=None):
+         wave_scans=(), wpqs=(), reps: int = 10, log=None):
     """Fastest (tau_A, tau_B, m, ef, p) reaching recall@k >= target on the given sample
-    queries; taus lists the (tau_A, tau_B) fractions of the strategy rule to try.  The
-    visited-cache sizes in visit_caps, then the pre-filter chunk lengths in pre_chunks, are
-    timed on the best setting (results do not depend on either); one replaces the default
-    only when it is more than 3% faster.
+    queries; taus lists the (tau_A, tau_B) fractions of the strategy rule to try.  Then,
+    on the best setting, knobs that leave the results unchanged are timed one after
+    another, each replacing the current choice only when more than 3% faster: the
+    visited-cache sizes in visit_caps, the pre-filter chunk lengths in pre_chunks, the
+    per-wavefront pre-filter scan (wave_scans = (True,)) and the wavefronts of the
+    heaviest graph searches (wpqs, e.g. (2, 4)).
 
     Returns (best Setting or None, list of every Setting measured)."""
     import torch
@@ -126,22 +130,23 @@ def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256),
                 log(f"tune visit_cap={vc}: {qps:,.0f} QPS")
             if qps > 1.03 * best.qps:  # the default stays unless another size is clearly faster
                 best = cand
-        base = best
-        for pc in pre_chunks:
-            kw = dict(base.kwargs(), pre_chunk=pc)
-            index.search(Q, L, H, k, base.ef, **kw)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            for _ in range(reps):
+        for field, values in (("pre_chunk", pre_chunks), ("wave_scan", wave_scans), ("waves_per_query", wpqs)):
+            base = best
+            for val in values:
+                cand = dataclasses.replace(base, **{field: val})
+                kw = cand.kwargs()
                 index.search(Q, L, H, k, base.ef, **kw)
-            torch.cuda.synchronize()
-            qps = Q.shape[0] * reps / (time.perf_counter() - t)
-            cand = dataclasses.replace(base, qps=qps, pre_chunk=pc)
-            table.append(cand)
-            if log:
-                log(f"tune pre_chunk={pc}: {qps:,.0f} QPS")
-            if qps > 1.03 * best.qps:
-                best = cand
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(reps):
+                    index.search(Q, L, H, k, base.ef, **kw)
+                torch.cuda.synchronize()
+                cand.qps = Q.shape[0] * reps / (time.perf_counter() - t)
+                table.append(cand)
+                if log:
+                    log(f"tune {field}={val}: {cand.qps:,.0f} QPS")
+                if cand.qps > 1.03 * best.qps:
+                    best = cand
     return best, table
 
 

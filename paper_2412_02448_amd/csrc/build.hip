@@ -272,6 +272,7 @@ struct KnnMArgs {
   u64* lists;             // [nrows][S][KC]
   int32_t* lens;          // [nrows][S]
   u64* pend;              // [nrows][S][MK_PC]
+  const int32_t* rows;    // optional: the layer rows to process (rows[row0 + lr]; else row0 + lr)
 };
 
 __host__ __device__ constexpr size_t knn_mfma_lds(int ks) {
@@ -279,7 +280,7 @@ __host__ __device__ constexpr size_t knn_mfma_lds(int ks) {
 }
 
 template <int KS>
-__global__ void __launch_bounds__(256) b_knn_mfma(KnnMArgs A) {
+__global__ void __launch_bounds__(256, KS <= 3 ? 2 : 1) b_knn_mfma(KnnMArgs A) {
   extern __shared__ __align__(16) unsigned char knn_lds[];
   constexpr int stride = 32 * KS + 8;  // staged column (elements), padded against bank conflicts
   uint16_t* buf0 = reinterpret_cast<uint16_t*>(knn_lds);
@@ -295,14 +296,17 @@ __global__ void __launch_bounds__(256) b_knn_mfma(KnnMArgs A) {
   pcnt[tid] = 0;
   lenr[tid] = 0;
   const int mrow = lane & 15, kq = lane >> 4;  // MFMA lane roles: row / column, k quarter
+  // layer row of local row lr
+  auto row_of = [&](int64_t lr) { return A.rows ? (int64_t)A.rows[A.row0 + lr] : A.row0 + lr; };
   // A operands: rows 16 rt + mrow of this wavefront, elements 32 s + 8 kq .. + 7
   bf16x8_b a[MK_RT][KS];
 #pragma unroll
   for (int rt = 0; rt < MK_RT; ++rt) {
     const int64_t lr = lr0 + wv * 64 + 16 * rt + mrow;
+    const int64_t row = lr < A.nrows ? row_of(lr) : 0;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const uint4 w = lr < A.nrows ? *reinterpret_cast<const uint4*>(A.Xb + (A.row0 + lr) * dp + 32 * s + 8 * kq)
+      const uint4 w = lr < A.nrows ? *reinterpret_cast<const uint4*>(A.Xb + row * dp + 32 * s + 8 * kq)
                                    : make_uint4(0u, 0u, 0u, 0u);
       a[rt][s] = __builtin_bit_cast(bf16x8_b, w);
     }
@@ -314,7 +318,7 @@ __global__ void __launch_bounds__(256) b_knn_mfma(KnnMArgs A) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int64_t lr = lr0 + wv * 64 + 16 * rt + 4 * kq + i;
-      xr[rt][i] = lr < A.nrows ? A.xnb[A.row0 + lr] : 0.f;
+      xr[rt][i] = lr < A.nrows ? A.xnb[row_of(lr)] : 0.f;
     }
   const int64_t ncol = c_end - c_begin;
   const int nsteps = (int)((ncol + 63) / 64);
@@ -377,29 +381,36 @@ __global__ void __launch_bounds__(256) b_knn_mfma(KnnMArgs A) {
         for (int rt = 0; rt < MK_RT; ++rt)
           acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt][s], b, acc[rt][ct], 0, 0, 0);
       }
-    // filter: lane holds rows 16 rt + 4 kq + i against column 16 ct + mrow of the step
+    // filter: lane holds rows 16 rt + 4 kq + i against column 16 ct + mrow of the step.
+    // dist <= threshold  <=>  2 acc >= (xr - threshold) + xc: one add and one compare per
+    // product.  Rows past the end get hr = +inf and columns past the end xc = +inf (never
+    // pass: the sum is +inf or NaN); a row without K candidates yet has hr = -inf.
     const int64_t cb = c_begin + (int64_t)step * 64;
-    float tr[MK_RT][4];
+    float hr[MK_RT][4];
 #pragma unroll
     for (int rt = 0; rt < MK_RT; ++rt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) tr[rt][i] = tau[wv * 64 + 16 * rt + 4 * kq + i];
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * rt + 4 * kq + i;
+        hr[rt][i] = lr0 + wv * 64 + r < A.nrows ? xr[rt][i] - tau[wv * 64 + r] : __builtin_inff();
+      }
 #pragma unroll
     for (int ct = 0; ct < MK_CT; ++ct) {
       const int64_t col = cb + 16 * ct + mrow;
-      if (col >= c_end) continue;
-      const float xc = A.xnb[col];
+      const float xc = col < c_end ? A.xnb[col] : __builtin_inff();  // past the end: never passes
 #pragma unroll
       for (int rt = 0; rt < MK_RT; ++rt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int r = 16 * rt + 4 * kq + i;  // local row of the wavefront
-          const int64_t lr = lr0 + wv * 64 + r;
-          float dist = __builtin_fmaf(-2.0f, acc[rt][ct][i], xr[rt][i] + xc);
-          dist = dist > 0.f ? dist : 0.f;
-          if (lr < A.nrows && dist <= tr[rt][i] && col != A.row0 + lr) {
-            const int slot = atomicAdd(&wp[r], 1);
-            A.pend[((lr * S + j) * MK_PC) + slot] = make_key(dist, (int32_t)col);
+          if (2.0f * acc[rt][ct][i] >= hr[rt][i] + xc) {
+            const int r = 16 * rt + 4 * kq + i;  // local row of the wavefront
+            const int64_t lr = lr0 + wv * 64 + r;
+            if (col != row_of(lr)) {
+              float dist = __builtin_fmaf(-2.0f, acc[rt][ct][i], xr[rt][i] + xc);
+              dist = dist > 0.f ? dist : 0.f;
+              const int slot = atomicAdd(&wp[r], 1);
+              A.pend[((lr * S + j) * MK_PC) + slot] = make_key(dist, (int32_t)col);
+            }
           }
         }
     }
@@ -822,6 +833,26 @@ __global__ void b_keys_to_ids(const u64* __restrict__ keys, int64_t cnt, int32_t
     ids[i] = keys[i] == KEY_MAX ? -1 : key_id(keys[i]);
 }
 
+// Launches b_knn_mfma for rows [row0, row0 + nrows) against every segment.
+int run_knn_mfma(const KnnMArgs& km) {
+  const dim3 grid((unsigned)((km.nrows + MK_ROWS - 1) / MK_ROWS), (unsigned)km.S);
+  switch (km.dp / 32) {
+#define KNN_CASE(KS)                                                                                              \
+  case KS:                                                                                                        \
+    BHIP(hipFuncSetAttribute(reinterpret_cast<const void*>(b_knn_mfma<KS>),                                       \
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)knn_mfma_lds(KS)));                 \
+    hipLaunchKernelGGL(b_knn_mfma<KS>, grid, dim3(256), knn_mfma_lds(KS), 0, km);                                 \
+    break;
+    KNN_CASE(1) KNN_CASE(2) KNN_CASE(3) KNN_CASE(4) KNN_CASE(5) KNN_CASE(6) KNN_CASE(7) KNN_CASE(8)
+#undef KNN_CASE
+    default:
+      set_error("build: rows too wide for the matrix-core candidate pass");
+      return UNIFY_EINVAL;
+  }
+  BHIP(hipGetLastError());
+  return UNIFY_OK;
+}
+
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -913,19 +944,8 @@ int build_layer(const float* dX, int d, int S, int M, int K, const std::vector<i
   for (int64_t r0 = 0; r0 < nl; r0 += rows_per) {
     const int64_t nr = std::min(rows_per, nl - r0);
     if (mfma) {
-      KnnMArgs km{Xb, xnb, dp, S, K, r0, nr, dsst, lists, lens, pendm};
-      const dim3 grid((unsigned)((nr + MK_ROWS - 1) / MK_ROWS), (unsigned)S);
-      const int ks = dp / 32;
-      switch (ks) {
-#define KNN_CASE(KS)                                                                                              \
-  case KS:                                                                                                        \
-    BHIP(hipFuncSetAttribute(reinterpret_cast<const void*>(b_knn_mfma<KS>),                                       \
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)knn_mfma_lds(KS)));                 \
-    hipLaunchKernelGGL(b_knn_mfma<KS>, grid, dim3(256), knn_mfma_lds(KS), 0, km);                                 \
-    break;
-        KNN_CASE(1) KNN_CASE(2) KNN_CASE(3) KNN_CASE(4) KNN_CASE(5) KNN_CASE(6) KNN_CASE(7) KNN_CASE(8)
-#undef KNN_CASE
-      }
+      const int rc = run_knn_mfma(KnnMArgs{Xb, xnb, dp, S, K, r0, nr, dsst, lists, lens, pendm, nullptr});
+      if (rc) return rc;
     } else {
       KnnArgs ka{X, xn, d, S, K, r0, nr, dsst, lists, lens, pend};
       hipLaunchKernelGGL(b_knn, dim3((unsigned)((nr + KT_R - 1) / KT_R), (unsigned)S), dim3(256), 0, 0, ka);
@@ -1410,17 +1430,28 @@ int insert_layer(const float* dX, int d, int S, int mc, int K, const std::vector
   // 1-2: candidates of the new objects in every segment of the layer, forward chunks
   double t0 = now_s();
   const int64_t rows_per = std::min<int64_t>(nnew, 131072);
+  // rows of at most MK_DMAX elements: candidates on the matrix cores (BF16 copies)
+  const int dp = (d + 31) / 32 * 32;
+  const bool mfma = dp <= MK_DMAX;
   u64* lists = buf.alloc<u64>((size_t)rows_per * S * KC);
   int32_t* lens = buf.alloc<int32_t>((size_t)rows_per * S);
-  u64* pend = buf.alloc<u64>((size_t)rows_per * S * KT_C);
-  if (!lists || !lens || !pend) {
+  u64* pend = buf.alloc<u64>((size_t)rows_per * S * (mfma ? MK_PC : KT_C));
+  uint16_t* Xb = mfma ? buf.alloc<uint16_t>((size_t)nl * dp) : nullptr;
+  float* xnb = mfma ? buf.alloc<float>(nl) : nullptr;
+  if (!lists || !lens || !pend || (mfma && (!Xb || !xnb))) {
     set_error("insert: out of device memory");
     return UNIFY_ENOMEM;
   }
+  if (mfma) hipLaunchKernelGGL(b_bf16_rows, dim3(2048), dim3(256), 0, 0, X, d, dp, nl, Xb, xnb);
   for (int64_t r0 = 0; r0 < nnew; r0 += rows_per) {
     const int64_t nr = std::min(rows_per, nnew - r0);
-    KnnArgs ka{X, xn, d, S, K, r0, nr, dsst, lists, lens, pend, dnew};
-    hipLaunchKernelGGL(b_knn, dim3((unsigned)((nr + KT_R - 1) / KT_R), (unsigned)S), dim3(256), 0, 0, ka);
+    if (mfma) {
+      const int rc = run_knn_mfma(KnnMArgs{Xb, xnb, dp, S, K, r0, nr, dsst, lists, lens, pend, dnew});
+      if (rc) return rc;
+    } else {
+      KnnArgs ka{X, xn, d, S, K, r0, nr, dsst, lists, lens, pend, dnew};
+      hipLaunchKernelGGL(b_knn, dim3((unsigned)((nr + KT_R - 1) / KT_R), (unsigned)S), dim3(256), 0, 0, ka);
+    }
     BHIP(hipGetLastError());
     PruneArgs pa{};
     pa.X = X;
@@ -1442,6 +1473,10 @@ int insert_layer(const float* dX, int d, int S, int mc, int K, const std::vector
   buf.release(lists);
   buf.release(lens);
   buf.release(pend);
+  if (mfma) {
+    buf.release(Xb);
+    buf.release(xnb);
+  }
   hipLaunchKernelGGL(i_scatter_keys, dim3(grid_for(nnew * W)), dim3(256), 0, 0, fwd, nnew, W, dnew, chunks);
   BHIP(hipGetLastError());
   if (verbose)

@@ -98,8 +98,10 @@ struct SearchArgs {
   int64_t bwords;         // words of a row's bitmap (ceil(n / 32), padded)
   int64_t nslots;
   const struct ConjArgs* conj;  // conjunctive queries (written by the plan kernel), or null
-  // cooperative searches: heavy queries work[0, *nheavy), their counter, first visited row
+  // cooperative searches: heavy queries work[0, *nheavy), the graph searches work[0, *nbeam)
+  // (the rest of the work list holds pre-filter chunks), the heavy counter, first visited row
   const int32_t* nheavy;
+  const int32_t* nbeam;
   int32_t* mw_next;
   int64_t mw_row0;
 };
@@ -267,8 +269,8 @@ __device__ __forceinline__ int graph_bucket(const QPlan& P) {
 
 __global__ void k_worklist(QPlan* __restrict__ plan, int64_t nq, int64_t n, int64_t pcap, int32_t heavy_cap,
                            int32_t* __restrict__ work, int32_t* __restrict__ wchunk,
-                           int32_t* __restrict__ counters /* nwork, next, fb_count, fb_next, -, tile items,
-                                                             heavy, heavy next */) {
+                           int32_t* __restrict__ counters /* nwork, next, fb_count, fb_next, graph searches,
+                                                             tile items, heavy, heavy next */) {
   constexpr int NB = 1024, NG = 64;
   __shared__ int32_t spart[1024];
   __shared__ int64_t tpart[1024];
@@ -360,6 +362,7 @@ __global__ void k_worklist(QPlan* __restrict__ plan, int64_t nq, int64_t n, int6
     counters[1] = nheavy;
     counters[2] = 0;
     counters[3] = 0;
+    counters[4] = nbeam;
     counters[6] = nheavy;
     counters[7] = 0;
   }
@@ -1535,7 +1538,7 @@ __global__ void __launch_bounds__(64 * MW) k_search_mw(SearchArgs A) {
   p += sizeof(u64) * (A.nbr_cap + MW * WAVE);
   L.hash = reinterpret_cast<uint32_t*>(p);
   L.sh = sh;
-  const int32_t nwork = *A.nwork, nheavy = *A.nheavy;
+  const int32_t nwork = *A.nwork, nheavy = *A.nheavy, nbeam = *A.nbeam;
   const VRow R = vrow_of(A, A.mw_row0 + blockIdx.x);  // the workgroup's visited row
   bool heavy = true;  // thread 0's view
   while (true) {
@@ -1545,7 +1548,20 @@ __global__ void __launch_bounds__(64 * MW) k_search_mw(SearchArgs A) {
         w = atomicAdd(A.mw_next, 1);
         if (w >= nheavy) heavy = false;
       }
-      if (!heavy) w = atomicAdd(A.next, 1);
+      if (!heavy) {
+        // a graph search of the shared remainder, never a pre-filter chunk (those follow the
+        // graph searches in the work list and are the one-wavefront kernel's)
+        w = nwork;
+        int32_t cur = __hip_atomic_load(A.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (cur < nbeam) {
+          const int32_t seen = atomicCAS(A.next, cur, cur + 1);
+          if (seen == cur) {
+            w = cur;
+            break;
+          }
+          cur = seen;
+        }
+      }
       sh[SH_W] = w;
     }
     __syncthreads();
@@ -2582,6 +2598,7 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
   A.fb_list = X.S.fb;
   A.fb_count = X.S.counters + 2;
   A.nheavy = X.S.counters + 6;
+  A.nbeam = X.S.counters + 4;
   A.mw_next = X.S.counters + 7;
   A.mw_row0 = 0;
   // second pass over the abandoned queries with the largest LDS that fits

@@ -293,17 +293,21 @@ def test_matrix_core_scan_record_overflow(tmp_path):
 
 
 @pytest.mark.parametrize("wpq", [2, 4])
-@pytest.mark.parametrize("strategy,p", [(hsig.HYBRID, 1), (hsig.HYBRID, 4), (hsig.POST, 2), (hsig.AUTO, 4)])
+@pytest.mark.parametrize("strategy,p", [(hsig.HYBRID, 1), (hsig.HYBRID, 4), (hsig.POST, 2), (hsig.AUTO, 4),
+                                        (hsig.PRE, 1)])
 def test_parity_cooperative_search(c1, wpq, strategy, p):
     """Heavy graph searches run by 2 or 4 wavefronts together (the adjacency gather, the
     visited checks and the distance evaluations split between them, admissions by one):
-    every row equals the oracle's, for a few heavy queries and for all of them."""
+    every row equals the oracle's, for a few heavy queries and for all of them.  The
+    cooperative kernel takes graph searches only: with per-wavefront pre-filter scans
+    every pre-filter chunk stays with the one-wavefront kernel (forced pre-filter: no
+    graph search at all)."""
     W, ix, g = c1
     print(f"[case] cooperative wpq={wpq} strategy={strategy} p={p}", flush=True)
     ref = ix.search(W.queries, W.l, W.h, 10, 48, p=p, strategy=strategy)
     for heavy in (16, 100000):
         got = gpu_search(g, W, 10, 48, strategy=None if strategy == hsig.AUTO else strategy, beam_p=p,
-                         waves_per_query=wpq, heavy_queries=heavy)
+                         waves_per_query=wpq, heavy_queries=heavy, wave_scan=strategy in (hsig.AUTO, hsig.PRE))
         assert_parity(ref, got, f"cooperative wpq={wpq} heavy={heavy}")
         coop = (got[3][:, 3] & 0x200) != 0
         graph = np.isin(got[3][:, 5], [hsig.HYBRID, hsig.POST])
