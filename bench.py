@@ -75,9 +75,11 @@ def parse():
     ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--no-insert", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
-    ap.add_argument("--wide-n", type=int, default=250_000, help="objects of the 960-wide workload")
+    ap.add_argument("--wide-n", type=int, default=1_000_000, help="objects of the 960-wide workload")
     ap.add_argument("--wide-M", type=int, default=0, help="chunk capacity of the 960-wide index (0: the recipe's)")
-    ap.add_argument("--wide-efc", type=int, default=0, help="efCons of the 960-wide index (0: the recipe's)")
+    ap.add_argument("--wide-efc", type=int, default=256,
+                    help="efCons of the 960-wide index (0: the recipe's 100, which leaves layer 0 without links "
+                         "out of a cluster at n = 1M: 244 objects of a cluster per segment, more than 100 candidates)")
     ap.add_argument("--cpu-queries", type=int, default=0, help="queries in the CPU sample (0: all)")
     ap.add_argument("--wpq", type=int, default=0, help="wavefronts per heavy graph search (0: the library default)")
     ap.add_argument("--heavy", type=int, default=0, help="heavy graph searches per batch (0: the library default)")
@@ -291,12 +293,13 @@ def main():
     index.set_precision(head)
     log(f"headline store: {head} (m={m} ef={ef} p={bp} tau=({ta}, {tb}))")
 
-    recalls = {}
+    # the auto strategy's QPS-recall curve over the ef grid of the 1M configuration (headline store)
+    recalls, qps_by_ef = {}, {}
     for e in (32, 64, 128, 256):
-        ids, _, _ = index.search(Q, L, H, k, e, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
-        torch.cuda.synchronize()
-        recalls[e] = recall_of(ids)
-    log("recall@10 by ef: " + ", ".join(f"ef={e}: {r:.4f}" for e, r in recalls.items()))
+        s_e, o_e = timed(m, e, bp, steps=3, warmup=1, ta=ta, tb=tb, vc=vc)
+        recalls[e] = recall_of(o_e[0])
+        qps_by_ef[e] = round(nq / s_e, 1)
+    log("recall@10 by ef: " + ", ".join(f"ef={e}: {r:.4f} ({qps_by_ef[e]:,.0f} QPS)" for e, r in recalls.items()))
 
     # ---- timed region of the headline: K steps of the whole path ----
     # A step is one replay of the captured launch sequence (plan, work list, search, merge,
@@ -323,6 +326,17 @@ def main():
         s, o = timed(m, ef, bp, sv, steps=max(1, args.steps // 2 + 1), warmup=1, ta=ta, tb=tb, vc=vc)
         per_strategy[name] = {"qps": round(nq / s, 1), "recall@10": round(recall_of(o[0]), 4)}
         log(f"{name}: {nq / s:,.0f} QPS recall {per_strategy[name]['recall@10']}")
+    # each strategy timed separately on the FP32 store over the ef grid of the 1M configuration
+    index.set_precision("fp32")
+    fp32_by_ef = {}
+    for e in (32, 64, 128, 256):
+        row = {}
+        for name, sv in (("auto", None), ("pre", u.PRE), ("hybrid", u.HYBRID), ("post", u.POST)):
+            s, o = timed(m, e, bp, sv, steps=2, warmup=1, ta=ta, tb=tb, vc=vc)
+            row[name] = {"qps": round(nq / s, 1), "recall@10": round(recall_of(o[0]), 4)}
+        fp32_by_ef[e] = row
+        log(f"fp32 ef={e}: " + ", ".join(f"{nm} {r['qps']:,.0f} QPS r={r['recall@10']}" for nm, r in row.items()))
+    index.set_precision(head)
 
     # ---- hybrid neighbour selections S1 and S2 (Sec. 4.2) on the forced hybrid search ----
     selection = {}
@@ -382,6 +396,14 @@ def main():
         except Exception as e:  # the headline line is still reported
             log(f"batch100k failed: {e!r}")
             b100 = {"failed": repr(e)}
+
+    # ---- the small plain-FP32 hybrid configuration ----
+    c1 = None
+    try:
+        c1 = c1_bench(args)
+    except Exception as e:  # the headline line is still reported
+        log(f"c1 failed: {e!r}")
+        c1 = {"failed": repr(e)}
 
     # ---- the 960-wide workload: every store on the GIST-like shape ----
     wide = None
@@ -446,13 +468,14 @@ def main():
                    "tau_a": ta, "tau_b": tb, "visit_cap": vc,
                    "recall@10": round(recall_of(out[0]), 4),
                    "recall@10_vs_fp64_sample": (fp64 or {}).get("headline_graph_replay", {}).get("recall@10"),
-                   "recall_by_ef": {str(e): round(r, 4) for e, r in recalls.items()},
+                   "qps_by_ef": {str(e_): v for e_, v in qps_by_ef.items()}, "recall_by_ef": {str(e): round(r, 4) for e, r in recalls.items()},
                    "strategy_mix": {"pre": int(mix[1]), "hybrid": int(mix[2]), "post": int(mix[3])},
                    "build_s": round(build_s, 1)},
         "eager": {"qps": round(nq / sec_eager, 1), "ms_per_step": round(sec_eager * 1e3, 4),
                   "same_ids_as_graph": same},
         "by_precision": by_prec,
         "per_strategy": per_strategy,
+        "fp32_strategies_by_ef": fp32_by_ef,
         "hybrid_selection": selection,
         "roofline": roofline,
         "roofline_tile_scan": roofline_tile,
@@ -462,6 +485,7 @@ def main():
         "insertion": ins,
         "two_attribute": multi,
         "serving": serving,
+        "c1_hybrid_fp32": c1,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -835,6 +859,44 @@ def serve_bench(args, index, spec, W, m, ef, bp, ta, tb, vc, prec):
     return {"workload": f"mixed1m index ({prec} store, m={m} ef={ef} p={bp} tau=({ta}, {tb})), k={k}, "
                         f"serving range mix",
             "max_batch": 4096, "inflight": args.inflight, "admitted": limits, "rates": rows, "k100": k100}
+
+
+def c1_bench(args):
+    """The plain FP32 hybrid search of the small configuration: 10,000 x 128 vectors
+    (16-centre mixture, sigma 0.3), attribute a permutation, HSIG S = 8, M = 16, efCons =
+    100 built on the GPU, FP32 store; 200 queries with in-range fractions in {0.01, 0.1,
+    0.5} (random placement), k = 10, ef = 64, every query forced to the hybrid search."""
+    import numpy as np
+    import torch
+
+    import paper_2412_02448_amd as u
+    from paper_2412_02448_amd import autotune
+    from synth import workloads as w
+    spec = w.SPECS["hybrid10k"]
+    dev = torch.device("cuda", 0)
+    W = w.make(spec, base_seed=0)
+    index = u.Index.build(W.base, W.attr, W.level_u, spec.S, spec.M, spec.ef_cons, device=0, precision="fp32")
+    Q, L, H = (torch.from_numpy(a).to(dev) for a in (W.queries, W.l, W.h))
+    truth = autotune.exact_answers(index, Q, L, H, spec.k)
+    out = {"workload": "hybrid10k: n=10000 d=128 (16-centre mixture, sigma 0.3), permutation attribute, HSIG S=8 "
+                       "M=16 efCons=100 built on GPU, FP32 store; 200 queries, fractions {0.01, 0.1, 0.5}, k=10, "
+                       "ef=64, hybrid forced"}
+    for p in (1, 4):
+        kw = dict(strategy=u.HYBRID, m=0, beam_p=p)
+        for _ in range(3):
+            index.search(Q, L, H, spec.k, 64, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(50):
+            o = index.search(Q, L, H, spec.k, 64, **kw)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / 50
+        rec = autotune.recall_at_k(o[0].cpu().numpy(), truth)
+        out[f"p{p}"] = {"qps": round(len(W.queries) / sec, 1), "ms_per_batch": round(sec * 1e3, 4),
+                        "recall@10": round(rec, 4)}
+        log(f"c1 hybrid FP32 ef=64 p={p}: {len(W.queries) / sec:,.0f} QPS ({sec * 1e3:.3f} ms per 200), recall {rec:.4f}")
+    index.close()
+    return out
 
 
 def c5_bench(args):

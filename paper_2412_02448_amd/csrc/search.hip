@@ -754,7 +754,40 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
       }
     }
     __syncthreads();
-    for (int base = 0; base < ntot; base += WAVE) {
+    // tagged mode: the visited checks of up to TB blocks of entries are issued together, so a
+    // step waits for one round of atomics on the visited row instead of one per block (which
+    // lane of a batch claims a repeated id does not matter: the evaluated keys are admitted
+    // against the pre-step threshold and kept in key order)
+    // (4 blocks in the BF16 kernel, 2 in the FP32 one; the FP8 kernel has no registers to
+    // spare for it and keeps one block at a time)
+    constexpr int TB = PREC == UNIFY_BF16 ? 4 : 2;
+    int tb0 = 0;
+    if (PREC != UNIFY_FP8E4M3 && tagged) {
+      for (; tb0 < ntot; tb0 += TB * WAVE) {
+        int32_t vv[TB];
+        bool isn[TB];
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          const int e = tb0 + u * WAVE + lane;
+          vv[u] = e < ntot ? (int32_t)(uint32_t)L.bkeys[e] : -1;
+        }
+        __syncthreads();  // these blocks are read before new ids are written over them
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          bool fresh = false;
+          isn[u] = vv[u] >= 0 && visit_tagged(L.hash, setbits, R.bits, vv[u], fresh);
+          log_words(R, nlog, fresh, vv[u]);
+        }
+        wave_fence();
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          const u64 nm = ballot(isn[u]);
+          if (isn[u]) L.bkeys[nn + rank_in(nm)] = (uint32_t)vv[u];
+          nn += __popcll(nm);
+        }
+      }
+    }
+    for (int base = tb0; base < ntot; base += WAVE) {
       {
         const int e = base + lane;
         const int32_t v = e < ntot ? (int32_t)(uint32_t)L.bkeys[e] : -1;
@@ -2085,8 +2118,10 @@ __global__ void __launch_bounds__(256) k_tile_final(TileArgs T, int64_t* __restr
       const bool valid = e < total && (e % kcq) < rc[u];
       const u64 key = valid ? make_key(ru[u], key_id(rk[u])) : KEY_MAX;
       const u64 Tk = al == k ? lst[k - 1] : KEY_MAX;
-      list_insert(lst, al, k, key < Tk ? key : KEY_MAX);
-      wave_lds_sync();
+      if (__any(key < Tk)) {  // once the list is full most blocks hold nothing below its end
+        list_insert(lst, al, k, key < Tk ? key : KEY_MAX);
+        wave_lds_sync();
+      }
     }
   }
   const float thr = al == k ? key_dist(lst[k - 1]) : __builtin_inff();
@@ -2118,8 +2153,10 @@ __global__ void __launch_bounds__(256) k_tile_final(TileArgs T, int64_t* __restr
         wave_lds_sync();
         const u64 key = lane < nb ? keys[lane] : KEY_MAX;
         const u64 Tk = al == k ? lst[k - 1] : KEY_MAX;
-        list_insert(lst, al, k, key < Tk ? key : KEY_MAX);
-        wave_lds_sync();
+        if (__any(key < Tk)) {
+          list_insert(lst, al, k, key < Tk ? key : KEY_MAX);
+          wave_lds_sync();
+        }
         nres += nb;
       }
     }

@@ -116,3 +116,33 @@ def test_sampled_queries_equal_oracle_other_stores(full, name):
     assert np.array_equal(ids[sample], rid)
     assert np.array_equal(dist[sample].view(np.uint32), rd.view(np.uint32))
     assert set(rc[:, hsig.STRAT].tolist()) == {hsig.PRE, hsig.HYBRID, hsig.POST}
+
+
+def test_wide_beam_sample_equals_oracle_twice(full):
+    """ef = 256 on the 1M index: layer searches visit thousands of objects, spill from the
+    on-chip visited cache to the HBM visited rows, and some set more words than a row's log
+    holds, so the whole bitmap is cleared at their end.  A sample of hybrid and
+    post-filter queries equals the oracle, and a second identical call equals the first
+    (a bit left set in a visited row would hide an object from a later search)."""
+    import torch
+    import paper_2412_02448_amd as u
+    W, (ids, dist, strat, st, _), path = full
+    sel = np.nonzero(np.isin(strat, [hsig.HYBRID, hsig.POST]))[0][::60][:80]
+    print(f"[case] ef=256 on {len(sel)} graph queries, twice", flush=True)
+    g = u.Index.load(path, device=0, precision="bf16")
+    dev = torch.device("cuda", 0)
+    Q, L, H = (torch.from_numpy(np.ascontiguousarray(a[sel])).to(dev) for a in (W.queries, W.l, W.h))
+    runs = []
+    for _ in range(2):
+        r = g.search(Q, L, H, 10, 256, m=64, beam_p=4, tau_a=0.01, tau_b=0.5, stats=True)
+        torch.cuda.synchronize()
+        runs.append([t.cpu().numpy() for t in r])
+    g.close()
+    assert (runs[0][3][:, 3] & 0x100).any()  # some layer search spilled to the visited rows
+    for a, b in zip(runs[0][:3], runs[1][:3]):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    ref = hsig.Index.read(path)
+    ref.set_store(hsig.BF16, 4)
+    rid, rd = ref.search(W.queries[sel], W.l[sel], W.h[sel], 10, 256, m=64, p=4, tau_a=0.01, tau_b=0.5)
+    assert np.array_equal(runs[0][0], rid)
+    assert np.array_equal(runs[0][1].view(np.uint32), rd.view(np.uint32))
