@@ -880,9 +880,9 @@ def c1_bench(args):
     truth = autotune.exact_answers(index, Q, L, H, spec.k)
     out = {"workload": "hybrid10k: n=10000 d=128 (16-centre mixture, sigma 0.3), permutation attribute, HSIG S=8 "
                        "M=16 efCons=100 built on GPU, FP32 store; 200 queries, fractions {0.01, 0.1, 0.5}, k=10, "
-                       "ef=64, hybrid forced"}
-    for p in (1, 4):
-        kw = dict(strategy=u.HYBRID, m=0, beam_p=p)
+                       "ef=64; p1, p4: hybrid forced with beam width 1, 4; auto_p4: the range-aware rule"}
+    for name, strat, p in (("p1", u.HYBRID, 1), ("p4", u.HYBRID, 4), ("auto_p4", None, 4)):
+        kw = dict(strategy=strat, m=0, beam_p=p)
         for _ in range(3):
             index.search(Q, L, H, spec.k, 64, **kw)
         torch.cuda.synchronize()
@@ -892,9 +892,10 @@ def c1_bench(args):
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t) / 50
         rec = autotune.recall_at_k(o[0].cpu().numpy(), truth)
-        out[f"p{p}"] = {"qps": round(len(W.queries) / sec, 1), "ms_per_batch": round(sec * 1e3, 4),
-                        "recall@10": round(rec, 4)}
-        log(f"c1 hybrid FP32 ef=64 p={p}: {len(W.queries) / sec:,.0f} QPS ({sec * 1e3:.3f} ms per 200), recall {rec:.4f}")
+        out[name] = {"qps": round(len(W.queries) / sec, 1), "ms_per_batch": round(sec * 1e3, 4),
+                     "recall@10": round(rec, 4)}
+        log(f"c1 FP32 ef=64 {name} ({'hybrid forced' if strat else 'auto strategy'}): {len(W.queries) / sec:,.0f} "
+            f"QPS ({sec * 1e3:.3f} ms per 200), recall {rec:.4f}")
     index.close()
     return out
 

@@ -237,10 +237,10 @@ int unify_search(unify_index_t index, const float* queries, int64_t nq, const in
  *              scan whose bounds could not settle the result, 2 = capacity exceeded even
  *              then: the row is padded, 3 = the requested strategy is not one of
  *              UNIFY_AUTO..UNIFY_POST: the row is padded) and flag bits above: bit 8 =
- *              a layer search's visited set outgrew the on-chip cache and continued in
- *              HBM (same results), bit 9 = several wavefronts ran the graph search
- *              together (waves_per_query; such a search keeps its visited set in HBM,
- *              and which searches run so can differ between calls), [4] adjacency
+ *              a layer search met ids whose set of the on-chip visited cache was full
+ *              and recorded them in HBM (same results), bit 9 = several wavefronts ran
+ *              the graph search together (waves_per_query; which searches run so can
+ *              differ between calls), [4] adjacency
  *              entries read (a pre-filter row answered
  *              by the matrix-core scan: the super-blocks its slice spans; 0 when it was
  *              scanned per wavefront), [5] strategy run (-1 for

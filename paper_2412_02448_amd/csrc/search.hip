@@ -487,16 +487,17 @@ struct Lds {
   u64* sel;    // selection S1: the ranked list (sel_cap - 64 entries), then 64 scratch keys
 };
 
-// Visited set of one layer search.  An 8-way set-associative cache of ids in
-// LDS is exact while no set has overflowed ("local" mode: a miss proves the id
-// new).  When an insert finds its set full, the wave sets the bits of every
-// cached id and of the overflowing ones in its HBM visited row and switches to
-// "tagged" mode: a cache miss then sets the id's bit, and the bit's old value
-// says whether it was visited.  A row is a bitmap of n bits, all clear between
-// layer searches, followed by a log of the bitmap words the layer search made
-// non-zero, which it clears at its end (the whole bitmap if the log overflowed).
-// Only this wave (workgroup) uses its row; workgroup-scope fences order its own
-// stores and loads.
+// Visited set of one layer search, decided per id.  An 8-way set-associative
+// cache of ids in LDS holds an id while its set has room (a set never loses an
+// entry within a layer search, so a miss in a set with room proves the id new);
+// an id whose set is full is decided by its bit in the wave's (workgroup's) HBM
+// visited row: an atomic OR sets it, and the bit's old value says whether the id
+// was visited.  Each id thus lives in exactly one of the two, and concurrent
+// lanes (or wavefronts) claim it exactly once through the LDS compare-and-swap
+// or the OR.  A row is a bitmap of n bits, all clear between layer searches,
+// followed by a log of the bitmap words the layer search made non-zero, which it
+// clears at its end (the whole bitmap if the log overflowed).  Only this wave
+// (workgroup) uses its row; workgroup-scope fences order its own stores and loads.
 constexpr int VWAYS = 8;
 constexpr int VLOG_CAP = 8192;  // logged words per row
 
@@ -548,16 +549,15 @@ __device__ __forceinline__ bool mark_bit(uint32_t* bits, int32_t v, bool& fresh)
   return (old & m) == 0u;
 }
 
-// Tagged mode: the bitmap is authoritative, the cache only saves reads.  The
-// atomic OR lets exactly one lane of a batch claim an id the batch holds twice.
-__device__ __forceinline__ bool visit_tagged(uint32_t* cache, int setbits, uint32_t* bits, int32_t v,
-                                             bool& fresh) {
-  uint32_t* base = cache_set(cache, setbits, v);
+// True when v is new.  `spill`: v's set was full and the row decided; `fresh`: the
+// row's word was zero before (its index belongs in the log).
+__device__ __forceinline__ bool visit(uint32_t* cache, int setbits, uint32_t* bits, int32_t v, bool& spill,
+                                      bool& fresh) {
+  bool full = false;
   fresh = false;
-  if (cache_hit(base, v)) return false;
-  if (!mark_bit(bits, v, fresh)) return false;
-  base[(uint32_t)v & (VWAYS - 1)] = (uint32_t)v;
-  return true;
+  const bool isnew = visit_local(cache, setbits, v, full);
+  spill = full;
+  return full ? mark_bit(bits, v, fresh) : isnew;
 }
 
 // Appends the words that `fresh` lanes made non-zero to the log (one wavefront;
@@ -622,11 +622,11 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
   const int lane = lane_id();
   int hbits = 0;
   while ((1 << hbits) < A.hcap) ++hbits;
-  int nlog = 0;  // tagged mode: words logged in R
+  int nlog = 0;  // words logged in R
   for (int i = lane; i < A.hcap; i += WAVE) L.hash[i] = HASH_EMPTY;
   __syncthreads();
   const int setbits = hbits - 3;  // hcap / VWAYS sets
-  bool tagged = false;
+  bool spilled = false;  // some id was decided by the HBM row
   bool overflow = false;
   if (lane == 0) L.hash[(cache_set(L.hash, setbits, ep) - L.hash)] = (uint32_t)ep;
   // cand = {ep}; ann = {ep} unless filtered out
@@ -754,67 +754,32 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
       }
     }
     __syncthreads();
-    // tagged mode: the visited checks of up to TB blocks of entries are issued together, so a
-    // step waits for one round of atomics on the visited row instead of one per block (which
-    // lane of a batch claims a repeated id does not matter: the evaluated keys are admitted
-    // against the pre-step threshold and kept in key order)
-    // (4 blocks in the BF16 kernel, 2 in the FP32 one; the FP8 kernel has no registers to
-    // spare for it and keeps one block at a time)
-    constexpr int TB = PREC == UNIFY_BF16 ? 4 : 2;
-    int tb0 = 0;
-    if (PREC != UNIFY_FP8E4M3 && tagged) {
-      for (; tb0 < ntot; tb0 += TB * WAVE) {
-        int32_t vv[TB];
-        bool isn[TB];
+    // the visited checks of up to TB blocks of entries are issued together, so a step waits
+    // for one round of atomics on the visited row instead of one per block (which lane of
+    // a batch claims a repeated id does not matter: the evaluated keys are admitted against
+    // the pre-step threshold and kept in key order).  4 blocks in the BF16 kernel, 2 in the
+    // FP32 one; the FP8 kernel has no registers to spare and takes one at a time.
+    constexpr int TB = PREC == UNIFY_BF16 ? 4 : (PREC == UNIFY_FP32 ? 2 : 1);
+    for (int b0 = 0; b0 < ntot; b0 += TB * WAVE) {
+      int32_t vv[TB];
+      bool isn[TB];
 #pragma unroll
-        for (int u = 0; u < TB; ++u) {
-          const int e = tb0 + u * WAVE + lane;
-          vv[u] = e < ntot ? (int32_t)(uint32_t)L.bkeys[e] : -1;
-        }
-        __syncthreads();  // these blocks are read before new ids are written over them
-#pragma unroll
-        for (int u = 0; u < TB; ++u) {
-          bool fresh = false;
-          isn[u] = vv[u] >= 0 && visit_tagged(L.hash, setbits, R.bits, vv[u], fresh);
-          log_words(R, nlog, fresh, vv[u]);
-        }
-        wave_fence();
-#pragma unroll
-        for (int u = 0; u < TB; ++u) {
-          const u64 nm = ballot(isn[u]);
-          if (isn[u]) L.bkeys[nn + rank_in(nm)] = (uint32_t)vv[u];
-          nn += __popcll(nm);
-        }
+      for (int u = 0; u < TB; ++u) {
+        const int e = b0 + u * WAVE + lane;
+        vv[u] = e < ntot ? (int32_t)(uint32_t)L.bkeys[e] : -1;
       }
-    }
-    for (int base = tb0; base < ntot; base += WAVE) {
-      {
-        const int e = base + lane;
-        const int32_t v = e < ntot ? (int32_t)(uint32_t)L.bkeys[e] : -1;
-        __syncthreads();  // this block is read before new ids are written over it
-        bool isnew = false, full = false, fresh = false;
-        if (v >= 0) {
-          isnew = tagged ? visit_tagged(L.hash, setbits, R.bits, v, fresh)
-                         : visit_local(L.hash, setbits, v, full);
-        }
-        if (tagged) log_words(R, nlog, fresh, v);
-        if (!tagged && __any(full)) {
-          // switch to tagged mode: set the bit of every visited id in the row
-          for (int i = lane; i < A.hcap; i += WAVE) {
-            const uint32_t id = L.hash[i];
-            bool fr = false;
-            if (id != HASH_EMPTY) (void)mark_bit(R.bits, (int32_t)id, fr);
-            log_words(R, nlog, fr, (int32_t)id);
-          }
-          // an id that found its set full may appear twice in the batch: one lane claims it
-          bool fr = false;
-          if (full) isnew = mark_bit(R.bits, v, fr);
-          log_words(R, nlog, fr, v);
-          tagged = true;
-        }
-        if (tagged) wave_fence();
-        const u64 nm = ballot(isnew);
-        if (isnew) L.bkeys[nn + rank_in(nm)] = (uint32_t)v;
+      __syncthreads();  // these blocks are read before new ids are written over them
+#pragma unroll
+      for (int u = 0; u < TB; ++u) {
+        bool sp = false, fresh = false;
+        isn[u] = vv[u] >= 0 && visit(L.hash, setbits, R.bits, vv[u], sp, fresh);
+        spilled |= __any(sp);
+        log_words(R, nlog, fresh, vv[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < TB; ++u) {
+        const u64 nm = ballot(isn[u]);
+        if (isn[u]) L.bkeys[nn + rank_in(nm)] = (uint32_t)vv[u];
         nn += __popcll(nm);
       }
     }
@@ -860,7 +825,7 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
     }
     if (overflow) break;
   }
-  if (tagged) {
+  if (spilled) {
     cnt.spill = 1;
     wave_fence();  // the log's stores before their loads
     clear_row(R, nlog, A.bwords, lane, WAVE);
@@ -1252,9 +1217,10 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
 // gather, visited checks and distance evaluations over MW wavefronts shortens
 // them.  Wavefront 0 pops the candidates and admits the evaluated keys by the
 // rule of the one-wavefront search (so the same ann list results); the visited
-// set is the workgroup's HBM tag row from the start (the LDS cache only saves
-// reads), so whichever wavefront meets an id first claims it by one atomic
-// exchange.  Three workgroup barriers per step.
+// set is the workgroup's LDS cache, shared by its wavefronts, with the HBM row for
+// ids whose cache set is full, so whichever wavefront meets an id first claims it
+// by one compare-and-swap in LDS (or one atomic OR on the row).  Three workgroup
+// barriers per step.
 // ---------------------------------------------------------------------------
 struct LdsMW {
   u64* ann;
@@ -1265,7 +1231,7 @@ struct LdsMW {
   int32_t* sh;  // broadcast slots
 };
 enum { SH_NPOP = 8, SH_POPPED = 9 /* 8 slots */, SH_CL = 17, SH_AL = 18, SH_OVER = 19, SH_EP = 20, SH_TOP = 21,
-       SH_W = 22, SH_EPKEY = 24 /* 2 slots */, SH_NLOG = 26, SH_SLOTS = 27 };
+       SH_W = 22, SH_EPKEY = 24 /* 2 slots */, SH_NLOG = 26, SH_SPILL = 27, SH_SLOTS = 28 };
 
 // LDS bytes of a cooperative search's workgroup (besides the broadcast slots).
 __host__ __device__ inline size_t lds_bytes_mw(int ef_blocks, int ccap, int hcap, int nbr_cap, int mw) {
@@ -1287,10 +1253,8 @@ __device__ bool layer_search_mw(const SearchArgs& A, const LdsMW& L, const float
   for (int i = tid; i < A.hcap; i += NT) L.hash[i] = HASH_EMPTY;
   __syncthreads();
   if (tid == 0) {
-    bool fresh = false;
-    (void)mark_bit(R.bits, ep, fresh);
-    R.log[0] = (uint32_t)ep >> 5;
-    L.sh[SH_NLOG] = 1;
+    L.sh[SH_NLOG] = 0;
+    L.sh[SH_SPILL] = 0;
     L.hash[cache_set(L.hash, setbits, ep) - L.hash] = (uint32_t)ep;
     L.cand[0] = ep_key;
   }
@@ -1370,8 +1334,10 @@ __device__ bool layer_search_mw(const SearchArgs& A, const LdsMW& L, const float
 #pragma unroll
       for (int u = 0; u < GB; ++u) {
         const int32_t v = vv[u];
-        bool fresh = false;
-        const bool isnew = v >= 0 && visit_tagged(L.hash, setbits, R.bits, v, fresh);
+        bool sp = false, fresh = false;
+        const bool isnew = v >= 0 && visit(L.hash, setbits, R.bits, v, sp, fresh);
+        const bool anysp = __any(sp);
+        if (lane == 0 && anysp) L.sh[SH_SPILL] = 1;
         // the words this wavefront made non-zero go to the shared log
         const u64 fm = ballot(fresh);
         if (fm) {
@@ -1445,9 +1411,11 @@ __device__ bool layer_search_mw(const SearchArgs& A, const LdsMW& L, const float
     }
     if (overflow) break;
   }
-  cnt.spill = 1;  // the visited set lives in the row
   __syncthreads();  // every wavefront's bits and log entries before the clear
-  clear_row(R, L.sh[SH_NLOG], A.bwords, tid, NT);
+  if (L.sh[SH_SPILL]) {
+    cnt.spill = 1;
+    clear_row(R, L.sh[SH_NLOG], A.bwords, tid, NT);
+  }
   __syncthreads();  // the clears before the row's next use
   return !overflow;
 }
