@@ -62,6 +62,16 @@ def lib():
         L.orc_search.argtypes = [P, P, I64, P, P, I32, I32, I32, I32, I32, D, D, P, P, P, I32, I32, P, P]
         L.orc_set_attr2.restype = I32
         L.orc_set_attr2.argtypes = [P, P, I64]
+        L.orc_zorder_map.restype = I32
+        L.orc_zorder_map.argtypes = [P, P, I64, P]
+        L.orc_zorder_keys.restype = I32
+        L.orc_zorder_keys.argtypes = [P, P, P, I64, P]
+        L.orc_zorder_range.restype = I32
+        L.orc_zorder_range.argtypes = [P, P, P, P, P, I64, P, P]
+        L.orc_set_zorder.restype = I32
+        L.orc_set_zorder.argtypes = [P, P, P, P, I64]
+        L.orc_search_box.restype = I32
+        L.orc_search_box.argtypes = [P, P, I64, P, P, P, P, I32, I32, I32, I32, I32, D, D, P, P, P, I32, I32]
         L.orc_layer_search.restype = I32
         L.orc_layer_search.argtypes = [P, P, I32, I32, I32, I32, I32, I32, I32, I32, I64, I64, P, P]
         L.orc_prune.restype = I32
@@ -300,6 +310,32 @@ class Index:
             raise ValueError(lib().orc_last_error().decode())
         return (ids, dist, cnt) if counters else (ids, dist)
 
+    def set_zorder(self, zmap, a1, a2) -> None:
+        """Both attributes of a z-order index, indexed by external id (box searches); the
+        index must have been built on zorder_keys(zmap, a1, a2)."""
+        m = np.ascontiguousarray(zmap, np.int64)
+        a1 = np.ascontiguousarray(a1, np.int64)
+        a2 = np.ascontiguousarray(a2, np.int64)
+        if a1.size != a2.size or m.size != 4:
+            raise ValueError("one pair per object and a map of 4 values")
+        if lib().orc_set_zorder(self._h, _p(m), _p(a1), _p(a2), a1.size) != 0:
+            raise ValueError(lib().orc_last_error().decode())
+
+    def search_box(self, Q, l1, h1, l2, h2, k, ef, m=0, p=1, strategy=AUTO, tau_a=0.01, tau_b=0.5,
+                   counters=False, batch_form=False, select_s1=False):
+        """Box search on a z-order index: objects with l1 <= A1 <= h1 and l2 <= A2 <= h2."""
+        Q = np.ascontiguousarray(Q, np.float32)
+        r = [np.ascontiguousarray(x, np.int64) for x in (l1, h1, l2, h2)]
+        nq = Q.shape[0]
+        ids = np.zeros((nq, k), np.int64)
+        dist = np.zeros((nq, k), np.float32)
+        cnt = np.zeros((nq, NCOUNT), np.int64)
+        rc = lib().orc_search_box(self._h, _p(Q), nq, *[_p(x) for x in r], k, ef, m, p, strategy, tau_a, tau_b,
+                                  _p(ids), _p(dist), _p(cnt), int(batch_form), int(select_s1))
+        if rc != 0:
+            raise ValueError(lib().orc_last_error().decode())
+        return (ids, dist, cnt) if counters else (ids, dist)
+
     def layer_search(self, q, ep, layer, ef, hybrid, a=0, b=0, c=0, filter=False, l=0, h=0):
         q = np.ascontiguousarray(q, np.float32)
         ids = np.zeros(max(ef, 1), np.int32)
@@ -307,6 +343,39 @@ class Index:
         cnt = lib().orc_layer_search(self._h, _p(q), ep, layer, ef, int(hybrid), a, b, c, int(filter),
                                      l, h, _p(ids), _p(dist))
         return ids[:cnt], dist[:cnt]
+
+
+def zorder_map(a1, a2) -> np.ndarray:
+    """The z-order key map of two attributes (the multi-attribute extension, approach 2):
+    [base1, shift1, base2, shift2]: each attribute's smallest value, and the shift that puts its
+    largest value in the upper half of a 2^31-cell axis (negative: a left shift)."""
+    a1 = np.ascontiguousarray(a1, np.int64)
+    a2 = np.ascontiguousarray(a2, np.int64)
+    out = np.zeros(4, np.int64)
+    lib().orc_zorder_map(_p(a1), _p(a2), a1.size, _p(out))
+    return out
+
+
+def zorder_keys(zmap, a1, a2) -> np.ndarray:
+    """The z-order keys of the pairs (a1[i], a2[i]): the two coordinates' bits interleaved,
+    a1's in the odd positions."""
+    m = np.ascontiguousarray(zmap, np.int64)
+    a1 = np.ascontiguousarray(a1, np.int64)
+    a2 = np.ascontiguousarray(a2, np.int64)
+    out = np.zeros(a1.size, np.int64)
+    if lib().orc_zorder_keys(_p(m), _p(a1), _p(a2), a1.size, _p(out)) != 0:
+        raise ValueError(lib().orc_last_error().decode())
+    return out
+
+
+def zorder_range(zmap, l1, h1, l2, h2):
+    """The key range [lo, hi] a box search runs on (lo > hi for an empty box)."""
+    m = np.ascontiguousarray(zmap, np.int64)
+    r = [np.ascontiguousarray(x, np.int64) for x in (l1, h1, l2, h2)]
+    lo = np.zeros(r[0].size, np.int64)
+    hi = np.zeros(r[0].size, np.int64)
+    lib().orc_zorder_range(_p(m), *[_p(x) for x in r], r[0].size, _p(lo), _p(hi))
+    return lo, hi
 
 
 def merge_or(ids_a, dist_a, ids_b, dist_b):

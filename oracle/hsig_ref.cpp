@@ -538,6 +538,13 @@ struct View {
   // sorted sample of attr2 for the strategy rule: the value at rank floor(j n / ns)
   // of the sorted attr2, j < ns = min(n, 2048)
   std::vector<int64_t> attr2_sample;
+  // z-order composite attribute (the multi-attribute discussion of Sec. 5.9, approach 2):
+  // the index's attribute is the key of the pair (A1, A2); both attributes of every
+  // object (internal order; empty when not set), the key map, and the pairs of the
+  // objects at internal ids floor(j n / ns), j < ns = min(n, 2048), for the strategy rule.
+  std::vector<int64_t> za1, za2, zs1, zs2;
+  int64_t zbase1 = 0, zbase2 = 0;
+  int zshift1 = 0, zshift2 = 0;
 
   const float* vec(int v) const { return &X[(size_t)v * d]; }
   const float* svec(int v) const { return XS.empty() ? vec(v) : &XS[(size_t)v * d]; }
@@ -829,8 +836,13 @@ struct Query {
   bool s1 = false;         // hybrid neighbour selection S1 instead of S2
   bool multi = false;      // also require l2 <= attr2 <= h2 (conjunctive query)
   int64_t l2 = 0, h2 = 0;
+  bool box = false;        // z-order index: require l1 <= A1 <= h1 and l2 <= A2 <= h2
+  int64_t l1 = 0, h1 = 0;
   int64_t* cnt;
-  bool second_ok(int v) const { return !multi || (V->attr2[v] >= l2 && V->attr2[v] <= h2); }
+  bool second_ok(int v) const {
+    if (box) return V->za1[v] >= l1 && V->za1[v] <= h1 && V->za2[v] >= l2 && V->za2[v] <= h2;
+    return !multi || (V->attr2[v] >= l2 && V->attr2[v] <= h2);
+  }
   // the filter of Alg. 7 (its ann admission) and of the post-filter: every range of the query
   bool in_range(int v) const { return V->attr[v] >= l && V->attr[v] <= h && second_ok(v); }
   // distance in the store the graph searches use
@@ -1090,6 +1102,77 @@ struct OrcIndex {
   View V;
 };
 
+// ---- z-order composite attribute (Sec. 5.9, multiple attributes, approach 2) ----
+// Reading: each attribute becomes an order-preserving coordinate on a grid of 2^31 cells,
+//   u(x) = 0 if x <= base, else min(scale(x - base), 2^31 - 1)   (x - base modulo 2^64),
+// scale(t) = t >> shift for shift >= 0 and t << -shift (2^31 - 1 when that overflows) else,
+// with base the attribute's smallest value over the objects and shift = bits(largest - base)
+// - 31 (0 when all values are equal), so that both attributes spread over the whole grid
+// (the largest value lands in its upper half); the key interleaves the coordinates' bits
+// (Orenstein's z-order), bit j of u1 becoming bit 2j + 1 of the key and bit j of u2 bit 2j.
+// Every coordinate function is non-decreasing, and so is the key in each coordinate, so
+// an object inside the box [l1, h1] x [l2, h2] has a key between key(u1(l1), u2(l2)) and
+// key(u1(h1), u2(h2)): the search runs on that key range and admits only box objects.
+static uint64_t z_coord(int64_t x, int64_t base, int shift) {
+  const uint64_t top = (1ull << 31) - 1;
+  if (x <= base) return 0;
+  const uint64_t t = (uint64_t)x - (uint64_t)base;
+  uint64_t u;
+  if (shift >= 0) u = t >> shift;
+  else u = t > (top >> -shift) ? top : t << -shift;
+  return u < top ? u : top;
+}
+static int64_t z_key(uint64_t u1, uint64_t u2) {
+  uint64_t z = 0;
+  for (int j = 0; j < 31; ++j) {
+    z |= ((u1 >> j) & 1ull) << (2 * j + 1);
+    z |= ((u2 >> j) & 1ull) << (2 * j);
+  }
+  return (int64_t)z;
+}
+static void z_axis(const int64_t* a, int64_t n, int64_t& base, int& shift) {
+  base = 0;
+  shift = 0;
+  if (n == 0) return;
+  int64_t lo = a[0], hi = a[0];
+  for (int64_t i = 1; i < n; ++i) {
+    lo = std::min(lo, a[i]);
+    hi = std::max(hi, a[i]);
+  }
+  base = lo;
+  const uint64_t span = (uint64_t)hi - (uint64_t)lo;
+  if (span == 0) return;
+  int bits = 0;
+  while (bits < 64 && (span >> bits) != 0) ++bits;
+  shift = bits - 31;
+}
+
+// Runs one planned query under strategy st and writes its k results (external ids,
+// FP32 distances; (-1, +inf) padding) and the strategy and slice counters.
+static void run_query(Searcher& srch, Query& qq, int st, int k, int ef, int m, int p, int batch_form,
+                      int64_t* out_ids, float* out_dist) {
+  const View& V = *qq.V;
+  int64_t* cnt = qq.cnt;
+  cnt[C_STRAT] = st;
+  cnt[C_LO] = qq.lo;
+  cnt[C_HI] = qq.hi;
+  std::vector<FI> res;
+  if (qq.hi > qq.lo) {
+    if (st == ST_PRE) res = srch.pre(qq, k);
+    else if (st == ST_HYBRID) res = srch.hybrid(qq, k, ef, m, p, batch_form != 0);
+    else res = srch.post(qq, k, ef, p, batch_form != 0);
+  }
+  for (int t = 0; t < k; ++t) {
+    if (t < (int)res.size()) {
+      out_ids[t] = V.ext[res[t].second];
+      out_dist[t] = res[t].first;
+    } else {
+      out_ids[t] = -1;
+      out_dist[t] = std::numeric_limits<float>::infinity();
+    }
+  }
+}
+
 extern "C" {
 
 const char* orc_last_error() { return g_err.c_str(); }
@@ -1339,24 +1422,135 @@ int orc_search(void* h, const float* Q, int64_t nq, const int64_t* L, const int6
     } else if (st == ST_AUTO) {
       st = Y <= tA ? ST_PRE : (Y >= tB ? ST_POST : ST_HYBRID);
     }
-    cnt[C_STRAT] = st;
-    cnt[C_LO] = qq.lo;
-    cnt[C_HI] = qq.hi;
-    std::vector<FI> res;
-    if (Y > 0) {
-      if (st == ST_PRE) res = srch.pre(qq, k);
-      else if (st == ST_HYBRID) res = srch.hybrid(qq, k, ef, m, p, batch_form != 0);
-      else res = srch.post(qq, k, ef, p, batch_form != 0);
+    run_query(srch, qq, st, k, ef, m, p, batch_form, out_ids + i * k, out_dist + i * k);
+  }
+  return 0;
+}
+
+// The z-order key map of two attributes given per object: out = {base1, shift1, base2, shift2}.
+int orc_zorder_map(const int64_t* a1, const int64_t* a2, int64_t n, int64_t* out) {
+  int s1 = 0, s2 = 0;
+  z_axis(a1, n, out[0], s1);
+  z_axis(a2, n, out[2], s2);
+  out[1] = s1;
+  out[3] = s2;
+  return 0;
+}
+
+// z-order keys of n pairs under map {base1, shift1, base2, shift2}.
+int orc_zorder_keys(const int64_t* map, const int64_t* a1, const int64_t* a2, int64_t n, int64_t* out) {
+  if (map[1] < -30 || map[1] > 63 || map[3] < -30 || map[3] > 63) {
+    g_err = "orc_zorder_keys: bad map";
+    return -22;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    out[i] = z_key(z_coord(a1[i], map[0], (int)map[1]), z_coord(a2[i], map[2], (int)map[3]));
+  return 0;
+}
+
+// The key range [out_lo, out_hi] searched for each box (out_lo > out_hi: an empty box).
+int orc_zorder_range(const int64_t* map, const int64_t* L1, const int64_t* H1, const int64_t* L2,
+                     const int64_t* H2, int64_t nq, int64_t* out_lo, int64_t* out_hi) {
+  for (int64_t i = 0; i < nq; ++i) {
+    if (L1[i] > H1[i] || L2[i] > H2[i]) {
+      out_lo[i] = 1;
+      out_hi[i] = 0;
+      continue;
     }
-    for (int t = 0; t < k; ++t) {
-      if (t < (int)res.size()) {
-        out_ids[i * k + t] = V.ext[res[t].second];
-        out_dist[i * k + t] = res[t].first;
-      } else {
-        out_ids[i * k + t] = -1;
-        out_dist[i * k + t] = std::numeric_limits<float>::infinity();
-      }
+    out_lo[i] = z_key(z_coord(L1[i], map[0], (int)map[1]), z_coord(L2[i], map[2], (int)map[3]));
+    out_hi[i] = z_key(z_coord(H1[i], map[0], (int)map[1]), z_coord(H2[i], map[2], (int)map[3]));
+  }
+  return 0;
+}
+
+// Attaches the two attributes of a z-order index: a1[e], a2[e] belong to the object with
+// external id e (ids 0 .. n-1), and the index's attribute of every object must be the key
+// of its pair under map.  Returns 0, or -22.
+int orc_set_zorder(void* h, const int64_t* map, const int64_t* a1, const int64_t* a2, int64_t n) {
+  View& V = ((OrcIndex*)h)->V;
+  if (n != V.n || map[1] < -30 || map[1] > 63 || map[3] < -30 || map[3] > 63) {
+    g_err = "orc_set_zorder: one pair per object and a valid map";
+    return -22;
+  }
+  std::vector<int64_t> b1(n), b2(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t e = V.ext[i];
+    if (e < 0 || e >= n) {
+      g_err = "orc_set_zorder: external ids are not 0 .. n-1";
+      return -22;
     }
+    b1[i] = a1[e];
+    b2[i] = a2[e];
+    if (V.attr[i] != z_key(z_coord(b1[i], map[0], (int)map[1]), z_coord(b2[i], map[2], (int)map[3]))) {
+      g_err = "orc_set_zorder: the index is not built on these pairs' keys";
+      return -22;
+    }
+  }
+  const int64_t ns = std::min<int64_t>(n, 2048);
+  V.zs1.resize(ns);
+  V.zs2.resize(ns);
+  for (int64_t j = 0; j < ns; ++j) {
+    V.zs1[j] = b1[(size_t)(j * n / ns)];
+    V.zs2[j] = b2[(size_t)(j * n / ns)];
+  }
+  V.za1.swap(b1);
+  V.za2.swap(b2);
+  V.zbase1 = map[0];
+  V.zshift1 = (int)map[1];
+  V.zbase2 = map[2];
+  V.zshift2 = (int)map[3];
+  return 0;
+}
+
+// Box search on a z-order index: the k nearest objects with L1 <= A1 <= H1 and
+// L2 <= A2 <= H2.  The HSIG is searched on the key range of the box (orc_zorder_range)
+// and admits only box objects (Alg. 7's ann admission and the post-filter test; the
+// pre-filter scans the key range and keeps box objects).  Strategy rule (auto): with Y
+// the objects in the key range and c the sampled pairs inside the box, pre-filter when
+// Y <= tau_a n or c n <= tau_a n ns, post-filter when c n >= tau_b n ns, else hybrid.
+// Other arguments and outputs as orc_search.
+int orc_search_box(void* h, const float* Q, int64_t nq, const int64_t* L1, const int64_t* H1, const int64_t* L2,
+                   const int64_t* H2, int k, int ef, int m, int p, int strategy, double tau_a, double tau_b,
+                   int64_t* out_ids, float* out_dist, int64_t* counters, int batch_form, int select_s1) {
+  OrcIndex* ix = (OrcIndex*)h;
+  const View& V = ix->V;
+  if (k < 1 || ef < 1 || p < 1 || strategy < 0 || strategy > 3 || V.za1.empty()) {
+    g_err = "orc_search_box: bad arguments (or no z-order attributes)";
+    return -22;
+  }
+  if (m <= 0) m = V.M0;
+  const int64_t tA = (int64_t)std::floor(tau_a * (double)V.n);
+  const int64_t tB = (int64_t)std::ceil(tau_b * (double)V.n);
+  const int64_t map[4] = {V.zbase1, V.zshift1, V.zbase2, V.zshift2};
+  const int64_t ns = (int64_t)V.zs1.size();
+  Searcher srch(&V);
+  std::vector<int64_t> dummy(C_NCOUNT);
+  for (int64_t i = 0; i < nq; ++i) {
+    int64_t* cnt = counters ? counters + i * C_NCOUNT : dummy.data();
+    for (int t = 0; t < C_NCOUNT; ++t) cnt[t] = 0;
+    cnt[C_ENTRY] = -1;
+    Query qq;
+    qq.V = &V;
+    qq.q = Q + (size_t)i * V.d;
+    qq.cnt = cnt;
+    qq.s1 = select_s1 != 0;
+    qq.box = true;
+    qq.l1 = L1[i];
+    qq.h1 = H1[i];
+    qq.l2 = L2[i];
+    qq.h2 = H2[i];
+    int64_t zl = 0, zh = 0;
+    orc_zorder_range(map, L1 + i, H1 + i, L2 + i, H2 + i, 1, &zl, &zh);
+    srch.plan(qq, zl, zh);
+    const int64_t Y = qq.hi - qq.lo;
+    int st = strategy;
+    if (st == ST_AUTO) {
+      int64_t c = 0;
+      for (int64_t j = 0; j < ns; ++j)
+        c += V.zs1[j] >= qq.l1 && V.zs1[j] <= qq.h1 && V.zs2[j] >= qq.l2 && V.zs2[j] <= qq.h2;
+      st = (Y <= tA || c * V.n <= tA * ns) ? ST_PRE : (c * V.n >= tB * ns ? ST_POST : ST_HYBRID);
+    }
+    run_query(srch, qq, st, k, ef, m, p, batch_form, out_ids + i * k, out_dist + i * k);
   }
   return 0;
 }
