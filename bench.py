@@ -666,7 +666,8 @@ def multi_bench(args, index, spec, W, Q, L, H, k, m, ef, bp, ta, tb, vc, prec):
     range (fraction log-uniform in [0.05, 1]) on an independent uniform second attribute.
     Conjunctive (AND) on the mixed1m index, recall against the exact conjunctive answer
     (the pre-filter scan with both ranges); disjunctive (OR) with a second index built on
-    the second attribute, recall against the merge of the two exact answers."""
+    the second attribute, recall against the merge of the two exact answers; the same
+    conjunctive boxes on one index over the z-order key of both attributes."""
     import numpy as np
     import torch
 
@@ -679,6 +680,7 @@ def multi_bench(args, index, spec, W, Q, L, H, k, m, ef, bp, ta, tb, vc, prec):
     L2 = torch.from_numpy(l2).to(dev)
     H2 = torch.from_numpy(h2).to(dev)
     truth = index.search(Q, L, H, k, k, strategy=u.PRE, l2=L2, h2=H2)[0].cpu().numpy()
+    truth_and = truth
     out = {"workload": f"mixed1m index ({prec} store), the {nq} benchmark queries plus a second range "
                        f"(fraction log-uniform in [0.05, 1]) on an independent uniform attribute; k={k}"}
     for name, sv, e in (("auto", None, ef), ("auto_ef64", None, 64), ("hybrid", u.HYBRID, ef)):
@@ -731,6 +733,38 @@ def multi_bench(args, index, spec, W, Q, L, H, k, m, ef, bp, ta, tb, vc, prec):
             log(f"disjunctive (two indexes, merged; ef={e}): {nq / sec:,.0f} QPS, recall {rec:.4f}")
     finally:
         other.close()
+    # approach 2: one index over the z-order key of (attribute, second attribute), searched
+    # with the same boxes; recall against the exact conjunctive answer above
+    zmap = u.zorder_map(W.attr, a2)
+    t0 = time.time()
+    zix = u.Index.build(W.base, u.zorder_keys(zmap, W.attr, a2), W.level_u, spec.S, spec.M, spec.ef_cons,
+                        device=0, precision=prec)
+    build3 = time.time() - t0
+    try:
+        zix.set_zorder(zmap, W.attr, a2)
+        for name, e in (("zorder", ef), ("zorder_ef64", 64)):
+            for _ in range(2):
+                o = zix.search(Q, L, H, k, e, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, l2=L2, h2=H2,
+                               box=True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(5):
+                o = zix.search(Q, L, H, k, e, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, l2=L2, h2=H2,
+                               box=True)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t) / 5
+            ids = o[0].cpu().numpy()
+            sr = o[2].cpu().numpy()
+            rec = float(np.mean([len(set(ids[i][ids[i] >= 0]) & set(truth_and[i][truth_and[i] >= 0]))
+                                 / max(1, (truth_and[i] >= 0).sum()) if (truth_and[i] >= 0).any() else 1.0
+                                 for i in range(nq)]))
+            mix = {nm: int((sr == v).sum()) for nm, v in (("pre", u.PRE), ("hybrid", u.HYBRID), ("post", u.POST))}
+            out[name] = {"ef": e, "qps": round(nq / sec, 1), "recall@10": round(rec, 4), "strategies": mix,
+                         "zorder_index_build_s": round(build3, 1)}
+            log(f"z-order composite (one index, box search; ef={e}): {nq / sec:,.0f} QPS, recall {rec:.4f}, "
+                f"strategies {mix}")
+    finally:
+        zix.close()
     return out
 
 

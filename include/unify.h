@@ -212,7 +212,8 @@ int unify_index_info(unify_index_t index, int64_t* n, int32_t* d, int32_t* S, in
  *   params        host, or NULL for defaults
  *   out_ids       device, [nq][k] int64
  *   out_dist      device, [nq][k] float32
- *   out_strategy  device, [nq] int8 strategy actually run (-1: empty range, -2:
+ *   out_strategy  device, [nq] int8 strategy of each row (the rule's choice or the
+ *                 requested one; an empty range runs nothing and pads its row; -2:
  *                 unknown requested strategy), or NULL
  *   hip_stream    hipStream_t to enqueue on, or NULL
  * nq = 0 is a no-op.  Scratch space is allocated by the library per call.
@@ -299,6 +300,70 @@ int unify_search_multi(unify_index_t index, const float* queries, int64_t nq, co
                        const int64_t* h, const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef,
                        const int8_t* strategy, const unify_params* params, int64_t* out_ids,
                        float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* hip_stream);
+
+/*
+ * The z-order composite attribute (the paper's multi-attribute extension, approach 2,
+ * Sec. 5.9: one HSIG built on a one-dimensional z-order attribute of the pair (A1, A2)).
+ * Each attribute maps to an order-preserving coordinate on an axis of 2^31 cells:
+ *   u(x) = 0 for x <= base, else min(scale(x - base), 2^31 - 1)   (x - base modulo 2^64),
+ *   scale(t) = t >> shift for shift >= 0, t << -shift (2^31 - 1 when that overflows) else,
+ * and the key of a pair interleaves the coordinates' bits: bit j of u1 is bit 2j + 1
+ * of the key, bit j of u2 bit 2j (keys are in [0, 2^62)).  Build the index with the
+ * keys as its attribute (unify_build_index), attach the pairs (unify_set_zorder), and
+ * search boxes (unify_search_box).
+ */
+typedef struct {
+  int64_t base1, base2;    /* each attribute's smallest value */
+  int32_t shift1, shift2;  /* in [-30, 63] */
+} unify_zmap;
+
+/*
+ * The map of n pairs: base = the attribute's smallest value, shift = bits(largest -
+ * base) - 31 (0 when all values are equal), so both attributes spread over the whole
+ * axis (the largest value lands in its upper half).
+ *   a1, a2  host, [n] int64
+ *   out     host
+ * Errors: UNIFY_EINVAL (null argument, n < 0).
+ */
+int unify_zorder_map(const int64_t* a1, const int64_t* a2, int64_t n, unify_zmap* out);
+
+/*
+ * The z-order keys of n pairs under map (the build's attribute values).
+ *   a1, a2  host, [n] int64;  out  host, [n] int64
+ * Errors: UNIFY_EINVAL (null argument, n < 0, a shift outside [-30, 63]).
+ */
+int unify_zorder_keys(const unify_zmap* map, const int64_t* a1, const int64_t* a2, int64_t n, int64_t* out);
+
+/*
+ * Attaches both attributes to an index built on their z-order keys under map: the
+ * pair of the object with external id e is (a1[e], a2[e]) (external ids 0 .. n-1).
+ * Every object's attribute must equal its pair's key.  Replaces earlier pairs once
+ * the searches already enqueued have finished; unify_insert drops them.
+ *   map     host;  a1, a2  host, [n] int64
+ * Errors: UNIFY_EINVAL (n is not the index's object count, external ids not dense, an
+ * object whose attribute is not its pair's key, a bad map), UNIFY_ENOMEM, UNIFY_EDEVICE.
+ */
+int unify_set_zorder(unify_index_t index, const unify_zmap* map, const int64_t* a1, const int64_t* a2,
+                     int64_t n);
+
+/*
+ * Box search on a z-order index: the k nearest objects with l1 <= A1 <= h1 AND
+ * l2 <= A2 <= h2.  The HSIG is searched on the key range [key(u1(l1), u2(l2)),
+ * key(u1(h1), u2(h2))], which holds every object of the box, and admits box objects
+ * only (Alg. 7's ann admission, the post-filter test and the pre-filter scan test
+ * both attributes).  Strategy rule (UNIFY_AUTO): with Y the objects of the key range
+ * and c the sampled pairs in the box (the pairs of the objects at internal ids
+ * floor(j n / ns), j < ns = min(n, 2048)), pre-filter when Y <= tau_a n or
+ * c n <= tau_a n ns, post-filter when c n >= tau_b n ns, else hybrid (tau_a n rounded
+ * down, tau_b n up).  Arguments as unify_search_ex, with
+ *   l1, h1, l2, h2  device, [nq] int64, inclusive ranges on A1 and A2 (an empty range
+ *                   pads the row)
+ * Errors: as unify_search, and UNIFY_EINVAL when no pairs are attached.
+ */
+int unify_search_box(unify_index_t index, const float* queries, int64_t nq, const int64_t* l1,
+                     const int64_t* h1, const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef,
+                     const int8_t* strategy, const unify_params* params, int64_t* out_ids, float* out_dist,
+                     int8_t* out_strategy, int32_t* out_stats, void* hip_stream);
 
 /*
  * Disjunctive two-attribute queries (the paper's multi-attribute extension,

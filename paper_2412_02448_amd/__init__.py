@@ -44,6 +44,40 @@ class _Params(C.Structure):
                 ("waves_per_query", C.c_int32), ("heavy_queries", C.c_int32)]
 
 
+class _ZMap(C.Structure):
+    _fields_ = [("base1", C.c_int64), ("base2", C.c_int64), ("shift1", C.c_int32), ("shift2", C.c_int32)]
+
+
+def _zmap(zmap) -> _ZMap:
+    b1, s1, b2, s2 = (int(x) for x in zmap)
+    return _ZMap(base1=b1, base2=b2, shift1=s1, shift2=s2)
+
+
+def zorder_map(a1, a2) -> np.ndarray:
+    """The z-order key map of two attributes (the multi-attribute extension, approach 2), as
+    [base1, shift1, base2, shift2]: each attribute's smallest value and the shift that puts its
+    largest value in the upper half of a 2^31-cell axis (negative: a left shift)."""
+    a1 = np.ascontiguousarray(a1, np.int64)
+    a2 = np.ascontiguousarray(a2, np.int64)
+    if a1.shape != a2.shape or a1.ndim != 1:
+        raise ValueError("a1 and a2 are [n] arrays")
+    m = _ZMap()
+    _check(load_library().unify_zorder_map(a1.ctypes.data, a2.ctypes.data, a1.size, C.byref(m)))
+    return np.array([m.base1, m.shift1, m.base2, m.shift2], np.int64)
+
+
+def zorder_keys(zmap, a1, a2) -> np.ndarray:
+    """The z-order keys of the pairs (a1[i], a2[i]) under zmap: the attribute to build the index on."""
+    a1 = np.ascontiguousarray(a1, np.int64)
+    a2 = np.ascontiguousarray(a2, np.int64)
+    if a1.shape != a2.shape or a1.ndim != 1:
+        raise ValueError("a1 and a2 are [n] arrays")
+    out = np.empty(a1.size, np.int64)
+    m = _zmap(zmap)
+    _check(load_library().unify_zorder_keys(C.byref(m), a1.ctypes.data, a2.ctypes.data, a1.size, out.ctypes.data))
+    return out
+
+
 def _params(m=0, beam_p=0, rerank_mult=0, tau_a=0.0, tau_b=0.0, flags=0, cand_cap=0, visit_cap=0,
             pre_chunk=0, waves_per_query=0, heavy_queries=0) -> _Params:
     return _Params(m=m, beam_p=beam_p, rerank_mult=rerank_mult, tau_a_frac=tau_a, tau_b_frac=tau_b, flags=flags,
@@ -72,6 +106,10 @@ SIGNATURES = {
     "unify_set_attr2": (_I32, [_P, _P, _I64]),
     "unify_merge_or": (_I32, [_P, _P, _P, _P, _I64, _I32, _P, _P, _P]),
     "unify_search_multi": (_I32, [_P, _P, _I64, _P, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "unify_zorder_map": (_I32, [_P, _P, _I64, _P]),
+    "unify_zorder_keys": (_I32, [_P, _P, _P, _I64, _P]),
+    "unify_set_zorder": (_I32, [_P, _P, _P, _P, _I64]),
+    "unify_search_box": (_I32, [_P, _P, _I64, _P, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "unify_batch_create": (_I32, [_P, _P, _I64, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "unify_server_create": (_I32, [_P, _P, _P]),
     "unify_server_submit": (_I32, [_P, _I64, _P, _P, _P, _P, _P, _P]),
@@ -223,6 +261,16 @@ class Index:
         a = np.ascontiguousarray(attr2, np.int64)
         _check(load_library().unify_set_attr2(self._h, a.ctypes.data, a.size))
 
+    def set_zorder(self, zmap, a1, a2) -> None:
+        """Both attributes of an index built on zorder_keys(zmap, a1, a2), indexed by external id,
+        for box searches (search with box=True).  Dropped by insert()."""
+        a1 = np.ascontiguousarray(a1, np.int64)
+        a2 = np.ascontiguousarray(a2, np.int64)
+        if a1.shape != a2.shape:
+            raise ValueError("a1 and a2 differ in size")
+        m = _zmap(zmap)
+        _check(load_library().unify_set_zorder(self._h, C.byref(m), a1.ctypes.data, a2.ctypes.data, a1.size))
+
     def set_precision(self, precision) -> None:
         """Store later searches rank by ("fp32", "bf16", "fp8"); builds the copy on first use."""
         prec = self._prec(precision)
@@ -282,7 +330,7 @@ class Index:
                rerank_mult: int = 0, tau_a: float = 0.0, tau_b: float = 0.0, stats: bool = False,
                out=None, stream=None, timing: bool = False, cand_cap: int = 0, visit_cap: int = 0, pre_chunk: int = 0,
                select_s1: bool = False, l2=None, h2=None, wave_scan: bool = False, waves_per_query: int = 0,
-               heavy_queries: int = 0, serial_phases: bool = False):
+               heavy_queries: int = 0, serial_phases: bool = False, box: bool = False):
         """Enqueues a search on the current stream (or `stream`) and returns torch tensors.
 
         queries: cuda float32 [nq, d]; l, h: cuda int64 [nq] (inclusive); strategy: None (auto),
@@ -292,7 +340,9 @@ class Index:
         attribute (conjunctive query; set_attr2 first).  wave_scan: pre-filter scans per
         wavefront instead of the shared matrix-core scan (same results).  serial_phases: the
         matrix-core scan before the graph search rather than beside it (same results; for
-        timing each phase alone).  Returns (ids, dist, strategy[, stats]).
+        timing each phase alone).  box: a box search on a z-order index (set_zorder first): l, h
+        range over the first attribute and l2, h2 over the second.  Returns (ids, dist,
+        strategy[, stats]).
         """
         import torch
         dev = torch.device("cuda", self.device)
@@ -323,15 +373,15 @@ class Index:
                       heavy_queries)
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         lib = load_library()
-        if (l2 is None) != (h2 is None):
-            raise ValueError("l2 and h2 go together")
+        if (l2 is None) != (h2 is None) or (box and l2 is None):
+            raise ValueError("l2 and h2 go together (and a box search needs them)")
         if l2 is not None:
             for t in (l2, h2):
                 if t.dtype != torch.int64 or t.device != dev or not t.is_contiguous() or t.shape != (nq,):
                     raise ValueError("l2 and h2 must be contiguous int64 [nq] tensors on the index's device")
-            rc = lib.unify_search_multi(self._h, _ptr(queries), nq, _ptr(l), _ptr(h), _ptr(l2), _ptr(h2), k, ef,
-                                        _ptr(st), C.byref(prm), _ptr(ids), _ptr(dist), _ptr(ost), _ptr(sts),
-                                        s.cuda_stream)
+            fn = lib.unify_search_box if box else lib.unify_search_multi
+            rc = fn(self._h, _ptr(queries), nq, _ptr(l), _ptr(h), _ptr(l2), _ptr(h2), k, ef, _ptr(st), C.byref(prm),
+                    _ptr(ids), _ptr(dist), _ptr(ost), _ptr(sts), s.cuda_stream)
         elif stats:
             rc = lib.unify_search_ex(self._h, _ptr(queries), nq, _ptr(l), _ptr(h), k, ef, _ptr(st), C.byref(prm),
                                      _ptr(ids), _ptr(dist), _ptr(ost), _ptr(sts), s.cuda_stream)

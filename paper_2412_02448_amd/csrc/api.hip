@@ -7,6 +7,7 @@
 #include <string>
 
 #include "unify_internal.h"
+#include "zorder.h"
 
 namespace unify {
 
@@ -19,6 +20,10 @@ int search_multi_impl(unify_index_t ix, const float* queries, int64_t nq, const 
                       const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef, const int8_t* strategy,
                       const unify_params* prm, int64_t* out_ids, float* out_dist, int8_t* out_strategy,
                       int32_t* out_stats, void* stream);
+int search_box_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l1, const int64_t* h1,
+                    const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef, const int8_t* strategy,
+                    const unify_params* prm, int64_t* out_ids, float* out_dist, int8_t* out_strategy,
+                    int32_t* out_stats, void* stream);
 int search_impl_noalloc(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
                         int32_t k, int32_t ef, const int8_t* strategy, const unify_params* prm, int64_t* out_ids,
                         float* out_dist, int8_t* out_strategy, int32_t* out_stats, void* stream);
@@ -318,6 +323,128 @@ int unify_search_multi(unify_index_t ix, const float* queries, int64_t nq, const
                        int32_t* out_stats, void* hip_stream) {
   return search_multi_impl(ix, queries, nq, l, h, l2, h2, k, ef, strategy, params, out_ids, out_dist, out_strategy,
                            out_stats, hip_stream);
+}
+
+int unify_search_box(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l1, const int64_t* h1,
+                     const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef, const int8_t* strategy,
+                     const unify_params* params, int64_t* out_ids, float* out_dist, int8_t* out_strategy,
+                     int32_t* out_stats, void* hip_stream) {
+  return search_box_impl(ix, queries, nq, l1, h1, l2, h2, k, ef, strategy, params, out_ids, out_dist, out_strategy,
+                         out_stats, hip_stream);
+}
+
+int unify_zorder_map(const int64_t* a1, const int64_t* a2, int64_t n, unify_zmap* out) {
+  if (!out || n < 0 || (n > 0 && (!a1 || !a2))) {
+    set_error("unify_zorder_map: null argument or negative count");
+    return UNIFY_EINVAL;
+  }
+  auto axis = [n](const int64_t* a, int64_t& base, int32_t& shift) {
+    base = 0;
+    shift = 0;
+    if (n == 0) return;
+    const auto mm = std::minmax_element(a, a + n);
+    base = *mm.first;
+    const uint64_t span = static_cast<uint64_t>(*mm.second) - static_cast<uint64_t>(*mm.first);
+    // the span's top bit lands on the axis's bit 30
+    if (span) shift = (64 - __builtin_clzll(span)) - 31;
+  };
+  axis(a1, out->base1, out->shift1);
+  axis(a2, out->base2, out->shift2);
+  return UNIFY_OK;
+}
+
+namespace {
+bool zmap_ok(const unify_zmap* m) {
+  return m && m->shift1 >= -30 && m->shift1 <= 63 && m->shift2 >= -30 && m->shift2 <= 63;
+}
+}  // namespace
+
+int unify_zorder_keys(const unify_zmap* map, const int64_t* a1, const int64_t* a2, int64_t n, int64_t* out) {
+  if (!zmap_ok(map) || n < 0 || (n > 0 && (!a1 || !a2 || !out))) {
+    set_error("unify_zorder_keys: null argument, negative count or a shift outside [-30, 63]");
+    return UNIFY_EINVAL;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    out[i] = zkey(zcoord(a1[i], map->base1, map->shift1), zcoord(a2[i], map->base2, map->shift2));
+  return UNIFY_OK;
+}
+
+int unify_set_zorder(unify_index_t ix, const unify_zmap* map, const int64_t* a1, const int64_t* a2, int64_t n) {
+  if (!ix || !zmap_ok(map) || (n > 0 && (!a1 || !a2))) {
+    set_error("unify_set_zorder: null argument or a shift outside [-30, 63]");
+    return UNIFY_EINVAL;
+  }
+  if (hipSetDevice(ix->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return UNIFY_EDEVICE;
+  }
+  std::unique_lock<std::shared_mutex> version(ix->version_mu);
+  const int64_t N = ix->dv.n;
+  if (n != N) {
+    set_error("unify_set_zorder: one pair per object of the index");
+    return UNIFY_EINVAL;
+  }
+  const std::vector<int64_t>& ext = ix->host.ext;
+  const std::vector<int64_t>& attr = ix->host.attr;
+  const int64_t ns = std::min<int64_t>(N, 2048);
+  const int64_t Nr = std::max<int64_t>(N, 1);
+  // a1, a2 in internal order, then the sampled pairs
+  std::vector<int64_t> buf((size_t)(2 * Nr + 2 * ns));
+  int64_t* b1 = buf.data();
+  int64_t* b2 = b1 + Nr;
+  for (int64_t i = 0; i < N; ++i) {
+    const int64_t e = ext[i];
+    if (e < 0 || e >= N) {
+      set_error("unify_set_zorder: the index's external ids are not 0 .. n-1");
+      return UNIFY_EINVAL;
+    }
+    b1[i] = a1[e];
+    b2[i] = a2[e];
+    if (attr[i] != zkey(zcoord(b1[i], map->base1, map->shift1), zcoord(b2[i], map->base2, map->shift2))) {
+      set_error("unify_set_zorder: the index is not built on these pairs' z-order keys");
+      return UNIFY_EINVAL;
+    }
+  }
+  int64_t* s1 = b2 + Nr;
+  int64_t* s2 = s1 + ns;
+  for (int64_t j = 0; j < ns; ++j) {
+    s1[j] = b1[j * N / ns];
+    s2[j] = b2[j * N / ns];
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(int64_t) * buf.size()) != hipSuccess) {
+    set_error("device allocation failed (z-order attributes)");
+    return UNIFY_ENOMEM;
+  }
+  if (hipMemcpy(p, buf.data(), sizeof(int64_t) * buf.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p);
+    set_error("host-to-device copy failed");
+    return UNIFY_EDEVICE;
+  }
+  // searches enqueued before (on any visited pool) may still read the previous arrays
+  if (hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(p);
+    set_error("hipDeviceSynchronize failed");
+    return UNIFY_EDEVICE;
+  }
+  void* old = const_cast<int64_t*>(ix->z.a1);
+  if (old) {
+    for (auto& q : ix->allocs)
+      if (q == old) q = nullptr;
+    (void)hipFree(old);
+  }
+  ix->allocs.push_back(p);
+  const int64_t* d = static_cast<const int64_t*>(p);
+  ix->z.a1 = d;
+  ix->z.a2 = d + Nr;
+  ix->z.s1 = d + 2 * Nr;
+  ix->z.s2 = d + 2 * Nr + ns;
+  ix->z.ns = (int32_t)ns;
+  ix->z.base1 = map->base1;
+  ix->z.base2 = map->base2;
+  ix->z.shift1 = map->shift1;
+  ix->z.shift2 = map->shift2;
+  return UNIFY_OK;
 }
 
 int unify_set_attr2(unify_index_t ix, const int64_t* attr2, int64_t n) {

@@ -1831,6 +1831,7 @@ int insert_impl(unify_index_t ix, const float* vectors, const int64_t* attr, con
   for (auto& e : ix->eps_of) e = nullptr;
   for (auto& e : ix->nrm_of) e = nullptr;
   ix->dv = nv;
+  ix->z = ZOrder{};  // the z-order attributes are set again for the grown index
   ix->host = std::move(H);
   ++ix->version;
   const int rc = quantize_store(ix, precision);

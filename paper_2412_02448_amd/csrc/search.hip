@@ -35,6 +35,7 @@
 #include "lowp.h"
 #include "unify_internal.h"
 #include "wave.h"
+#include "zorder.h"
 
 // Scratch of the allocation-free entry point (plans, work list and partial
 // lists of one call): one array in every GPU's memory from the moment the code
@@ -106,23 +107,28 @@ struct SearchArgs {
   int64_t mw_row0;
 };
 
-// Second attribute and per-query inclusive ranges of a conjunctive search.  The
-// search kernel reaches them through one pointer, read where a test is made, so
-// single-attribute searches hold no extra registers.
+// Second attribute and per-query inclusive ranges of a conjunctive search; for a
+// box search on a z-order index, both attributes and both ranges (attr1 is null
+// otherwise).  The search kernel reaches them through one pointer, read where a
+// test is made, so single-attribute searches hold no extra registers.
 struct ConjArgs {
   const int64_t* attr2;
   const int64_t* l2;
   const int64_t* h2;
+  const int64_t* attr1;
+  const int64_t* l1;
+  const int64_t* h1;
 };
 
-// The second-attribute test of a conjunctive query (always true for others).
+// The attribute test of a conjunctive or box query (always true for others).
 struct Sec {
   int32_t q;
 };
 __device__ __forceinline__ bool sec_ok(const SearchArgs& A, Sec s, int32_t v) {
   if (!A.conj) return true;
   const ConjArgs c = *A.conj;
-  return c.attr2[v] >= c.l2[s.q] && c.attr2[v] <= c.h2[s.q];
+  const bool in2 = c.attr2[v] >= c.l2[s.q] && c.attr2[v] <= c.h2[s.q];
+  return c.attr1 ? in2 && c.attr1[v] >= c.l1[s.q] && c.attr1[v] <= c.h1[s.q] : in2;
 }
 
 constexpr uint32_t HASH_EMPTY = 0xFFFFFFFFu;
@@ -170,8 +176,13 @@ __device__ int64_t upper_bound_i64(const int64_t* a, int64_t n, int64_t x) {
   return lo;
 }
 
+// Plans every query: its in-range id interval, strategy, active segments and the
+// pre-filter's chunks.  A box search (box != 0, z-order index z) takes l, h as the
+// first attribute's ranges and l2, h2 as the second's, and searches the key range
+// between the keys of the box's lower and upper corners, which holds every object
+// of the box (the coordinates and the key are non-decreasing).
 __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t* __restrict__ h,
-                       const int64_t* __restrict__ l2, const int64_t* __restrict__ h2,
+                       const int64_t* __restrict__ l2, const int64_t* __restrict__ h2, ZOrder z, int32_t box,
                        ConjArgs* __restrict__ conj, const int8_t* __restrict__ strat_in, int64_t nq, int64_t tauA, int64_t tauB,
                        int32_t k, int32_t chunk, int32_t tile_on, QPlan* __restrict__ plan,
                        int8_t* __restrict__ out_strat, int64_t* __restrict__ out_ids, float* __restrict__ out_dist,
@@ -183,10 +194,21 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
   const int64_t ns = (ix.n + stride - 1) / stride;
   for (int64_t j = threadIdx.x; j < ns; j += blockDim.x) samp[j] = ix.attr[j * stride];
   __syncthreads();
-  if (conj && blockIdx.x == 0 && threadIdx.x == 0) *conj = ConjArgs{ix.attr2, l2, h2};
+  if (conj && blockIdx.x == 0 && threadIdx.x == 0)
+    *conj = box ? ConjArgs{z.a2, l2, h2, z.a1, l, h} : ConjArgs{ix.attr2, l2, h2, nullptr, nullptr, nullptr};
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
-  const int64_t lq = l[q], hq = h[q];
+  int64_t lq = l[q], hq = h[q];
+  if (box) {
+    if (lq <= hq && l2[q] <= h2[q]) {
+      const int64_t zl = zkey(zcoord(lq, z.base1, z.shift1), zcoord(l2[q], z.base2, z.shift2));
+      hq = zkey(zcoord(hq, z.base1, z.shift1), zcoord(h2[q], z.base2, z.shift2));
+      lq = zl;
+    } else {
+      lq = 1;
+      hq = 0;
+    }
+  }
   int64_t lo = 0, hi = 0;
   if (lq <= hq) {
     // samp[a - 1] < lq <= samp[a] bounds the first attr >= lq to ((a-1) stride, a stride];
@@ -205,7 +227,22 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
   const bool bad = s < UNIFY_AUTO || s > UNIFY_POST;
   if (bad) Y = 0;
   if (s == UNIFY_AUTO) {
-    if (l2 && ix.n2s > 0) {
+    if (box) {
+      // box query: c of the ns sampled pairs lie in the box, an estimate of c n / ns
+      // objects.  Box objects lie in [lo, hi), so only the pairs at ids
+      // floor(j n / ns) in [lo, hi) -- j0 <= j < j1 -- can count.
+      int64_t c = 0;
+      if (Y > 0) {
+        const int64_t j0 = (lo * z.ns + ix.n - 1) / ix.n, j1 = (hi * z.ns + ix.n - 1) / ix.n;
+        const int64_t a1 = l[q], b1 = h[q], a2 = l2[q], b2 = h2[q];
+        for (int64_t j = j0; j < j1; ++j) {
+          const int64_t x = z.s1[j], y = z.s2[j];
+          c += x >= a1 && x <= b1 && y >= a2 && y <= b2;
+        }
+      }
+      const int64_t cn = c * ix.n;
+      s = (Y <= tauA || cn <= tauA * z.ns) ? UNIFY_PRE : (cn >= tauB * z.ns ? UNIFY_POST : UNIFY_HYBRID);
+    } else if (l2 && ix.n2s > 0) {
       // conjunctive query: the objects passing both ranges are estimated as Y times the
       // fraction c2 / n2s of the second attribute's sample inside its range
       const int64_t a2 = l2[q], b2 = h2[q];
@@ -2512,7 +2549,9 @@ struct Launch {
   const float* queries;
   int64_t nq;
   const int64_t *l, *h;
-  const int64_t *l2 = nullptr, *h2 = nullptr;  // conjunctive searches
+  const int64_t *l2 = nullptr, *h2 = nullptr;  // conjunctive and box searches
+  bool box = false;                             // box search on the z-order index z
+  ZOrder z;
   const int8_t* strategy;
   int64_t* out_ids;
   float* out_dist;
@@ -2728,7 +2767,8 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, const SideSt
   }
   const unsigned qb4 = (unsigned)((nq + 3) / 4);
   if (ev) HIP_OK(hipEventRecord(ev[0], st));
-  hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, X.dv, X.l, X.h, X.l2, X.h2,
+  hipLaunchKernelGGL(k_plan, dim3((unsigned)((nq + pb - 1) / pb)), dim3(pb), 0, st, X.dv, X.l, X.h, X.l2, X.h2, X.z,
+                     (int32_t)X.box,
                      const_cast<ConjArgs*>(X.A.conj), X.strategy, nq,
                      X.R.tauA, X.R.tauB, X.R.k, X.R.pre_chunk, (int32_t)X.tile, X.S.plan, X.out_strategy,
                      X.out_ids, X.out_dist, X.out_stats);
@@ -2797,15 +2837,19 @@ namespace {
 int search_common(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l, const int64_t* h,
                   const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef, const int8_t* strategy,
                   const unify_params* prm, int64_t* out_ids, float* out_dist, int8_t* out_strategy,
-                  int32_t* out_stats, void* stream) {
+                  int32_t* out_stats, void* stream, bool box = false) {
   if (!ix) {
     set_error("null index");
     return UNIFY_EINVAL;
   }
   std::shared_lock<std::shared_mutex> version(ix->version_mu);
-  if ((!l2) != (!h2) || (l2 && !ix->dv.attr2)) {
-    set_error(l2 && h2 ? "the index has no second attribute (unify_set_attr2)"
-                       : "l2 and h2 are given together");
+  if ((!l2) != (!h2)) {
+    set_error("l2 and h2 are given together");
+    return UNIFY_EINVAL;
+  }
+  if (box ? !ix->z.a1 : (l2 && !ix->dv.attr2)) {
+    set_error(box ? "the index has no z-order attributes (unify_set_zorder)"
+                  : "the index has no second attribute (unify_set_attr2)");
     return UNIFY_EINVAL;
   }
   Resolved R;
@@ -2833,6 +2877,8 @@ int search_common(unify_index_t ix, const float* queries, int64_t nq, const int6
   Launch X;
   rc = prepare_launch(ix, R, queries, nq, l, h, strategy, out_ids, out_dist, out_strategy, out_stats, scratch, pcap,
                       ix->pool, X, l2, h2);
+  X.box = box;
+  X.z = ix->z;
   if (timing) ix->timed_side = tile_beside(X);
   if (rc == UNIFY_OK) rc = make_side_for(ix->pool.side, X);
   if (rc == UNIFY_OK) rc = enqueue_launch(X, st, timing ? ix->ev : nullptr, ix->pool.side, &ix->pool);
@@ -2858,6 +2904,18 @@ int search_multi_impl(unify_index_t ix, const float* queries, int64_t nq, const 
   }
   return search_common(ix, queries, nq, l, h, l2, h2, k, ef, strategy, prm, out_ids, out_dist, out_strategy,
                        out_stats, stream);
+}
+
+int search_box_impl(unify_index_t ix, const float* queries, int64_t nq, const int64_t* l1, const int64_t* h1,
+                    const int64_t* l2, const int64_t* h2, int32_t k, int32_t ef, const int8_t* strategy,
+                    const unify_params* prm, int64_t* out_ids, float* out_dist, int8_t* out_strategy,
+                    int32_t* out_stats, void* stream) {
+  if (nq > 0 && (!l2 || !h2)) {
+    set_error("null second range");
+    return UNIFY_EINVAL;
+  }
+  return search_common(ix, queries, nq, l1, h1, l2, h2, k, ef, strategy, prm, out_ids, out_dist, out_strategy,
+                       out_stats, stream, true);
 }
 
 

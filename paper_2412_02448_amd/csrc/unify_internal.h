@@ -130,6 +130,19 @@ void pool_free(VisitPool& p);
 // version becomes resident).
 int ensure_pool(unify_index_t ix);
 
+// The two attributes of an index built on their z-order keys (box searches): device
+// arrays in internal-id order, the key map, and the pairs of the objects at internal
+// ids floor(j n / ns), j < ns = min(n, 2048), for the strategy rule.
+struct ZOrder {
+  const int64_t* a1 = nullptr;
+  const int64_t* a2 = nullptr;
+  const int64_t* s1 = nullptr;
+  const int64_t* s2 = nullptr;
+  int64_t base1 = 0, base2 = 0;
+  int32_t shift1 = 0, shift2 = 0;
+  int32_t ns = 0;
+};
+
 }  // namespace unify
 
 struct unify_index {
@@ -152,6 +165,7 @@ struct unify_index {
   uint64_t version = 0;
   std::map<std::pair<const void*, size_t>, int> occupancy;  // (kernel, LDS bytes) -> waves per CU
   unify::DevIndex dv{};
+  unify::ZOrder z;        // set by unify_set_zorder; dropped by an insertion
   unify::HostIndex host;  // small tables kept on the host; large ones released after upload
   std::vector<void*> allocs;
 };

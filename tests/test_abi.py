@@ -92,6 +92,11 @@ def test_entry_points_reject_bad_arguments_on_the_host():
     assert lib.unify_search_ex(null, null, 1, null, null, 10, 10, null, null, null, null, null, null, null) == EINVAL
     assert lib.unify_search_multi(null, null, 1, null, null, null, null, 10, 10, null, null, null, null, null, null,
                                   null) == EINVAL
+    assert lib.unify_search_box(null, null, 1, null, null, null, null, 10, 10, null, null, null, null, null, null,
+                                null) == EINVAL
+    assert lib.unify_set_zorder(null, null, null, null, 5) == EINVAL
+    assert lib.unify_zorder_map(null, null, 5, null) == EINVAL
+    assert lib.unify_zorder_keys(null, null, null, 5, null) == EINVAL
     assert lib.unify_insert(null, null, null, null, 5) == EINVAL
     assert lib.unify_set_attr2(null, null, 5) == EINVAL
     assert lib.unify_set_precision(null, 1) == EINVAL
@@ -153,3 +158,39 @@ def test_server_config_struct_matches_header():
         fields += [(n.strip(), typ) for n in names.split(",")]
     ctype = {"int32_t": C.c_int32, "int64_t": C.c_int64, "double": C.c_double, "unify_params": u._Params}
     assert [(n, ctype[t]) for n, t in fields] == list(u._ServerConfig._fields_)
+
+
+@pytest.mark.parametrize("kind", ["narrow", "wide", "full", "constant"])
+def test_zorder_map_and_keys_equal_oracle(kind):
+    # the library's host-side z-order map and keys (mask-spread interleave) against the
+    # oracle's bit-by-bit ones, integer for integer
+    import paper_2412_02448_amd as u
+    from oracle import hsig
+    rng = np.random.default_rng({"narrow": 1, "wide": 2, "full": 3, "constant": 4}[kind])
+    n = 5000
+    if kind == "narrow":
+        a1 = rng.integers(0, 1000, n, dtype=np.int64)
+        a2 = rng.integers(-50, 50, n, dtype=np.int64)
+    elif kind == "wide":
+        a1 = rng.integers(-(1 << 50), 1 << 50, n, dtype=np.int64)
+        a2 = rng.integers(0, 1 << 33, n, dtype=np.int64)
+    elif kind == "full":
+        a1 = rng.integers(-(1 << 63), (1 << 63) - 1, n, dtype=np.int64)
+        a2 = rng.integers(-(1 << 63), (1 << 63) - 1, n, dtype=np.int64)
+    else:
+        a1 = np.full(n, 7, np.int64)
+        a2 = rng.integers(0, 2, n, dtype=np.int64)
+    m = u.zorder_map(a1, a2)
+    assert m.tolist() == hsig.zorder_map(a1, a2).tolist()
+    # keys of the objects and of query bounds around and beyond them
+    b1 = np.concatenate([a1, a1 - 1, a1 + 1, [-(1 << 63), (1 << 63) - 1]])
+    b2 = np.concatenate([a2, a2 + 3, a2 - 3, [(1 << 63) - 1, -(1 << 63)]])
+    assert np.array_equal(u.zorder_keys(m, b1, b2), hsig.zorder_keys(m, b1, b2))
+
+
+def test_zorder_bad_map():
+    import paper_2412_02448_amd as u
+    with pytest.raises(u.UnifyError):
+        u.zorder_keys([0, -31, 0, 0], np.zeros(3, np.int64), np.zeros(3, np.int64))
+    with pytest.raises(u.UnifyError):
+        u.zorder_keys([0, 0, 0, 64], np.zeros(3, np.int64), np.zeros(3, np.int64))
