@@ -351,7 +351,8 @@ int unify_set_zorder(unify_index_t index, const unify_zmap* map, const int64_t* 
  * l2 <= A2 <= h2.  The HSIG is searched on the key range [key(u1(l1), u2(l2)),
  * key(u1(h1), u2(h2))], which holds every object of the box, and admits box objects
  * only (Alg. 7's ann admission, the post-filter test and the pre-filter scan test
- * both attributes).  Strategy rule (UNIFY_AUTO): with Y the objects of the key range
+ * both attributes; the pre-filter scan jumps over the key runs whose cells lie outside
+ * the box).  Strategy rule (UNIFY_AUTO): with Y the objects of the key range
  * and c the sampled pairs in the box (the pairs of the objects at internal ids
  * floor(j n / ns), j < ns = min(n, 2048)), pre-filter when Y <= tau_a n or
  * c n <= tau_a n ns, post-filter when c n >= tau_b n ns, else hybrid (tau_a n rounded

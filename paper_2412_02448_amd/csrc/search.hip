@@ -118,6 +118,8 @@ struct ConjArgs {
   const int64_t* attr1;
   const int64_t* l1;
   const int64_t* h1;
+  int64_t zb1, zb2;  // box searches: the key map
+  int32_t zs1, zs2;
 };
 
 // The attribute test of a conjunctive or box query (always true for others).
@@ -195,7 +197,8 @@ __global__ void k_plan(DevIndex ix, const int64_t* __restrict__ l, const int64_t
   for (int64_t j = threadIdx.x; j < ns; j += blockDim.x) samp[j] = ix.attr[j * stride];
   __syncthreads();
   if (conj && blockIdx.x == 0 && threadIdx.x == 0)
-    *conj = box ? ConjArgs{z.a2, l2, h2, z.a1, l, h} : ConjArgs{ix.attr2, l2, h2, nullptr, nullptr, nullptr};
+    *conj = box ? ConjArgs{z.a2, l2, h2, z.a1, l, h, z.base1, z.base2, z.shift1, z.shift2}
+                : ConjArgs{ix.attr2, l2, h2, nullptr, nullptr, nullptr, 0, 0, 0, 0};
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
   int64_t lq = l[q], hq = h[q];
@@ -871,6 +874,24 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
   return !__any(overflow);
 }
 
+// The pre-filter scan of a box query steps over the runs of its key range that lie
+// outside the box: from id i (inside the slice, below hi), the first id not before i
+// whose key can lie in the box -- i itself when its cell is in the box's cells, else
+// the first key at or above the next box key after i's (hi when there is none).  Cells
+// in the box hold every box object; wave-uniform.  Not inlined: its registers stay out
+// of the search kernels' budgets.
+__device__ __attribute__((noinline)) int32_t box_next(const SearchArgs& A, Sec s, int32_t i, int32_t hi) {
+  const ConjArgs c = *A.conj;
+  const uint64_t z = static_cast<uint64_t>(A.ix.attr[i]);
+  const uint64_t x = zcompact(z >> 1), y = zcompact(z);
+  const uint64_t x0 = zcoord(c.l1[s.q], c.zb1, c.zs1), x1 = zcoord(c.h1[s.q], c.zb1, c.zs1);
+  const uint64_t y0 = zcoord(c.l2[s.q], c.zb2, c.zs2), y1 = zcoord(c.h2[s.q], c.zb2, c.zs2);
+  if (x >= x0 && x <= x1 && y >= y0 && y <= y1) return i;
+  const int64_t nz = znext(z, static_cast<uint64_t>(zkey(x0, y0)), static_cast<uint64_t>(zkey(x1, y1)));
+  if (nz < 0) return hi;
+  return i + 1 + (int32_t)lower_bound_i64(A.ix.attr + i + 1, hi - i - 1, nz);
+}
+
 // Strategy A: exact top-k over the id slice [lo, hi) (FP32 store; PREC names
 // the kernel's ranking store, for which this is the fallback when it is not FP32).
 template <int NG, int PREC>
@@ -897,7 +918,7 @@ __device__ void pre_scan(const SearchArgs& A, const Lds& L, const float4 (&qv)[N
 // Strategy A for a conjunctive query: the slice's second attributes are tested
 // first, and the objects that pass are gathered (up to a wavefront's worth) and
 // scored with the FP32 distance.
-template <int NG, int PREC>
+template <int NG, int PREC, bool SKIP>
 __device__ void pre_scan_multi(const SearchArgs& A, const Lds& L, const float4 (&qv)[NG], const QPlan& P, Sec sec,
                                int& al, Counters& cnt) {
   const int lane = lane_id();
@@ -905,7 +926,8 @@ __device__ void pre_scan_multi(const SearchArgs& A, const Lds& L, const float4 (
   al = 0;
   for (int blk = 0; blk * WAVE < k; ++blk) L.ann[blk * WAVE + lane] = KEY_MAX;
   __syncthreads();
-  int base = P.lo;
+  const bool box = SKIP && A.conj->attr1 != nullptr;
+  int base = box && P.lo < P.hi ? box_next(A, sec, P.lo, P.hi) : P.lo;
   while (true) {
     // gather up to a wavefront's worth of passing ids into L.bkeys
     int nb = 0;
@@ -918,6 +940,7 @@ __device__ void pre_scan_multi(const SearchArgs& A, const Lds& L, const float4 (
       if (pass) L.bkeys[nb + rank_in(pm)] = (uint32_t)v;
       nb += c;
       base += WAVE;
+      if (box && base < P.hi) base = box_next(A, sec, base, P.hi);
     }
     if (nb == 0) break;
     __syncthreads();
@@ -1170,7 +1193,8 @@ __device__ void run_query(const SearchArgs& A, const Lds& L, int32_t q, int chun
     constexpr bool GATHER = NG <= 4 && PREC != UNIFY_FP8E4M3;
     bool fell = false;
     if (GATHER && A.conj) {
-      pre_scan_multi<NG, PREC>(A, L, qv, Pc, sec, al, cnt);
+      // (the S1 kernels, at the edge of their register budget, scan box slices whole)
+      pre_scan_multi<NG, PREC, !S1>(A, L, qv, Pc, sec, al, cnt);
     } else if (PREC == UNIFY_FP32 || A.conj || !pre_scan_lowp<NG, PREC>(A, L, qv, Pc, al, cnt)) {
       fell = PREC != UNIFY_FP32 && !A.conj;
       pre_scan<NG, PREC>(A, L, qv, Pc, sec, al, cnt);
