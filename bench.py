@@ -39,6 +39,8 @@ sys.path.insert(0, ROOT)
 os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
 
 HBM_PEAK_GBS = 8000.0
+# searches whose HIP-event phases are averaged for the rooflines (each synchronised)
+TIMED_REPS = 10
 HOST_SHARE = 16  # host cores that go with one GPU of the box
 METRIC = "QPS @ recall@10≥0.95, 1M×128 mixed ranges, FP32 vs BF16/FP8; HBM GB/s"
 PRECISIONS = ("fp32", "bf16", "fp8")
@@ -246,11 +248,9 @@ def main():
         sec, out = timed(m, ef, bp, ta=ta, tb=tb, vc=vc)
         rec = recall_of(out[0])
         store_rows[prec] = (out[0].cpu().numpy(), out[1].cpu().numpy())
-        ids, _, _, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True,
-                                        timing=True, **coop)
-        torch.cuda.synchronize()
-        pre_ms, _, rerun_ms = index.last_timing()
-        ph = index.last_timing_phases()
+        ph, _, (ids, _, _, stats) = timed_calls(index, Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb,
+                                                visit_cap=vc, **coop)
+        pre_ms, rerun_ms = ph["plan"], ph["rerun"]
         search_ms = ph["search"]
         st = stats.cpu().numpy().astype(np.int64)
         first = ((st[:, 3] & 0xFF) == 0) & ~tile_rows(st)
@@ -349,12 +349,10 @@ def main():
             f"ef={e}: {selection[f'{sel_name}_ef{e}']['qps']:,.0f} QPS r={selection[f'{sel_name}_ef{e}']['recall@10']}"
             for e in (16, 32, 64, 128)))
 
-    # ---- roofline of the search kernel: counters of one more (identical) call ----
-    ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True,
-                                           timing=True, **coop)
-    torch.cuda.synchronize()
-    pre_ms, _, rerun_ms = index.last_timing()
-    phases = index.last_timing_phases()
+    # ---- roofline of the search kernel: counters of identical calls, HIP events averaged ----
+    phases, (smin, smax), (ids, dist, strat, stats) = timed_calls(index, Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta,
+                                                                  tau_b=tb, visit_cap=vc, **coop)
+    pre_ms, rerun_ms = phases["plan"], phases["rerun"]
     search_ms = phases["search"]
     st = stats.cpu().numpy().astype(np.int64)
     first = ((st[:, 3] & 0xFF) == 0) & ~tile_rows(st)
@@ -368,7 +366,8 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(head, m, ef, bp, ta, tb, vc, coop.get("wave_scan"),
                                             coop.get("waves_per_query")), "bytes_per_launch": bytes_first,
-                "launch_ms": round(search_ms, 4), "rerun_launch_ms": round(rerun_ms, 4),
+                "launch_ms": round(search_ms, 4), "launch_ms_min_max": [round(smin, 4), round(smax, 4)],
+                "timed_calls": TIMED_REPS, "rerun_launch_ms": round(rerun_ms, 4),
                 "measured_copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "rerun_queries": int(((st[:, 3] & 0xFF) == 1).sum()), "failed_queries": int(((st[:, 3] & 0xFF) == 2).sum()),
                 "phases_ms": {kk: round(v, 4) for kk, v in phases.items()}}
@@ -641,9 +640,9 @@ def wide_bench(args):
             o = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t) / 5
-        ids, _, _, st = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True, timing=True)
-        torch.cuda.synchronize()
-        search_ms = index.last_timing()[1]
+        ph, _, (_, _, _, st) = timed_calls(index, Q, L, H, k, ef, reps=5, m=m, beam_p=bp, tau_a=ta, tau_b=tb,
+                                           visit_cap=vc)
+        search_ms = ph["search"]
         st = st.cpu().numpy().astype(np.int64)
         b = int(bytes_per_query(st, d, k, prec)[(st[:, 3] & 0xFF) == 0].sum())
         ids = o[0].cpu().numpy()
@@ -1151,9 +1150,26 @@ def cpu_baseline(args, W, index, ids, k, ef, m, bp, ta, tb, nq, prec):
     return cpu
 
 
+def timed_calls(index, Q, L, H, k, ef, reps=TIMED_REPS, **kw):
+    """reps searches with HIP-event timing, each synchronised before the next: the mean of
+    every phase (ms), its min and max for the graph-search phase, and the last call's
+    outputs (ids, dist, strategy, stats)."""
+    import torch
+    acc, lo, hi, out = {}, float("inf"), 0.0, None
+    for _ in range(reps):
+        out = index.search(Q, L, H, k, ef, stats=True, timing=True, **kw)
+        torch.cuda.synchronize()
+        ph = index.last_timing_phases()
+        for kk, v in ph.items():
+            acc[kk] = acc.get(kk, 0.0) + v
+        lo, hi = min(lo, ph["search"]), max(hi, ph["search"])
+    mean = {kk: v / reps for kk, v in acc.items()}
+    return mean, (lo, hi), out
+
+
 def source_hash():
     src = b"".join(open(os.path.join(ROOT, "paper_2412_02448_amd", "csrc", x), "rb").read()
-                   for x in ("search.hip", "wave.h", "lowp.h", "unify_internal.h"))
+                   for x in ("search.hip", "wave.h", "lowp.h", "unify_internal.h", "zorder.h"))
     return hashlib.sha256(src).hexdigest()
 
 
@@ -1189,11 +1205,9 @@ def profile_run(args, index, Q, L, H, k, spec, nq, build_s, prec):
         index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, **xk)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t) / args.steps
-    ids, dist, strat, stats = index.search(Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, stats=True,
-                                           timing=True, **xk)
-    torch.cuda.synchronize()
-    pre_ms, search_ms, rerun_ms = index.last_timing()
-    ph = index.last_timing_phases()
+    ph, (smin, smax), (ids, dist, strat, stats) = timed_calls(index, Q, L, H, k, ef, m=m, beam_p=bp, tau_a=ta,
+                                                              tau_b=tb, visit_cap=vc, **xk)
+    search_ms, rerun_ms = ph["search"], ph["rerun"]
     st = stats.cpu().numpy().astype(np.int64)
     b = int(bytes_per_query(st, spec.d, k, prec)[((st[:, 3] & 0xFF) == 0) & ~tile_rows(st)].sum())
     print(json.dumps({"profile_run": True, "store": prec, "m": m, "ef": ef, "beam_p": bp, "tau_a": ta, "tau_b": tb,
@@ -1201,6 +1215,7 @@ def profile_run(args, index, Q, L, H, k, spec, nq, build_s, prec):
                       "qps": round(nq / sec, 1), "phases_ms": {kk: round(v, 4) for kk, v in ph.items()},
                       "tile_scan": tile_roofline(st, ph, spec.d, k, prec, spec.n),
                       "ms_per_step": round(sec * 1e3, 4), "search_launch_ms": round(search_ms, 4),
+                      "search_launch_ms_min_max": [round(smin, 4), round(smax, 4)], "timed_calls": TIMED_REPS,
                       "rerun_launch_ms": round(rerun_ms, 4), "bytes_per_launch": b,
                       "achieved_GBps": round(b / (search_ms * 1e-3) / 1e9, 1), "build_s": round(build_s, 1),
                       "source_sha256": source_hash()}),

@@ -798,8 +798,9 @@ __device__ bool layer_search(const SearchArgs& A, const Lds& L, const float4 (&q
     // for one round of atomics on the visited row instead of one per block (which lane of
     // a batch claims a repeated id does not matter: the evaluated keys are admitted against
     // the pre-step threshold and kept in key order).  4 blocks in the BF16 kernel, 2 in the
-    // FP32 one; the FP8 kernel has no registers to spare and takes one at a time.
-    constexpr int TB = PREC == UNIFY_BF16 ? 4 : (PREC == UNIFY_FP32 ? 2 : 1);
+    // FP32 one; the FP8 kernel, and every kernel for rows wider than 256 elements (whose
+    // query alone holds 4 NG registers), have none to spare and take one at a time.
+    constexpr int TB = NG > 4 ? 1 : (PREC == UNIFY_BF16 ? 4 : (PREC == UNIFY_FP32 ? 2 : 1));
     for (int b0 = 0; b0 < ntot; b0 += TB * WAVE) {
       int32_t vv[TB];
       bool isn[TB];
