@@ -85,7 +85,7 @@ def parse():
     ap.add_argument("--cpu-queries", type=int, default=0, help="queries in the CPU sample (0: all)")
     ap.add_argument("--wpq", type=int, default=0, help="wavefronts per heavy graph search (0: the library default)")
     ap.add_argument("--heavy", type=int, default=0, help="heavy graph searches per batch (0: the library default)")
-    ap.add_argument("--inflight", type=int, default=2, help="serving slots in flight")
+    ap.add_argument("--inflight", type=int, default=3, help="serving slots in flight")
     ap.add_argument("--wave-scan", action="store_true",
                     help="--profile-run: pre-filter scans per wavefront instead of the matrix-core scan")
     ap.add_argument("--c5-only", action="store_true",
