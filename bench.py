@@ -321,6 +321,32 @@ def main():
     qps = nq / sec
     log(f"auto ({head}): {qps:,.0f} QPS ({sec * 1e3:.3f} ms/step) as a graph replay; "
         f"{nq / sec_eager:,.0f} QPS ({sec_eager * 1e3:.3f} ms/step) through per-call launches; same ids {same}")
+    # the same step from pinned host buffers: queries and ranges copied in, results copied out
+    # (the boundary takes device buffers; this is the rate a host-side caller sees)
+    hq, hl, hh = Q.cpu().pin_memory(), L.cpu().pin_memory(), H.cpu().pin_memory()
+    hids = torch.empty((nq, k), dtype=torch.int64).pin_memory()
+    hdist = torch.empty((nq, k), dtype=torch.float32).pin_memory()
+    dq, dl, dh = torch.empty_like(Q), torch.empty_like(L), torch.empty_like(H)
+
+    def host_step():
+        dq.copy_(hq, non_blocking=True)
+        dl.copy_(hl, non_blocking=True)
+        dh.copy_(hh, non_blocking=True)
+        o = index.search(dq, dl, dh, k, ef, m=m, beam_p=bp, tau_a=ta, tau_b=tb, visit_cap=vc, **coop)
+        hids.copy_(o[0], non_blocking=True)
+        hdist.copy_(o[1], non_blocking=True)
+
+    for _ in range(args.warmup):
+        host_step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        host_step()
+    torch.cuda.synchronize()
+    sec_host = (time.perf_counter() - t) / args.steps
+    host_same = bool(torch.equal(hids, out[0].cpu()))
+    log(f"from pinned host buffers (PCIe copies in the step): {nq / sec_host:,.0f} QPS "
+        f"({sec_host * 1e3:.3f} ms/step); same ids {host_same}")
     per_strategy = {}
     for name, sv in (("pre", u.PRE), ("hybrid", u.HYBRID), ("post", u.POST)):
         s, o = timed(m, ef, bp, sv, steps=max(1, args.steps // 2 + 1), warmup=1, ta=ta, tb=tb, vc=vc)
@@ -472,6 +498,10 @@ def main():
                    "build_s": round(build_s, 1)},
         "eager": {"qps": round(nq / sec_eager, 1), "ms_per_step": round(sec_eager * 1e3, 4),
                   "same_ids_as_graph": same},
+        "host_buffers": {"qps": round(nq / sec_host, 1), "ms_per_step": round(sec_host * 1e3, 4),
+                         "same_ids_as_graph": host_same,
+                         "what": "per-call search with the queries and ranges copied from pinned host "
+                                 "memory and the ids and distances copied back inside the step"},
         "by_precision": by_prec,
         "per_strategy": per_strategy,
         "fp32_strategies_by_ef": fp32_by_ef,

@@ -117,3 +117,45 @@ def test_box_edges_and_errors(zc):
         g.search(e[0], e[1], e[2], 10, 32, l2=e[3], h2=e[4], box=True)
     finally:
         g.close()
+
+
+def test_gpu_built_zorder_index_and_insertion():
+    """A z-order index built on the GPU: box pre-filter answers equal brute force; an
+    insertion drops the attached pairs (box searches refused) until they are attached again
+    for the grown index, whose box pre-filter answers again equal brute force."""
+    torch = _torch()
+    import paper_2412_02448_amd as u
+    spec = w.scaled(w.SPECS["hybrid10k"], n=3000, nq=40)
+    W = w.make(spec, base_seed=31)
+    a2, l2, h2 = w.second_attribute(spec.n, len(W.queries), base_seed=31)
+    zmap = u.zorder_map(W.attr, a2)
+    z = u.zorder_keys(zmap, W.attr, a2)
+    print("[case] GPU-built z-order index, then an insertion", flush=True)
+    g = u.Index.build(W.base[:2400], z[:2400], W.level_u[:2400], spec.S, spec.M, spec.ef_cons)
+    try:
+        Q, L, H, L2, H2 = _dev(W.queries, W.l, W.h, l2, h2)
+
+        def check(nobj):
+            ids, dist, _ = g.search(Q, L, H, 10, 32, strategy=hsig.PRE, l2=L2, h2=H2, box=True)
+            torch.cuda.synchronize()
+            ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+            X, A1, A2 = W.base[:nobj], W.attr[:nobj], a2[:nobj]
+            for i in range(len(W.queries)):
+                ok = (A1 >= W.l[i]) & (A1 <= W.h[i]) & (A2 >= l2[i]) & (A2 <= h2[i])
+                idx = np.nonzero(ok)[0]
+                dd = ((X[idx].astype(np.float64) - W.queries[i].astype(np.float64)) ** 2).sum(1)
+                want = np.sort(dd)[:10]
+                got = ids[i][ids[i] >= 0]
+                assert len(got) == len(want) and ok[got].all(), i
+                gd = ((X[got].astype(np.float64) - W.queries[i].astype(np.float64)) ** 2).sum(1)
+                np.testing.assert_allclose(gd, want, rtol=1e-6)  # the exact top 10 (ties aside)
+
+        g.set_zorder(zmap, W.attr[:2400], a2[:2400])
+        check(2400)
+        g.insert(W.base[2400:], z[2400:], W.level_u[2400:])
+        with pytest.raises(u.UnifyError):
+            g.search(Q, L, H, 10, 32, l2=L2, h2=H2, box=True)
+        g.set_zorder(zmap, W.attr, a2)
+        check(3000)
+    finally:
+        g.close()
