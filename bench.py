@@ -345,8 +345,25 @@ def main():
     torch.cuda.synchronize()
     sec_host = (time.perf_counter() - t) / args.steps
     host_same = bool(torch.equal(hids, out[0].cpu()))
+    # the copies alone, for the split of that step
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        dq.copy_(hq, non_blocking=True)
+        dl.copy_(hl, non_blocking=True)
+        dh.copy_(hh, non_blocking=True)
+    torch.cuda.synchronize()
+    sec_in = (time.perf_counter() - t) / args.steps
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        hids.copy_(out[0], non_blocking=True)
+        hdist.copy_(out[1], non_blocking=True)
+    torch.cuda.synchronize()
+    sec_out = (time.perf_counter() - t) / args.steps
+    in_b = hq.numel() * 4 + hl.numel() * 8 + hh.numel() * 8
+    out_b = hids.numel() * 8 + hdist.numel() * 4
     log(f"from pinned host buffers (PCIe copies in the step): {nq / sec_host:,.0f} QPS "
-        f"({sec_host * 1e3:.3f} ms/step); same ids {host_same}")
+        f"({sec_host * 1e3:.3f} ms/step); same ids {host_same}; copies alone: in {sec_in * 1e3:.3f} ms "
+        f"({in_b / sec_in / 1e9:.1f} GB/s), out {sec_out * 1e3:.3f} ms ({out_b / sec_out / 1e9:.1f} GB/s)")
     per_strategy = {}
     for name, sv in (("pre", u.PRE), ("hybrid", u.HYBRID), ("post", u.POST)):
         s, o = timed(m, ef, bp, sv, steps=max(1, args.steps // 2 + 1), warmup=1, ta=ta, tb=tb, vc=vc)
@@ -499,7 +516,9 @@ def main():
         "eager": {"qps": round(nq / sec_eager, 1), "ms_per_step": round(sec_eager * 1e3, 4),
                   "same_ids_as_graph": same},
         "host_buffers": {"qps": round(nq / sec_host, 1), "ms_per_step": round(sec_host * 1e3, 4),
-                         "same_ids_as_graph": host_same,
+                         "same_ids_as_graph": host_same, "copy_in_ms": round(sec_in * 1e3, 4),
+                         "copy_out_ms": round(sec_out * 1e3, 4), "copy_in_bytes": int(in_b),
+                         "copy_out_bytes": int(out_b),
                          "what": "per-call search with the queries and ranges copied from pinned host "
                                  "memory and the ids and distances copied back inside the step"},
         "by_precision": by_prec,

@@ -12,17 +12,18 @@
 // The choice between them is the range-aware rule of Sec. 4.2.
 //
 // A layer search keeps three structures in LDS:
-//   visited  an 8-way set-associative cache of ids, exact until a set
-//            overflows; then per-wave epoch tags in HBM (one u32 per object)
-//            take over, with the cache saving reads;
+//   visited  an 8-way set-associative cache of ids; an id whose set is full
+//            is decided by its bit in the wave's HBM bitmap row instead (each
+//            id lives in exactly one of the two), and a layer search that used
+//            the row clears the words it set before it returns;
 //   cand     an unsorted array of keys with tombstones; pop = wave argmin;
 //   ann      a sorted key list kept by bitonic block merges.
 // One step pops up to p candidates (p = 1 is the sequential loop), gathers
 // their unvisited neighbours, evaluates all distances at once, and admits each
 // neighbour against the threshold taken before the step.  With a strict total
 // order on keys this gives the same ann and the same stopping point as
-// evaluating the neighbours one at a time (the batch-admission argument of
-// the design notes).  If a query's candidate array outgrows its LDS capacity,
+// evaluating the neighbours one at a time: an entry a batch admits that the
+// sequential loop would reject has a key at or above the final threshold).  If a query's candidate array outgrows its LDS capacity,
 // the query is abandoned and re-run by a second launch with a larger array.
 // With a BF16 / FP8 store, graph results are re-scored in FP32 and the
 // pre-filter scan proves its result with error bounds.
@@ -646,7 +647,7 @@ __device__ __forceinline__ void lsync() {
 
 struct Counters {
   int32_t ndist = 0, nexp = 0, nrerank = 0, nadj = 0;
-  int32_t spill = 0;  // a layer search's visited set left the LDS cache for the HBM tag row
+  int32_t spill = 0;  // a layer search decided some ids in its HBM bitmap row (a cache set was full)
   int32_t coop = 0;   // the query ran as a cooperative (several-wavefront) search
 };
 constexpr int32_t STAT_SPILL_BIT = 0x100;  // status counter flag: the visited set spilled to HBM
@@ -1754,7 +1755,7 @@ struct TileArgs {
 // query, its threshold, and the count of queries per super-block.
 __global__ void __launch_bounds__(256) k_tile_prep(TileArgs T) {
   const int lane = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (q >= T.nq) return;  // uniform per wavefront
   const QPlan P = T.plan[q];
   if (P.strat != UNIFY_PRE || P.tsb == 0) return;
@@ -1789,50 +1790,53 @@ __global__ void __launch_bounds__(256) k_tile_prep(TileArgs T) {
 }
 
 // Offsets of the super-blocks' query lists and of their work items (one item =
-// one super-block and up to TILE_Q of its queries).  One block.
-__global__ void __launch_bounds__(1024) k_tile_index(TileArgs T) {
-  __shared__ int32_t sa[1024], sb[1024];
-  const int t = threadIdx.x, NT = blockDim.x;
-  const int64_t per = (T.nsb + NT - 1) / NT;
-  const int64_t b0 = std::min<int64_t>(T.nsb, t * per), b1 = std::min<int64_t>(T.nsb, b0 + per);
-  int32_t ca = 0, ci = 0;
-  for (int64_t b = b0; b < b1; ++b) {
-    const int32_t c = T.cnt_sb[b];
-    ca += c;
-    ci += (c + TILE_Q - 1) / TILE_Q;
+// one super-block and up to TILE_Q of its queries).  One wavefront: 64 super-blocks
+// per round, their counts scanned across the lanes, 8 rounds' counts loaded ahead.
+__global__ void __launch_bounds__(64) k_tile_index(TileArgs T) {
+  const int lane = lane_id();
+  constexpr int R = 8;
+  int32_t pa = 0, pi = 0;  // list entries and work items before this round (wave-uniform)
+  for (int64_t base = 0; base < T.nsb; base += R * WAVE) {
+    int32_t c[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t b = base + r * WAVE + lane;
+      c[r] = b < T.nsb ? T.cnt_sb[b] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t b = base + r * WAVE + lane;
+      const int32_t ni = (c[r] + TILE_Q - 1) / TILE_Q;
+      int32_t sa = c[r], si = ni;  // inclusive prefix sums over the lanes
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const int32_t va = __shfl_up(sa, o, WAVE), vi = __shfl_up(si, o, WAVE);
+        if (lane >= o) {
+          sa += va;
+          si += vi;
+        }
+      }
+      if (b < T.nsb) {
+        const int32_t oi = pi + si - ni;
+        T.off_sb[b] = pa + sa - c[r];
+        T.ioff[b] = oi;
+        T.fill_sb[b] = 0;
+        for (int j = 0; j < ni; ++j) T.item_sb[oi + j] = (int32_t)b;
+      }
+      pa += __shfl(sa, WAVE - 1, WAVE);
+      pi += __shfl(si, WAVE - 1, WAVE);
+    }
   }
-  sa[t] = ca;
-  sb[t] = ci;
-  __syncthreads();
-  for (int off = 1; off < NT; off <<= 1) {
-    const int32_t va = t >= off ? sa[t - off] : 0, vb = t >= off ? sb[t - off] : 0;
-    __syncthreads();
-    sa[t] += va;
-    sb[t] += vb;
-    __syncthreads();
-  }
-  int32_t pa = sa[t] - ca, pi = sb[t] - ci;
-  for (int64_t b = b0; b < b1; ++b) {
-    const int32_t c = T.cnt_sb[b];
-    T.off_sb[b] = pa;
-    T.ioff[b] = pi;
-    T.fill_sb[b] = 0;
-    const int ni = (c + TILE_Q - 1) / TILE_Q;
-    for (int j = 0; j < ni; ++j) T.item_sb[pi + j] = (int32_t)b;
-    pa += c;
-    pi += ni;
-  }
-  if (t == NT - 1) {
-    T.off_sb[T.nsb] = sa[t];
-    T.ioff[T.nsb] = sb[t];
-    T.counters[5] = sb[t];
+  if (lane == 0) {
+    T.off_sb[T.nsb] = pa;
+    T.ioff[T.nsb] = pi;
+    T.counters[5] = pi;
   }
 }
 
 // Every query of the matrix-core scan joins the list of each super-block it touches.
 __global__ void __launch_bounds__(256) k_tile_fill(TileArgs T) {
   const int lane = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (q >= T.nq) return;
   const QPlan P = T.plan[q];
   if (P.strat != UNIFY_PRE || P.tsb == 0) return;
@@ -2101,19 +2105,17 @@ __global__ void __launch_bounds__(64 * TILE_WAVES) k_tile_scan(TileArgs T) {
 // The records of a query are contiguous; they are read 4 entries per lane per
 // round (all loads of a round issued together).
 template <int NG>
-__global__ void __launch_bounds__(256) k_tile_final(TileArgs T, int64_t* __restrict__ out_ids,
-                                                    float* __restrict__ out_dist, int32_t* __restrict__ out_stats) {
-  __shared__ u64 lists[4][WAVE];  // list_insert works on whole 64-entry blocks
-  __shared__ u64 bk[4][WAVE];
-  const int lane = lane_id(), w = threadIdx.x >> 6;
-  const int64_t q = (int64_t)blockIdx.x * 4 + w;
-  if (q >= T.nq) return;  // uniform per wavefront
+__global__ void __launch_bounds__(64) k_tile_final(TileArgs T, int64_t* __restrict__ out_ids,
+                                                   float* __restrict__ out_dist, int32_t* __restrict__ out_stats) {
+  __shared__ u64 lst[WAVE];  // list_insert works on whole 64-entry blocks
+  __shared__ u64 keys[WAVE];
+  const int lane = lane_id();
+  const int64_t q = blockIdx.x;  // one wavefront per workgroup and query
+  if (q >= T.nq) return;
   const QPlan P = T.plan[q];
   if (P.strat != UNIFY_PRE || P.tsb == 0) return;
   const DevIndex& ix = T.ix;
   const int k = T.k, kcq = T.kcq;
-  u64* lst = lists[w];
-  u64* keys = bk[w];
   float4 qv[NG];
   {
     const int s = lane & 15, G = ix.d >> 2;
@@ -2815,13 +2817,15 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, const SideSt
     ts = side.tstream;
   }
   if (X.tile) {
-    hipLaunchKernelGGL(k_tile_prep, dim3(qb4), dim3(256), 0, ts, X.T);
-    hipLaunchKernelGGL(k_tile_index, dim3(1), dim3(1024), 0, ts, X.T);
-    hipLaunchKernelGGL(k_tile_fill, dim3(qb4), dim3(256), 0, ts, X.T);
+    // one-wavefront workgroups: beside the graph search they start as soon as any of its
+    // wavefronts leaves a SIMD, rather than waiting for several to leave one compute unit
+    hipLaunchKernelGGL(k_tile_prep, dim3((unsigned)nq), dim3(64), 0, ts, X.T);
+    hipLaunchKernelGGL(k_tile_index, dim3(1), dim3(64), 0, ts, X.T);
+    hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)nq), dim3(64), 0, ts, X.T);
     if (ev) HIP_OK(hipEventRecord(ev[2], ts));
     hipLaunchKernelGGL(X.scan_fn, dim3(X.scan_grid), dim3(64 * TILE_WAVES), X.scan_lds, ts, X.T);
     if (ev) HIP_OK(hipEventRecord(ev[3], ts));
-    hipLaunchKernelGGL(X.final_fn, dim3(qb4), dim3(256), 0, ts, X.T, X.out_ids, X.out_dist, X.out_stats);
+    hipLaunchKernelGGL(X.final_fn, dim3((unsigned)nq), dim3(64), 0, ts, X.T, X.out_ids, X.out_dist, X.out_stats);
     HIP_OK(hipGetLastError());
     if (ev) HIP_OK(hipEventRecord(ev[4], ts));
     if (tside) HIP_OK(hipEventRecord(side.tjoin, ts));
