@@ -1868,7 +1868,10 @@ __device__ __forceinline__ uint32_t kth_smallest4(const uint32_t (&u)[4], int k)
 // A operands, then lb / ub of every (query, object) of the super-block.
 constexpr int TILE_WAVES = 4;
 template <int PREC>
-__global__ void __launch_bounds__(64 * TILE_WAVES) k_tile_scan(TileArgs T) {
+__global__ void __launch_bounds__(64 * TILE_WAVES, 4) k_tile_scan(TileArgs T) {
+  // k-steps of loads in flight: 2 keeps a wavefront within 128 registers, so beside the
+  // graph search it fits where one search wavefront has left a SIMD
+  constexpr int KPF = PREC == UNIFY_BF16 ? 1 : 2;
   extern __shared__ __align__(16) unsigned char tile_lds[];
   const int lane = lane_id(), wv = threadIdx.x >> 6, tid = threadIdx.x;
   constexpr int NT = 64 * TILE_WAVES;
@@ -1952,11 +1955,11 @@ __global__ void __launch_bounds__(64 * TILE_WAVES) k_tile_scan(TileArgs T) {
         if constexpr (PREC == UNIFY_FP32) {
           // 16x16x4 FP32 MFMA: a k-step of 16 elements = 4 instructions; lane (n, kq) holds
           // elements 16 s + 4 kq .. + 3 of object n and of query n (as the A row).  Loads of
-          // 4 k-steps are issued before their products.
-          for (int s0 = 0; s0 < d / 16; s0 += 4) {
-            float4 x[4][4];
+          // KPF k-steps are issued before their products.
+          for (int s0 = 0; s0 < d / 16; s0 += KPF) {
+            float4 x[KPF][4];
 #pragma unroll
-            for (int ss = 0; ss < 4; ++ss)
+            for (int ss = 0; ss < KPF; ++ss)
 #pragma unroll
               for (int t = 0; t < 4; ++t) {
                 const int row = r0 + 16 * t + mrow, s = s0 + ss;
@@ -1965,7 +1968,7 @@ __global__ void __launch_bounds__(64 * TILE_WAVES) k_tile_scan(TileArgs T) {
                                : make_float4(0.f, 0.f, 0.f, 0.f);
               }
 #pragma unroll
-            for (int ss = 0; ss < 4; ++ss) {
+            for (int ss = 0; ss < KPF; ++ss) {
               if (s0 + ss >= d / 16) break;
               const float4 qa = *reinterpret_cast<const float4*>(af + mrow * stride + 16 * (s0 + ss) + 4 * kq);
 #pragma unroll
@@ -1980,11 +1983,11 @@ __global__ void __launch_bounds__(64 * TILE_WAVES) k_tile_scan(TileArgs T) {
         } else {
           // 16x16x32 BF16 MFMA: a k-step of 32 elements; lane (n, kq) holds elements
           // 32 s + 8 kq .. + 7 of object n and of query n (A); the query in two parts.
-          // Loads of 4 k-steps are issued before their products.
-          for (int s0 = 0; s0 < d / 32; s0 += 4) {
-            uint4 x[4][4];
+          // Loads of KPF k-steps are issued before their products.
+          for (int s0 = 0; s0 < d / 32; s0 += KPF) {
+            uint4 x[KPF][4];
 #pragma unroll
-            for (int ss = 0; ss < 4; ++ss)
+            for (int ss = 0; ss < KPF; ++ss)
 #pragma unroll
               for (int t = 0; t < 4; ++t) {
                 const int row = r0 + 16 * t + mrow, s = s0 + ss;
@@ -1999,7 +2002,7 @@ __global__ void __launch_bounds__(64 * TILE_WAVES) k_tile_scan(TileArgs T) {
                 }
               }
 #pragma unroll
-            for (int ss = 0; ss < 4; ++ss) {
+            for (int ss = 0; ss < KPF; ++ss) {
               if (s0 + ss >= d / 32) break;
               const int s = s0 + ss;
               const bf16x8_t qh = *reinterpret_cast<const bf16x8_t*>(ahi + mrow * stride + 32 * s + 8 * kq);
