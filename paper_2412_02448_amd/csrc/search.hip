@@ -1790,18 +1790,46 @@ __global__ void __launch_bounds__(256) k_tile_prep(TileArgs T) {
 }
 
 // Offsets of the super-blocks' query lists and of their work items (one item =
-// one super-block and up to TILE_Q of its queries).  One wavefront: 64 super-blocks
-// per round, their counts scanned across the lanes, 8 rounds' counts loaded ahead.
-__global__ void __launch_bounds__(64) k_tile_index(TileArgs T) {
-  const int lane = lane_id();
+// one super-block and up to TILE_Q of its queries).  One workgroup of NW wavefronts
+// (one for the index sizes whose scan runs beside the graph search, where a single
+// wavefront starts soonest; up to 16 for large indexes): wavefront w takes a
+// contiguous range of super-blocks, finds the list entries and items before it from
+// the other wavefronts' totals, and walks its range 64 super-blocks per round, their
+// counts scanned across the lanes, 8 rounds' counts loaded ahead.
+__global__ void __launch_bounds__(1024) k_tile_index(TileArgs T) {
+  __shared__ int32_t wa[16], wi[16];
+  const int lane = lane_id(), w = threadIdx.x >> 6, NW = blockDim.x >> 6;
+  const int64_t per = ((T.nsb + NW - 1) / NW + WAVE - 1) / WAVE * WAVE;
+  const int64_t b0 = std::min<int64_t>(T.nsb, w * per), b1 = std::min<int64_t>(T.nsb, b0 + per);
+  int32_t pa = 0, pi = 0;  // list entries and work items before the current round (wave-uniform)
+  if (NW > 1) {
+    int32_t ta = 0, ti = 0;
+    for (int64_t b = b0 + lane; b < b1; b += WAVE) {
+      const int32_t c = T.cnt_sb[b];
+      ta += c;
+      ti += (c + TILE_Q - 1) / TILE_Q;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      ta += __shfl_xor(ta, o, WAVE);
+      ti += __shfl_xor(ti, o, WAVE);
+    }
+    if (lane == 0) {
+      wa[w] = ta;
+      wi[w] = ti;
+    }
+    __syncthreads();
+    for (int j = 0; j < w; ++j) {
+      pa += wa[j];
+      pi += wi[j];
+    }
+  }
   constexpr int R = 8;
-  int32_t pa = 0, pi = 0;  // list entries and work items before this round (wave-uniform)
-  for (int64_t base = 0; base < T.nsb; base += R * WAVE) {
+  for (int64_t base = b0; base < b1; base += R * WAVE) {
     int32_t c[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t b = base + r * WAVE + lane;
-      c[r] = b < T.nsb ? T.cnt_sb[b] : 0;
+      c[r] = b < b1 ? T.cnt_sb[b] : 0;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -1815,7 +1843,7 @@ __global__ void __launch_bounds__(64) k_tile_index(TileArgs T) {
           si += vi;
         }
       }
-      if (b < T.nsb) {
+      if (b < b1) {
         const int32_t oi = pi + si - ni;
         T.off_sb[b] = pa + sa - c[r];
         T.ioff[b] = oi;
@@ -1826,7 +1854,8 @@ __global__ void __launch_bounds__(64) k_tile_index(TileArgs T) {
       pi += __shfl(si, WAVE - 1, WAVE);
     }
   }
-  if (lane == 0) {
+  // the last wavefront's range ends at nsb: its running totals are the grand totals
+  if (w == NW - 1 && lane == 0) {
     T.off_sb[T.nsb] = pa;
     T.ioff[T.nsb] = pi;
     T.counters[5] = pi;
@@ -2823,7 +2852,8 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, const SideSt
     // one-wavefront workgroups: beside the graph search they start as soon as any of its
     // wavefronts leaves a SIMD, rather than waiting for several to leave one compute unit
     hipLaunchKernelGGL(k_tile_prep, dim3((unsigned)nq), dim3(64), 0, ts, X.T);
-    hipLaunchKernelGGL(k_tile_index, dim3(1), dim3(64), 0, ts, X.T);
+    hipLaunchKernelGGL(k_tile_index, dim3(1), dim3(64 * (int)std::min<int64_t>(16, std::max<int64_t>(1, X.S.nsb / 4096))),
+                       0, ts, X.T);
     hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)nq), dim3(64), 0, ts, X.T);
     if (ev) HIP_OK(hipEventRecord(ev[2], ts));
     hipLaunchKernelGGL(X.scan_fn, dim3(X.scan_grid), dim3(64 * TILE_WAVES), X.scan_lds, ts, X.T);
