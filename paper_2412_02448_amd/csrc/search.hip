@@ -1791,8 +1791,8 @@ __global__ void __launch_bounds__(256) k_tile_prep(TileArgs T) {
 
 // Offsets of the super-blocks' query lists and of their work items (one item =
 // one super-block and up to TILE_Q of its queries).  One workgroup of NW wavefronts
-// (one for the index sizes whose scan runs beside the graph search, where a single
-// wavefront starts soonest; up to 16 for large indexes): wavefront w takes a
+// (beside the graph search, one for indexes up to a million objects, where a single
+// wavefront starts soonest, up to 16 for larger ones; 16 when it runs alone): wavefront w takes a
 // contiguous range of super-blocks, finds the list entries and items before it from
 // the other wavefronts' totals, and walks its range 64 super-blocks per round, their
 // counts scanned across the lanes, 8 rounds' counts loaded ahead.
@@ -1896,11 +1896,12 @@ __device__ __forceinline__ uint32_t kth_smallest4(const uint32_t (&u)[4], int k)
 // super-block and selects for queries w, w + 4, ...  LDS: the queries as MFMA
 // A operands, then lb / ub of every (query, object) of the super-block.
 constexpr int TILE_WAVES = 4;
-template <int PREC>
-__global__ void __launch_bounds__(64 * TILE_WAVES, 4) k_tile_scan(TileArgs T) {
-  // k-steps of loads in flight: 2 keeps a wavefront within 128 registers, so beside the
-  // graph search it fits where one search wavefront has left a SIMD
-  constexpr int KPF = PREC == UNIFY_BF16 ? 1 : 2;
+template <int PREC, bool ALONE>
+__global__ void __launch_bounds__(64 * TILE_WAVES, ALONE ? 1 : 4) k_tile_scan(TileArgs T) {
+  // k-steps of loads in flight: beside the graph search 1 (BF16) or 2 keep a wavefront
+  // within 128 registers, so it fits where one search wavefront has left a SIMD; run
+  // alone (before the graph search), 4 hide more latency
+  constexpr int KPF = ALONE ? 4 : (PREC == UNIFY_BF16 ? 1 : 2);
   extern __shared__ __align__(16) unsigned char tile_lds[];
   const int lane = lane_id(), wv = threadIdx.x >> 6, tid = threadIdx.x;
   constexpr int NT = 64 * TILE_WAVES;
@@ -2756,8 +2757,13 @@ int prepare_launch(unify_index_t ix, const Resolved& R, const float* queries, in
     T.bC = (float)(std::sqrt(1.0 + g) * (1.0 + w));
     T.bD = T.bC;
     X.T = T;
-    X.scan_fn = dv.precision == UNIFY_BF16 ? k_tile_scan<UNIFY_BF16>
-                : dv.precision == UNIFY_FP8E4M3 ? k_tile_scan<UNIFY_FP8E4M3> : k_tile_scan<UNIFY_FP32>;
+    // the scan runs alone when the phases run one after another, else beside the search
+    if (R.flags & UNIFY_FLAG_SERIAL_PHASES)
+      X.scan_fn = dv.precision == UNIFY_BF16 ? k_tile_scan<UNIFY_BF16, true>
+                  : dv.precision == UNIFY_FP8E4M3 ? k_tile_scan<UNIFY_FP8E4M3, true> : k_tile_scan<UNIFY_FP32, true>;
+    else
+      X.scan_fn = dv.precision == UNIFY_BF16 ? k_tile_scan<UNIFY_BF16, false>
+                  : dv.precision == UNIFY_FP8E4M3 ? k_tile_scan<UNIFY_FP8E4M3, false> : k_tile_scan<UNIFY_FP32, false>;
     const int ng = (dv.d + 63) / 64;
     X.final_fn = ng <= 2 ? k_tile_final<2> : (ng <= 4 ? k_tile_final<4> : k_tile_final<8>);
     X.scan_lds = (size_t)TILE_Q * (dv.d + 8) * 4 + 2 * (size_t)TILE_Q * TILE_ROWS * sizeof(float);
@@ -2852,8 +2858,8 @@ int enqueue_launch(const Launch& X, hipStream_t st, hipEvent_t* ev, const SideSt
     // one-wavefront workgroups: beside the graph search they start as soon as any of its
     // wavefronts leaves a SIMD, rather than waiting for several to leave one compute unit
     hipLaunchKernelGGL(k_tile_prep, dim3((unsigned)nq), dim3(64), 0, ts, X.T);
-    hipLaunchKernelGGL(k_tile_index, dim3(1), dim3(64 * (int)std::min<int64_t>(16, std::max<int64_t>(1, X.S.nsb / 4096))),
-                       0, ts, X.T);
+    const int nw = tside ? (int)std::min<int64_t>(16, std::max<int64_t>(1, X.S.nsb / 4096)) : 16;
+    hipLaunchKernelGGL(k_tile_index, dim3(1), dim3(64 * nw), 0, ts, X.T);
     hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)nq), dim3(64), 0, ts, X.T);
     if (ev) HIP_OK(hipEventRecord(ev[2], ts));
     hipLaunchKernelGGL(X.scan_fn, dim3(X.scan_grid), dim3(64 * TILE_WAVES), X.scan_lds, ts, X.T);
