@@ -63,7 +63,8 @@ def parse():
     ap.add_argument("--p", type=int, default=0, help="fixed beam width (0: tuned)")
     ap.add_argument("--tau-a", type=float, default=0.0, help="fixed tau_A fraction (0: tuned, with --tau-b)")
     ap.add_argument("--tau-b", type=float, default=0.5, help="tau_B fraction used with --tau-a")
-    ap.add_argument("--visit-cap", type=int, default=0, help="visited-cache entries for --profile-run (0: default)")
+    ap.add_argument("--visit-cap", type=int, default=0,
+                    help="visited-cache entries for --profile-run and the --c5-only server (0: default)")
     ap.add_argument("--precisions", default=",".join(PRECISIONS),
                     help="comma-separated vector stores to measure (fp32, bf16, fp8)")
     ap.add_argument("--recall-target", type=float, default=0.95)
@@ -1067,7 +1068,8 @@ def c5_bench(args):
         for rate in rates:
             cnt = min(n_eval, max(2000, int(rate * 0.5)))
             arrive = np.cumsum(rng.exponential(1.0 / rate, cnt))
-            srv = u.Server(index, kk, e2, max_batch=4096, inflight=args.inflight, m=m, beam_p=bp)
+            srv = u.Server(index, kk, e2, max_batch=4096, inflight=args.inflight, m=m, beam_p=bp,
+                           visit_cap=args.visit_cap)
             batch_cap, vrows, dev_b = srv.limits()
             t1 = time.perf_counter()
             got, _, lat = srv.wait(srv.submit(q[:cnt], l[:cnt], h[:cnt], arrive_s=arrive), timeout_s=300)
