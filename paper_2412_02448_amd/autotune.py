@@ -109,9 +109,11 @@ def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256),
     ok = [s for s in table if s.recall >= target and s.qps > 0]
     best = None
     if ok:
-        # settings within 2% of the fastest are within the timing noise: take the most accurate
+        # settings within 2% of the fastest are within the timing noise: take the smallest beam
+        # width among them (the least work per search, so the slowest search of a batch, which
+        # ends its step, is the shortest), then the most accurate
         top = max(s.qps for s in ok)
-        best = max((s for s in ok if s.qps >= 0.98 * top), key=lambda s: (s.recall, s.qps))
+        best = min((s for s in ok if s.qps >= 0.98 * top), key=lambda s: (s.beam_p, -s.recall, -s.qps))
     if best is not None:
         # the on-chip visited cache trades LDS (waves per CU) against HBM tag reads;
         # results do not depend on it

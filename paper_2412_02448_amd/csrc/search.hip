@@ -2195,7 +2195,20 @@ __global__ void __launch_bounds__(64) k_tile_final(TileArgs T, int64_t* __restri
   lst[lane] = KEY_MAX;
   al = 0;
   if (!over) {
-    // pass 2: canonical FP32 distances of the objects whose lb is not above thr
+    // pass 2: canonical FP32 distances of the objects whose lb is not above thr, gathered
+    // across the records into batches of up to a wavefront's worth before each evaluation
+    int acc = 0;  // gathered ids in keys[0, acc)
+    auto flush = [&]() {
+      wave_lds_sync();
+      eval_keys<NG, UNIFY_FP32, STREAM>(ix, qv, acc, [&](int x) { return key_id(keys[x]); }, keys);
+      wave_lds_sync();
+      const u64 key = lane < acc ? keys[lane] : KEY_MAX;
+      const u64 Tk = al == k ? lst[k - 1] : KEY_MAX;
+      if (__any(key < Tk)) list_insert(lst, al, k, key < Tk ? key : KEY_MAX);
+      wave_lds_sync();
+      nres += acc;
+      acc = 0;
+    };
     for (int b0 = 0; b0 < total; b0 += U * WAVE) {
       u64 rk[U];
       int rc[U];
@@ -2212,19 +2225,12 @@ __global__ void __launch_bounds__(64) k_tile_final(TileArgs T, int64_t* __restri
         const u64 um = ballot(use);
         const int nb = __popcll(um);
         if (nb == 0) continue;
-        if (use) keys[rank_in(um)] = (uint32_t)key_id(rk[u]);
-        wave_lds_sync();
-        eval_keys<NG, UNIFY_FP32, STREAM>(ix, qv, nb, [&](int x) { return key_id(keys[x]); }, keys);
-        wave_lds_sync();
-        const u64 key = lane < nb ? keys[lane] : KEY_MAX;
-        const u64 Tk = al == k ? lst[k - 1] : KEY_MAX;
-        if (__any(key < Tk)) {
-          list_insert(lst, al, k, key < Tk ? key : KEY_MAX);
-          wave_lds_sync();
-        }
-        nres += nb;
+        if (acc + nb > WAVE) flush();
+        if (use) keys[acc + rank_in(um)] = (uint32_t)key_id(rk[u]);
+        acc += nb;
       }
     }
+    if (acc > 0) flush();
   } else {
     for (int base = P.lo; base < P.hi; base += WAVE) {
       const int cntv = min(WAVE, P.hi - base);
