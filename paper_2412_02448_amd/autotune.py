@@ -39,6 +39,19 @@ class Setting:
                     pre_chunk=self.pre_chunk, wave_scan=self.wave_scan, waves_per_query=self.waves_per_query)
 
 
+
+def pick_best(table, target: float):
+    """The setting to keep among those measured: of the settings reaching the recall target,
+    those within 2% of the fastest are within the timing noise; among them the smallest beam
+    width (the least work per search, so the slowest search of a batch, which ends its step,
+    is the shortest), then the most accurate, then the fastest.  None when none reaches it."""
+    ok = [s for s in table if s.recall >= target and s.qps > 0]
+    if not ok:
+        return None
+    top = max(s.qps for s in ok)
+    return min((s for s in ok if s.qps >= 0.98 * top), key=lambda s: (s.beam_p, -s.recall, -s.qps))
+
+
 def recall_at_k(ids: np.ndarray, truth: np.ndarray) -> float:
     """Mean over queries of |found & exact| / |exact| (Eq. 1; |exact| = min(k, |R|)).
     Rows hold distinct ids padded with -1; a query with no exact answer counts 1."""
@@ -106,14 +119,7 @@ def tune(index, Q, L, H, k: int, target: float, ms=None, efs=(32, 64, 128, 256),
                     pending.remove(p)  # larger ef only costs more once the target is met
                     if log:
                         log(f"tune tau=({ta}, {tb}) m={m} ef={ef} p={p}: recall {rec:.4f}, {qps:,.0f} QPS")
-    ok = [s for s in table if s.recall >= target and s.qps > 0]
-    best = None
-    if ok:
-        # settings within 2% of the fastest are within the timing noise: take the smallest beam
-        # width among them (the least work per search, so the slowest search of a batch, which
-        # ends its step, is the shortest), then the most accurate
-        top = max(s.qps for s in ok)
-        best = min((s for s in ok if s.qps >= 0.98 * top), key=lambda s: (s.beam_p, -s.recall, -s.qps))
+    best = pick_best(table, target)
     if best is not None:
         # the on-chip visited cache trades LDS (waves per CU) against HBM tag reads;
         # results do not depend on it
